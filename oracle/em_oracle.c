@@ -1,0 +1,428 @@
+/*
+ * em_oracle.c -- plain, slow FP64 CPU oracle for the accelerated FFT scheme
+ * that computes the effective thermal conductivity tensor of a periodic
+ * voxelized three-phase RVE.
+ *
+ * TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the GPU path; both only consume the same
+ * phase image produced by the seeded input generator.
+ *
+ * Paper: S. Lemaitre, V. Salnikov, D. Choi, P. Karamian, "Computation of
+ * thermal properties via 3D homogenization of multiphase materials using
+ * FFT-based accelerated scheme", arXiv:1504.07499.
+ *   Sec. 3  problem statement (periodic RVE, Fourier's law, div phi = 0,
+ *           imposed mean gradient), eq. (1) polarization, eq. (3) Fourier
+ *           Lippmann-Schwinger equation, the Green operator Gamma^0 and the
+ *           Algorithm "FFT-based homogenization scheme for thermal
+ *           conductivity case" (steps 1-7), and L_hom from <phi>.
+ *   Sec. 5  reference medium L0 = -sqrt(min k * max k) I.
+ *
+ * Readings of the paper taken here (each is listed with its reason in the
+ * design notes of the repository):
+ *  R1  L0 = -k0 I with k0 = sqrt(min k * max k) > 0 (Sec. 5).  Putting this
+ *      negative L0 into steps 2, 4 and 7 gives
+ *          tau   = (k - k0) e                      (step 2, overall sign
+ *                                                   cancels with step 4)
+ *          c^(xi)= -xi (xi . tau^) / (k0 |xi|^2),  xi != 0   (step 4)
+ *          e+    = e + 2 k0/(k + k0) (c - e)        (step 7)
+ *      where e is the gradient iterate and c the compatible field.
+ *  R2  c^(0) = E (step 4): with the unnormalised DFT used here this is
+ *      c^(0) = M E, M = N^3.
+ *  R3  xi are the signed integer wavenumbers (the 2 pi / L factor cancels in
+ *      Gamma^0).  On an even grid the index N/2 is both +N/2 and -N/2: the
+ *      sign of such a Nyquist component is undetermined.  The operator used
+ *      at a mode is the average of xi xi^T / |xi|^2 over both signs of every
+ *      Nyquist component (each axis independently).  This keeps the discrete
+ *      problem covariant under the reflection of any single axis (a choice of
+ *      one sign, or the average over +-xi only, does not at modes with two or
+ *      more Nyquist components) and leaves every other mode unchanged.  The
+ *      averaged operator is even in xi, so the inverse DFT of the compatible
+ *      field is real; its real part is taken to drop rounding residue.
+ *  R4  Stop when eps_comp (step 6) < tol.  With the option eq_check the
+ *      paper's two-stage test of step 1 is used instead: stop only when
+ *      eps_comp < tol and eps_eq < tol, with the scale-free
+ *      eps_eq = sqrt(sum' |xi . phi^|^2 / |xi|^2) / |phi^(0)|, where sum'
+ *      runs over the modes xi != 0 on which the averaged operator of R3 is
+ *      the projection on xi: modes without a Nyquist component, and modes
+ *      whose only nonzero component is one Nyquist component.  On the other
+ *      Nyquist modes the sign average makes the operator a non-projection
+ *      and the discrete fixed point does not zero xi . phi^ there.
+ *  R5  <phi> (after the algorithm) is taken on the field updated in the
+ *      stopping iteration; column j of L_hom is <k e> for E = e_j.
+ *  R6  The three load cases E = e_1, e_2, e_3 are solved independently.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+#define ORC_OK 0
+#define ORC_NOT_CONVERGED 1
+#define ORC_ERR_ARG -1
+#define ORC_ERR_NONFINITE -5
+
+/* ------------------------------------------------------------------------
+ * Own FFT: recursive mixed-radix decimation in time.  Factors 2 and 3 are
+ * split off recursively; any other prime length falls back to the direct
+ * O(n^2) sum.  sign = -1 is the forward transform
+ *     X[k] = sum_n x[n] exp(-2 pi i k n / N),
+ * sign = +1 the unnormalised inverse.
+ * ---------------------------------------------------------------------- */
+
+/* w[j] = exp(sign 2 pi i j / N), j < N, computed directly in FP64. */
+static void twiddle_table(int n, int sign, cplx *w)
+{
+    for (int j = 0; j < n; ++j) {
+        double a = 2.0 * M_PI * (double)j / (double)n;
+        w[j] = cos(a) + (double)sign * sin(a) * I;
+    }
+}
+
+static int smallest_factor(int n)
+{
+    if (n % 2 == 0) return 2;
+    if (n % 3 == 0) return 3;
+    for (int p = 5; p * p <= n; p += 2)
+        if (n % p == 0) return p;
+    return n;
+}
+
+/* Transform n = ntop / stride_factor points read from in[0], in[is], ...,
+ * into out[0..n-1].  w is the table for the top-level length ntop. */
+static void fft_rec(const cplx *in, int is, cplx *out, int n, int ntop,
+                    const cplx *w)
+{
+    if (n == 1) {
+        out[0] = in[0];
+        return;
+    }
+    int p = smallest_factor(n);
+    int m = n / p;
+    int step = ntop / n; /* w_n^j = w_ntop^(j * step) */
+    if (p == n) {
+        /* direct sum for a prime length that is not 2 or 3 */
+        for (int k = 0; k < n; ++k) {
+            cplx s = 0;
+            for (int j = 0; j < n; ++j)
+                s += in[j * is] * w[((long)j * k % n) * step];
+            out[k] = s;
+        }
+        return;
+    }
+    /* sub-transforms of the p decimated sequences */
+    for (int q = 0; q < p; ++q)
+        fft_rec(in + q * is, is * p, out + q * m, m, ntop, w);
+    /* combine: X[k + s m] = sum_q w_n^(q (k + s m)) Y_q[k] */
+    cplx t[3];
+    for (int k = 0; k < m; ++k) {
+        for (int q = 0; q < p; ++q)
+            t[q] = out[q * m + k] * w[(q * k) * step];
+        for (int s = 0; s < p; ++s) {
+            cplx acc = 0;
+            for (int q = 0; q < p; ++q)
+                acc += t[q] * w[((q * s * m) % n) * step];
+            out[k + s * m] = acc;
+        }
+    }
+}
+
+/* 1D transform of a contiguous line in place; buf holds n points. */
+static void fft_line(cplx *line, int n, const cplx *w, cplx *buf)
+{
+    memcpy(buf, line, sizeof(cplx) * (size_t)n);
+    fft_rec(buf, 1, line, n, n, w);
+}
+
+/* Full complex 3D DFT of a [z][y][x] array (x fastest), in place,
+ * unnormalised, applied one axis at a time. */
+void orc_fft3(int n, double *data_ri, int sign)
+{
+    cplx *a = (cplx *)data_ri;
+    size_t nn = (size_t)n * n;
+    cplx *w = malloc(sizeof(cplx) * (size_t)n);
+    twiddle_table(n, sign, w);
+    #pragma omp parallel
+    {
+        cplx *line = malloc(sizeof(cplx) * (size_t)n);
+        cplx *buf = malloc(sizeof(cplx) * (size_t)n);
+        /* axis x */
+        #pragma omp for schedule(static)
+        for (long zy = 0; zy < (long)nn; ++zy)
+            fft_line(a + (size_t)zy * n, n, w, buf);
+        /* axis y */
+        #pragma omp for schedule(static)
+        for (long zx = 0; zx < (long)nn; ++zx) {
+            size_t z = (size_t)zx / n, x = (size_t)zx % n;
+            for (int y = 0; y < n; ++y) line[y] = a[z * nn + (size_t)y * n + x];
+            fft_line(line, n, w, buf);
+            for (int y = 0; y < n; ++y) a[z * nn + (size_t)y * n + x] = line[y];
+        }
+        /* axis z */
+        #pragma omp for schedule(static)
+        for (long yx = 0; yx < (long)nn; ++yx) {
+            for (int z = 0; z < n; ++z) line[z] = a[(size_t)z * nn + (size_t)yx];
+            fft_line(line, n, w, buf);
+            for (int z = 0; z < n; ++z) a[(size_t)z * nn + (size_t)yx] = line[z];
+        }
+        free(line);
+        free(buf);
+    }
+    free(w);
+}
+
+/* Signed wavenumber of index k on an n-point grid (R3). */
+static double wavenumber(int k, int n)
+{
+    return (k < (n + 1) / 2) ? (double)k : (double)(k - n);
+}
+
+static int is_nyquist(int k, int n)
+{
+    return n % 2 == 0 && k == n / 2;
+}
+
+/* Green symbol xi xi^T / |xi|^2 of mode (kx, ky, kz), averaged over the two
+ * signs of every Nyquist component (R3).  Mode 0 is not passed here. */
+static void green_symbol(int n, const int kk[3], double G[3][3])
+{
+    double xi[3];
+    int flip = 0;
+    for (int d = 0; d < 3; ++d) {
+        xi[d] = wavenumber(kk[d], n);
+        if (is_nyquist(kk[d], n)) flip |= 1 << d;
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) G[i][j] = 0.0;
+    int count = 0;
+    for (int s = 0; s < 8; ++s) {
+        if (s & ~flip) continue; /* only Nyquist components change sign */
+        double v[3];
+        for (int d = 0; d < 3; ++d) v[d] = ((s >> d) & 1) ? -xi[d] : xi[d];
+        double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) G[i][j] += v[i] * v[j] / v2;
+        ++count;
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) G[i][j] /= (double)count;
+}
+
+/* Step 4 (Sec. 3, Algorithm) with the Green operator of Sec. 3 for
+ * L0 = -k0 I:  c^(xi) = -G(xi) tau^(xi) / k0 for xi != 0, where
+ * G = xi xi^T / |xi|^2 (R3), and c^(0) = M E (R2).  tau_hat and c_hat are
+ * three full complex spectra (interleaved re/im), [comp][z][y][x]; they may
+ * alias. */
+void orc_green_apply(int n, double k0, const double E[3],
+                     const double *tau_hat_ri, double *c_hat_ri)
+{
+    size_t M = (size_t)n * n * n;
+    const cplx *t = (const cplx *)tau_hat_ri;
+    cplx *c = (cplx *)c_hat_ri;
+    #pragma omp parallel for schedule(static)
+    for (long idx = 0; idx < (long)M; ++idx) {
+        int kk[3] = {(int)(idx % n), (int)((idx / n) % n), (int)(idx / ((long)n * n))};
+        if (kk[0] == 0 && kk[1] == 0 && kk[2] == 0) {
+            for (int i = 0; i < 3; ++i) c[i * M + idx] = (double)M * E[i];
+            continue;
+        }
+        double G[3][3];
+        green_symbol(n, kk, G);
+        cplx tv[3] = {t[idx], t[M + idx], t[2 * M + idx]};
+        for (int i = 0; i < 3; ++i) {
+            cplx acc = 0;
+            for (int j = 0; j < 3; ++j) acc += G[i][j] * tv[j];
+            c[i * M + idx] = -acc / k0;
+        }
+    }
+}
+
+/* eps_eq of R4: phi^ = FFT(k e) for one load case; returns
+ * sqrt(sum_{xi != 0} |xi . phi^|^2 / |xi|^2) / |phi^(0)|. */
+static double equilibrium_error(int n, const double *kvox, const double *e3,
+                                cplx *work3)
+{
+    size_t M = (size_t)n * n * n;
+    for (int i = 0; i < 3; ++i) {
+        for (size_t v = 0; v < M; ++v) work3[i * M + v] = kvox[v] * e3[i * M + v];
+        orc_fft3(n, (double *)(work3 + i * M), -1);
+    }
+    double num = 0.0;
+    for (size_t idx = 1; idx < M; ++idx) {
+        int kk[3] = {(int)(idx % n), (int)((idx / n) % n), (int)(idx / ((size_t)n * n))};
+        int nnyq = 0, nreg = 0;
+        for (int d = 0; d < 3; ++d) {
+            if (is_nyquist(kk[d], n)) ++nnyq;
+            else if (kk[d] != 0) ++nreg;
+        }
+        /* R4: only modes where the averaged symbol is the projection on xi */
+        if (!(nnyq == 0 || (nnyq == 1 && nreg == 0))) continue;
+        double xi[3] = {wavenumber(kk[0], n), wavenumber(kk[1], n), wavenumber(kk[2], n)};
+        double xi2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+        cplx div = 0;
+        for (int j = 0; j < 3; ++j) div += xi[j] * work3[j * M + idx];
+        num += creal(div * conj(div)) / xi2;
+    }
+    double den = 0.0;
+    for (int i = 0; i < 3; ++i) den += creal(work3[i * M] * conj(work3[i * M]));
+    return sqrt(num) / sqrt(den);
+}
+
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
+/*
+ * The Algorithm of Sec. 3, run for the three load cases E = e_1, e_2, e_3.
+ *
+ *  n          grid points per side (M = n^3 voxels), n >= 1
+ *  phase      M phase ids, [z][y][x], 0 = matrix, 1 = inclusion, 2 = coating
+ *  kph        conductivities of the three phases (> 0)
+ *  tol        convergence criterion acc (>= 0; 0 runs exactly max_iter)
+ *  max_iter   iteration cap (>= 1)
+ *  eq_check   0: stop on eps_comp < tol;  1: two-stage test of step 1
+ *  init_field optional start field [lc][comp][z][y][x] (9 M), NULL = E
+ *  K          out, 9 doubles, K[i*3+j] = <k e_i> for load case j
+ *  iters      out, iterations (FFT round trips) per load case
+ *  status     out, per load case: 0 converged, 1 not converged, -5 non-finite
+ *  final_res  out, last eps_comp per load case
+ *  eps_eq     out (may be NULL), eps_eq of the final field per load case
+ *  hist       out (may be NULL), [lc][hist_cap] eps_comp history
+ *  out_field  out (may be NULL), final field, same layout as init_field
+ *  lc_mask    load cases to run (bit j = e_(j+1)); others are left at E with
+ *             K column, iters and residual zero
+ */
+int orc_homogenize(int n, const uint8_t *phase, const double kph[3], double tol,
+                   int max_iter, int eq_check, const double *init_field,
+                   double *K, int *iters, int *status, double *final_res,
+                   double *eps_eq, double *hist, int hist_cap, double *out_field,
+                   int lc_mask)
+{
+    if (n < 1 || max_iter < 1 || !(tol >= 0.0) || !phase || !kph || !K) return ORC_ERR_ARG;
+    for (int p = 0; p < 3; ++p)
+        if (!(kph[p] > 0.0) || !isfinite(kph[p])) return ORC_ERR_ARG;
+    size_t M = (size_t)n * n * n;
+    for (size_t v = 0; v < M; ++v)
+        if (phase[v] > 2) return ORC_ERR_ARG;
+
+    /* Sec. 5: L0 = -sqrt(min k * max k) I over the three given k (R1). */
+    double kmin = fmin(kph[0], fmin(kph[1], kph[2]));
+    double kmax = fmax(kph[0], fmax(kph[1], kph[2]));
+    double k0 = sqrt(kmin * kmax);
+
+    double *kvox = malloc(sizeof(double) * M);
+    double *e = malloc(sizeof(double) * 3 * M);
+    cplx *t = malloc(sizeof(cplx) * 3 * M);
+    if (!kvox || !e || !t) {
+        free(kvox); free(e); free(t);
+        return ORC_ERR_ARG;
+    }
+    for (size_t v = 0; v < M; ++v) kvox[v] = kph[phase[v]];
+
+    for (int lc = 0; lc < 3; ++lc) {
+        double E[3] = {0.0, 0.0, 0.0};
+        E[lc] = 1.0;
+        if (!((lc_mask >> lc) & 1)) {
+            for (int i = 0; i < 3; ++i) K[i * 3 + lc] = 0.0;
+            if (iters) iters[lc] = 0;
+            if (status) status[lc] = ORC_OK;
+            if (final_res) final_res[lc] = 0.0;
+            if (eps_eq) eps_eq[lc] = -1.0;
+            if (out_field)
+                for (int i = 0; i < 3; ++i)
+                    for (size_t v = 0; v < M; ++v)
+                        out_field[(size_t)(lc * 3 + i) * M + v] = E[i];
+            continue;
+        }
+        /* Initialize: grad theta^0 = grad Theta */
+        for (int i = 0; i < 3; ++i)
+            for (size_t v = 0; v < M; ++v)
+                e[i * M + v] = init_field ? init_field[(lc * 3 + i) * M + v] : E[i];
+
+        double F[3] = {0.0, 0.0, 0.0}, r = 0.0, eq = -1.0;
+        int st = ORC_NOT_CONVERGED, it = 0;
+        while (it < max_iter) {
+            eq = -1.0;
+            /* step 2: tau = (k - k0) e */
+            for (int i = 0; i < 3; ++i)
+                for (size_t v = 0; v < M; ++v)
+                    t[i * M + v] = (kvox[v] - k0) * e[i * M + v];
+            /* step 3: tau^ = FFT(tau) */
+            for (int i = 0; i < 3; ++i) orc_fft3(n, (double *)(t + i * M), -1);
+            /* step 4: Green operator, xi = 0 pinned to E */
+            orc_green_apply(n, k0, E, (const double *)t, (double *)t);
+            /* step 5: grad theta_comp = FFT^-1, real part (R3) */
+            for (int i = 0; i < 3; ++i) orc_fft3(n, (double *)(t + i * M), +1);
+            /* step 6: eps_comp = sqrt(<|e - c|^2>) / |E| */
+            double r2 = 0.0;
+            for (int i = 0; i < 3; ++i)
+                for (size_t v = 0; v < M; ++v) {
+                    double d = e[i * M + v] - creal(t[i * M + v]) / (double)M;
+                    r2 += d * d;
+                }
+            r = sqrt(r2 / (double)M);
+            /* step 7: e+ = e + 2 k0 / (k + k0) (c - e) */
+            for (int i = 0; i < 3; ++i)
+                for (size_t v = 0; v < M; ++v) {
+                    double c = creal(t[i * M + v]) / (double)M;
+                    double wgt = 2.0 * k0 / (kvox[v] + k0);
+                    e[i * M + v] += wgt * (c - e[i * M + v]);
+                }
+            /* <phi> of the updated field (R5): F_i = <k e_i> */
+            for (int i = 0; i < 3; ++i) {
+                double s = 0.0;
+                for (size_t v = 0; v < M; ++v) s += kvox[v] * e[i * M + v];
+                F[i] = s / (double)M;
+            }
+            if (hist && it < hist_cap) hist[lc * hist_cap + it] = r;
+            ++it;
+            if (!isfinite(r)) {
+                st = ORC_ERR_NONFINITE;
+                break;
+            }
+            if (r < tol) {
+                if (!eq_check) {
+                    st = ORC_OK;
+                    break;
+                }
+                /* step 1: second stage on the current iterate */
+                eq = equilibrium_error(n, kvox, e, t);
+                if (eq < tol) {
+                    st = ORC_OK;
+                    break;
+                }
+            }
+        }
+        for (int i = 0; i < 3; ++i) K[i * 3 + lc] = F[i];
+        if (iters) iters[lc] = it;
+        if (status) status[lc] = st;
+        if (final_res) final_res[lc] = r;
+        if (eps_eq) eps_eq[lc] = (eq >= 0.0) ? eq : equilibrium_error(n, kvox, e, t);
+        if (out_field) memcpy(out_field + (size_t)lc * 3 * M, e, sizeof(double) * 3 * M);
+    }
+    free(kvox);
+    free(e);
+    free(t);
+    return ORC_OK;
+}
