@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Throughput of the accelerated FFT homogenization solve on one MI355X.
+
+Workload (one "step" = one full solve, all three unit load cases, until every
+load case has eps_comp < 1e-6): a 128^3 periodic RVE with 50 RSA spheres at
+volume fraction 0.30 (coating included), coating layer l = 0.2, seed 2;
+conductivities matrix 0.2, inclusion 0.3, coating 400; FP32 FFT/update with
+FP64 reductions.  The phase image is generated and uploaded before the timed
+region; the timed region holds exactly --steps solves.
+
+metric: voxel-iterations per second per load case, i.e. sum over load cases
+of N^3 * iterations, divided by the wall time of the solves.
+
+Also reported: the roofline of the dominant kernel (algorithmic bytes per
+launch over its HIP-event-timed launch duration, against 8 TB/s), and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel-iters/s per load case; RVE solves/s + p50/p99 at 1e-4 tensor err"
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = {"workload": "rve128_50sph_f0.30_l0.20_seed2", "n": 128, "n_spheres": 50,
+            "volume_fraction": 0.30, "layer": 0.2, "seed": 2, "k_phases": [0.2, 0.3, 400.0],
+            "tol": 1e-6, "precision": "fp32 fft/update, fp64 reductions",
+            "load_cases": 3}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rve128_fp32.txt")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1504_07499_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, launches_bytes: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != kernel_source_hash():
+        return None
+    key = f"{kernel}_hbm_bytes_per_launch"
+    return float(vals[key]) if key in vals else None
+
+
+def cpu_baseline(phases, k, sample_iters: int):
+    import oracle
+
+    t0 = time.perf_counter()
+    r = oracle.homogenize(phases, k, tol=0.0, max_iter=sample_iters, lc_mask=1)
+    dt = time.perf_counter() - t0
+    m = phases.size
+    return {"value": m * int(r.iters[0]) / dt, "unit": "voxel-iters/s per load case",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{sample_iters} iterations of load case e_1 on the same 128^3 RVE "
+                      f"(FP64, own FFT, OpenMP), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-iters", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true",
+                    help="skip the per-launch HIP events (no roofline)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the solve of one RVE runs on one device and "
+              "independent RVEs need no communication; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+
+    import paper_1504_07499_amd as rh
+
+    w = WORKLOAD
+    n = w["n"]
+    k = np.array(w["k_phases"])
+    rve = rh.rve_create(n, w["n_spheres"], w["volume_fraction"], w["layer"], w["seed"])
+    for _ in range(args.warmup):
+        rh.homogenize(rve, k, w["tol"], precision=0)
+    timing = not args.no_timing
+    totals = {}
+    step_iters, step_ms, results = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = rh.homogenize(rve, k, w["tol"], precision=0, timing=timing)
+        results.append(res)
+        if timing:
+            for name, v in rh.rve_get_kernel_times(rve).items():
+                t = totals.setdefault(name, {"total_ms": 0.0, "launches": 0, "total_bytes": 0.0})
+                for key in t:
+                    t[key] += v[key]
+    wall = time.perf_counter() - t0
+    for res in results:
+        step_iters.append([int(i) for i in res.iters])
+        step_ms.append(res.solve_ms)
+    m = n ** 3
+    voxel_iters = sum(m * sum(it) for it in step_iters)
+    value = voxel_iters / wall
+    last = results[-1]
+
+    roofline = None
+    if timing and totals:
+        passes = {kname: v for kname, v in totals.items() if kname != "reduce" and v["launches"]}
+        dom = max(passes, key=lambda kk: passes[kk]["total_ms"])
+        d = passes[dom]
+        avg_ms = d["total_ms"] / d["launches"]
+        bytes_per_launch = d["total_bytes"] / d["launches"]
+        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        tr = measured_traffic(dom, bytes_per_launch)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
+                    "kernel": dom, "avg_launch_ms": round(avg_ms, 5),
+                    "algorithmic_bytes_per_launch": bytes_per_launch,
+                    "per_kernel_avg_ms": {kk: round(v["total_ms"] / max(v["launches"], 1), 5)
+                                          for kk, v in totals.items()}}
+
+    err = None
+    refs_path = os.path.join(ROOT, "tests", "golden", "oracle_refs.json")
+    if os.path.exists(refs_path):
+        with open(refs_path) as f:
+            refs = json.load(f)
+        ref = refs.get(w["workload"])
+        if ref:
+            Kr = np.array(ref["K"])
+            err = float(np.abs(last.K - Kr).max() / np.abs(Kr).max())
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from paper_1504_07499_amd import geom
+
+        ph, _, _ = geom.generate(n, w["n_spheres"], w["volume_fraction"], w["layer"], w["seed"])
+        cpu = cpu_baseline(ph, k, args.cpu_iters)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "voxel-iters/s per load case", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded RSA RVE)", "config": w,
+        "iters_per_load_case": step_iters[-1], "solves_per_s": args.steps / wall,
+        "device_solve_ms_median": float(np.median(step_ms)),
+        "tensor_err_vs_oracle": err, "lc_status": [int(s) for s in last.lc_status],
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    rve.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,173 @@
+/*
+ * rvehom.h -- C ABI of the MI355X library that computes the effective thermal
+ * conductivity tensor of a periodic voxelized three-phase RVE with the
+ * accelerated (Eyre-Milton) FFT scheme.
+ *
+ * Paper: S. Lemaitre, V. Salnikov, D. Choi, P. Karamian, arXiv:1504.07499.
+ *   Sec. 2  RVE generation (RSA spheres, voxelization, coating layer l).
+ *   Sec. 3  problem: periodic RVE V, phi = -L grad(theta), div(phi) = 0,
+ *           <grad(theta)> = grad(Theta) imposed; polarization eq. (1);
+ *           Lippmann-Schwinger eq. (3); Green operator Gamma^0; the
+ *           Algorithm "FFT-based homogenization scheme for thermal
+ *           conductivity case"; L_hom from <phi> = -L_hom grad(Theta).
+ *   Sec. 5  phase tensors k I and the reference medium
+ *           L0 = -sqrt(min k * max k) I.
+ *
+ * Conventions shared by every call:
+ *  - phase images are N^3 bytes, [z][y][x] with x fastest; 0 = matrix,
+ *    1 = inclusion, 2 = coating;
+ *  - k_phases[3] are the conductivities of matrix, inclusion, coating
+ *    (finite, > 0);
+ *  - the three load cases are the unit gradients E = e_1, e_2, e_3; column j
+ *    of K (K[i*3 + j], row-major) is <k e_i> for load case j, i.e. L_hom e_j;
+ *  - fields exchanged with the host are FP64, [lc][comp][z][y][x] (9 N^3);
+ *  - N must be one of the grid sizes the library was built for
+ *    (rve_supported_n); every call validates its arguments and returns an
+ *    rve_status; no call aborts or throws across the ABI;
+ *  - handles are not thread-safe: do not use one handle from two threads at
+ *    once.  Distinct handles may be used concurrently.
+ */
+#ifndef RVEHOM_H
+#define RVEHOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RVE_OK = 0,             /* converged: eps_comp < tol (and eps_eq < tol if asked) */
+    RVE_NOT_CONVERGED = 1,  /* max_iter reached; K holds the last iterate */
+    RVE_STALLED = 2,        /* no new residual minimum over stall_window iterations */
+    RVE_PENDING = 3,        /* serving: request not finished yet */
+    RVE_ERR_ARG = -1,       /* invalid argument; nothing was computed */
+    RVE_ERR_JAMMED = -2,    /* spheres could not be placed */
+    RVE_ERR_OOM = -3,       /* device or host allocation failed */
+    RVE_ERR_DEVICE = -4,    /* a HIP runtime call failed */
+    RVE_ERR_NONFINITE = -5  /* NaN/Inf met in the FP64 residual */
+} rve_status;
+
+typedef struct rve_s *rve_t;
+
+/* Geometry of Sec. 2: N^3 voxels, n_spheres identical spheres of volume
+ * fraction f (coating included), coating layer l = width / radius. */
+typedef struct {
+    int n;
+    int n_spheres;
+    double volume_fraction;
+    double layer;
+    uint64_t seed;
+} rve_geom;
+
+typedef struct {
+    int max_iter;           /* iteration cap; 0 = default 10000 */
+    int precision;          /* 0 = FP32 FFT/update with FP64 reductions, 1 = FP64 */
+    int equilibrium_check;  /* 1 = two-stage stop of step 1 (eps_comp then eps_eq) */
+    int stall_window;       /* -1 = default (50 in FP32, off in FP64), 0 = off */
+    int lc_mask;            /* load cases to solve, bit j = e_(j+1); 0 = all three */
+    int timing;             /* 1 = time every kernel launch with HIP events */
+    void *stream;           /* hipStream_t for all work, NULL = the handle's own */
+    const double *init_field; /* host, 9 N^3 FP64 start field, NULL = E */
+    double *out_field;      /* host, 9 N^3 FP64 final field, NULL = not returned */
+    void *workspace;        /* device buffer of >= rve_workspace_size bytes, or NULL
+                               (the library then allocates and caches its own) */
+    size_t workspace_bytes;
+} rve_opts;
+
+typedef struct {
+    double K[9];               /* L_hom, row-major, column j = load case e_(j+1) */
+    int iters[3];              /* FFT round trips per load case */
+    int status[3];             /* rve_status per load case */
+    double final_residual[3];  /* last eps_comp per load case */
+    double eps_eq[3];          /* equilibrium error of the final field (-1 if not computed) */
+    double solve_ms;           /* device time of the iteration phase (HIP events) */
+} rve_result;
+
+/* Per-kernel device time of the last homogenize call with opts.timing = 1,
+ * over the launches that did work (those of iterations before the last load
+ * case finished).  names: "fwd_plane", "zgreen", "inv_plane", "reduce".
+ * total_bytes: algorithmic HBM bytes of those launches (each pass reads and
+ * writes its fields once; load cases already converged are not counted). */
+typedef struct {
+    const char *name[4];
+    double total_ms[4];
+    int launches[4];
+    double total_bytes[4];
+} rve_kernel_times;
+
+/* Grid sizes N this build supports for a precision (0 FP32, 1 FP64).
+ * out: up to cap ints; count receives the number. */
+rve_status rve_supported_n(int precision, int *out, int cap, int *count);
+
+/* Sec. 2: RSA placement + voxelization of g, uploaded to the current HIP
+ * device.  RVE_ERR_ARG for n unsupported, n_spheres < 1, f or l outside
+ * (0, 1) or a sphere radius >= 0.5; RVE_ERR_JAMMED if the spheres do not
+ * fit.  *out is owned by the caller (rve_destroy). */
+rve_status rve_create(const rve_geom *g, rve_t *out);
+
+/* Same, from a caller phase image (host, n^3 bytes, copied). */
+rve_status rve_create_from_phases(int n, const uint8_t *phases, rve_t *out);
+
+/* Copy the phase image back (cap >= n^3 bytes). */
+rve_status rve_get_phases(rve_t rve, uint8_t *out, size_t cap);
+
+/* Sphere list of Sec. 2 (centre x, y, z and radius per sphere; coating
+ * included in the radius).  count = spheres written; layer may be NULL.
+ * An RVE made from a phase image has no spheres (count = 0). */
+rve_status rve_get_spheres(rve_t rve, double *xyzr, int cap, int *count, double *layer);
+
+/* Grid size of an RVE. */
+int rve_n(rve_t rve);
+
+/* Device workspace bytes homogenize needs for this RVE and precision. */
+size_t rve_workspace_size(rve_t rve, int precision);
+
+/* The Algorithm of Sec. 3 for the three load cases, on the GPU.
+ * k_phases: host, 3 conductivities; tol: convergence criterion acc (> 0,
+ * or 0 to run exactly max_iter iterations); opts may be NULL; out: host.
+ * residual_history: host [3][hist_cap] eps_comp per iteration, or NULL.
+ * Returns the worst per-load-case status (an error < 0 first, then
+ * NONFINITE, STALLED, NOT_CONVERGED, OK).  Stream-ordered on opts->stream;
+ * returns after the results are on the host. */
+rve_status homogenize(rve_t rve, const double k_phases[3], double tol, const rve_opts *opts,
+                      rve_result *out, double *residual_history, int hist_cap);
+
+/* Several RVEs (any mix of grid sizes) solved concurrently on the device.
+ * k_phases: [3*count]; tol: [count]; opts applies to all (its fields and
+ * workspace must be NULL); out: [count]. */
+rve_status homogenize_batch(int count, const rve_t *rves, const double *k_phases,
+                            const double *tol, const rve_opts *opts, rve_result *out);
+
+/* Kernel timings of the last homogenize call on this handle. */
+rve_status rve_get_kernel_times(rve_t rve, rve_kernel_times *out);
+
+/* Serving: a request loop that keeps fields resident on the device,
+ * admits requests by device-memory footprint and free slots, and advances
+ * all admitted requests together one iteration at a time (continuous
+ * batching).  precision as in rve_opts. */
+typedef struct rve_server_s *rve_server_t;
+rve_status rve_server_create(size_t hbm_budget_bytes, int max_slots, int precision,
+                             rve_server_t *out);
+/* Queue one solve; the geometry is generated on a host worker.  ticket out. */
+rve_status rve_server_submit(rve_server_t s, const rve_geom *g, const double k_phases[3],
+                             double tol, uint64_t *ticket);
+/* RVE_PENDING until done; then the result and latency (seconds from submit
+ * to completion).  A ticket can be collected once. */
+rve_status rve_server_poll(rve_server_t s, uint64_t ticket, rve_result *out, double *latency_s);
+/* Block until every submitted request has finished. */
+rve_status rve_server_drain(rve_server_t s);
+void rve_server_destroy(rve_server_t s);
+
+void rve_destroy(rve_t rve);
+
+/* Message of the last failed call on this thread ("" if none); valid until
+ * the next call on this thread. */
+const char *rve_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RVEHOM_H */

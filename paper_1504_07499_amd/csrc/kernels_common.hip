@@ -1,0 +1,167 @@
+// kernels_common.hip -- precision-independent kernels (the FP64 convergence
+// reduction) and the list of grid sizes compiled into this build.
+#include <hip/hip_runtime.h>
+
+#include "solver_ops.hpp"
+#include "solver_state.hpp"
+
+namespace rvehom {
+
+// ---------------------------------------------------------------------------
+// Fixed-order FP64 reduction of the partials, steps 6 / 1 convergence test,
+// <phi> of the updated field (L_hom column), per-load-case freeze.
+// One workgroup of 256 threads.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ part, int nper,
+                                                const DevParams *__restrict__ prm,
+                                                DevState *__restrict__ st, double *__restrict__ hist) {
+    __shared__ double red[4 * 4];
+    __shared__ double tot[3][4];
+    const int tid = threadIdx.x;
+    for (int lc = 0; lc < 3; ++lc) {
+        double r2 = 0.0, f[3] = {0.0, 0.0, 0.0};
+        if (!st->done[lc]) {
+            for (int c = 0; c < 3; ++c) {
+                const double *pc = part + (size_t)(3 * lc + c) * nper * 2;
+                for (int b = tid; b < nper; b += 256) {
+                    r2 += pc[2 * b];
+                    f[c] += pc[2 * b + 1];
+                }
+            }
+        }
+        double v[4] = {r2, f[0], f[1], f[2]};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_down(v[q], o, 64);
+        const int lane = tid & 63, wv = tid >> 6;
+        if (lane == 0)
+            for (int q = 0; q < 4; ++q) red[4 * wv + q] = v[q];
+        __syncthreads();
+        if (tid == 0)
+            for (int q = 0; q < 4; ++q) tot[lc][q] = red[q] + red[4 + q] + red[8 + q] + red[12 + q];
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    const int it = st->iter;
+    int all = 1;
+    for (int lc = 0; lc < 3; ++lc) {
+        if (st->done[lc]) continue;
+        const double eps = sqrt(tot[lc][0] * prm->invM);  // |E| = 1
+        st->res[lc] = eps;
+        for (int c = 0; c < 3; ++c) st->K[3 * c + lc] = tot[lc][1 + c] * prm->invM;
+        if (it < prm->hist_cap) hist[lc * prm->hist_cap + it] = eps;
+        int fin = 0, status = ST_NOT_CONVERGED;
+        if (!(eps == eps) || eps > 1e300) {
+            fin = 1;
+            status = ST_NONFINITE;
+        } else if (eps < prm->tol) {
+            if (prm->eq_check) {
+                // step 1, second stage: the equilibrium error decides (k_eq_reduce)
+                st->eq_pending[lc] = 1;
+                if (it + 1 >= prm->max_iter) fin = 1;
+            } else {
+                fin = 1;
+                status = ST_OK;
+            }
+        } else {
+            if (eps < st->best[lc]) {
+                st->best[lc] = eps;
+                st->best_it[lc] = it;
+            } else if (prm->stall_window > 0 && it - st->best_it[lc] >= prm->stall_window) {
+                fin = 1;
+                status = ST_STALLED;
+            }
+            if (!fin && it + 1 >= prm->max_iter) fin = 1;
+        }
+        if (fin) {
+            st->done[lc] = 1;
+            st->status[lc] = status;
+            st->iters[lc] = it + 1;
+        } else {
+            all = 0;
+        }
+    }
+    st->iter = it + 1;
+    st->all_done = all;
+}
+
+// Equilibrium error of the load cases marked eq_pending: fixed-order sum of
+// the k_zeq partials, eps_eq = sqrt(num) / sqrt(den).  During the solve
+// (final = 0, two-stage stop of step 1) a load case finishes when
+// eps_eq < tol; at the end of a solve (final = 1) the value is only stored.
+__global__ __launch_bounds__(256) void k_eq_reduce(const double *__restrict__ peq, int per_lc, int final,
+                                                   const DevParams *__restrict__ prm,
+                                                   DevState *__restrict__ st) {
+    __shared__ double red[2 * 4];
+    __shared__ double tot[3][2];
+    const int tid = threadIdx.x;
+    for (int lc = 0; lc < 3; ++lc) {
+        double v[2] = {0.0, 0.0};
+        if (st->eq_pending[lc])
+            for (int b = tid; b < per_lc; b += 256) {
+                v[0] += peq[((size_t)lc * per_lc + b) * 2];
+                v[1] += peq[((size_t)lc * per_lc + b) * 2 + 1];
+            }
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_down(v[q], o, 64);
+        const int lane = tid & 63, wv = tid >> 6;
+        if (lane == 0) {
+            red[2 * wv] = v[0];
+            red[2 * wv + 1] = v[1];
+        }
+        __syncthreads();
+        if (tid == 0)
+            for (int q = 0; q < 2; ++q) tot[lc][q] = red[q] + red[2 + q] + red[4 + q] + red[6 + q];
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    int all = 1;
+    for (int lc = 0; lc < 3; ++lc) {
+        if (st->eq_pending[lc]) {
+            const double eq = sqrt(tot[lc][0]) / sqrt(tot[lc][1]);
+            st->eps_eq[lc] = eq;
+            st->eq_pending[lc] = 0;
+            if (!final && eq < prm->tol) {
+                // converged in the iteration just reduced (iter already advanced)
+                st->done[lc] = 1;
+                st->status[lc] = ST_OK;
+                st->iters[lc] = st->iter;
+            }
+        }
+        all &= st->done[lc];
+    }
+    st->all_done = all;
+}
+
+// Mark every solved load case for a final equilibrium-error evaluation.
+__global__ void k_eq_request(const DevParams *__restrict__ prm, DevState *__restrict__ st) {
+    if (threadIdx.x == 0)
+        for (int lc = 0; lc < 3; ++lc) st->eq_pending[lc] = (prm->lc_mask >> lc) & 1;
+}
+
+void launch_eq_reduce(const LaunchArgs &a, int per_lc, int final, hipStream_t s) {
+    hipLaunchKernelGGL(k_eq_reduce, dim3(1), dim3(256), 0, s, a.peq, per_lc, final, a.prm, a.st);
+}
+
+void launch_eq_request(const LaunchArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_eq_request, dim3(1), dim3(64), 0, s, a.prm, a.st);
+}
+
+void launch_reduce(const LaunchArgs &a, int nper, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, a.part, nper, a.prm, a.st, a.hist);
+}
+
+static const int kSizesF32[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 256};
+static const int kSizesF64[] = {8, 12, 16, 24, 32, 48, 64, 96, 128};
+
+int supported_sizes(int precision, const int **list) {
+    if (precision == 0) {
+        *list = kSizesF32;
+        return (int)(sizeof(kSizesF32) / sizeof(int));
+    }
+    *list = kSizesF64;
+    return (int)(sizeof(kSizesF64) / sizeof(int));
+}
+
+}  // namespace rvehom

@@ -1,0 +1,684 @@
+// rvehom_api.hip -- host side of the C ABI declared in include/rvehom.h:
+// RVE handles, device workspaces, the iteration driver with on-device
+// convergence, batched solves and kernel timing.
+//
+// Paper: arXiv:1504.07499.  The driver runs the Algorithm of Sec. 3
+// (initialise with grad Theta, iterate steps 2-7 until eps_comp < acc, then
+// L_hom from <phi>) for the three unit load cases at once; the reference
+// medium is the one of Sec. 5.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rvegeom.h"
+#include "rvehom.h"
+#include "rvehom_internal.hpp"
+#include "solver_ops.hpp"
+#include "solver_state.hpp"
+
+namespace rvehom {
+
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+void clear_error() { g_err.clear(); }
+
+const SolverOps *lookup_ops(int precision, int n) {
+    if (precision == 0) return ops_f32(n);
+    if (precision == 1) return ops_f64(n);
+    return nullptr;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+WsLayout ws_layout(const SolverOps *o) {
+    WsLayout L{};
+    const size_t n = (size_t)o->n, M = n * n * n, rb = o->real_bytes;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off += align256(bytes);
+        return at;
+    };
+    L.e = take(9 * M * rb);
+    L.spec = take(o->spec_elems * 2 * rb);
+    L.nyq = take(o->nyq_elems * 2 * rb);
+    L.tw = take(n * 2 * rb);
+    L.part = take((size_t)9 * o->nper * 2 * sizeof(double));
+    L.prm = take(sizeof(DevParams));
+    L.st = take(sizeof(DevState));
+    L.hist = take((size_t)3 * kHistCap * sizeof(double));
+    L.peq = take((size_t)3 * o->eq_tiles * 2 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+#define HIP_CHECK(call)                                                                   \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            set_error("%s failed: %s", #call, hipGetErrorString(e_));                     \
+            return RVE_ERR_DEVICE;                                                        \
+        }                                                                                 \
+    } while (0)
+
+Solver::~Solver() { release(); }
+
+void Solver::release() {
+    if (owned && ws) (void)hipFree(ws);
+    ws = nullptr;
+    owned = false;
+    ws_bytes = 0;
+    tw_ready = false;
+    if (own_stream) (void)hipStreamDestroy(own_stream);
+    own_stream = nullptr;
+    for (auto ev : poll_ev) (void)hipEventDestroy(ev);
+    poll_ev.clear();
+    for (auto ev : time_ev) (void)hipEventDestroy(ev);
+    time_ev.clear();
+    if (run_ev[0]) (void)hipEventDestroy(run_ev[0]);
+    if (run_ev[1]) (void)hipEventDestroy(run_ev[1]);
+    run_ev[0] = run_ev[1] = nullptr;
+    if (h_pinned) (void)hipHostFree(h_pinned);
+    h_pinned = nullptr;
+}
+
+// Allocate (or adopt) the workspace and the per-solver HIP objects.
+int Solver::prepare(const SolverOps *o, void *user_ws, size_t user_bytes) {
+    if (ops != o) {
+        release();
+        ops = o;
+    }
+    const WsLayout L = ws_layout(o);
+    if (user_ws) {
+        if (user_bytes < L.total) {
+            set_error("workspace of %zu bytes is smaller than the %zu bytes needed", user_bytes, L.total);
+            return RVE_ERR_ARG;
+        }
+        if (((uintptr_t)user_ws & 255) != 0) {
+            set_error("workspace must be 256-byte aligned");
+            return RVE_ERR_ARG;
+        }
+        if (owned && ws) (void)hipFree(ws);
+        if (ws != user_ws) tw_ready = false;
+        ws = user_ws;
+        owned = false;
+        ws_bytes = user_bytes;
+    } else if (!ws || !owned) {
+        void *p = nullptr;
+        if (hipMalloc(&p, L.total) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("hipMalloc of %zu workspace bytes failed", L.total);
+            return RVE_ERR_OOM;
+        }
+        ws = p;
+        owned = true;
+        ws_bytes = L.total;
+        tw_ready = false;
+    }
+    layout = L;
+    if (!own_stream) HIP_CHECK(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
+    if (poll_ev.empty()) {
+        poll_ev.resize(kPollSlots);
+        for (auto &ev : poll_ev) HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    if (!run_ev[0]) {
+        HIP_CHECK(hipEventCreate(&run_ev[0]));
+        HIP_CHECK(hipEventCreate(&run_ev[1]));
+    }
+    if (!h_pinned) {
+        // [DevParams | DevState | poll flags] in one pinned block
+        HIP_CHECK(hipHostMalloc(&h_pinned, 4096, hipHostMallocDefault));
+    }
+    return RVE_OK;
+}
+
+LaunchArgs Solver::args(const uint8_t *d_phase) const {
+    char *b = (char *)ws;
+    LaunchArgs a;
+    a.e = b + layout.e;
+    a.ph = d_phase;
+    a.spec = b + layout.spec;
+    a.nyq = b + layout.nyq;
+    a.tw = b + layout.tw;
+    a.prm = (const DevParams *)(b + layout.prm);
+    a.st = (DevState *)(b + layout.st);
+    a.part = (double *)(b + layout.part);
+    a.hist = (double *)(b + layout.hist);
+    a.peq = (double *)(b + layout.peq);
+    return a;
+}
+
+int Solver::ensure_twiddles(hipStream_t s) {
+    if (tw_ready) return RVE_OK;
+    const int n = ops->n;
+    std::vector<double> w64(2 * (size_t)n);
+    for (int m = 0; m < n; ++m) {
+        // exp(-2 pi i m / n) in FP64, rounded once to the working precision
+        const double a = 2.0 * M_PI * (double)m / (double)n;
+        w64[2 * m] = std::cos(a);
+        w64[2 * m + 1] = -std::sin(a);
+    }
+    char *dst = (char *)ws + layout.tw;
+    if (ops->real_bytes == sizeof(float)) {
+        std::vector<float> w32(w64.begin(), w64.end());
+        HIP_CHECK(hipMemcpyAsync(dst, w32.data(), w32.size() * sizeof(float), hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+    } else {
+        HIP_CHECK(hipMemcpyAsync(dst, w64.data(), w64.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+    }
+    tw_ready = true;
+    return RVE_OK;
+}
+
+}  // namespace rvehom
+
+using namespace rvehom;
+
+// ---------------------------------------------------------------------------
+// Handles
+// ---------------------------------------------------------------------------
+extern "C" const char *rve_last_error(void) { return g_err.c_str(); }
+
+extern "C" rve_status rve_supported_n(int precision, int *out, int cap, int *count) {
+    clear_error();
+    if ((precision != 0 && precision != 1) || !count || (cap > 0 && !out) || cap < 0) {
+        set_error("rve_supported_n: bad arguments");
+        return RVE_ERR_ARG;
+    }
+    const int *list = nullptr;
+    const int k = supported_sizes(precision, &list);
+    for (int i = 0; i < k && i < cap; ++i) out[i] = list[i];
+    *count = k;
+    return RVE_OK;
+}
+
+static bool size_supported(int n) {
+    return lookup_ops(0, n) != nullptr || lookup_ops(1, n) != nullptr;
+}
+
+static rve_status upload_rve(rve_s *r) {
+    const size_t M = (size_t)r->n * r->n * r->n;
+    HIP_CHECK(hipGetDevice(&r->device));
+    if (hipMalloc(&r->d_phase, M) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of the %zu-byte phase image failed", M);
+        return RVE_ERR_OOM;
+    }
+    HIP_CHECK(hipMemcpy(r->d_phase, r->h_phase.data(), M, hipMemcpyHostToDevice));
+    return RVE_OK;
+}
+
+extern "C" rve_status rve_create_from_phases(int n, const uint8_t *phases, rve_t *out) {
+    clear_error();
+    if (!out || !phases || !size_supported(n)) {
+        set_error("rve_create_from_phases: null pointer or unsupported grid size %d", n);
+        return RVE_ERR_ARG;
+    }
+    *out = nullptr;
+    const size_t M = (size_t)n * n * n;
+    for (size_t v = 0; v < M; ++v)
+        if (phases[v] > 2) {
+            set_error("phase id %d at voxel %zu is not 0, 1 or 2", (int)phases[v], v);
+            return RVE_ERR_ARG;
+        }
+    rve_s *r = new (std::nothrow) rve_s();
+    if (!r) return RVE_ERR_OOM;
+    r->n = n;
+    r->h_phase.assign(phases, phases + M);
+    rve_status st = upload_rve(r);
+    if (st != RVE_OK) {
+        delete r;
+        return st;
+    }
+    *out = r;
+    return RVE_OK;
+}
+
+extern "C" rve_status rve_create(const rve_geom *g, rve_t *out) {
+    clear_error();
+    if (!g || !out) {
+        set_error("rve_create: null pointer");
+        return RVE_ERR_ARG;
+    }
+    *out = nullptr;
+    if (!size_supported(g->n) || g->n_spheres < 1 || !(g->volume_fraction > 0.0 && g->volume_fraction < 1.0) ||
+        !(g->layer > 0.0 && g->layer < 1.0) || !(rvegeom_radius(g->n_spheres, g->volume_fraction) < 0.5)) {
+        set_error("rve_create: invalid geometry (n=%d, spheres=%d, f=%g, l=%g)", g->n, g->n_spheres,
+                  g->volume_fraction, g->layer);
+        return RVE_ERR_ARG;
+    }
+    rve_s *r = new (std::nothrow) rve_s();
+    if (!r) return RVE_ERR_OOM;
+    const size_t M = (size_t)g->n * g->n * g->n;
+    r->n = g->n;
+    r->h_phase.resize(M);
+    r->centers.resize(3 * (size_t)g->n_spheres);
+    int method = 0;
+    int rc = rvegeom_generate(g->n, g->n_spheres, g->volume_fraction, g->layer, g->seed, r->h_phase.data(),
+                              r->centers.data(), &method);
+    if (rc != 0) {
+        delete r;
+        set_error(rc == -2 ? "spheres could not be placed (jammed)" : "invalid geometry");
+        return rc == -2 ? RVE_ERR_JAMMED : RVE_ERR_ARG;
+    }
+    r->radius = rvegeom_radius(g->n_spheres, g->volume_fraction);
+    r->layer = g->layer;
+    r->method = method;
+    rve_status st = upload_rve(r);
+    if (st != RVE_OK) {
+        delete r;
+        return st;
+    }
+    *out = r;
+    return RVE_OK;
+}
+
+extern "C" rve_status rve_get_phases(rve_t r, uint8_t *out, size_t cap) {
+    clear_error();
+    if (!r || !out || cap < r->h_phase.size()) {
+        set_error("rve_get_phases: null pointer or buffer too small");
+        return RVE_ERR_ARG;
+    }
+    std::memcpy(out, r->h_phase.data(), r->h_phase.size());
+    return RVE_OK;
+}
+
+extern "C" rve_status rve_get_spheres(rve_t r, double *xyzr, int cap, int *count, double *layer) {
+    clear_error();
+    if (!r || !count || cap < 0 || (cap > 0 && !xyzr)) {
+        set_error("rve_get_spheres: bad arguments");
+        return RVE_ERR_ARG;
+    }
+    const int ns = (int)(r->centers.size() / 3);
+    const int k = std::min(ns, cap);
+    for (int i = 0; i < k; ++i) {
+        for (int d = 0; d < 3; ++d) xyzr[4 * i + d] = r->centers[3 * i + d];
+        xyzr[4 * i + 3] = r->radius;
+    }
+    *count = ns;
+    if (layer) *layer = r->layer;
+    return RVE_OK;
+}
+
+extern "C" int rve_n(rve_t r) { return r ? r->n : 0; }
+
+extern "C" size_t rve_workspace_size(rve_t r, int precision) {
+    if (!r) return 0;
+    const SolverOps *o = lookup_ops(precision, r->n);
+    return o ? ws_layout(o).total : 0;
+}
+
+extern "C" void rve_destroy(rve_t r) {
+    if (!r) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(r->device);
+    r->sol[0].release();
+    r->sol[1].release();
+    if (r->d_phase) (void)hipFree(r->d_phase);
+    (void)hipSetDevice(cur);
+    delete r;
+}
+
+// ---------------------------------------------------------------------------
+// Solve driver
+// ---------------------------------------------------------------------------
+namespace rvehom {
+
+int validate_k(const double k[3], double tol) {
+    if (!k) {
+        set_error("k_phases is NULL");
+        return RVE_ERR_ARG;
+    }
+    for (int p = 0; p < 3; ++p)
+        if (!(k[p] > 0.0) || !std::isfinite(k[p])) {
+            set_error("conductivity of phase %d must be finite and > 0 (got %g)", p, k[p]);
+            return RVE_ERR_ARG;
+        }
+    if (!(tol >= 0.0) || !std::isfinite(tol)) {
+        set_error("tol must be finite and >= 0 (got %g)", tol);
+        return RVE_ERR_ARG;
+    }
+    return RVE_OK;
+}
+
+void fill_params(DevParams &p, const double k[3], double tol, int n, const SolverOpts &o) {
+    std::memset(&p, 0, sizeof(p));
+    // Sec. 5: L0 = -sqrt(min k * max k) I over the three given conductivities.
+    const double kmin = std::min(k[0], std::min(k[1], k[2]));
+    const double kmax = std::max(k[0], std::max(k[1], k[2]));
+    const double k0 = std::sqrt(kmin * kmax);
+    const double M = (double)n * n * n;
+    for (int i = 0; i < 3; ++i) {
+        p.k[i] = k[i];
+        p.dk[i] = k[i] - k0;
+        p.w[i] = 2.0 * k0 / (k[i] + k0);
+    }
+    p.k0 = k0;
+    p.inv_k0M = 1.0 / (k0 * M);
+    p.tol = tol;
+    p.invM = 1.0 / M;
+    p.max_iter = o.max_iter;
+    p.stall_window = o.stall_window;
+    p.hist_cap = kHistCap;
+    p.eq_check = o.eq_check;
+    p.lc_mask = o.lc_mask;
+}
+
+SolverOpts resolve_opts(const rve_opts *opts) {
+    SolverOpts o;
+    o.precision = opts ? opts->precision : 0;
+    o.max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 10000;
+    o.eq_check = opts ? (opts->equilibrium_check != 0) : 0;
+    int sw = opts ? opts->stall_window : -1;
+    o.stall_window = sw < 0 ? (o.precision == 0 ? 50 : 0) : sw;
+    o.lc_mask = (opts && (opts->lc_mask & 7)) ? (opts->lc_mask & 7) : 7;
+    o.timing = opts ? opts->timing != 0 : false;
+    o.stream = opts ? (hipStream_t)opts->stream : nullptr;
+    o.init_field = opts ? opts->init_field : nullptr;
+    o.out_field = opts ? opts->out_field : nullptr;
+    o.workspace = opts ? opts->workspace : nullptr;
+    o.workspace_bytes = opts ? opts->workspace_bytes : 0;
+    return o;
+}
+
+// Enqueue init (and optional warm start) on s.
+int Solver::begin(const uint8_t *d_phase, const double k[3], double tol, const SolverOpts &o, hipStream_t s) {
+    d_phase_last = d_phase;
+    int rc = ensure_twiddles(s);
+    if (rc != RVE_OK) return rc;
+    DevParams *hp = (DevParams *)h_pinned;
+    fill_params(*hp, k, tol, ops->n, o);
+    LaunchArgs a = args(d_phase);
+    HIP_CHECK(hipMemcpyAsync((void *)a.prm, hp, sizeof(DevParams), hipMemcpyHostToDevice, s));
+    const size_t M = (size_t)ops->n * ops->n * ops->n;
+    ops->init(a, M, s);
+    HIP_CHECK(hipGetLastError());
+    if (o.init_field) {
+        // stage the FP64 field through the spectrum buffer region if it fits,
+        // else through a temporary device buffer
+        double *tmp = nullptr;
+        HIP_CHECK(hipMalloc(&tmp, 9 * M * sizeof(double)));
+        HIP_CHECK(hipMemcpyAsync(tmp, o.init_field, 9 * M * sizeof(double), hipMemcpyHostToDevice, s));
+        ops->from_f64(a.e, tmp, 9 * M, s);
+        HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipStreamSynchronize(s));
+        HIP_CHECK(hipFree(tmp));
+    }
+    issued = 0;
+    inflight.clear();
+    finished = false;
+    slot = 0;
+    launches.clear();
+    eq_check = o.eq_check != 0;
+    return RVE_OK;
+}
+
+// Enqueue up to `count` iterations (never beyond max_iter) and a poll point.
+int Solver::enqueue(const uint8_t *d_phase, int count, int max_iter, bool timing, hipStream_t s) {
+    LaunchArgs a = args(d_phase);
+    for (int i = 0; i < count && issued < max_iter; ++i, ++issued) {
+        for (int kk = 0; kk < 4; ++kk) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (timing) {
+                size_t need = 2 * (launches.size() + 1);
+                while (time_ev.size() < need) {
+                    hipEvent_t ev;
+                    HIP_CHECK(hipEventCreate(&ev));
+                    time_ev.push_back(ev);
+                }
+                e0 = time_ev[need - 2];
+                e1 = time_ev[need - 1];
+                HIP_CHECK(hipEventRecord(e0, s));
+            }
+            switch (kk) {
+            case 0: ops->fwd(a, s); break;
+            case 1: ops->zgreen(a, s); break;
+            case 2: ops->inv(a, s); break;
+            default: launch_reduce(a, ops->nper, s); break;
+            }
+            if (timing) {
+                HIP_CHECK(hipEventRecord(e1, s));
+                launches.push_back({kk, issued});
+            }
+        }
+        if (eq_check) {
+            // second stage of step 1 for load cases whose eps_comp fell below tol
+            ops->fwd_phi(a, s);
+            ops->zeq(a, s);
+            launch_eq_reduce(a, ops->eq_tiles, 0, s);
+        }
+    }
+    HIP_CHECK(hipGetLastError());
+    int *flags = (int *)((char *)h_pinned + kFlagsOffset);
+    HIP_CHECK(hipMemcpyAsync(&flags[slot], &a.st->all_done, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipEventRecord(poll_ev[slot], s));
+    inflight.push_back(slot);
+    slot = (slot + 1) % kPollSlots;
+    return RVE_OK;
+}
+
+// Non-blocking (wait = false) or blocking check of the oldest poll point.
+// Returns 1 when the solve has finished, 0 otherwise, < 0 on error.
+int Solver::poll(bool wait, int max_iter) {
+    if (finished) return 1;
+    if (inflight.empty()) return (issued >= max_iter) ? 1 : 0;
+    const int sl = inflight.front();
+    if (wait) {
+        HIP_CHECK(hipEventSynchronize(poll_ev[sl]));
+    } else {
+        hipError_t q = hipEventQuery(poll_ev[sl]);
+        if (q == hipErrorNotReady) return 0;
+        if (q != hipSuccess) {
+            set_error("hipEventQuery failed: %s", hipGetErrorString(q));
+            return RVE_ERR_DEVICE;
+        }
+    }
+    inflight.pop_front();
+    const int *flags = (const int *)((const char *)h_pinned + kFlagsOffset);
+    if (flags[sl]) finished = true;
+    if (issued >= max_iter && inflight.empty()) finished = true;
+    return finished ? 1 : 0;
+}
+
+// Copy results back after the stream has drained.
+int Solver::collect(const SolverOpts &o, hipStream_t s, rve_result *out, double *hist, int hist_cap,
+                    rve_kernel_times *kt) {
+    LaunchArgs a = args(d_phase_last);
+    // equilibrium error of the final field (step 1 quantity, reported at exit)
+    launch_eq_request(a, s);
+    ops->fwd_phi(a, s);
+    ops->zeq(a, s);
+    launch_eq_reduce(a, ops->eq_tiles, 1, s);
+    HIP_CHECK(hipGetLastError());
+    DevState *hs = (DevState *)((char *)h_pinned + sizeof(DevParams));
+    HIP_CHECK(hipMemcpyAsync(hs, a.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    const size_t M = (size_t)ops->n * ops->n * ops->n;
+    double *tmp = nullptr;
+    if (o.out_field) {
+        HIP_CHECK(hipMalloc(&tmp, 9 * M * sizeof(double)));
+        ops->to_f64(tmp, a.e, 9 * M, s);
+        HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipMemcpyAsync(o.out_field, tmp, 9 * M * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (tmp) HIP_CHECK(hipFree(tmp));
+    if (out) {
+        for (int i = 0; i < 9; ++i) out->K[i] = hs->K[i];
+        for (int j = 0; j < 3; ++j) {
+            out->iters[j] = hs->iters[j];
+            out->status[j] = hs->status[j];
+            out->final_residual[j] = hs->res[j];
+            out->eps_eq[j] = hs->eps_eq[j];
+        }
+    }
+    if (hist && hist_cap > 0) {
+        const int cap = std::min(hist_cap, kHistCap);
+        for (int j = 0; j < 3; ++j) {
+            const int cnt = std::min(cap, hs->iters[j]);
+            if (cnt > 0)
+                HIP_CHECK(hipMemcpy(hist + (size_t)j * hist_cap, a.hist + (size_t)j * kHistCap,
+                                    cnt * sizeof(double), hipMemcpyDeviceToHost));
+        }
+    }
+    if (kt) {
+        static const char *names[4] = {"fwd_plane", "zgreen", "inv_plane", "reduce"};
+        std::memset(kt, 0, sizeof(*kt));
+        for (int q = 0; q < 4; ++q) kt->name[q] = names[q];
+        int maxit = 0;
+        for (int j = 0; j < 3; ++j) maxit = std::max(maxit, hs->iters[j]);
+        for (size_t i = 0; i < launches.size(); ++i) {
+            const int kk = launches[i].kernel, it = launches[i].iter;
+            if (it >= maxit) continue;  // launches after convergence exit at once
+            float ms = 0.f;
+            HIP_CHECK(hipEventElapsedTime(&ms, time_ev[2 * i], time_ev[2 * i + 1]));
+            int active = 0;
+            for (int j = 0; j < 3; ++j) active += (hs->iters[j] > it) ? 1 : 0;
+            kt->total_ms[kk] += ms;
+            kt->launches[kk] += 1;
+            kt->total_bytes[kk] += (kk < 3) ? ops->bytes[kk] * active / 3.0 : 0.0;
+        }
+    }
+    return RVE_OK;
+}
+
+rve_status worst_status(const rve_result &r, int lc_mask) {
+    int worst = RVE_OK;
+    auto rank = [](int s) { return s < 0 ? 100 - s : s == RVE_STALLED ? 3 : s == RVE_NOT_CONVERGED ? 2 : 0; };
+    for (int j = 0; j < 3; ++j)
+        if ((lc_mask >> j) & 1)
+            if (rank(r.status[j]) > rank(worst)) worst = r.status[j];
+    return (rve_status)worst;
+}
+
+// One RVE, start to finish, on stream s.
+rve_status solve_one(rve_s *r, const double k[3], double tol, const SolverOpts &o, rve_result *out,
+                     double *hist, int hist_cap) {
+    const SolverOps *ops = lookup_ops(o.precision, r->n);
+    if (!ops) {
+        set_error("grid size %d is not built for precision %d", r->n, o.precision);
+        return RVE_ERR_ARG;
+    }
+    int cur = 0;
+    HIP_CHECK(hipGetDevice(&cur));
+    if (cur != r->device) HIP_CHECK(hipSetDevice(r->device));
+    Solver &sv = r->sol[o.precision];
+    int rc = sv.prepare(ops, o.workspace, o.workspace_bytes);
+    if (rc != RVE_OK) return (rve_status)rc;
+    hipStream_t s = o.stream ? o.stream : sv.own_stream;
+    rc = sv.begin(r->d_phase, k, tol, o, s);
+    if (rc != RVE_OK) return (rve_status)rc;
+    HIP_CHECK(hipEventRecord(sv.run_ev[0], s));
+    // Poll points every `chunk` iterations, at most kLookahead chunks ahead of
+    // the host; launches after convergence exit at once on the device flags.
+    const int chunk = kChunk;
+    while (true) {
+        if (sv.issued < o.max_iter) {
+            rc = sv.enqueue(r->d_phase, chunk, o.max_iter, o.timing, s);
+            if (rc != RVE_OK) return (rve_status)rc;
+        }
+        const bool must_wait = (int)sv.inflight.size() >= kLookahead || sv.issued >= o.max_iter;
+        if (must_wait) {
+            rc = sv.poll(true, o.max_iter);
+            if (rc < 0) return (rve_status)rc;
+            if (rc == 1) break;
+        }
+    }
+    HIP_CHECK(hipEventRecord(sv.run_ev[1], s));
+    rve_result res{};
+    rc = sv.collect(o, s, &res, hist, hist_cap, o.timing ? &r->times : nullptr);
+    if (rc != RVE_OK) return (rve_status)rc;
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, sv.run_ev[0], sv.run_ev[1]));
+    res.solve_ms = ms;
+    if (out) *out = res;
+    if (cur != r->device) HIP_CHECK(hipSetDevice(cur));
+    return worst_status(res, o.lc_mask);
+}
+
+}  // namespace rvehom
+
+extern "C" rve_status homogenize(rve_t r, const double k_phases[3], double tol, const rve_opts *opts,
+                                 rve_result *out, double *residual_history, int hist_cap) {
+    clear_error();
+    if (!r || !out) {
+        set_error("homogenize: null rve or result pointer");
+        return RVE_ERR_ARG;
+    }
+    int rc = validate_k(k_phases, tol);
+    if (rc != RVE_OK) return (rve_status)rc;
+    if (opts && (opts->precision != 0 && opts->precision != 1)) {
+        set_error("precision must be 0 (FP32) or 1 (FP64)");
+        return RVE_ERR_ARG;
+    }
+    if (hist_cap < 0 || (hist_cap > 0 && !residual_history)) {
+        set_error("residual_history is NULL but hist_cap > 0");
+        return RVE_ERR_ARG;
+    }
+    SolverOpts o = resolve_opts(opts);
+    if (o.timing) std::memset(&r->times, 0, sizeof(r->times));
+    return solve_one(r, k_phases, tol, o, out, residual_history, hist_cap);
+}
+
+extern "C" rve_status rve_get_kernel_times(rve_t r, rve_kernel_times *out) {
+    clear_error();
+    if (!r || !out) {
+        set_error("rve_get_kernel_times: null pointer");
+        return RVE_ERR_ARG;
+    }
+    *out = r->times;
+    return RVE_OK;
+}
+
+// Several RVEs at once: one stream per RVE, chunks enqueued round-robin so the
+// device works on all of them together; each finishes on its own flags.
+extern "C" rve_status homogenize_batch(int count, const rve_t *rves, const double *k_phases, const double *tol,
+                                       const rve_opts *opts, rve_result *out) {
+    clear_error();
+    if (count < 0 || (count > 0 && (!rves || !k_phases || !tol || !out))) {
+        set_error("homogenize_batch: bad arguments");
+        return RVE_ERR_ARG;
+    }
+    if (opts && (opts->init_field || opts->out_field || opts->workspace || opts->stream)) {
+        set_error("homogenize_batch: init_field, out_field, workspace and stream must be NULL");
+        return RVE_ERR_ARG;
+    }
+    SolverOpts o = resolve_opts(opts);
+    o.timing = false;
+    for (int i = 0; i < count; ++i) {
+        if (!rves[i]) {
+            set_error("homogenize_batch: rve %d is NULL", i);
+            return RVE_ERR_ARG;
+        }
+        int rc = validate_k(k_phases + 3 * i, tol[i]);
+        if (rc != RVE_OK) return (rve_status)rc;
+        if (!lookup_ops(o.precision, rves[i]->n)) {
+            set_error("grid size %d is not built for precision %d", rves[i]->n, o.precision);
+            return RVE_ERR_ARG;
+        }
+        for (int j = 0; j < i; ++j)
+            if (rves[j] == rves[i]) {
+                set_error("homogenize_batch: rve %d appears twice", i);
+                return RVE_ERR_ARG;
+            }
+    }
+    return batch_solve(count, rves, k_phases, tol, o, out);
+}

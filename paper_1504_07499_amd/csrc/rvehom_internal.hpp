@@ -1,0 +1,103 @@
+// rvehom_internal.hpp -- host-side objects behind the C ABI handles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <deque>
+#include <vector>
+
+#include "rvehom.h"
+#include "solver_ops.hpp"
+#include "solver_state.hpp"
+
+namespace rvehom {
+
+constexpr int kHistCap = 16384;  // residual history entries kept per load case
+constexpr int kChunk = 8;        // iterations between host poll points
+constexpr int kLookahead = 2;    // poll points in flight before the host waits
+constexpr int kPollSlots = 4;
+constexpr size_t kFlagsOffset = 2048;  // poll flags inside the pinned block
+
+struct WsLayout {
+    size_t e, spec, nyq, tw, part, prm, st, hist, peq, total;
+};
+WsLayout ws_layout(const SolverOps *o);
+
+struct SolverOpts {
+    int precision = 0;
+    int max_iter = 10000;
+    int eq_check = 0;
+    int stall_window = 0;
+    int lc_mask = 7;
+    bool timing = false;
+    hipStream_t stream = nullptr;
+    const double *init_field = nullptr;
+    double *out_field = nullptr;
+    void *workspace = nullptr;
+    size_t workspace_bytes = 0;
+};
+
+struct LaunchRec {
+    int kernel;
+    int iter;
+};
+
+// Device workspace + HIP objects of one (RVE, precision).
+struct Solver {
+    const SolverOps *ops = nullptr;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool owned = false;
+    bool tw_ready = false;
+    WsLayout layout{};
+    hipStream_t own_stream = nullptr;
+    std::vector<hipEvent_t> poll_ev;
+    std::vector<hipEvent_t> time_ev;
+    hipEvent_t run_ev[2] = {nullptr, nullptr};
+    void *h_pinned = nullptr;  // [DevParams | DevState | ... | flags @ kFlagsOffset]
+    // per-solve driver state
+    int issued = 0;
+    int slot = 0;
+    bool finished = false;
+    std::deque<int> inflight;
+    std::vector<LaunchRec> launches;
+    bool eq_check = false;
+    const uint8_t *d_phase_last = nullptr;
+
+    ~Solver();
+    void release();
+    int prepare(const SolverOps *o, void *user_ws, size_t user_bytes);
+    LaunchArgs args(const uint8_t *d_phase) const;
+    int ensure_twiddles(hipStream_t s);
+    int begin(const uint8_t *d_phase, const double k[3], double tol, const SolverOpts &o, hipStream_t s);
+    int enqueue(const uint8_t *d_phase, int count, int max_iter, bool timing, hipStream_t s);
+    int poll(bool wait, int max_iter);
+    int collect(const SolverOpts &o, hipStream_t s, rve_result *out, double *hist, int hist_cap,
+                rve_kernel_times *kt);
+};
+
+const SolverOps *lookup_ops(int precision, int n);
+void set_error(const char *fmt, ...);
+void clear_error();
+int validate_k(const double k[3], double tol);
+SolverOpts resolve_opts(const rve_opts *opts);
+rve_status worst_status(const rve_result &r, int lc_mask);
+rve_status solve_one(struct ::rve_s *r, const double k[3], double tol, const SolverOpts &o, rve_result *out,
+                     double *hist, int hist_cap);
+rve_status batch_solve(int count, const rve_t *rves, const double *k, const double *tol, const SolverOpts &o,
+                       rve_result *out);
+
+}  // namespace rvehom
+
+struct rve_s {
+    int n = 0;
+    int device = 0;
+    uint8_t *d_phase = nullptr;
+    std::vector<uint8_t> h_phase;
+    std::vector<double> centers;
+    double radius = 0.0;
+    double layer = 0.0;
+    int method = -1;
+    rvehom::Solver sol[2];
+    rve_kernel_times times{};
+};

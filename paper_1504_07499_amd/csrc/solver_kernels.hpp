@@ -1,0 +1,522 @@
+// solver_kernels.hpp -- gfx950 kernels of one iteration of the accelerated
+// (Eyre-Milton) FFT scheme for the thermal conductivity of a periodic voxel
+// RVE (arXiv:1504.07499, Sec. 3, Algorithm steps 2-7; Sec. 5 for L0).
+//
+// Data in HBM (T = float or double, M = N^3, 9 channels ch = 3*lc + comp):
+//   e     [ch][z][y][x]            real gradient iterate, x fastest
+//   ph    [z][y][x]                uint8 phase id (0 matrix, 1 inclusion, 2 coating)
+//   spec  [ch][z][ky][kx], kx<N/2  half spectrum without the kx = N/2 column
+//   nyq   [ch][z][ky]              the kx = N/2 column
+//   part  [ch][block][2]           FP64 partials {sum |e - c|^2, sum k e+}
+//
+// One iteration = three passes over HBM plus a tiny reduction:
+//   P1 (k_fwd_plane):   tau = (k - k0) e (step 2) fused into the load, then the
+//                       2D real-to-complex FFT of each (ch, z) xy-plane in LDS;
+//   P2 (k_zgreen):      z-FFT of the three components of one load case, the
+//                       Green operator with the xi = 0 pin (step 4), inverse
+//                       z-FFT, in place;
+//   P3 (k_inv_plane):   2D complex-to-real inverse of each xy-plane in LDS,
+//                       then the residual (step 6), the update (step 7) and the
+//                       flux <k e+>, with FP64 block partials;
+//   k_reduce:           fixed-order FP64 reduction, convergence test and
+//                       per-load-case freeze, all on the device.
+// With L0 = -k0 I (Sec. 5) the steps read tau = (k - k0) e,
+// c^ = -xi (xi . tau^) / (k0 |xi|^2) for xi != 0, c^(0) = E, and
+// e+ = e + 2 k0 / (k + k0) (c - e).
+//
+// Nyquist modes (even N): the index N/2 stands for both +N/2 and -N/2, so the
+// operator used is xi xi^T / |xi|^2 averaged over both signs of every Nyquist
+// component.  With A the non-Nyquist and B the Nyquist components of a mode,
+// that average is (xi_A xi_A^T + diag(xi_B^2)) / |xi|^2: components in A see
+// xi_i (xi_A . tau^), each component in B sees xi_i^2 tau^_i.  The result is
+// even in xi (so the half-spectrum inverse is exact) and keeps the discrete
+// problem covariant under mirroring any axis.
+//
+// Planes too large for LDS are split in S row-parities (S = 2): the first
+// radix-2 step of the y transform is done while loading, so each workgroup
+// holds N/2 rows.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_lds.hpp"
+#include "solver_state.hpp"
+
+namespace rvehom {
+
+template <typename T> struct VecOf;
+template <> struct VecOf<float> {
+    static constexpr int V = 4;
+    using type = float4;
+    using ptype = uchar4;
+};
+template <> struct VecOf<double> {
+    static constexpr int V = 2;
+    using type = double2;
+    using ptype = uchar2;
+};
+
+template <typename T> __device__ __forceinline__ void vload(const T *p, T *out);
+template <> __device__ __forceinline__ void vload<float>(const float *p, float *o) {
+    float4 v = *reinterpret_cast<const float4 *>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+template <> __device__ __forceinline__ void vload<double>(const double *p, double *o) {
+    double2 v = *reinterpret_cast<const double2 *>(p);
+    o[0] = v.x; o[1] = v.y;
+}
+template <typename T> __device__ __forceinline__ void vstore(T *p, const T *in);
+template <> __device__ __forceinline__ void vstore<float>(float *p, const float *i) {
+    *reinterpret_cast<float4 *>(p) = make_float4(i[0], i[1], i[2], i[3]);
+}
+template <> __device__ __forceinline__ void vstore<double>(double *p, const double *i) {
+    *reinterpret_cast<double2 *>(p) = make_double2(i[0], i[1]);
+}
+template <int V> __device__ __forceinline__ void pload(const uint8_t *p, int *o);
+template <> __device__ __forceinline__ void pload<4>(const uint8_t *p, int *o) {
+    uchar4 v = *reinterpret_cast<const uchar4 *>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+template <> __device__ __forceinline__ void pload<2>(const uint8_t *p, int *o) {
+    uchar2 v = *reinterpret_cast<const uchar2 *>(p);
+    o[0] = v.x; o[1] = v.y;
+}
+
+// phase-indexed lookup without a memory table: p in {0,1,2}
+template <typename T> __device__ __forceinline__ T pick(int p, T a0, T a1, T a2) {
+    return p == 0 ? a0 : (p == 1 ? a1 : a2);
+}
+
+// Block index -> (channel, z, parity).  For S = 2 the two parities of one
+// plane are 8 blocks apart, so that both run on the same XCD (blocks are
+// dealt round-robin to the 8 XCDs) and the second read of the plane hits L2.
+template <int N, int S> __device__ __forceinline__ void plane_of_block(int b, int &ch, int &z, int &h) {
+    if constexpr (S == 1) {
+        ch = b / N;
+        z = b - ch * N;
+        h = 0;
+    } else {
+        const int g = b / (8 * S), r = b - g * 8 * S;
+        h = r / 8;
+        const int pr = g * 8 + (r - h * 8);
+        ch = pr / N;
+        z = pr - ch * N;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// P1: tau = (k - k0) e fused into the load; 2D R2C of the (ch, z) plane.
+// With PHI the same pass transforms the flux k e for the equilibrium check.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int S, int NT, bool PHI = false>
+__global__ __launch_bounds__(NT) void k_fwd_plane(const T *__restrict__ e, const uint8_t *__restrict__ ph,
+                                                  Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
+                                                  const Cx<T> *__restrict__ tw,
+                                                  const DevParams *__restrict__ prm,
+                                                  const DevState *__restrict__ st) {
+    constexpr int H = N / 2, RS = H + 1, ROWS = N / S, V = VecOf<T>::V, NN = N * N;
+    static_assert(N % 4 == 0 && (S == 1 || S == 2), "plane kernel needs N % 4 == 0");
+    __shared__ Cx<T> plane[ROWS * RS];
+    const int tid = threadIdx.x;
+    int ch, z, h;
+    plane_of_block<N, S>(blockIdx.x, ch, z, h);
+    const int lc = ch / 3;
+    // PHI: the flux k e of the equilibrium check (step 1); else tau = (k - k0) e
+    if (PHI ? !st->eq_pending[lc] : st->done[lc]) return;
+    const double *lut = PHI ? prm->k : prm->dk;
+    const T d0 = (T)lut[0], d1 = (T)lut[1], d2 = (T)lut[2];
+    const T *eb = e + (size_t)ch * N * NN + (size_t)z * NN;
+    const uint8_t *pb = ph + (size_t)z * NN;
+
+    // load rows (S = 2: combine rows y and y + N/2 with sign (-1)^h)
+    for (int idx = tid; idx < ROWS * N / V; idx += NT) {
+        const int y = idx / (N / V), x = (idx - y * (N / V)) * V;
+        T a[V], u[V];
+        int p[V];
+        vload<T>(eb + y * N + x, a);
+        pload<V>(pb + y * N + x, p);
+#pragma unroll
+        for (int i = 0; i < V; ++i) u[i] = pick<T>(p[i], d0, d1, d2) * a[i];
+        if constexpr (S == 2) {
+            T b[V];
+            int q[V];
+            vload<T>(eb + (y + ROWS) * N + x, b);
+            pload<V>(pb + (y + ROWS) * N + x, q);
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                const T t2 = pick<T>(q[i], d0, d1, d2) * b[i];
+                u[i] = h ? u[i] - t2 : u[i] + t2;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < V; i += 2) plane[y * RS + (x + i) / 2] = Cx<T>{u[i], u[i + 1]};
+    }
+    __syncthreads();
+    // x: complex FFT of length N/2 of the packed even/odd samples
+    fft_lds<T, H, false, ROWS, 1, NT, N, SeqStride<RS>>(plane, tw, tid);
+    // unpack to the real-input spectrum X[0..N/2]
+    for (int idx = tid; idx < ROWS * (H / 2 + 1); idx += NT) {
+        const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
+        Cx<T> *row = plane + y * RS;
+        Cx<T> rot = {(T)1, (T)0};
+        if constexpr (S == 2) {
+            if (h) rot = tw[y];  // w_N^y of the row-parity split
+        }
+        if (k == 0) {
+            const Cx<T> z0 = row[0];
+            Cx<T> x0 = {z0.x + z0.y, (T)0}, xh = {z0.x - z0.y, (T)0};
+            if constexpr (S == 2) {
+                x0 = x0 * rot;
+                xh = xh * rot;
+            }
+            row[0] = x0;
+            row[H] = xh;
+        } else {
+            const Cx<T> a = row[k], b = conj(row[H - k]);
+            const Cx<T> A = scale(a + b, (T)0.5);
+            const Cx<T> D = scale(a - b, (T)0.5);
+            const Cx<T> B = {D.y, -D.x};  // (a - b) / (2 i)
+            const Cx<T> wB = B * tw[k];
+            Cx<T> xk = A + wB, xm = conj(A - wB);
+            if constexpr (S == 2) {
+                xk = xk * rot;
+                xm = xm * rot;
+            }
+            row[k] = xk;
+            if (k != H - k) row[H - k] = xm;
+        }
+    }
+    __syncthreads();
+    // y: complex FFT of length N/S down the N/2 + 1 columns
+    fft_lds<T, ROWS, false, RS, RS, NT, N, SeqStride<1>>(plane, tw, tid);
+    Cx<T> *sb = spec + ((size_t)ch * N + z) * N * H;
+    for (int idx = tid; idx < ROWS * H; idx += NT) {
+        const int m = idx / H, kx = idx - m * H;
+        sb[(size_t)(S * m + h) * H + kx] = plane[m * RS + kx];
+    }
+    Cx<T> *nb = nyq + ((size_t)ch * N + z) * N;
+    for (int m = tid; m < ROWS; m += NT) nb[S * m + h] = plane[m * RS + H];
+}
+
+// ---------------------------------------------------------------------------
+// P2: z-FFT, Green operator (step 4), inverse z-FFT for one load case.
+// Tiles: W consecutive kx of one ky (main), or W consecutive ky of the
+// kx = N/2 column (nyq).  All three components sit in LDS together.
+// ---------------------------------------------------------------------------
+template <int N, int W> struct ZTiles {
+    static constexpr int H = N / 2;
+    static constexpr int MAIN = N * (H / W);
+    static constexpr int NYQ = N / W;
+    static constexpr int PER_LC = MAIN + NYQ;
+};
+
+template <typename T, int N, int W, int NT>
+__global__ __launch_bounds__(NT) void k_zgreen(Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
+                                               const Cx<T> *__restrict__ tw,
+                                               const DevParams *__restrict__ prm,
+                                               const DevState *__restrict__ st) {
+    using TL = ZTiles<N, W>;
+    constexpr int H = N / 2, NW = N * W;
+    static_assert(H % W == 0 && N % W == 0, "tile width must divide N/2");
+    __shared__ Cx<T> buf[3 * NW];
+    const int tid = threadIdx.x;
+    const int lc = blockIdx.x / TL::PER_LC, t = blockIdx.x - lc * TL::PER_LC;
+    if (st->done[lc]) return;
+    Cx<T> *base;
+    size_t cstride, zstride;
+    int kx0, ky0, dkx, dky;  // kx(w) = kx0 + dkx*w, ky(w) = ky0 + dky*w
+    if (t < TL::MAIN) {
+        const int ky = t / (H / W);
+        kx0 = (t - ky * (H / W)) * W;
+        ky0 = ky;
+        dkx = 1;
+        dky = 0;
+        base = spec + (size_t)(3 * lc) * N * N * H + (size_t)ky * H + kx0;
+        cstride = (size_t)N * N * H;
+        zstride = (size_t)N * H;
+    } else {
+        kx0 = H;
+        ky0 = (t - TL::MAIN) * W;
+        dkx = 0;
+        dky = 1;
+        base = nyq + (size_t)(3 * lc) * N * N + ky0;
+        cstride = (size_t)N * N;
+        zstride = N;
+    }
+    for (int idx = tid; idx < 3 * NW; idx += NT) {
+        const int c = idx / NW, r = idx - c * NW, zz = r / W, w = r - zz * W;
+        buf[idx] = base[c * cstride + zz * zstride + w];
+    }
+    __syncthreads();
+    fft_lds<T, N, false, 3 * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
+    const T sc = (T)prm->inv_k0M;
+    for (int idx = tid; idx < NW; idx += NT) {
+        const int kz = idx / W, w = idx - kz * W;
+        const int ki[3] = {kx0 + dkx * w, ky0 + dky * w, kz};
+        T xi[3];
+        bool nq[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            nq[d] = (ki[d] == H);
+            xi[d] = (T)(ki[d] <= H ? ki[d] : ki[d] - N);
+        }
+        Cx<T> tv[3] = {buf[idx], buf[NW + idx], buf[2 * NW + idx]};
+        Cx<T> out[3];
+        if (ki[0] == 0 && ki[1] == 0 && ki[2] == 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) out[c] = Cx<T>{c == lc ? (T)1 : (T)0, (T)0};
+        } else {
+            Cx<T> sA = {(T)0, (T)0};
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                if (!nq[d]) sA = sA + scale(tv[d], xi[d]);
+            const T x2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+            const T f = -sc / x2;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) out[c] = scale(nq[c] ? scale(tv[c], xi[c]) : sA, f * xi[c]);
+        }
+        buf[idx] = out[0];
+        buf[NW + idx] = out[1];
+        buf[2 * NW + idx] = out[2];
+    }
+    __syncthreads();
+    fft_lds<T, N, true, 3 * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
+    for (int idx = tid; idx < 3 * NW; idx += NT) {
+        const int c = idx / NW, r = idx - c * NW, zz = r / W, w = r - zz * W;
+        base[c * cstride + zz * zstride + w] = buf[idx];
+    }
+}
+
+// FP64 block sum of two values; result valid in thread 0.
+template <int NT> __device__ __forceinline__ void block_sum2(double &a, double &b, double *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_down(a, o, 64);
+        b += __shfl_down(b, o, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[2 * wv] = a;
+        red[2 * wv + 1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0;
+        for (int i = 0; i < NT / 64; ++i) {
+            sa += red[2 * i];
+            sb += red[2 * i + 1];
+        }
+        a = sa;
+        b = sb;
+    }
+}
+
+// Equilibrium error of step 1 (option): after P1<PHI> the z-FFT of the flux
+// spectrum, then per block sum' |xi . phi^|^2 / |xi|^2 over the modes where
+// the sign-averaged operator is the projection on xi (no Nyquist component,
+// or a single Nyquist component and nothing else), each half-spectrum mode
+// counted with its Hermitian partner, and |phi^(0)|^2 from the tile holding
+// mode 0.  Partials: peq[lc][tile] = {num, den}.
+template <typename T, int N, int W, int NT>
+__global__ __launch_bounds__(NT) void k_zeq(const Cx<T> *__restrict__ spec, const Cx<T> *__restrict__ nyq,
+                                            const Cx<T> *__restrict__ tw, const DevState *__restrict__ st,
+                                            double *__restrict__ peq) {
+    using TL = ZTiles<N, W>;
+    constexpr int H = N / 2, NW = N * W;
+    __shared__ Cx<T> buf[3 * NW];
+    __shared__ double red[2 * (NT / 64)];
+    const int tid = threadIdx.x;
+    const int lc = blockIdx.x / TL::PER_LC, t = blockIdx.x - lc * TL::PER_LC;
+    if (!st->eq_pending[lc]) return;
+    const Cx<T> *base;
+    size_t cstride, zstride;
+    int kx0, ky0, dkx, dky;
+    if (t < TL::MAIN) {
+        const int ky = t / (H / W);
+        kx0 = (t - ky * (H / W)) * W;
+        ky0 = ky;
+        dkx = 1;
+        dky = 0;
+        base = spec + (size_t)(3 * lc) * N * N * H + (size_t)ky * H + kx0;
+        cstride = (size_t)N * N * H;
+        zstride = (size_t)N * H;
+    } else {
+        kx0 = H;
+        ky0 = (t - TL::MAIN) * W;
+        dkx = 0;
+        dky = 1;
+        base = nyq + (size_t)(3 * lc) * N * N + ky0;
+        cstride = (size_t)N * N;
+        zstride = N;
+    }
+    for (int idx = tid; idx < 3 * NW; idx += NT) {
+        const int c = idx / NW, r = idx - c * NW, zz = r / W, w = r - zz * W;
+        buf[idx] = base[c * cstride + zz * zstride + w];
+    }
+    __syncthreads();
+    fft_lds<T, N, false, 3 * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
+    double num = 0.0, den = 0.0;
+    for (int idx = tid; idx < NW; idx += NT) {
+        const int kz = idx / W, w = idx - kz * W;
+        const int ki[3] = {kx0 + dkx * w, ky0 + dky * w, kz};
+        Cx<double> v[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const Cx<T> q = buf[c * NW + idx];
+            v[c] = Cx<double>{(double)q.x, (double)q.y};
+        }
+        if (ki[0] == 0 && ki[1] == 0 && ki[2] == 0) {
+            den = v[0].x * v[0].x + v[0].y * v[0].y + v[1].x * v[1].x + v[1].y * v[1].y +
+                  v[2].x * v[2].x + v[2].y * v[2].y;
+            continue;
+        }
+        int nnyq = 0, nreg = 0;
+        double xi[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (ki[d] == H) ++nnyq;
+            else if (ki[d] != 0) ++nreg;
+            xi[d] = (double)(ki[d] <= H ? ki[d] : ki[d] - N);
+        }
+        if (!(nnyq == 0 || (nnyq == 1 && nreg == 0))) continue;
+        const double dr = xi[0] * v[0].x + xi[1] * v[1].x + xi[2] * v[2].x;
+        const double di = xi[0] * v[0].y + xi[1] * v[1].y + xi[2] * v[2].y;
+        const double wgt = (ki[0] == 0 || ki[0] == H) ? 1.0 : 2.0;  // Hermitian partner
+        num += wgt * (dr * dr + di * di) / (xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+    }
+    block_sum2<NT>(num, den, red);
+    if (tid == 0) {
+        peq[((size_t)lc * TL::PER_LC + t) * 2] = num;
+        peq[((size_t)lc * TL::PER_LC + t) * 2 + 1] = den;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// P3: 2D C2R of the (ch, z) plane, then steps 6-7 and the flux, fused.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int S, int NT>
+__global__ __launch_bounds__(NT) void k_inv_plane(T *__restrict__ e, const uint8_t *__restrict__ ph,
+                                                  const Cx<T> *__restrict__ spec,
+                                                  const Cx<T> *__restrict__ nyq,
+                                                  const Cx<T> *__restrict__ tw,
+                                                  const DevParams *__restrict__ prm,
+                                                  const DevState *__restrict__ st,
+                                                  double *__restrict__ part) {
+    constexpr int H = N / 2, RS = H + 1, ROWS = N / S, V = VecOf<T>::V, NN = N * N;
+    __shared__ Cx<T> plane[ROWS * RS];
+    __shared__ double red[2 * (NT / 64)];
+    const int tid = threadIdx.x;
+    int ch, z, h;
+    plane_of_block<N, S>(blockIdx.x, ch, z, h);
+    const int lc = ch / 3;
+    if (st->done[lc]) return;
+
+    const Cx<T> *sb = spec + ((size_t)ch * N + z) * N * H;
+    const Cx<T> *nb = nyq + ((size_t)ch * N + z) * N;
+    for (int idx = tid; idx < ROWS * RS; idx += NT) {
+        const int m = idx / RS, kx = idx - m * RS;
+        Cx<T> v = (kx < H) ? sb[(size_t)m * H + kx] : nb[m];
+        if constexpr (S == 2) {
+            const Cx<T> u = (kx < H) ? sb[(size_t)(m + ROWS) * H + kx] : nb[m + ROWS];
+            v = h ? (v - u) * conj(tw[m]) : v + u;
+        }
+        plane[idx] = v;
+    }
+    __syncthreads();
+    fft_lds<T, ROWS, true, RS, RS, NT, N, SeqStride<1>>(plane, tw, tid);
+    // pack the Hermitian half row into a length-N/2 complex sequence
+    for (int idx = tid; idx < ROWS * (H / 2 + 1); idx += NT) {
+        const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
+        Cx<T> *row = plane + y * RS;
+        if (k == 0) {
+            const T x0 = row[0].x, xh = row[H].x;
+            row[0] = Cx<T>{x0 + xh, x0 - xh};
+        } else {
+            const Cx<T> a = row[k], b = conj(row[H - k]);
+            const Cx<T> A = a + b;
+            const Cx<T> B = (a - b) * conj(tw[k]);
+            const Cx<T> iB = {-B.y, B.x};
+            row[k] = A + iB;
+            if (k != H - k) row[H - k] = conj(A) + Cx<T>{B.y, B.x};  // conj(A) + i conj(B)
+        }
+    }
+    __syncthreads();
+    fft_lds<T, H, true, ROWS, 1, NT, N, SeqStride<RS>>(plane, tw, tid);
+
+    const T w0 = (T)prm->w[0], w1 = (T)prm->w[1], w2 = (T)prm->w[2];
+    const double k0d = prm->k[0], k1d = prm->k[1], k2d = prm->k[2];
+    T *eb = e + (size_t)ch * N * NN + (size_t)z * NN;
+    const uint8_t *pb = ph + (size_t)z * NN;
+    double r2 = 0.0, fl = 0.0;
+    for (int idx = tid; idx < ROWS * N / V; idx += NT) {
+        const int m = idx / (N / V), x = (idx - m * (N / V)) * V;
+        const int y = S * m + h;
+        T a[V], c[V];
+        int p[V];
+        vload<T>(eb + y * N + x, a);
+        pload<V>(pb + y * N + x, p);
+#pragma unroll
+        for (int i = 0; i < V; i += 2) {
+            const Cx<T> zz = plane[m * RS + (x + i) / 2];
+            c[i] = zz.x;
+            c[i + 1] = zz.y;
+        }
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const T d = a[i] - c[i];
+            r2 += (double)d * (double)d;
+            const T wi = pick<T>(p[i], w0, w1, w2);
+            a[i] = a[i] + wi * (c[i] - a[i]);
+            fl += pick<double>(p[i], k0d, k1d, k2d) * (double)a[i];
+        }
+        vstore<T>(eb + y * N + x, a);
+    }
+    block_sum2<NT>(r2, fl, red);
+    if (tid == 0) {
+        double *pp = part + ((size_t)ch * (N * S) + (size_t)z * S + h) * 2;
+        pp[0] = r2;
+        pp[1] = fl;
+    }
+}
+
+// e = E_lc for every voxel; solver state reset.  Load cases outside the mask
+// start frozen.
+template <typename T>
+__global__ void k_init(T *__restrict__ e, size_t M, const DevParams *__restrict__ prm, DevState *__restrict__ st) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < 9 * M; i += stride) {
+        const int ch = (int)(i / M);
+        e[i] = (ch % 4 == 0) ? (T)1 : (T)0;  // ch = 3 lc + comp, comp == lc <=> ch in {0, 4, 8}
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->iter = 0;
+        int all = 1;
+        for (int lc = 0; lc < 3; ++lc) {
+            const int on = (prm->lc_mask >> lc) & 1;
+            st->done[lc] = on ? 0 : 1;
+            all &= !on;
+            st->status[lc] = on ? ST_NOT_CONVERGED : ST_OK;
+            st->iters[lc] = 0;
+            st->best_it[lc] = 0;
+            st->eq_pending[lc] = 0;
+            st->res[lc] = 0.0;
+            st->best[lc] = 1e308;
+            st->eps_eq[lc] = -1.0;
+        }
+        for (int i = 0; i < 9; ++i) st->K[i] = 0.0;
+        st->all_done = all;
+    }
+}
+
+// Warm start / field export between FP64 host staging and the working field.
+template <typename T> __global__ void k_from_f64(T *__restrict__ e, const double *__restrict__ src, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) e[i] = (T)src[i];
+}
+template <typename T> __global__ void k_to_f64(double *__restrict__ dst, const T *__restrict__ e, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = (double)e[i];
+}
+
+}  // namespace rvehom

@@ -1,0 +1,60 @@
+// solver_ops.hpp -- host-side table of launchers for one (precision, N).
+// The kernel translation units (kernels_f32.hip, kernels_f64.hip) fill it;
+// the C ABI (rvehom_api.hip) only sees these function pointers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace rvehom {
+
+struct DevParams;
+struct DevState;
+
+struct LaunchArgs {
+    void *e;
+    const uint8_t *ph;
+    void *spec;
+    void *nyq;
+    const void *tw;
+    const DevParams *prm;
+    DevState *st;
+    double *part;
+    double *hist;
+    double *peq;  // equilibrium-error partials [3][eq_tiles][2]
+};
+
+struct SolverOps {
+    int n;
+    int precision;       // 0 FP32, 1 FP64
+    int split;           // S: plane rows split in S parities
+    int ztile;           // W: z-pencil tile width
+    int nper;            // P3 partials per channel
+    size_t real_bytes;   // sizeof(T)
+    size_t spec_elems;   // complex elements of spec (9 N N N/2)
+    size_t nyq_elems;    // complex elements of nyq (9 N N)
+    int grid[3];         // blocks of P1, P2, P3
+    int threads[3];      // threads per block of P1, P2, P3
+    double bytes[3];     // algorithmic HBM bytes of one launch of P1, P2, P3 (all 3 load cases)
+    int eq_tiles;        // k_zeq blocks per load case
+    void (*fwd)(const LaunchArgs &, hipStream_t);
+    void (*fwd_phi)(const LaunchArgs &, hipStream_t);
+    void (*zeq)(const LaunchArgs &, hipStream_t);
+    void (*zgreen)(const LaunchArgs &, hipStream_t);
+    void (*inv)(const LaunchArgs &, hipStream_t);
+    void (*init)(const LaunchArgs &, size_t M, hipStream_t);
+    void (*from_f64)(void *e, const double *src, size_t count, hipStream_t);
+    void (*to_f64)(double *dst, const void *e, size_t count, hipStream_t);
+};
+
+const SolverOps *ops_f32(int n);
+const SolverOps *ops_f64(int n);
+void launch_reduce(const LaunchArgs &a, int nper, hipStream_t s);
+void launch_eq_reduce(const LaunchArgs &a, int per_lc, int final, hipStream_t s);
+void launch_eq_request(const LaunchArgs &a, hipStream_t s);
+
+// Sizes compiled into this build (ascending), per precision.
+int supported_sizes(int precision, const int **list);
+
+}  // namespace rvehom

@@ -1,0 +1,109 @@
+"""GPU tests of the C ABI beyond numerics: error paths, workspaces and
+streams from PyTorch, batched solves and the serving loop."""
+import numpy as np
+import pytest
+
+import paper_1504_07499_amd as rh
+from paper_1504_07499_amd import geom
+
+pytestmark = pytest.mark.gpu
+
+K3 = np.array([0.2, 0.3, 400.0])
+
+
+def test_argument_errors():
+    print("\n[case] argument errors", flush=True)
+    ph = geom.random_phases(16, 1)
+    with rh.rve_create_from_phases(ph) as r:
+        for bad_k in ([0.0, 1.0, 2.0], [1.0, -1.0, 2.0], [1.0, np.nan, 2.0], [np.inf, 1, 1]):
+            with pytest.raises(rh.RveError) as ei:
+                rh.homogenize(r, bad_k, 1e-6)
+            assert ei.value.status == rh.RVE_ERR_ARG
+        with pytest.raises(rh.RveError):
+            rh.homogenize(r, K3, -1.0)
+        with pytest.raises(rh.RveError):
+            rh.homogenize(r, K3, 1e-6, precision=2)
+        g = rh.homogenize(r, K3, 1e-12, max_iter=1, precision=1)
+        assert g.status == rh.RVE_NOT_CONVERGED and list(g.iters) == [1, 1, 1]
+    bad = ph.copy()
+    bad[3, 2, 1] = 3
+    with pytest.raises(rh.RveError):
+        rh.rve_create_from_phases(bad)
+    with pytest.raises(rh.RveError):
+        rh.rve_create_from_phases(np.zeros((10, 10, 10), np.uint8))  # unsupported N
+
+
+def test_fp32_stall_detection():
+    """tol below the FP32 floor: stops as STALLED, not after max_iter."""
+    print("\n[case] stall", flush=True)
+    ph, _, _ = geom.generate(32, 8, 0.2, 0.1, 1)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize(r, K3, 1e-14, precision=0, max_iter=3000)
+    assert g.status == rh.RVE_STALLED
+    assert g.iters.max() < 3000
+
+
+def test_torch_workspace_and_stream():
+    """Device memory and the stream may come from PyTorch; the result is the
+    same as with the library's own workspace."""
+    torch = pytest.importorskip("torch")
+    print("\n[case] torch workspace", flush=True)
+    ph, _, _ = geom.generate(32, 8, 0.2, 0.1, 1)
+    with rh.rve_create_from_phases(ph) as r:
+        own = rh.homogenize(r, K3, 1e-6, precision=0)
+        nbytes = rh.rve_workspace_size(r, 0)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            ext = rh.homogenize(r, K3, 1e-6, precision=0, workspace=ws,
+                                stream=torch.cuda.current_stream())
+        small = torch.empty(nbytes // 2, dtype=torch.uint8, device="cuda")
+        with pytest.raises(rh.RveError):
+            rh.homogenize(r, K3, 1e-6, precision=0, workspace=small)
+    assert np.array_equal(own.K, ext.K) and np.array_equal(own.iters, ext.iters)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_equals_alone(precision):
+    """Mixed grid sizes in one batched solve: each result is bitwise the
+    result of solving that RVE alone."""
+    print(f"\n[case] batch precision={precision}", flush=True)
+    specs = [(16, 3, 0.2, 0.2, 1), (24, 5, 0.25, 0.1, 2), (32, 8, 0.2, 0.1, 3),
+             (48, 10, 0.3, 0.2, 4), (32, 4, 0.1, 0.3, 5)]
+    rves = [rh.rve_create(*s) for s in specs]
+    ks = np.array([K3, [1.0, 0.2, 400.0], K3, [0.2, 0.3, 20.0], K3])
+    tols = np.array([1e-6, 1e-6, 1e-5, 1e-6, 1e-6])
+    alone = [rh.homogenize(r, kk, t, precision=precision) for r, kk, t in zip(rves, ks, tols)]
+    mixed = rh.homogenize_batch(rves, ks, tols, precision=precision)
+    for a, b in zip(alone, mixed):
+        assert np.array_equal(a.K, b.K)
+        assert np.array_equal(a.iters, b.iters)
+    for r in rves:
+        r.close()
+
+
+def test_server_results_match_alone():
+    """Continuous batching: requests of different sizes and contrasts admitted
+    while others run; every served tensor equals the alone solve."""
+    print("\n[case] server", flush=True)
+    reqs = [(32, 8, 0.2, 0.1, 11, [0.2, 0.3, 400.0], 1e-6),
+            (16, 4, 0.2, 0.2, 12, [0.2, 0.3, 20.0], 1e-6),
+            (64, 20, 0.2, 0.2, 13, [0.2, 0.3, 2000.0], 1e-6),
+            (32, 10, 0.3, 0.1, 14, [0.2, 0.3, 2.0], 1e-6),
+            (48, 12, 0.25, 0.3, 15, [0.2, 0.3, 200.0], 1e-6),
+            (16, 2, 0.1, 0.3, 16, [0.2, 0.3, 400.0], 1e-6)]
+    srv = rh.rve_server_create(1 << 30, 3, 0)
+    tickets = [rh.rve_server_submit(srv, *q[:5], q[5], q[6]) for q in reqs]
+    rh.rve_server_drain(srv)
+    served = []
+    for t in tickets:
+        got = rh.rve_server_poll(srv, t)
+        assert got is not None
+        served.append(got)
+    rh.rve_server_destroy(srv)
+    for q, (res, lat) in zip(reqs, served):
+        assert lat > 0
+        with rh.rve_create(*q[:5]) as r:
+            alone = rh.homogenize(r, q[5], q[6], precision=0)
+        assert np.array_equal(res.K, alone.K)
+        assert np.array_equal(res.iters, alone.iters)

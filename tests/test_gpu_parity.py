@@ -1,0 +1,133 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Inputs are seeded phase images from the input generator; the oracle and the
+HIP path share nothing else.  Bars: FP64 mode 1e-9 per tensor entry
+(relative to the largest entry), FP32 mode 1e-4 (the two tolerances the
+build targets); fields compared element by element after a fixed number of
+iterations.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1504_07499_amd as rh
+from paper_1504_07499_amd import geom
+
+pytestmark = pytest.mark.gpu
+
+K_PAPER_CFG = np.array([0.2, 0.3, 400.0])  # matrix, inclusion, coating
+
+
+def tensor_err(K, Kref):
+    return float(np.abs(K - Kref).max() / np.abs(Kref).max())
+
+
+def field_err(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("n", [8, 12, 16, 24, 32, 48, 64])
+def test_field_after_fixed_iterations(n, precision):
+    """Three iterations from E on an i.i.d. phase image: every voxel of every
+    channel matches the oracle (steps 2-7 of the Algorithm end to end)."""
+    print(f"\n[case] field n={n} precision={precision}", flush=True)
+    ph = geom.random_phases(n, seed=100 + n)
+    ref = oracle.homogenize(ph, K_PAPER_CFG, tol=0.0, max_iter=3, want_field=True)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize(r, K_PAPER_CFG, 0.0, max_iter=3, precision=precision,
+                          want_field=True, hist_cap=8)
+    bar = 1e-11 if precision == 1 else 3e-5
+    assert field_err(g.field, ref.field) <= bar
+    assert tensor_err(g.K, ref.K) <= bar
+    assert list(g.iters) == [3, 3, 3]
+    for j in range(3):
+        np.testing.assert_allclose(g.history[j], ref.history[j], rtol=bar * 10)
+
+
+@pytest.mark.parametrize("n", [8, 16, 32])
+def test_homogeneous_medium(n):
+    """Every voxel one phase: K = k I after one iteration with residual 0."""
+    print(f"\n[case] homogeneous n={n}", flush=True)
+    ph = np.full((n, n, n), 1, dtype=np.uint8)
+    with rh.rve_create_from_phases(ph) as r:
+        for prec in (1, 0):
+            g = rh.homogenize(r, [1.0, 3.5, 400.0], 1e-10, precision=prec)
+            assert g.status == rh.RVE_OK
+            assert list(g.iters) == [1, 1, 1]
+            np.testing.assert_allclose(g.K, 3.5 * np.eye(3), atol=1e-12 if prec else 1e-5)
+
+
+def test_config1_fp64_converged():
+    """32^3, 8 RSA spheres, f = 0.2, l = 0.1, seed 1, k = (0.2, 0.3, 400),
+    tol 1e-6, FP64: tensor within 1e-9 of the oracle, same iteration counts."""
+    print("\n[case] config1 fp64", flush=True)
+    ph, _, _ = geom.generate(32, 8, 0.2, 0.1, 1)
+    ref = oracle.homogenize(ph, K_PAPER_CFG, tol=1e-6)
+    with rh.rve_create(32, 8, 0.2, 0.1, 1) as r:
+        assert np.array_equal(rh.rve_get_phases(r), ph)
+        g = rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=1, hist_cap=1000)
+    assert g.status == rh.RVE_OK
+    assert list(g.iters) == list(ref.iters)
+    assert tensor_err(g.K, ref.K) <= 1e-9
+    for j in range(3):
+        np.testing.assert_allclose(g.history[j], ref.history[j], rtol=1e-9)
+
+
+@pytest.mark.parametrize("n", [32, 48, 64])
+def test_fp32_converged_vs_oracle(n):
+    """FP32 FFT/update with FP64 reductions: tensor within 1e-4 of the oracle."""
+    print(f"\n[case] fp32 converged n={n}", flush=True)
+    ph, _, _ = geom.generate(n, 8, 0.2, 0.1, 7)
+    ref = oracle.homogenize(ph, K_PAPER_CFG, tol=1e-6)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=0)
+    assert g.status in (rh.RVE_OK, rh.RVE_STALLED)
+    assert tensor_err(g.K, ref.K) <= 1e-4
+
+
+def test_split_plane_path_256_fp32():
+    """256^3 in FP32 uses the row-parity split of the xy-plane (two
+    workgroups per plane): two iterations of load case e_1 on an RSA RVE,
+    field compared voxel by voxel with the oracle."""
+    print("\n[case] split plane 256 fp32", flush=True)
+    ph, _, _ = geom.generate(256, 100, 0.3, 0.2, 3)
+    ref = oracle.homogenize(ph, K_PAPER_CFG, tol=0.0, max_iter=2, want_field=True, lc_mask=1)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize(r, K_PAPER_CFG, 0.0, max_iter=2, precision=0, lc_mask=1,
+                          want_field=True)
+    assert field_err(g.field[0], ref.field[0]) <= 3e-5
+    assert np.array_equal(g.field[1:], ref.field[1:])
+    assert tensor_err(g.K[:, 0], ref.K[:, 0]) <= 3e-5
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mirror_covariance_on_gpu(precision):
+    """Mirroring the microstructure along x flips the sign of row/column x
+    of K (the Nyquist treatment keeps this exact on even grids)."""
+    print(f"\n[case] mirror precision={precision}", flush=True)
+    ph, _, _ = geom.generate(32, 6, 0.25, 0.3, 12)
+    with rh.rve_create_from_phases(ph) as a, \
+            rh.rve_create_from_phases(np.ascontiguousarray(ph[:, :, ::-1])) as b:
+        ka = rh.homogenize(a, K_PAPER_CFG, 1e-9, precision=precision, stall_window=0).K
+        kb = rh.homogenize(b, K_PAPER_CFG, 1e-9, precision=precision, stall_window=0).K
+    R = np.diag([-1.0, 1.0, 1.0])
+    assert tensor_err(kb, R @ ka @ R) <= (1e-9 if precision else 1e-4)
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_equilibrium_error_fp64(n):
+    """eps_eq of step 1 at exit (fixed iteration count) and the two-stage
+    stop (eps_comp then eps_eq below tol) against the oracle."""
+    print(f"\n[case] equilibrium n={n}", flush=True)
+    ph, _, _ = geom.generate(n, 4, 0.2, 0.3, 4)
+    ref = oracle.homogenize(ph, K_PAPER_CFG, tol=0.0, max_iter=25)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize(r, K_PAPER_CFG, 0.0, max_iter=25, precision=1)
+        np.testing.assert_allclose(g.eps_eq, ref.eps_eq, rtol=1e-9)
+        ref2 = oracle.homogenize(ph, K_PAPER_CFG, tol=1e-6, eq_check=True)
+        g2 = rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=1, equilibrium_check=True)
+    assert g2.status == rh.RVE_OK
+    assert list(g2.iters) == list(ref2.iters)
+    assert np.all(g2.eps_eq < 1e-6)
+    assert tensor_err(g2.K, ref2.K) <= 1e-9
