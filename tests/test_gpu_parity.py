@@ -131,3 +131,35 @@ def test_equilibrium_error_fp64(n):
     assert list(g2.iters) == list(ref2.iters)
     assert np.all(g2.eps_eq < 1e-6)
     assert tensor_err(g2.K, ref2.K) <= 1e-9
+
+
+def _golden(name):
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_refs.json")
+    with open(path) as f:
+        return json.load(f)[name]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_config2_128_vs_stored_oracle(precision):
+    """The benchmark workload (128^3, 50 RSA spheres, f = 0.3, l = 0.2,
+    seed 2, tol 1e-6) in the launch configuration bench.py times, against
+    the stored oracle tensor (tests/golden/make_oracle_refs.py)."""
+    print(f"\n[case] config2 128 precision={precision}", flush=True)
+    ref = _golden("rve128_50sph_f0.30_l0.20_seed2")
+    g0 = ref["geometry"]
+    with rh.rve_create(g0["n"], g0["n_spheres"], g0["volume_fraction"], g0["layer"],
+                       g0["seed"]) as r:
+        frac = np.bincount(rh.rve_get_phases(r).ravel(), minlength=3) / 128 ** 3
+        np.testing.assert_allclose(frac, ref["phase_fractions"], atol=1e-12)
+        g = rh.homogenize(r, ref["k_phases"], ref["tol"], precision=precision)
+    Kr = np.array(ref["K"])
+    if precision == 1:
+        assert g.status == rh.RVE_OK
+        assert list(g.iters) == ref["iters"]
+        assert tensor_err(g.K, Kr) <= 1e-9
+    else:
+        assert g.status in (rh.RVE_OK, rh.RVE_STALLED)
+        assert tensor_err(g.K, Kr) <= 1e-4
