@@ -16,10 +16,23 @@ template <typename T, int N> constexpr int plane_split() {
                                                                                    : 0;
 }
 
-// z-tile width: largest W <= 16 dividing N/2 and N with 3 N W complex <= 64 KiB.
-template <typename T, int N> constexpr int ztile() {
+// z-tile width: largest W <= 16 dividing N/2 and N with 3 N W complex in
+// 64 KiB of LDS; if that leaves fewer than 8 columns (long pencils), up to
+// 96 KiB is allowed so that global accesses keep >= 64-byte segments.
+template <typename T, int N> constexpr int ztile_cap(size_t cap) {
     for (int w = 16; w >= 1; --w)
-        if ((N / 2) % w == 0 && N % w == 0 && (size_t)3 * N * w * sizeof(Cx<T>) <= 64 * 1024) return w;
+        if ((N / 2) % w == 0 && N % w == 0 && (size_t)3 * N * w * sizeof(Cx<T>) <= cap) return w;
+    return 1;
+}
+template <typename T, int N> constexpr int ztile() {
+    return ztile_cap<T, N>(64 * 1024) >= 8 ? ztile_cap<T, N>(64 * 1024) : ztile_cap<T, N>(96 * 1024);
+}
+
+// Five-pass form: rows per block of the x passes, columns per block of the y passes.
+template <typename T, int N> constexpr int row_group() { return N >= 16 ? 16 : N; }
+template <typename T, int N> constexpr int col_tile() {
+    for (int w = 16; w >= 1; --w)
+        if ((N / 2) % w == 0 && N % w == 0 && (size_t)N * w * sizeof(Cx<T>) <= 64 * 1024) return w;
     return 1;
 }
 
@@ -33,21 +46,32 @@ template <typename T, int N> constexpr int plane_threads() {
 
 template <typename T, int N> struct Instance {
     static constexpr int S = plane_split<T, N>();
+    static constexpr bool FIVE = (S == 0);  // plane does not fit in LDS
+    static constexpr int SP = FIVE ? 1 : S;
     static constexpr int W = ztile<T, N>();
     static constexpr int NTP = plane_threads<T, N>();
     static constexpr int NTZ = 256;
-    static_assert(S == 1 || S == 2, "plane does not fit in LDS");
+    static constexpr int G = row_group<T, N>();
+    static constexpr int WC = col_tile<T, N>();
+    static constexpr int NTR = 256;
+    static constexpr int NPER = FIVE ? N * (N / G) : N * S;
 
-    static void fwd(const LaunchArgs &a, hipStream_t s) {
-        hipLaunchKernelGGL((k_fwd_plane<T, N, S, NTP>), dim3(9 * N * S), dim3(NTP), 0, s,
-                           (const T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq,
-                           (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st);
+    template <bool PHI> static void fwd_t(const LaunchArgs &a, hipStream_t s) {
+        if constexpr (FIVE) {
+            hipLaunchKernelGGL((k_fwd_rows<T, N, G, NTR, PHI>), dim3(9 * N * (N / G)), dim3(NTR), 0, s,
+                               (const T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq,
+                               (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st);
+            hipLaunchKernelGGL((k_cols<T, N, WC, NTR, false, PHI>), dim3(ColTiles<N, WC>::ALL), dim3(NTR), 0,
+                               s, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw,
+                               (const DevState *)a.st);
+        } else {
+            hipLaunchKernelGGL((k_fwd_plane<T, N, SP, NTP, PHI>), dim3(9 * N * SP), dim3(NTP), 0, s,
+                               (const T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq,
+                               (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st);
+        }
     }
-    static void fwd_phi(const LaunchArgs &a, hipStream_t s) {
-        hipLaunchKernelGGL((k_fwd_plane<T, N, S, NTP, true>), dim3(9 * N * S), dim3(NTP), 0, s,
-                           (const T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq,
-                           (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st);
-    }
+    static void fwd(const LaunchArgs &a, hipStream_t s) { fwd_t<false>(a, s); }
+    static void fwd_phi(const LaunchArgs &a, hipStream_t s) { fwd_t<true>(a, s); }
     static void zeq(const LaunchArgs &a, hipStream_t s) {
         hipLaunchKernelGGL((k_zeq<T, N, W, NTZ>), dim3(3 * ZTiles<N, W>::PER_LC), dim3(NTZ), 0, s,
                            (const Cx<T> *)a.spec, (const Cx<T> *)a.nyq, (const Cx<T> *)a.tw,
@@ -59,9 +83,17 @@ template <typename T, int N> struct Instance {
                            (const DevState *)a.st);
     }
     static void inv(const LaunchArgs &a, hipStream_t s) {
-        hipLaunchKernelGGL((k_inv_plane<T, N, S, NTP>), dim3(9 * N * S), dim3(NTP), 0, s, (T *)a.e,
-                           a.ph, (const Cx<T> *)a.spec, (const Cx<T> *)a.nyq, (const Cx<T> *)a.tw,
-                           a.prm, (const DevState *)a.st, a.part);
+        if constexpr (FIVE) {
+            hipLaunchKernelGGL((k_cols<T, N, WC, NTR, true>), dim3(ColTiles<N, WC>::ALL), dim3(NTR), 0, s,
+                               (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, (const DevState *)a.st);
+            hipLaunchKernelGGL((k_inv_rows<T, N, G, NTR>), dim3(9 * N * (N / G)), dim3(NTR), 0, s, (T *)a.e,
+                               a.ph, (const Cx<T> *)a.spec, (const Cx<T> *)a.nyq, (const Cx<T> *)a.tw,
+                               a.prm, (const DevState *)a.st, a.part);
+        } else {
+            hipLaunchKernelGGL((k_inv_plane<T, N, SP, NTP>), dim3(9 * N * SP), dim3(NTP), 0, s, (T *)a.e,
+                               a.ph, (const Cx<T> *)a.spec, (const Cx<T> *)a.nyq, (const Cx<T> *)a.tw,
+                               a.prm, (const DevState *)a.st, a.part);
+        }
     }
     static void init(const LaunchArgs &a, size_t M, hipStream_t s) {
         hipLaunchKernelGGL((k_init<T>), dim3(1024), dim3(256), 0, s, (T *)a.e, M, a.prm, a.st);
@@ -79,20 +111,23 @@ template <typename T, int N> struct Instance {
         constexpr double cb = (double)sizeof(Cx<T>);
         constexpr double rb = (double)sizeof(T);
         constexpr double spec_b = 9.0 * N * N * (H + 1) * cb;  // spec + nyq
+        // P1: read e + phases once per channel, write spectrum (five-pass:
+        // plus a read and write of the spectrum for y).  P2: read + write
+        // spectrum.  P3: read spectrum, e, phases; write e (five-pass: plus y).
+        constexpr double extra = FIVE ? 2.0 * spec_b : 0.0;
         static const SolverOps o = {
             N,
             precision,
-            S,
+            FIVE ? 0 : S,
             W,
-            N * S,
+            NPER,
             sizeof(T),
             (size_t)9 * N * N * H,
             (size_t)9 * N * N,
-            {9 * N * S, 3 * ZTiles<N, W>::PER_LC, 9 * N * S},
-            {NTP, NTZ, NTP},
-            // P1: read e + phases once per channel, write spectrum.
-            // P2: read + write spectrum.  P3: read spectrum, e, phases; write e.
-            {9.0 * M * rb + 9.0 * M + spec_b, 2.0 * spec_b, spec_b + 2.0 * 9.0 * M * rb + 9.0 * M},
+            {FIVE ? 9 * N * (N / G) : 9 * N * S, 3 * ZTiles<N, W>::PER_LC, FIVE ? 9 * N * (N / G) : 9 * N * S},
+            {FIVE ? NTR : NTP, NTZ, FIVE ? NTR : NTP},
+            {9.0 * M * rb + 9.0 * M + spec_b + extra, 2.0 * spec_b,
+             spec_b + 2.0 * 9.0 * M * rb + 9.0 * M + extra},
             ZTiles<N, W>::PER_LC,
             &fwd,
             &fwd_phi,

@@ -152,8 +152,8 @@ void launch_reduce(const LaunchArgs &a, int nper, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, a.part, nper, a.prm, a.st, a.hist);
 }
 
-static const int kSizesF32[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 256};
-static const int kSizesF64[] = {8, 12, 16, 24, 32, 48, 64, 96, 128};
+static const int kSizesF32[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 256, 512};
+static const int kSizesF64[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 256, 512};
 
 int supported_sizes(int precision, const int **list) {
     if (precision == 0) {

@@ -14,6 +14,8 @@ const SolverOps *ops_f64(int n) {
     case 64: return Instance<double, 64>::ops(1);
     case 96: return Instance<double, 96>::ops(1);
     case 128: return Instance<double, 128>::ops(1);
+    case 256: return Instance<double, 256>::ops(1);
+    case 512: return Instance<double, 512>::ops(1);
     default: return nullptr;
     }
 }

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <new>
@@ -97,6 +98,9 @@ void Solver::release() {
     run_ev[0] = run_ev[1] = nullptr;
     if (h_pinned) (void)hipHostFree(h_pinned);
     h_pinned = nullptr;
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+    g_ws = nullptr;
 }
 
 // Allocate (or adopt) the workspace and the per-solver HIP objects.
@@ -133,6 +137,10 @@ int Solver::prepare(const SolverOps *o, void *user_ws, size_t user_bytes) {
         tw_ready = false;
     }
     layout = L;
+    {
+        const char *g = getenv("RVEHOM_GRAPHS");
+        use_graphs = !(g && g[0] == '0');
+    }
     if (!own_stream) HIP_CHECK(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
     if (poll_ev.empty()) {
         poll_ev.resize(kPollSlots);
@@ -432,39 +440,86 @@ int Solver::begin(const uint8_t *d_phase, const double k[3], double tol, const S
     return RVE_OK;
 }
 
+// One iteration: the three passes, the reduction and (two-stage stop only)
+// the equilibrium check.  Every kernel exits at once for frozen load cases.
+void Solver::launch_iteration(const LaunchArgs &a, hipStream_t s) {
+    ops->fwd(a, s);
+    ops->zgreen(a, s);
+    ops->inv(a, s);
+    launch_reduce(a, ops->nper, s);
+    if (eq_check) {
+        ops->fwd_phi(a, s);
+        ops->zeq(a, s);
+        launch_eq_reduce(a, ops->eq_tiles, 0, s);
+    }
+}
+
+// Capture kChunk iterations into a graph on the solver's own stream.
+int Solver::ensure_graph(const uint8_t *d_phase) {
+    if (gexec && g_ws == ws && g_ph == d_phase && g_eq == eq_check) return RVE_OK;
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+    LaunchArgs a = args(d_phase);
+    hipGraph_t g = nullptr;
+    HIP_CHECK(hipStreamBeginCapture(own_stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < kChunk; ++i) launch_iteration(a, own_stream);
+    hipError_t cap = hipStreamEndCapture(own_stream, &g);
+    if (cap != hipSuccess) {
+        set_error("graph capture failed: %s", hipGetErrorString(cap));
+        return RVE_ERR_DEVICE;
+    }
+    hipError_t inst = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (inst != hipSuccess) {
+        gexec = nullptr;
+        set_error("graph instantiation failed: %s", hipGetErrorString(inst));
+        return RVE_ERR_DEVICE;
+    }
+    g_ws = ws;
+    g_ph = d_phase;
+    g_eq = eq_check;
+    return RVE_OK;
+}
+
 // Enqueue up to `count` iterations (never beyond max_iter) and a poll point.
+// Full chunks replay the captured graph; timed runs and partial chunks launch
+// kernel by kernel (timed runs bracket every launch with events).
 int Solver::enqueue(const uint8_t *d_phase, int count, int max_iter, bool timing, hipStream_t s) {
     LaunchArgs a = args(d_phase);
-    for (int i = 0; i < count && issued < max_iter; ++i, ++issued) {
-        for (int kk = 0; kk < 4; ++kk) {
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (timing) {
+    if (!timing && use_graphs && count == kChunk && issued + kChunk <= max_iter) {
+        int rc = ensure_graph(d_phase);
+        if (rc != RVE_OK) return rc;
+        HIP_CHECK(hipGraphLaunch(gexec, s));
+        issued += kChunk;
+    } else {
+        for (int i = 0; i < count && issued < max_iter; ++i, ++issued) {
+            if (!timing) {
+                launch_iteration(a, s);
+                continue;
+            }
+            for (int kk = 0; kk < 4; ++kk) {
                 size_t need = 2 * (launches.size() + 1);
                 while (time_ev.size() < need) {
                     hipEvent_t ev;
                     HIP_CHECK(hipEventCreate(&ev));
                     time_ev.push_back(ev);
                 }
-                e0 = time_ev[need - 2];
-                e1 = time_ev[need - 1];
+                hipEvent_t e0 = time_ev[need - 2], e1 = time_ev[need - 1];
                 HIP_CHECK(hipEventRecord(e0, s));
-            }
-            switch (kk) {
-            case 0: ops->fwd(a, s); break;
-            case 1: ops->zgreen(a, s); break;
-            case 2: ops->inv(a, s); break;
-            default: launch_reduce(a, ops->nper, s); break;
-            }
-            if (timing) {
+                switch (kk) {
+                case 0: ops->fwd(a, s); break;
+                case 1: ops->zgreen(a, s); break;
+                case 2: ops->inv(a, s); break;
+                default: launch_reduce(a, ops->nper, s); break;
+                }
                 HIP_CHECK(hipEventRecord(e1, s));
                 launches.push_back({kk, issued});
             }
-        }
-        if (eq_check) {
-            // second stage of step 1 for load cases whose eps_comp fell below tol
-            ops->fwd_phi(a, s);
-            ops->zeq(a, s);
-            launch_eq_reduce(a, ops->eq_tiles, 0, s);
+            if (eq_check) {
+                ops->fwd_phi(a, s);
+                ops->zeq(a, s);
+                launch_eq_reduce(a, ops->eq_tiles, 0, s);
+            }
         }
     }
     HIP_CHECK(hipGetLastError());

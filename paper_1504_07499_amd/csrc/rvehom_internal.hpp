@@ -63,6 +63,13 @@ struct Solver {
     std::vector<LaunchRec> launches;
     bool eq_check = false;
     const uint8_t *d_phase_last = nullptr;
+    // captured graph of kChunk iterations (kernels only; all parameters are
+    // read from device memory, so one graph serves every call on this workspace)
+    hipGraphExec_t gexec = nullptr;
+    const void *g_ws = nullptr;
+    const uint8_t *g_ph = nullptr;
+    bool g_eq = false;
+    bool use_graphs = true;
 
     ~Solver();
     void release();
@@ -71,6 +78,8 @@ struct Solver {
     int ensure_twiddles(hipStream_t s);
     int begin(const uint8_t *d_phase, const double k[3], double tol, const SolverOpts &o, hipStream_t s);
     int enqueue(const uint8_t *d_phase, int count, int max_iter, bool timing, hipStream_t s);
+    void launch_iteration(const LaunchArgs &a, hipStream_t s);
+    int ensure_graph(const uint8_t *d_phase);
     int poll(bool wait, int max_iter);
     int collect(const SolverOpts &o, hipStream_t s, rve_result *out, double *hist, int hist_cap,
                 rve_kernel_times *kt);

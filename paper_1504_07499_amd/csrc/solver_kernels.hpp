@@ -88,6 +88,69 @@ template <typename T> __device__ __forceinline__ T pick(int p, T a0, T a1, T a2)
     return p == 0 ? a0 : (p == 1 ? a1 : a2);
 }
 
+// R2C unpack, item k in [0, N/4] of one row: the length-N/2 FFT Z of the
+// packed even/odd samples becomes X[k] and X[N/2 - k] of the real-input
+// spectrum (X[0] and X[N/2] for k = 0), optionally times a row factor.
+template <typename T, int N, bool ROT>
+__device__ __forceinline__ void r2c_unpack(Cx<T> *row, int k, const Cx<T> *__restrict__ tw, Cx<T> rot) {
+    constexpr int H = N / 2;
+    if (k == 0) {
+        const Cx<T> z0 = row[0];
+        Cx<T> x0 = {z0.x + z0.y, (T)0}, xh = {z0.x - z0.y, (T)0};
+        if (ROT) {
+            x0 = x0 * rot;
+            xh = xh * rot;
+        }
+        row[0] = x0;
+        row[H] = xh;
+    } else {
+        const Cx<T> a = row[k], b = conj(row[H - k]);
+        const Cx<T> A = scale(a + b, (T)0.5);
+        const Cx<T> D = scale(a - b, (T)0.5);
+        const Cx<T> B = {D.y, -D.x};  // (a - b) / (2 i)
+        const Cx<T> wB = B * tw[k];
+        Cx<T> xk = A + wB, xm = conj(A - wB);
+        if (ROT) {
+            xk = xk * rot;
+            xm = xm * rot;
+        }
+        row[k] = xk;
+        if (k != H - k) row[H - k] = xm;
+    }
+}
+
+// C2R pack, item k in [0, N/4]: Hermitian half row X[0..N/2] -> the
+// length-N/2 sequence whose inverse FFT holds the even/odd output samples.
+template <typename T, int N>
+__device__ __forceinline__ void c2r_pack(Cx<T> *row, int k, const Cx<T> *__restrict__ tw) {
+    constexpr int H = N / 2;
+    if (k == 0) {
+        const T x0 = row[0].x, xh = row[H].x;
+        row[0] = Cx<T>{x0 + xh, x0 - xh};
+    } else {
+        const Cx<T> a = row[k], b = conj(row[H - k]);
+        const Cx<T> A = a + b;
+        const Cx<T> B = (a - b) * conj(tw[k]);
+        row[k] = A + Cx<T>{-B.y, B.x};                               // A + i B
+        if (k != H - k) row[H - k] = conj(A) + Cx<T>{B.y, B.x};      // conj(A) + i conj(B)
+    }
+}
+
+// Steps 6-7 and the flux on V voxels of one row: e+ = e + w (c - e),
+// r2 += |e - c|^2, fl += k e+ (FP64 accumulation).
+template <typename T, int V>
+__device__ __forceinline__ void em_update(T *a, const T *c, const int *p, T w0, T w1, T w2, double k0d,
+                                          double k1d, double k2d, double &r2, double &fl) {
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+        const T d = a[i] - c[i];
+        r2 += (double)d * (double)d;
+        const T wi = pick<T>(p[i], w0, w1, w2);
+        a[i] = a[i] + wi * (c[i] - a[i]);
+        fl += pick<double>(p[i], k0d, k1d, k2d) * (double)a[i];
+    }
+}
+
 // Block index -> (channel, z, parity).  For S = 2 the two parities of one
 // plane are 8 blocks apart, so that both run on the same XCD (blocks are
 // dealt round-robin to the 8 XCDs) and the second read of the plane hits L2.
@@ -158,34 +221,13 @@ __global__ __launch_bounds__(NT) void k_fwd_plane(const T *__restrict__ e, const
     // unpack to the real-input spectrum X[0..N/2]
     for (int idx = tid; idx < ROWS * (H / 2 + 1); idx += NT) {
         const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
-        Cx<T> *row = plane + y * RS;
-        Cx<T> rot = {(T)1, (T)0};
         if constexpr (S == 2) {
-            if (h) rot = tw[y];  // w_N^y of the row-parity split
-        }
-        if (k == 0) {
-            const Cx<T> z0 = row[0];
-            Cx<T> x0 = {z0.x + z0.y, (T)0}, xh = {z0.x - z0.y, (T)0};
-            if constexpr (S == 2) {
-                x0 = x0 * rot;
-                xh = xh * rot;
+            if (h) {
+                r2c_unpack<T, N, true>(plane + y * RS, k, tw, tw[y]);  // w_N^y of the parity split
+                continue;
             }
-            row[0] = x0;
-            row[H] = xh;
-        } else {
-            const Cx<T> a = row[k], b = conj(row[H - k]);
-            const Cx<T> A = scale(a + b, (T)0.5);
-            const Cx<T> D = scale(a - b, (T)0.5);
-            const Cx<T> B = {D.y, -D.x};  // (a - b) / (2 i)
-            const Cx<T> wB = B * tw[k];
-            Cx<T> xk = A + wB, xm = conj(A - wB);
-            if constexpr (S == 2) {
-                xk = xk * rot;
-                xm = xm * rot;
-            }
-            row[k] = xk;
-            if (k != H - k) row[H - k] = xm;
         }
+        r2c_unpack<T, N, false>(plane + y * RS, k, tw, Cx<T>{(T)1, (T)0});
     }
     __syncthreads();
     // y: complex FFT of length N/S down the N/2 + 1 columns
@@ -428,18 +470,7 @@ __global__ __launch_bounds__(NT) void k_inv_plane(T *__restrict__ e, const uint8
     // pack the Hermitian half row into a length-N/2 complex sequence
     for (int idx = tid; idx < ROWS * (H / 2 + 1); idx += NT) {
         const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
-        Cx<T> *row = plane + y * RS;
-        if (k == 0) {
-            const T x0 = row[0].x, xh = row[H].x;
-            row[0] = Cx<T>{x0 + xh, x0 - xh};
-        } else {
-            const Cx<T> a = row[k], b = conj(row[H - k]);
-            const Cx<T> A = a + b;
-            const Cx<T> B = (a - b) * conj(tw[k]);
-            const Cx<T> iB = {-B.y, B.x};
-            row[k] = A + iB;
-            if (k != H - k) row[H - k] = conj(A) + Cx<T>{B.y, B.x};  // conj(A) + i conj(B)
-        }
+        c2r_pack<T, N>(plane + y * RS, k, tw);
     }
     __syncthreads();
     fft_lds<T, H, true, ROWS, 1, NT, N, SeqStride<RS>>(plane, tw, tid);
@@ -462,19 +493,183 @@ __global__ __launch_bounds__(NT) void k_inv_plane(T *__restrict__ e, const uint8
             c[i] = zz.x;
             c[i + 1] = zz.y;
         }
-#pragma unroll
-        for (int i = 0; i < V; ++i) {
-            const T d = a[i] - c[i];
-            r2 += (double)d * (double)d;
-            const T wi = pick<T>(p[i], w0, w1, w2);
-            a[i] = a[i] + wi * (c[i] - a[i]);
-            fl += pick<double>(p[i], k0d, k1d, k2d) * (double)a[i];
-        }
+        em_update<T, V>(a, c, p, w0, w1, w2, k0d, k1d, k2d, r2, fl);
         vstore<T>(eb + y * N + x, a);
     }
     block_sum2<NT>(r2, fl, red);
     if (tid == 0) {
         double *pp = part + ((size_t)ch * (N * S) + (size_t)z * S + h) * 2;
+        pp[0] = r2;
+        pp[1] = fl;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Five-pass form for grids whose xy-plane does not fit in LDS (FP64 256^3,
+// 512^3): the x and y transforms get passes of their own.
+//   k_fwd_rows:  tau (or flux) fused into the load, R2C of G rows;
+//   k_cols:      complex FFT down W columns of one (ch, z) plane (forward or
+//                inverse); the kx = N/2 column is a tile of W planes;
+//   k_zgreen:    as in the three-pass form;
+//   k_inv_rows:  C2R of G rows fused with steps 6-7 and the flux.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int G, int NT, bool PHI = false>
+__global__ __launch_bounds__(NT) void k_fwd_rows(const T *__restrict__ e, const uint8_t *__restrict__ ph,
+                                                 Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
+                                                 const Cx<T> *__restrict__ tw,
+                                                 const DevParams *__restrict__ prm,
+                                                 const DevState *__restrict__ st) {
+    constexpr int H = N / 2, RS = H + 1, V = VecOf<T>::V, NN = N * N, GP = N / G;
+    __shared__ Cx<T> rows[G * RS];
+    const int tid = threadIdx.x;
+    const int ch = blockIdx.x / (N * GP), rem = blockIdx.x - ch * (N * GP);
+    const int z = rem / GP, y0 = (rem - z * GP) * G;
+    const int lc = ch / 3;
+    if (PHI ? !st->eq_pending[lc] : st->done[lc]) return;
+    const double *lut = PHI ? prm->k : prm->dk;
+    const T d0 = (T)lut[0], d1 = (T)lut[1], d2 = (T)lut[2];
+    const T *eb = e + (size_t)ch * N * NN + (size_t)z * NN + (size_t)y0 * N;
+    const uint8_t *pb = ph + (size_t)z * NN + (size_t)y0 * N;
+    for (int idx = tid; idx < G * N / V; idx += NT) {
+        const int y = idx / (N / V), x = (idx - y * (N / V)) * V;
+        T a[V];
+        int p[V];
+        vload<T>(eb + y * N + x, a);
+        pload<V>(pb + y * N + x, p);
+#pragma unroll
+        for (int i = 0; i < V; i += 2)
+            rows[y * RS + (x + i) / 2] = Cx<T>{pick<T>(p[i], d0, d1, d2) * a[i],
+                                               pick<T>(p[i + 1], d0, d1, d2) * a[i + 1]};
+    }
+    __syncthreads();
+    fft_lds<T, H, false, G, 1, NT, N, SeqStride<RS>>(rows, tw, tid);
+    for (int idx = tid; idx < G * (H / 2 + 1); idx += NT) {
+        const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
+        r2c_unpack<T, N, false>(rows + y * RS, k, tw, Cx<T>{(T)1, (T)0});
+    }
+    __syncthreads();
+    Cx<T> *sb = spec + (((size_t)ch * N + z) * N + y0) * H;
+    for (int idx = tid; idx < G * H; idx += NT) {
+        const int y = idx / H, kx = idx - y * H;
+        sb[(size_t)y * H + kx] = rows[y * RS + kx];
+    }
+    Cx<T> *nb = nyq + ((size_t)ch * N + z) * N + y0;
+    for (int y = tid; y < G; y += NT) nb[y] = rows[y * RS + H];
+}
+
+template <int N, int W> struct ColTiles {
+    static constexpr int H = N / 2;
+    static constexpr int MAIN = 9 * N * (H / W);  // (ch, z, kx chunk)
+    static constexpr int NYQ = 9 * (N / W);       // (ch, chunk of W planes) of the kx = N/2 column
+    static constexpr int ALL = MAIN + NYQ;
+};
+
+// GATE_EQ: run for load cases awaiting the equilibrium check instead of the
+// ones still iterating.
+template <typename T, int N, int W, int NT, bool INV, bool GATE_EQ = false>
+__global__ __launch_bounds__(NT) void k_cols(Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
+                                             const Cx<T> *__restrict__ tw, const DevState *__restrict__ st) {
+    using TL = ColTiles<N, W>;
+    constexpr int H = N / 2, NW = N * W;
+    __shared__ Cx<T> buf[NW];  // [ky][w]
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x;
+    Cx<T> *base;
+    int ch;
+    size_t es, ss;  // global stride between ky and between w
+    if (b < TL::MAIN) {
+        ch = b / (N * (H / W));
+        const int rem = b - ch * (N * (H / W));
+        const int z = rem / (H / W), c0 = (rem - z * (H / W)) * W;
+        base = spec + ((size_t)ch * N + z) * N * H + c0;
+        es = H;
+        ss = 1;
+    } else {
+        const int t = b - TL::MAIN;
+        ch = t / (N / W);
+        const int z0 = (t - ch * (N / W)) * W;
+        base = nyq + ((size_t)ch * N + z0) * N;
+        es = 1;
+        ss = N;
+    }
+    const int lc = ch / 3;
+    if (GATE_EQ ? !st->eq_pending[lc] : st->done[lc]) return;
+    if (ss == 1) {
+        for (int idx = tid; idx < NW; idx += NT) {
+            const int ky = idx / W, w = idx - ky * W;
+            buf[idx] = base[(size_t)ky * es + w];
+        }
+    } else {
+        for (int idx = tid; idx < NW; idx += NT) {
+            const int w = idx / N, ky = idx - w * N;
+            buf[ky * W + w] = base[(size_t)w * ss + ky];
+        }
+    }
+    __syncthreads();
+    fft_lds<T, N, INV, W, W, NT, N, SeqStride<1>>(buf, tw, tid);
+    if (ss == 1) {
+        for (int idx = tid; idx < NW; idx += NT) {
+            const int ky = idx / W, w = idx - ky * W;
+            base[(size_t)ky * es + w] = buf[idx];
+        }
+    } else {
+        for (int idx = tid; idx < NW; idx += NT) {
+            const int w = idx / N, ky = idx - w * N;
+            base[(size_t)w * ss + ky] = buf[ky * W + w];
+        }
+    }
+}
+
+template <typename T, int N, int G, int NT>
+__global__ __launch_bounds__(NT) void k_inv_rows(T *__restrict__ e, const uint8_t *__restrict__ ph,
+                                                 const Cx<T> *__restrict__ spec, const Cx<T> *__restrict__ nyq,
+                                                 const Cx<T> *__restrict__ tw,
+                                                 const DevParams *__restrict__ prm,
+                                                 const DevState *__restrict__ st, double *__restrict__ part) {
+    constexpr int H = N / 2, RS = H + 1, V = VecOf<T>::V, NN = N * N, GP = N / G;
+    __shared__ Cx<T> rows[G * RS];
+    __shared__ double red[2 * (NT / 64)];
+    const int tid = threadIdx.x;
+    const int ch = blockIdx.x / (N * GP), rem = blockIdx.x - ch * (N * GP);
+    const int z = rem / GP, yg = rem - z * GP, y0 = yg * G;
+    const int lc = ch / 3;
+    if (st->done[lc]) return;
+    const Cx<T> *sb = spec + (((size_t)ch * N + z) * N + y0) * H;
+    const Cx<T> *nb = nyq + ((size_t)ch * N + z) * N + y0;
+    for (int idx = tid; idx < G * RS; idx += NT) {
+        const int y = idx / RS, kx = idx - y * RS;
+        rows[idx] = (kx < H) ? sb[(size_t)y * H + kx] : nb[y];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < G * (H / 2 + 1); idx += NT) {
+        const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
+        c2r_pack<T, N>(rows + y * RS, k, tw);
+    }
+    __syncthreads();
+    fft_lds<T, H, true, G, 1, NT, N, SeqStride<RS>>(rows, tw, tid);
+    const T w0 = (T)prm->w[0], w1 = (T)prm->w[1], w2 = (T)prm->w[2];
+    const double k0d = prm->k[0], k1d = prm->k[1], k2d = prm->k[2];
+    T *eb = e + (size_t)ch * N * NN + (size_t)z * NN + (size_t)y0 * N;
+    const uint8_t *pb = ph + (size_t)z * NN + (size_t)y0 * N;
+    double r2 = 0.0, fl = 0.0;
+    for (int idx = tid; idx < G * N / V; idx += NT) {
+        const int y = idx / (N / V), x = (idx - y * (N / V)) * V;
+        T a[V], c[V];
+        int p[V];
+        vload<T>(eb + y * N + x, a);
+        pload<V>(pb + y * N + x, p);
+#pragma unroll
+        for (int i = 0; i < V; i += 2) {
+            const Cx<T> zz = rows[y * RS + (x + i) / 2];
+            c[i] = zz.x;
+            c[i + 1] = zz.y;
+        }
+        em_update<T, V>(a, c, p, w0, w1, w2, k0d, k1d, k2d, r2, fl);
+        vstore<T>(eb + y * N + x, a);
+    }
+    block_sum2<NT>(r2, fl, red);
+    if (tid == 0) {
+        double *pp = part + ((size_t)ch * (N * GP) + (size_t)z * GP + yg) * 2;
         pp[0] = r2;
         pp[1] = fl;
     }

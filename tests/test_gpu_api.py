@@ -43,24 +43,52 @@ def test_fp32_stall_detection():
     assert g.iters.max() < 3000
 
 
+_TORCH_CHILD = r"""
+import sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+import torch
+torch.cuda.init()
+import paper_1504_07499_amd as rh
+from paper_1504_07499_amd import geom
+K3 = np.array([0.2, 0.3, 400.0])
+ph, _, _ = geom.generate(32, 8, 0.2, 0.1, 1)
+with rh.rve_create_from_phases(ph) as r:
+    own = rh.homogenize(r, K3, 1e-6, precision=0)
+    nbytes = rh.rve_workspace_size(r, 0)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ext = rh.homogenize(r, K3, 1e-6, precision=0, workspace=ws,
+                            stream=torch.cuda.current_stream())
+    small = torch.empty(nbytes // 2, dtype=torch.uint8, device="cuda")
+    try:
+        rh.homogenize(r, K3, 1e-6, precision=0, workspace=small)
+        raise SystemExit("undersized workspace accepted")
+    except rh.RveError:
+        pass
+assert np.array_equal(own.K, ext.K) and np.array_equal(own.iters, ext.iters)
+print("torch interop ok", list(ext.iters), flush=True)
+"""
+
+
 def test_torch_workspace_and_stream():
     """Device memory and the stream may come from PyTorch; the result is the
-    same as with the library's own workspace."""
-    torch = pytest.importorskip("torch")
-    print("\n[case] torch workspace", flush=True)
-    ph, _, _ = geom.generate(32, 8, 0.2, 0.1, 1)
-    with rh.rve_create_from_phases(ph) as r:
-        own = rh.homogenize(r, K3, 1e-6, precision=0)
-        nbytes = rh.rve_workspace_size(r, 0)
-        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        s = torch.cuda.Stream()
-        with torch.cuda.stream(s):
-            ext = rh.homogenize(r, K3, 1e-6, precision=0, workspace=ws,
-                                stream=torch.cuda.current_stream())
-        small = torch.empty(nbytes // 2, dtype=torch.uint8, device="cuda")
-        with pytest.raises(rh.RveError):
-            rh.homogenize(r, K3, 1e-6, precision=0, workspace=small)
-    assert np.array_equal(own.K, ext.K) and np.array_equal(own.iters, ext.iters)
+    same as with the library's own workspace.  Runs in a child process that
+    imports torch before the library, so both use torch's HIP runtime (a
+    process can hold only one)."""
+    import os
+    import subprocess
+    import sys
+
+    pytest.importorskip("torch")
+    print("\n[case] torch workspace (child process)", flush=True)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", _TORCH_CHILD, root], capture_output=True,
+                         text=True, timeout=300)
+    print(out.stdout[-2000:], out.stderr[-2000:])
+    assert out.returncode == 0
+    assert "torch interop ok" in out.stdout
 
 
 @pytest.mark.parametrize("precision", [0, 1])

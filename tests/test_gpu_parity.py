@@ -163,3 +163,54 @@ def test_config2_128_vs_stored_oracle(precision):
     else:
         assert g.status in (rh.RVE_OK, rh.RVE_STALLED)
         assert tensor_err(g.K, Kr) <= 1e-4
+
+
+def test_five_pass_256_fp64_vs_oracle():
+    """FP64 at 256^3 runs the five-pass form (the xy-plane does not fit in
+    LDS): two iterations of load case e_1, voxel by voxel against the oracle."""
+    print("\n[case] five-pass 256 fp64", flush=True)
+    ph, _, _ = geom.generate(256, 100, 0.3, 0.2, 3)
+    ref = oracle.homogenize(ph, K_PAPER_CFG, tol=0.0, max_iter=2, want_field=True, lc_mask=1)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize(r, K_PAPER_CFG, 0.0, max_iter=2, precision=1, lc_mask=1,
+                          want_field=True)
+    assert field_err(g.field[0], ref.field[0]) <= 1e-11
+    assert tensor_err(g.K[:, 0], ref.K[:, 0]) <= 1e-11
+
+
+@pytest.mark.parametrize("n,precision", [(512, 0), (256, 1)])
+def test_large_grid_laminate_exact(n, precision):
+    """Closed form at sizes the oracle cannot run in a test: a laminate
+    normal to y with odd layer widths gives K = diag(<k>, 1/<1/k>, <k>)."""
+    print(f"\n[case] laminate n={n} precision={precision}", flush=True)
+    k = np.array([1.0, 0.2, 4.0])
+    widths = [n // 2 - 1, 3, n // 2 - 2]
+    prof = np.concatenate([np.full(w, p, np.uint8) for w, p in zip(widths, [0, 2, 1])])
+    ph = np.ascontiguousarray(np.broadcast_to(prof.reshape(1, n, 1), (n, n, n)))
+    kv = k[prof]
+    Kex = np.eye(3) * kv.mean()
+    Kex[1, 1] = 1.0 / (1.0 / kv).mean()
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize(r, k, 1e-10 if precision else 1e-6, precision=precision)
+    assert tensor_err(g.K, Kex) <= (1e-9 if precision else 2e-5)
+
+
+def test_graph_replays_match_eager_launches():
+    """Chunks of iterations replayed from a captured graph give bitwise the
+    result of kernel-by-kernel launches, over several solves with host work
+    and synchronisation in between."""
+    import os
+
+    print("\n[case] graph replay vs eager", flush=True)
+    ph, _, _ = geom.generate(48, 10, 0.25, 0.2, 8)
+    with rh.rve_create_from_phases(ph) as r:
+        os.environ["RVEHOM_GRAPHS"] = "0"
+        try:
+            eager = rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=0)
+        finally:
+            os.environ.pop("RVEHOM_GRAPHS", None)
+        for rep in range(3):
+            g = rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=0)
+            assert np.array_equal(g.K, eager.K), rep
+            assert np.array_equal(g.iters, eager.iters), rep
+            _ = rh.rve_get_phases(r)
