@@ -74,6 +74,9 @@ typedef struct {
     void *workspace;        /* device buffer of >= rve_workspace_size bytes, or NULL
                                (the library then allocates and caches its own) */
     size_t workspace_bytes;
+    int scheme;             /* 0 = accelerated (Eyre-Milton, Sec. 3 Algorithm, k0 of Sec. 5);
+                               1 = basic scheme named in Sec. 3 (e+ = c, the compatible
+                               field, with k0 = (min k + max k) / 2) */
 } rve_opts;
 
 typedef struct {

@@ -312,12 +312,15 @@ void orc_set_threads(int t)
  *  out_field  out (may be NULL), final field, same layout as init_field
  *  lc_mask    load cases to run (bit j = e_(j+1)); others are left at E with
  *             K column, iters and residual zero
+ *  scheme     0 = the accelerated scheme of the Algorithm (k0 of Sec. 5);
+ *             1 = the basic scheme named in Sec. 3 as an alternative:
+ *             e+ = grad theta_comp, with k0 = (min k + max k) / 2
  */
 int orc_homogenize(int n, const uint8_t *phase, const double kph[3], double tol,
                    int max_iter, int eq_check, const double *init_field,
                    double *K, int *iters, int *status, double *final_res,
                    double *eps_eq, double *hist, int hist_cap, double *out_field,
-                   int lc_mask)
+                   int lc_mask, int scheme)
 {
     if (n < 1 || max_iter < 1 || !(tol >= 0.0) || !phase || !kph || !K) return ORC_ERR_ARG;
     for (int p = 0; p < 3; ++p)
@@ -326,10 +329,12 @@ int orc_homogenize(int n, const uint8_t *phase, const double kph[3], double tol,
     for (size_t v = 0; v < M; ++v)
         if (phase[v] > 2) return ORC_ERR_ARG;
 
-    /* Sec. 5: L0 = -sqrt(min k * max k) I over the three given k (R1). */
+    if (scheme != 0 && scheme != 1) return ORC_ERR_ARG;
+    /* Sec. 5: L0 = -sqrt(min k * max k) I over the three given k (R1);
+     * the basic scheme takes the arithmetic mean of the extremes. */
     double kmin = fmin(kph[0], fmin(kph[1], kph[2]));
     double kmax = fmax(kph[0], fmax(kph[1], kph[2]));
-    double k0 = sqrt(kmin * kmax);
+    double k0 = scheme == 1 ? 0.5 * (kmin + kmax) : sqrt(kmin * kmax);
 
     double *kvox = malloc(sizeof(double) * M);
     double *e = malloc(sizeof(double) * 3 * M);
@@ -382,12 +387,16 @@ int orc_homogenize(int n, const uint8_t *phase, const double kph[3], double tol,
                     r2 += d * d;
                 }
             r = sqrt(r2 / (double)M);
-            /* step 7: e+ = e + 2 k0 / (k + k0) (c - e) */
+            /* step 7: e+ = e + 2 k0 / (k + k0) (c - e); basic scheme: e+ = c */
             for (int i = 0; i < 3; ++i)
                 for (size_t v = 0; v < M; ++v) {
                     double c = creal(t[i * M + v]) / (double)M;
-                    double wgt = 2.0 * k0 / (kvox[v] + k0);
-                    e[i * M + v] += wgt * (c - e[i * M + v]);
+                    if (scheme == 1) {
+                        e[i * M + v] = c;
+                    } else {
+                        double wgt = 2.0 * k0 / (kvox[v] + k0);
+                        e[i * M + v] += wgt * (c - e[i * M + v]);
+                    }
                 }
             /* <phi> of the updated field (R5): F_i = <k e_i> */
             for (int i = 0; i < 3; ++i) {

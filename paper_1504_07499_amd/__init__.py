@@ -49,7 +49,7 @@ class _Opts(ctypes.Structure):
                 ("lc_mask", ctypes.c_int), ("timing", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("init_field", ctypes.POINTER(ctypes.c_double)),
                 ("out_field", ctypes.POINTER(ctypes.c_double)), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("scheme", ctypes.c_int)]
 
 
 class _Result(ctypes.Structure):
@@ -253,9 +253,14 @@ def _to_result(rc: int, r: _Result, hist=None, hist_cap=0, fld=None) -> HomResul
                      history, fld)
 
 
+SCHEMES = {"accelerated": 0, "basic": 1}
+
+
 def _opts(max_iter=0, precision=0, equilibrium_check=False, stall_window=-1, lc_mask=7,
-          timing=False, stream=None, init_field=None, out_field=None, workspace=None):
+          timing=False, stream=None, init_field=None, out_field=None, workspace=None,
+          scheme="accelerated"):
     o = _Opts()
+    o.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
     o.max_iter = int(max_iter)
     o.precision = int(precision)
     o.equilibrium_check = int(bool(equilibrium_check))
@@ -274,8 +279,13 @@ def _opts(max_iter=0, precision=0, equilibrium_check=False, stall_window=-1, lc_
 def homogenize(rve: RVE, k_phases, tol: float = 1e-6, *, max_iter: int = 0, precision: int = 0,
                equilibrium_check: bool = False, stall_window: int = -1, lc_mask: int = 7,
                timing: bool = False, stream=None, init_field: np.ndarray | None = None,
-               want_field: bool = False, workspace=None, hist_cap: int = 0) -> HomResult:
-    """The Algorithm of Sec. 3 for E = e_1, e_2, e_3 on the device."""
+               want_field: bool = False, workspace=None, hist_cap: int = 0,
+               scheme="accelerated") -> HomResult:
+    """The Algorithm of Sec. 3 for E = e_1, e_2, e_3 on the device.
+
+    scheme: "accelerated" (Eyre-Milton, the paper's choice) or "basic" (the
+    basic scheme the paper names as an alternative: e+ = c, k0 = mean of the
+    extreme conductivities)."""
     k = np.ascontiguousarray(k_phases, dtype=np.float64)
     if k.shape != (3,):
         raise RveError(RVE_ERR_ARG, "k_phases must hold 3 conductivities")
@@ -287,7 +297,7 @@ def homogenize(rve: RVE, k_phases, tol: float = 1e-6, *, max_iter: int = 0, prec
             raise RveError(RVE_ERR_ARG, "init_field must hold 9 n^3 values")
     fld = np.zeros((3, 3, n, n, n)) if want_field else None
     o = _opts(max_iter, precision, equilibrium_check, stall_window, lc_mask, timing, stream, init,
-              fld, workspace)
+              fld, workspace, scheme)
     res = _Result()
     hist = np.zeros(3 * hist_cap) if hist_cap > 0 else None
     rc = _check(_lib.homogenize(rve.handle, _dptr(k), float(tol), ctypes.byref(o), ctypes.byref(res),
@@ -296,13 +306,14 @@ def homogenize(rve: RVE, k_phases, tol: float = 1e-6, *, max_iter: int = 0, prec
 
 
 def homogenize_batch(rves, k_phases, tol, *, max_iter: int = 0, precision: int = 0,
-                     stall_window: int = -1, equilibrium_check: bool = False) -> list:
+                     stall_window: int = -1, equilibrium_check: bool = False,
+                     scheme="accelerated") -> list:
     """Several RVEs (mixed N) solved concurrently; returns one HomResult each."""
     count = len(rves)
     k = np.ascontiguousarray(np.broadcast_to(np.asarray(k_phases, dtype=np.float64), (count, 3)))
     t = np.ascontiguousarray(np.broadcast_to(np.asarray(tol, dtype=np.float64), (count,)))
     hs = (ctypes.c_void_p * max(count, 1))(*[r.handle.value for r in rves])
-    o = _opts(max_iter, precision, equilibrium_check, stall_window)
+    o = _opts(max_iter, precision, equilibrium_check, stall_window, scheme=scheme)
     out = (_Result * max(count, 1))()
     rc = _check(_lib.homogenize_batch(count, hs, _dptr(k), _dptr(t), ctypes.byref(o), out))
     res = []

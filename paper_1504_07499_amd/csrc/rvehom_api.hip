@@ -370,15 +370,17 @@ int validate_k(const double k[3], double tol) {
 
 void fill_params(DevParams &p, const double k[3], double tol, int n, const SolverOpts &o) {
     std::memset(&p, 0, sizeof(p));
-    // Sec. 5: L0 = -sqrt(min k * max k) I over the three given conductivities.
     const double kmin = std::min(k[0], std::min(k[1], k[2]));
     const double kmax = std::max(k[0], std::max(k[1], k[2]));
-    const double k0 = std::sqrt(kmin * kmax);
+    // Sec. 5: L0 = -sqrt(min k * max k) I over the three given conductivities
+    // (accelerated scheme); the basic scheme uses the arithmetic mean.
+    const double k0 = o.scheme == 1 ? 0.5 * (kmin + kmax) : std::sqrt(kmin * kmax);
     const double M = (double)n * n * n;
     for (int i = 0; i < 3; ++i) {
         p.k[i] = k[i];
         p.dk[i] = k[i] - k0;
-        p.w[i] = 2.0 * k0 / (k[i] + k0);
+        // step 7: e+ = e + 2 k0 / (k + k0) (c - e); basic scheme: e+ = c
+        p.w[i] = o.scheme == 1 ? 1.0 : 2.0 * k0 / (k[i] + k0);
     }
     p.k0 = k0;
     p.inv_k0M = 1.0 / (k0 * M);
@@ -405,6 +407,7 @@ SolverOpts resolve_opts(const rve_opts *opts) {
     o.out_field = opts ? opts->out_field : nullptr;
     o.workspace = opts ? opts->workspace : nullptr;
     o.workspace_bytes = opts ? opts->workspace_bytes : 0;
+    o.scheme = opts ? opts->scheme : 0;
     return o;
 }
 
@@ -682,6 +685,10 @@ extern "C" rve_status homogenize(rve_t r, const double k_phases[3], double tol, 
     if (rc != RVE_OK) return (rve_status)rc;
     if (opts && (opts->precision != 0 && opts->precision != 1)) {
         set_error("precision must be 0 (FP32) or 1 (FP64)");
+        return RVE_ERR_ARG;
+    }
+    if (opts && (opts->scheme != 0 && opts->scheme != 1)) {
+        set_error("scheme must be 0 (accelerated) or 1 (basic)");
         return RVE_ERR_ARG;
     }
     if (hist_cap < 0 || (hist_cap > 0 && !residual_history)) {

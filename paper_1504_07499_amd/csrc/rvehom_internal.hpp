@@ -29,6 +29,7 @@ struct SolverOpts {
     int eq_check = 0;
     int stall_window = 0;
     int lc_mask = 7;
+    int scheme = 0;
     bool timing = false;
     hipStream_t stream = nullptr;
     const double *init_field = nullptr;

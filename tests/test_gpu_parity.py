@@ -214,3 +214,14 @@ def test_graph_replays_match_eager_launches():
             assert np.array_equal(g.K, eager.K), rep
             assert np.array_equal(g.iters, eager.iters), rep
             _ = rh.rve_get_phases(r)
+
+
+def test_basic_scheme_fp64_vs_oracle():
+    """The basic scheme option: field after 5 iterations equals the oracle's."""
+    print("\n[case] basic scheme", flush=True)
+    ph = geom.random_phases(24, 77)
+    ref = oracle.homogenize(ph, K_PAPER_CFG, tol=0.0, max_iter=5, want_field=True, scheme=1)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize(r, K_PAPER_CFG, 0.0, max_iter=5, precision=1, want_field=True,
+                          scheme="basic")
+    assert field_err(g.field, ref.field) <= 1e-11

@@ -341,3 +341,22 @@ def test_rejects_bad_arguments():
     bad[0, 0, 0] = 3
     with pytest.raises(ValueError):
         oracle.homogenize(bad, K_CFG)
+
+
+def test_basic_scheme_same_fixed_point_odd_grid():
+    """The basic scheme named in Sec. 3 (e+ = compatible field, k0 the mean of
+    the extreme conductivities) reaches the same discrete solution on an odd
+    grid (the dense spectral solve), at the slower rate (c - 1) / (c + 1)."""
+    n = 5
+    ph = geom.random_phases(n, 1)
+    k = np.array([1.0, 0.2, 4.0])
+    ref = _spectral_direct_solve(ph, k)
+    r = oracle.homogenize(ph, k, tol=1e-13, max_iter=50000, scheme=1)
+    assert np.all(r.status == 0)
+    np.testing.assert_allclose(r.K, ref, atol=1e-10 * np.abs(ref).max())
+    c = k.max() / k.min()
+    h = r.history[0]
+    rate = (h[-1] / h[-21]) ** (1.0 / 20)
+    assert rate <= (c - 1) / (c + 1) * 1.02
+    acc = oracle.homogenize(ph, k, tol=1e-13, max_iter=50000)
+    assert acc.iters[0] < r.iters[0]
