@@ -74,6 +74,27 @@ def cpu_baseline(phases, k, sample_iters: int):
                       f"(FP64, own FFT, OpenMP), {dt:.1f} s"}
 
 
+def calibrate_copy(mib: int = 512, reps: int = 4) -> None:
+    """Device-to-device copies of a known size (the runtime's blit kernel),
+    run under rocprofv3 --pmc to scale FETCH_SIZE / WRITE_SIZE readings."""
+    import ctypes
+
+    import paper_1504_07499_amd as rh
+
+    rh.rve_supported_n(0)  # loads librvehom.so and with it the HIP runtime
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    n = mib << 20
+    a, b = ctypes.c_void_p(), ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(a), ctypes.c_size_t(n)) == 0
+    assert hip.hipMalloc(ctypes.byref(b), ctypes.c_size_t(n)) == 0
+    for _ in range(reps):
+        assert hip.hipMemcpy(b, a, ctypes.c_size_t(n), 3) == 0  # device to device
+    assert hip.hipDeviceSynchronize() == 0
+    hip.hipFree(a)
+    hip.hipFree(b)
+    print(json.dumps({"copy_bytes": n, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,7 +104,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="skip the per-launch HIP events (no roofline)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run device-to-device copies of known size (counter scaling)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the solve of one RVE runs on one device and "

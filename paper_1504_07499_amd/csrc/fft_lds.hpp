@@ -184,11 +184,14 @@ __device__ __forceinline__ void fft_stage(Cx<T> *buf, const Cx<T> *__restrict__ 
     constexpr int PER = (TOT + NT - 1) / NT;
     constexpr int TWS = TW / (NS * R);  // table stride of one twiddle step
     Cx<T> v[PER][R];
+    // Butterfly b = j * NSEQ + q: neighbouring threads take the same butterfly
+    // of neighbouring sequences, so they share one twiddle (a broadcast load)
+    // and, for sequences side by side in LDS, touch consecutive addresses.
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int b = tid + i * NT;
         if (TOT % NT == 0 || b < TOT) {
-            const int q = b / NB, j = b - q * NB;
+            const int j = b / NSEQ, q = b - j * NSEQ;
             const int off = Seq::base(q);
 #pragma unroll
             for (int r = 0; r < R; ++r) v[i][r] = buf[off + (j + r * NB) * ES];
@@ -199,7 +202,7 @@ __device__ __forceinline__ void fft_stage(Cx<T> *buf, const Cx<T> *__restrict__ 
     for (int i = 0; i < PER; ++i) {
         const int b = tid + i * NT;
         if (TOT % NT == 0 || b < TOT) {
-            const int q = b / NB, j = b - q * NB;
+            const int j = b / NSEQ, q = b - j * NSEQ;
             const int k = j % NS;
             if (NS > 1) {
 #pragma unroll
