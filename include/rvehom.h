@@ -67,7 +67,9 @@ typedef struct {
     int equilibrium_check;  /* 1 = two-stage stop of step 1 (eps_comp then eps_eq) */
     int stall_window;       /* -1 = default (50 in FP32, off in FP64), 0 = off */
     int lc_mask;            /* load cases to solve, bit j = e_(j+1); 0 = all three */
-    int timing;             /* 1 = time every kernel launch with HIP events */
+    int timing;             /* bitmask of kernels to time with HIP events: 1 fwd_plane,
+                               2 zgreen, 4 inv_plane, 8 reduce (15 = all); the events are
+                               recorded inside the replayed iteration graphs */
     void *stream;           /* hipStream_t for all work, NULL = the handle's own */
     const double *init_field; /* host, 9 N^3 FP64 start field, NULL = E */
     double *out_field;      /* host, 9 N^3 FP64 final field, NULL = not returned */
@@ -88,7 +90,7 @@ typedef struct {
     double solve_ms;           /* device time of the iteration phase (HIP events) */
 } rve_result;
 
-/* Per-kernel device time of the last homogenize call with opts.timing = 1,
+/* Per-kernel device time of the last homogenize call with opts.timing != 0,
  * over the launches that did work (those of iterations before the last load
  * case finished).  names: "fwd_plane", "zgreen", "inv_plane", "reduce".
  * total_bytes: algorithmic HBM bytes of those launches (each pass reads and

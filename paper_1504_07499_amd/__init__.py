@@ -266,7 +266,9 @@ def _opts(max_iter=0, precision=0, equilibrium_check=False, stall_window=-1, lc_
     o.equilibrium_check = int(bool(equilibrium_check))
     o.stall_window = int(stall_window)
     o.lc_mask = int(lc_mask)
-    o.timing = int(bool(timing))
+    # timing: True = all four kernels, or a bitmask (1 fwd_plane, 2 zgreen,
+    # 4 inv_plane, 8 reduce)
+    o.timing = 15 if timing is True else int(timing)
     o.stream = _stream_handle(stream)
     o.init_field = _dptr(init_field) if init_field is not None else None
     o.out_field = _dptr(out_field) if out_field is not None else None
@@ -278,7 +280,7 @@ def _opts(max_iter=0, precision=0, equilibrium_check=False, stall_window=-1, lc_
 
 def homogenize(rve: RVE, k_phases, tol: float = 1e-6, *, max_iter: int = 0, precision: int = 0,
                equilibrium_check: bool = False, stall_window: int = -1, lc_mask: int = 7,
-               timing: bool = False, stream=None, init_field: np.ndarray | None = None,
+               timing=False, stream=None, init_field: np.ndarray | None = None,
                want_field: bool = False, workspace=None, hist_cap: int = 0,
                scheme="accelerated") -> HomResult:
     """The Algorithm of Sec. 3 for E = e_1, e_2, e_3 on the device.

@@ -61,7 +61,7 @@ WsLayout ws_layout(const SolverOps *o) {
     L.spec = take(o->spec_elems * 2 * rb);
     L.nyq = take(o->nyq_elems * 2 * rb);
     L.tw = take(n * 2 * rb);
-    L.part = take((size_t)9 * o->nper * 2 * sizeof(double));
+    L.part = take((size_t)9 * o->nper * 3 * sizeof(double));
     L.prm = take(sizeof(DevParams));
     L.st = take(sizeof(DevState));
     L.hist = take((size_t)3 * kHistCap * sizeof(double));
@@ -91,16 +91,27 @@ void Solver::release() {
     own_stream = nullptr;
     for (auto ev : poll_ev) (void)hipEventDestroy(ev);
     poll_ev.clear();
-    for (auto ev : time_ev) (void)hipEventDestroy(ev);
-    time_ev.clear();
+    for (auto &si : slots) {
+        for (auto ev : si.ev) (void)hipEventDestroy(ev);
+        si.ev.clear();
+    }
     if (run_ev[0]) (void)hipEventDestroy(run_ev[0]);
     if (run_ev[1]) (void)hipEventDestroy(run_ev[1]);
     run_ev[0] = run_ev[1] = nullptr;
     if (h_pinned) (void)hipHostFree(h_pinned);
     h_pinned = nullptr;
+    drop_graphs();
+}
+
+void Solver::drop_graphs() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     gexec = nullptr;
     g_ws = nullptr;
+    for (auto &g : tgexec) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+    tg_mask = 0;
 }
 
 // Allocate (or adopt) the workspace and the per-solver HIP objects.
@@ -145,6 +156,10 @@ int Solver::prepare(const SolverOps *o, void *user_ws, size_t user_bytes) {
     if (poll_ev.empty()) {
         poll_ev.resize(kPollSlots);
         for (auto &ev : poll_ev) HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        for (auto &si : slots) {
+            si.ev.resize(2 * kChunk * 4);
+            for (auto &ev : si.ev) HIP_CHECK(hipEventCreate(&ev));
+        }
     }
     if (!run_ev[0]) {
         HIP_CHECK(hipEventCreate(&run_ev[0]));
@@ -401,7 +416,7 @@ SolverOpts resolve_opts(const rve_opts *opts) {
     int sw = opts ? opts->stall_window : -1;
     o.stall_window = sw < 0 ? (o.precision == 0 ? 50 : 0) : sw;
     o.lc_mask = (opts && (opts->lc_mask & 7)) ? (opts->lc_mask & 7) : 7;
-    o.timing = opts ? opts->timing != 0 : false;
+    o.timing = opts ? (opts->timing & 15) : 0;
     o.stream = opts ? (hipStream_t)opts->stream : nullptr;
     o.init_field = opts ? opts->init_field : nullptr;
     o.out_field = opts ? opts->out_field : nullptr;
@@ -445,23 +460,39 @@ int Solver::begin(const uint8_t *d_phase, const double k[3], double tol, const S
 
 // One iteration: the three passes, the reduction and (two-stage stop only)
 // the equilibrium check.  Every kernel exits at once for frozen load cases.
-void Solver::launch_iteration(const LaunchArgs &a, hipStream_t s) {
-    ops->fwd(a, s);
-    ops->zgreen(a, s);
-    ops->inv(a, s);
-    launch_reduce(a, ops->nper, s);
+// Kernels whose bit is set in mask are bracketed by the next two events of ev.
+int Solver::launch_iteration(const LaunchArgs &a, hipStream_t s, int mask, hipEvent_t *ev) {
+    int used = 0;
+    // "external" records become event-record nodes when captured into a graph
+    // (a plain record under capture is only an ordering marker, with no time)
+    for (int kk = 0; kk < 4; ++kk) {
+        const bool timed = (mask >> kk) & 1;
+        if (timed) HIP_CHECK(hipEventRecordWithFlags(ev[used], s, hipEventRecordExternal));
+        switch (kk) {
+        case 0: ops->fwd(a, s); break;
+        case 1: ops->zgreen(a, s); break;
+        case 2: ops->inv(a, s); break;
+        default: launch_reduce(a, ops->nper, s); break;
+        }
+        if (timed) {
+            HIP_CHECK(hipEventRecordWithFlags(ev[used + 1], s, hipEventRecordExternal));
+            used += 2;
+        }
+    }
     if (eq_check) {
         ops->fwd_phi(a, s);
         ops->zeq(a, s);
         launch_eq_reduce(a, ops->eq_tiles, 0, s);
     }
+    return RVE_OK;
 }
+
+static int popcount4(int m) { return (m & 1) + ((m >> 1) & 1) + ((m >> 2) & 1) + ((m >> 3) & 1); }
 
 // Capture kChunk iterations into a graph on the solver's own stream.
 int Solver::ensure_graph(const uint8_t *d_phase) {
     if (gexec && g_ws == ws && g_ph == d_phase && g_eq == eq_check) return RVE_OK;
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    gexec = nullptr;
+    drop_graphs();
     LaunchArgs a = args(d_phase);
     hipGraph_t g = nullptr;
     HIP_CHECK(hipStreamBeginCapture(own_stream, hipStreamCaptureModeThreadLocal));
@@ -484,46 +515,58 @@ int Solver::ensure_graph(const uint8_t *d_phase) {
     return RVE_OK;
 }
 
-// Enqueue up to `count` iterations (never beyond max_iter) and a poll point.
-// Full chunks replay the captured graph; timed runs and partial chunks launch
-// kernel by kernel (timed runs bracket every launch with events).
-int Solver::enqueue(const uint8_t *d_phase, int count, int max_iter, bool timing, hipStream_t s) {
+// Timed graphs: one per poll slot, with that slot's events recorded around
+// the masked kernels of every iteration (event records are graph nodes).
+int Solver::ensure_timed_graphs(const uint8_t *d_phase, int mask) {
+    int rc = ensure_graph(d_phase);
+    if (rc != RVE_OK) return rc;
+    if (tgexec[0] && tg_mask == mask) return RVE_OK;
+    for (auto &g : tgexec) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
     LaunchArgs a = args(d_phase);
-    if (!timing && use_graphs && count == kChunk && issued + kChunk <= max_iter) {
-        int rc = ensure_graph(d_phase);
-        if (rc != RVE_OK) return rc;
-        HIP_CHECK(hipGraphLaunch(gexec, s));
-        issued += kChunk;
-    } else {
-        for (int i = 0; i < count && issued < max_iter; ++i, ++issued) {
-            if (!timing) {
-                launch_iteration(a, s);
-                continue;
-            }
-            for (int kk = 0; kk < 4; ++kk) {
-                size_t need = 2 * (launches.size() + 1);
-                while (time_ev.size() < need) {
-                    hipEvent_t ev;
-                    HIP_CHECK(hipEventCreate(&ev));
-                    time_ev.push_back(ev);
-                }
-                hipEvent_t e0 = time_ev[need - 2], e1 = time_ev[need - 1];
-                HIP_CHECK(hipEventRecord(e0, s));
-                switch (kk) {
-                case 0: ops->fwd(a, s); break;
-                case 1: ops->zgreen(a, s); break;
-                case 2: ops->inv(a, s); break;
-                default: launch_reduce(a, ops->nper, s); break;
-                }
-                HIP_CHECK(hipEventRecord(e1, s));
-                launches.push_back({kk, issued});
-            }
-            if (eq_check) {
-                ops->fwd_phi(a, s);
-                ops->zeq(a, s);
-                launch_eq_reduce(a, ops->eq_tiles, 0, s);
-            }
+    const int per = 2 * popcount4(mask);
+    for (int sl = 0; sl < kPollSlots; ++sl) {
+        hipGraph_t g = nullptr;
+        HIP_CHECK(hipStreamBeginCapture(own_stream, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < kChunk; ++i) launch_iteration(a, own_stream, mask, slots[sl].ev.data() + i * per);
+        hipError_t cap = hipStreamEndCapture(own_stream, &g);
+        if (cap != hipSuccess) {
+            set_error("graph capture failed: %s", hipGetErrorString(cap));
+            return RVE_ERR_DEVICE;
         }
+        hipError_t inst = hipGraphInstantiate(&tgexec[sl], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (inst != hipSuccess) {
+            tgexec[sl] = nullptr;
+            set_error("graph instantiation failed: %s", hipGetErrorString(inst));
+            return RVE_ERR_DEVICE;
+        }
+    }
+    tg_mask = mask;
+    return RVE_OK;
+}
+
+// Enqueue up to `count` iterations (never beyond max_iter) and a poll point.
+// Full chunks replay a captured graph (the timed variant of the poll slot when
+// timing); partial chunks launch kernel by kernel.
+int Solver::enqueue(const uint8_t *d_phase, int count, int max_iter, int timing, hipStream_t s) {
+    LaunchArgs a = args(d_phase);
+    SlotInfo &si = slots[slot];
+    si.first_iter = issued;
+    si.mask = timing & 15;
+    const int per = 2 * popcount4(si.mask);
+    if (use_graphs && count == kChunk && issued + kChunk <= max_iter) {
+        int rc = si.mask ? ensure_timed_graphs(d_phase, si.mask) : ensure_graph(d_phase);
+        if (rc != RVE_OK) return rc;
+        HIP_CHECK(hipGraphLaunch(si.mask ? tgexec[slot] : gexec, s));
+        issued += kChunk;
+        si.count = kChunk;
+    } else {
+        si.count = 0;
+        for (int i = 0; i < count && issued < max_iter; ++i, ++issued, ++si.count)
+            launch_iteration(a, s, si.mask, si.ev.data() + i * per);
     }
     HIP_CHECK(hipGetLastError());
     int *flags = (int *)((char *)h_pinned + kFlagsOffset);
@@ -531,6 +574,25 @@ int Solver::enqueue(const uint8_t *d_phase, int count, int max_iter, bool timing
     HIP_CHECK(hipEventRecord(poll_ev[slot], s));
     inflight.push_back(slot);
     slot = (slot + 1) % kPollSlots;
+    return RVE_OK;
+}
+
+// After the poll point of slot sl has completed: keep its kernel times.
+int Solver::read_slot_times(int sl) {
+    SlotInfo &si = slots[sl];
+    if (!si.mask) return RVE_OK;
+    const int per = 2 * popcount4(si.mask);
+    for (int i = 0; i < si.count; ++i) {
+        int used = 0;
+        for (int kk = 0; kk < 4; ++kk) {
+            if (!((si.mask >> kk) & 1)) continue;
+            float ms = 0.f;
+            HIP_CHECK(hipEventElapsedTime(&ms, si.ev[i * per + used], si.ev[i * per + used + 1]));
+            launches.push_back({kk, si.first_iter + i, ms});
+            used += 2;
+        }
+    }
+    si.mask = 0;
     return RVE_OK;
 }
 
@@ -551,6 +613,7 @@ int Solver::poll(bool wait, int max_iter) {
         }
     }
     inflight.pop_front();
+    if (int rc = read_slot_times(sl); rc != RVE_OK) return rc;
     const int *flags = (const int *)((const char *)h_pinned + kFlagsOffset);
     if (flags[sl]) finished = true;
     if (issued >= max_iter && inflight.empty()) finished = true;
@@ -603,11 +666,14 @@ int Solver::collect(const SolverOpts &o, hipStream_t s, rve_result *out, double 
         for (int q = 0; q < 4; ++q) kt->name[q] = names[q];
         int maxit = 0;
         for (int j = 0; j < 3; ++j) maxit = std::max(maxit, hs->iters[j]);
+        while (!inflight.empty()) {  // stream drained: remaining slots are complete
+            if (int rc = read_slot_times(inflight.front()); rc != RVE_OK) return rc;
+            inflight.pop_front();
+        }
         for (size_t i = 0; i < launches.size(); ++i) {
             const int kk = launches[i].kernel, it = launches[i].iter;
             if (it >= maxit) continue;  // launches after convergence exit at once
-            float ms = 0.f;
-            HIP_CHECK(hipEventElapsedTime(&ms, time_ev[2 * i], time_ev[2 * i + 1]));
+            const float ms = launches[i].ms;
             int active = 0;
             for (int j = 0; j < 3; ++j) active += (hs->iters[j] > it) ? 1 : 0;
             kt->total_ms[kk] += ms;
@@ -724,7 +790,7 @@ extern "C" rve_status homogenize_batch(int count, const rve_t *rves, const doubl
         return RVE_ERR_ARG;
     }
     SolverOpts o = resolve_opts(opts);
-    o.timing = false;
+    o.timing = 0;
     for (int i = 0; i < count; ++i) {
         if (!rves[i]) {
             set_error("homogenize_batch: rve %d is NULL", i);

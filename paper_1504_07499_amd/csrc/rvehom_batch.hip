@@ -34,7 +34,7 @@ static int drive(std::vector<Active> &act, Finish finish) {
         for (auto &a : act) {
             Solver &sv = *a.sv;
             if ((int)sv.inflight.size() < kLookahead && sv.issued < a.max_iter) {
-                int rc = sv.enqueue(a.d_phase, kChunk, a.max_iter, false, a.stream);
+                int rc = sv.enqueue(a.d_phase, kChunk, a.max_iter, 0, a.stream);
                 if (rc != RVE_OK) return rc;
             }
         }
@@ -271,7 +271,7 @@ static void scheduler(rve_server_s *s) {
         // one scheduling round: top up every active request, retire finished ones
         for (auto &a : act)
             if ((int)a.sv->inflight.size() < kLookahead && a.sv->issued < a.max_iter)
-                if (a.sv->enqueue(a.d_phase, kChunk, a.max_iter, false, a.stream) != RVE_OK) {
+                if (a.sv->enqueue(a.d_phase, kChunk, a.max_iter, 0, a.stream) != RVE_OK) {
                     std::lock_guard<std::mutex> lk(s->mu);
                     s->fatal = RVE_ERR_DEVICE;
                 }

@@ -30,7 +30,7 @@ struct SolverOpts {
     int stall_window = 0;
     int lc_mask = 7;
     int scheme = 0;
-    bool timing = false;
+    int timing = 0;  // bitmask of timed kernels: 1 fwd, 2 zgreen, 4 inv, 8 reduce
     hipStream_t stream = nullptr;
     const double *init_field = nullptr;
     double *out_field = nullptr;
@@ -41,6 +41,16 @@ struct SolverOpts {
 struct LaunchRec {
     int kernel;
     int iter;
+    float ms;
+};
+
+// Iterations enqueued behind one poll point, and the timing events (one
+// pair per timed kernel launch) that belong to that poll slot.
+struct SlotInfo {
+    int first_iter = 0;
+    int count = 0;
+    int mask = 0;
+    std::vector<hipEvent_t> ev;  // 2 * kChunk * 4
 };
 
 // Device workspace + HIP objects of one (RVE, precision).
@@ -53,7 +63,7 @@ struct Solver {
     WsLayout layout{};
     hipStream_t own_stream = nullptr;
     std::vector<hipEvent_t> poll_ev;
-    std::vector<hipEvent_t> time_ev;
+    SlotInfo slots[kPollSlots];
     hipEvent_t run_ev[2] = {nullptr, nullptr};
     void *h_pinned = nullptr;  // [DevParams | DevState | ... | flags @ kFlagsOffset]
     // per-solve driver state
@@ -71,6 +81,9 @@ struct Solver {
     const uint8_t *g_ph = nullptr;
     bool g_eq = false;
     bool use_graphs = true;
+    // timed variants: one graph per poll slot (its own events), per mask
+    hipGraphExec_t tgexec[kPollSlots] = {};
+    int tg_mask = 0;
 
     ~Solver();
     void release();
@@ -78,9 +91,12 @@ struct Solver {
     LaunchArgs args(const uint8_t *d_phase) const;
     int ensure_twiddles(hipStream_t s);
     int begin(const uint8_t *d_phase, const double k[3], double tol, const SolverOpts &o, hipStream_t s);
-    int enqueue(const uint8_t *d_phase, int count, int max_iter, bool timing, hipStream_t s);
-    void launch_iteration(const LaunchArgs &a, hipStream_t s);
+    int enqueue(const uint8_t *d_phase, int count, int max_iter, int timing, hipStream_t s);
+    int launch_iteration(const LaunchArgs &a, hipStream_t s, int mask = 0, hipEvent_t *ev = nullptr);
     int ensure_graph(const uint8_t *d_phase);
+    int ensure_timed_graphs(const uint8_t *d_phase, int mask);
+    int read_slot_times(int sl);
+    void drop_graphs();
     int poll(bool wait, int max_iter);
     int collect(const SolverOpts &o, hipStream_t s, rve_result *out, double *hist, int hist_cap,
                 rve_kernel_times *kt);

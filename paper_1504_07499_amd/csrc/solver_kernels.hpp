@@ -7,7 +7,7 @@
 //   ph    [z][y][x]                uint8 phase id (0 matrix, 1 inclusion, 2 coating)
 //   spec  [ch][z][ky][kx], kx<N/2  half spectrum without the kx = N/2 column
 //   nyq   [ch][z][ky]              the kx = N/2 column
-//   part  [ch][block][2]           FP64 partials {sum |e - c|^2, sum k e+}
+//   part  [ch][block][3]           FP64 partials {sum |e - c|^2, sum k e+, sum e+}
 //
 // One iteration = three passes over HBM plus a tiny reduction:
 //   P1 (k_fwd_plane):   tau = (k - k0) e (step 2) fused into the load, then the
@@ -83,6 +83,27 @@ template <> __device__ __forceinline__ void pload<2>(const uint8_t *p, int *o) {
     o[0] = v.x; o[1] = v.y;
 }
 
+// Two consecutive complex values as one 16-byte global access (FP32) or two
+// (FP64); dst/src must be aligned to 2 complex values.
+template <typename T> __device__ __forceinline__ void gload2(const Cx<T> *src, Cx<T> &a, Cx<T> &b);
+template <> __device__ __forceinline__ void gload2<float>(const Cx<float> *src, Cx<float> &a, Cx<float> &b) {
+    const float4 v = *reinterpret_cast<const float4 *>(src);
+    a = Cx<float>{v.x, v.y};
+    b = Cx<float>{v.z, v.w};
+}
+template <> __device__ __forceinline__ void gload2<double>(const Cx<double> *src, Cx<double> &a, Cx<double> &b) {
+    a = src[0];
+    b = src[1];
+}
+template <typename T> __device__ __forceinline__ void gstore2(Cx<T> *dst, Cx<T> a, Cx<T> b);
+template <> __device__ __forceinline__ void gstore2<float>(Cx<float> *dst, Cx<float> a, Cx<float> b) {
+    *reinterpret_cast<float4 *>(dst) = make_float4(a.x, a.y, b.x, b.y);
+}
+template <> __device__ __forceinline__ void gstore2<double>(Cx<double> *dst, Cx<double> a, Cx<double> b) {
+    dst[0] = a;
+    dst[1] = b;
+}
+
 // phase-indexed lookup without a memory table: p in {0,1,2}
 template <typename T> __device__ __forceinline__ T pick(int p, T a0, T a1, T a2) {
     return p == 0 ? a0 : (p == 1 ? a1 : a2);
@@ -138,16 +159,21 @@ __device__ __forceinline__ void c2r_pack(Cx<T> *row, int k, const Cx<T> *__restr
 
 // Steps 6-7 and the flux on V voxels of one row: e+ = e + w (c - e),
 // r2 += |e - c|^2, fl += k e+ (FP64 accumulation).
+// c arrives without its mean E (added here).  Also sums e+ (its mean gives
+// the mean of tau for the next forward pass).
 template <typename T, int V>
 __device__ __forceinline__ void em_update(T *a, const T *c, const int *p, T w0, T w1, T w2, double k0d,
-                                          double k1d, double k2d, double &r2, double &fl) {
+                                          double k1d, double k2d, T ec, double &r2, double &fl,
+                                          double &se) {
 #pragma unroll
     for (int i = 0; i < V; ++i) {
-        const T d = a[i] - c[i];
+        const T ci = c[i] + ec;
+        const T d = a[i] - ci;
         r2 += (double)d * (double)d;
         const T wi = pick<T>(p[i], w0, w1, w2);
-        a[i] = a[i] + wi * (c[i] - a[i]);
+        a[i] = a[i] + wi * (ci - a[i]);
         fl += pick<double>(p[i], k0d, k1d, k2d) * (double)a[i];
+        se += (double)a[i];
     }
 }
 
@@ -189,31 +215,49 @@ __global__ __launch_bounds__(NT) void k_fwd_plane(const T *__restrict__ e, const
     if (PHI ? !st->eq_pending[lc] : st->done[lc]) return;
     const double *lut = PHI ? prm->k : prm->dk;
     const T d0 = (T)lut[0], d1 = (T)lut[1], d2 = (T)lut[2];
+    const T tm = PHI ? (T)0 : (T)st->tau_mean[ch];  // only the discarded mean mode changes
     const T *eb = e + (size_t)ch * N * NN + (size_t)z * NN;
     const uint8_t *pb = ph + (size_t)z * NN;
 
-    // load rows (S = 2: combine rows y and y + N/2 with sign (-1)^h)
-    for (int idx = tid; idx < ROWS * N / V; idx += NT) {
-        const int y = idx / (N / V), x = (idx - y * (N / V)) * V;
-        T a[V], u[V];
-        int p[V];
-        vload<T>(eb + y * N + x, a);
-        pload<V>(pb + y * N + x, p);
+    // load rows (S = 2: combine rows y and y + N/2 with sign (-1)^h); each
+    // batch issues all of its global loads before the first use
+    constexpr int TOTL = ROWS * N / V, PERL = (TOTL + NT - 1) / NT;
+    constexpr int BL = S == 2 ? 4 : 8;
 #pragma unroll
-        for (int i = 0; i < V; ++i) u[i] = pick<T>(p[i], d0, d1, d2) * a[i];
-        if constexpr (S == 2) {
-            T b[V];
-            int q[V];
-            vload<T>(eb + (y + ROWS) * N + x, b);
-            pload<V>(pb + (y + ROWS) * N + x, q);
+    for (int i0 = 0; i0 < PERL; i0 += BL) {
+        T a[BL][V], b[BL][V];
+        int p[BL][V], q[BL][V];
 #pragma unroll
-            for (int i = 0; i < V; ++i) {
-                const T t2 = pick<T>(q[i], d0, d1, d2) * b[i];
-                u[i] = h ? u[i] - t2 : u[i] + t2;
+        for (int i = 0; i < BL; ++i) {
+            const int idx = tid + (i0 + i) * NT;
+            if (i0 + i < PERL && (TOTL % NT == 0 || idx < TOTL)) {
+                const int y = idx / (N / V), x = (idx - y * (N / V)) * V;
+                vload<T>(eb + y * N + x, a[i]);
+                pload<V>(pb + y * N + x, p[i]);
+                if constexpr (S == 2) {
+                    vload<T>(eb + (y + ROWS) * N + x, b[i]);
+                    pload<V>(pb + (y + ROWS) * N + x, q[i]);
+                }
             }
         }
 #pragma unroll
-        for (int i = 0; i < V; i += 2) plane[y * RS + (x + i) / 2] = Cx<T>{u[i], u[i + 1]};
+        for (int i = 0; i < BL; ++i) {
+            const int idx = tid + (i0 + i) * NT;
+            if (i0 + i < PERL && (TOTL % NT == 0 || idx < TOTL)) {
+                const int y = idx / (N / V), x = (idx - y * (N / V)) * V;
+                T u[V];
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    u[j] = pick<T>(p[i][j], d0, d1, d2) * a[i][j] - tm;
+                    if constexpr (S == 2) {
+                        const T t2 = pick<T>(q[i][j], d0, d1, d2) * b[i][j] - tm;
+                        u[j] = h ? u[j] - t2 : u[j] + t2;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < V; j += 2) plane[y * RS + (x + j) / 2] = Cx<T>{u[j], u[j + 1]};
+            }
+        }
     }
     __syncthreads();
     // x: complex FFT of length N/2 of the packed even/odd samples
@@ -233,9 +277,9 @@ __global__ __launch_bounds__(NT) void k_fwd_plane(const T *__restrict__ e, const
     // y: complex FFT of length N/S down the N/2 + 1 columns
     fft_lds<T, ROWS, false, RS, RS, NT, N, SeqStride<1>>(plane, tw, tid);
     Cx<T> *sb = spec + ((size_t)ch * N + z) * N * H;
-    for (int idx = tid; idx < ROWS * H; idx += NT) {
-        const int m = idx / H, kx = idx - m * H;
-        sb[(size_t)(S * m + h) * H + kx] = plane[m * RS + kx];
+    for (int idx = tid; idx < ROWS * H / 2; idx += NT) {
+        const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
+        gstore2<T>(sb + (size_t)(S * m + h) * H + kx, plane[m * RS + kx], plane[m * RS + kx + 1]);
     }
     Cx<T> *nb = nyq + ((size_t)ch * N + z) * N;
     for (int m = tid; m < ROWS; m += NT) nb[S * m + h] = plane[m * RS + H];
@@ -260,7 +304,7 @@ __global__ __launch_bounds__(NT) void k_zgreen(Cx<T> *__restrict__ spec, Cx<T> *
                                                const DevState *__restrict__ st) {
     using TL = ZTiles<N, W>;
     constexpr int H = N / 2, NW = N * W;
-    static_assert(H % W == 0 && N % W == 0, "tile width must divide N/2");
+    static_assert(H % W == 0 && N % W == 0 && W % 2 == 0, "tile width must be even and divide N/2");
     __shared__ Cx<T> buf[3 * NW];
     const int tid = threadIdx.x;
     const int lc = blockIdx.x / TL::PER_LC, t = blockIdx.x - lc * TL::PER_LC;
@@ -286,9 +330,27 @@ __global__ __launch_bounds__(NT) void k_zgreen(Cx<T> *__restrict__ spec, Cx<T> *
         cstride = (size_t)N * N;
         zstride = N;
     }
-    for (int idx = tid; idx < 3 * NW; idx += NT) {
-        const int c = idx / NW, r = idx - c * NW, zz = r / W, w = r - zz * W;
-        buf[idx] = base[c * cstride + zz * zstride + w];
+    // load the three components' pencils, two complex values per access,
+    // every load of a thread in flight before the first LDS store
+    constexpr int NP = 3 * NW / 2, PERP = (NP + NT - 1) / NT;
+    {
+        Cx<T> va[PERP], vb[PERP];
+#pragma unroll
+        for (int i = 0; i < PERP; ++i) {
+            const int idx = tid + i * NT;
+            if (NP % NT == 0 || idx < NP) {
+                const int e0 = 2 * idx, c = e0 / NW, r = e0 - c * NW, zz = r / W, w = r - zz * W;
+                gload2<T>(base + c * cstride + zz * zstride + w, va[i], vb[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PERP; ++i) {
+            const int idx = tid + i * NT;
+            if (NP % NT == 0 || idx < NP) {
+                buf[2 * idx] = va[i];
+                buf[2 * idx + 1] = vb[i];
+            }
+        }
     }
     __syncthreads();
     fft_lds<T, N, false, 3 * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
@@ -306,8 +368,10 @@ __global__ __launch_bounds__(NT) void k_zgreen(Cx<T> *__restrict__ spec, Cx<T> *
         Cx<T> tv[3] = {buf[idx], buf[NW + idx], buf[2 * NW + idx]};
         Cx<T> out[3];
         if (ki[0] == 0 && ki[1] == 0 && ki[2] == 0) {
+            // step 4 pins the mean to E; E is added after the inverse
+            // transform instead (exact), so the mean mode carries 0 here
 #pragma unroll
-            for (int c = 0; c < 3; ++c) out[c] = Cx<T>{c == lc ? (T)1 : (T)0, (T)0};
+            for (int c = 0; c < 3; ++c) out[c] = Cx<T>{(T)0, (T)0};
         } else {
             Cx<T> sA = {(T)0, (T)0};
 #pragma unroll
@@ -324,34 +388,36 @@ __global__ __launch_bounds__(NT) void k_zgreen(Cx<T> *__restrict__ spec, Cx<T> *
     }
     __syncthreads();
     fft_lds<T, N, true, 3 * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
-    for (int idx = tid; idx < 3 * NW; idx += NT) {
-        const int c = idx / NW, r = idx - c * NW, zz = r / W, w = r - zz * W;
-        base[c * cstride + zz * zstride + w] = buf[idx];
+    for (int idx = tid; idx < NP; idx += NT) {
+        const int e0 = 2 * idx, c = e0 / NW, r = e0 - c * NW, zz = r / W, w = r - zz * W;
+        gstore2<T>(base + c * cstride + zz * zstride + w, buf[e0], buf[e0 + 1]);
     }
 }
 
-// FP64 block sum of two values; result valid in thread 0.
-template <int NT> __device__ __forceinline__ void block_sum2(double &a, double &b, double *red) {
+// FP64 block sums of NV values; results valid in thread 0.  red holds
+// NV * (NT / 64) doubles.
+template <int NT, int NV> __device__ __forceinline__ void block_sum(double *v, double *red) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        a += __shfl_down(a, o, 64);
-        b += __shfl_down(b, o, 64);
-    }
+    for (int q = 0; q < NV; ++q)
+        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_down(v[q], o, 64);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) {
-        red[2 * wv] = a;
-        red[2 * wv + 1] = b;
-    }
+    if (lane == 0)
+        for (int q = 0; q < NV; ++q) red[NV * wv + q] = v[q];
     __syncthreads();
     if (threadIdx.x == 0) {
-        double sa = 0.0, sb = 0.0;
-        for (int i = 0; i < NT / 64; ++i) {
-            sa += red[2 * i];
-            sb += red[2 * i + 1];
+        for (int q = 0; q < NV; ++q) {
+            double t = 0.0;
+            for (int i = 0; i < NT / 64; ++i) t += red[NV * i + q];
+            v[q] = t;
         }
-        a = sa;
-        b = sb;
     }
+}
+
+template <int NT> __device__ __forceinline__ void block_sum2(double &a, double &b, double *red) {
+    double v[2] = {a, b};
+    block_sum<NT, 2>(v, red);
+    a = v[0];
+    b = v[1];
 }
 
 // Equilibrium error of step 1 (option): after P1<PHI> the z-FFT of the flux
@@ -447,23 +513,56 @@ __global__ __launch_bounds__(NT) void k_inv_plane(T *__restrict__ e, const uint8
                                                   double *__restrict__ part) {
     constexpr int H = N / 2, RS = H + 1, ROWS = N / S, V = VecOf<T>::V, NN = N * N;
     __shared__ Cx<T> plane[ROWS * RS];
-    __shared__ double red[2 * (NT / 64)];
+    __shared__ double red[3 * (NT / 64)];
     const int tid = threadIdx.x;
     int ch, z, h;
     plane_of_block<N, S>(blockIdx.x, ch, z, h);
     const int lc = ch / 3;
     if (st->done[lc]) return;
+    const T ec = (ch % 4 == 0) ? (T)1 : (T)0;  // E_comp of this channel (ch = 3 lc + comp)
 
     const Cx<T> *sb = spec + ((size_t)ch * N + z) * N * H;
     const Cx<T> *nb = nyq + ((size_t)ch * N + z) * N;
-    for (int idx = tid; idx < ROWS * RS; idx += NT) {
-        const int m = idx / RS, kx = idx - m * RS;
-        Cx<T> v = (kx < H) ? sb[(size_t)m * H + kx] : nb[m];
-        if constexpr (S == 2) {
-            const Cx<T> u = (kx < H) ? sb[(size_t)(m + ROWS) * H + kx] : nb[m + ROWS];
-            v = h ? (v - u) * conj(tw[m]) : v + u;
+    {
+        // main columns, two complex values per access, all loads of a batch
+        // in flight before the LDS stores (S = 2: rows m and m + N/2 combined)
+        constexpr int NP = ROWS * H / 2, PERP = (NP + NT - 1) / NT, BP = S == 2 ? 4 : 8;
+#pragma unroll
+        for (int i0 = 0; i0 < PERP; i0 += BP) {
+            Cx<T> va[BP], vb[BP], ua[BP], ub[BP];
+#pragma unroll
+            for (int i = 0; i < BP; ++i) {
+                const int idx = tid + (i0 + i) * NT;
+                if (i0 + i < PERP && (NP % NT == 0 || idx < NP)) {
+                    const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
+                    gload2<T>(sb + (size_t)m * H + kx, va[i], vb[i]);
+                    if constexpr (S == 2) gload2<T>(sb + (size_t)(m + ROWS) * H + kx, ua[i], ub[i]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < BP; ++i) {
+                const int idx = tid + (i0 + i) * NT;
+                if (i0 + i < PERP && (NP % NT == 0 || idx < NP)) {
+                    const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
+                    Cx<T> a0 = va[i], a1 = vb[i];
+                    if constexpr (S == 2) {
+                        const Cx<T> r = conj(tw[m]);
+                        a0 = h ? (a0 - ua[i]) * r : a0 + ua[i];
+                        a1 = h ? (a1 - ub[i]) * r : a1 + ub[i];
+                    }
+                    plane[m * RS + kx] = a0;
+                    plane[m * RS + kx + 1] = a1;
+                }
+            }
         }
-        plane[idx] = v;
+        for (int m = tid; m < ROWS; m += NT) {
+            Cx<T> v = nb[m];
+            if constexpr (S == 2) {
+                const Cx<T> u = nb[m + ROWS];
+                v = h ? (v - u) * conj(tw[m]) : v + u;
+            }
+            plane[m * RS + H] = v;
+        }
     }
     __syncthreads();
     fft_lds<T, ROWS, true, RS, RS, NT, N, SeqStride<1>>(plane, tw, tid);
@@ -479,28 +578,45 @@ __global__ __launch_bounds__(NT) void k_inv_plane(T *__restrict__ e, const uint8
     const double k0d = prm->k[0], k1d = prm->k[1], k2d = prm->k[2];
     T *eb = e + (size_t)ch * N * NN + (size_t)z * NN;
     const uint8_t *pb = ph + (size_t)z * NN;
-    double r2 = 0.0, fl = 0.0;
-    for (int idx = tid; idx < ROWS * N / V; idx += NT) {
-        const int m = idx / (N / V), x = (idx - m * (N / V)) * V;
-        const int y = S * m + h;
-        T a[V], c[V];
-        int p[V];
-        vload<T>(eb + y * N + x, a);
-        pload<V>(pb + y * N + x, p);
+    double r2 = 0.0, fl = 0.0, se = 0.0;
+    constexpr int TOTL = ROWS * N / V, PERL = (TOTL + NT - 1) / NT, BL = 8;
 #pragma unroll
-        for (int i = 0; i < V; i += 2) {
-            const Cx<T> zz = plane[m * RS + (x + i) / 2];
-            c[i] = zz.x;
-            c[i + 1] = zz.y;
+    for (int i0 = 0; i0 < PERL; i0 += BL) {
+        T a[BL][V];
+        int p[BL][V];
+#pragma unroll
+        for (int i = 0; i < BL; ++i) {
+            const int idx = tid + (i0 + i) * NT;
+            if (i0 + i < PERL && (TOTL % NT == 0 || idx < TOTL)) {
+                const int m = idx / (N / V), x = (idx - m * (N / V)) * V, y = S * m + h;
+                vload<T>(eb + y * N + x, a[i]);
+                pload<V>(pb + y * N + x, p[i]);
+            }
         }
-        em_update<T, V>(a, c, p, w0, w1, w2, k0d, k1d, k2d, r2, fl);
-        vstore<T>(eb + y * N + x, a);
+#pragma unroll
+        for (int i = 0; i < BL; ++i) {
+            const int idx = tid + (i0 + i) * NT;
+            if (i0 + i < PERL && (TOTL % NT == 0 || idx < TOTL)) {
+                const int m = idx / (N / V), x = (idx - m * (N / V)) * V, y = S * m + h;
+                T c[V];
+#pragma unroll
+                for (int j = 0; j < V; j += 2) {
+                    const Cx<T> zz = plane[m * RS + (x + j) / 2];
+                    c[j] = zz.x;
+                    c[j + 1] = zz.y;
+                }
+                em_update<T, V>(a[i], c, p[i], w0, w1, w2, k0d, k1d, k2d, ec, r2, fl, se);
+                vstore<T>(eb + y * N + x, a[i]);
+            }
+        }
     }
-    block_sum2<NT>(r2, fl, red);
+    double v3[3] = {r2, fl, se};
+    block_sum<NT, 3>(v3, red);
     if (tid == 0) {
-        double *pp = part + ((size_t)ch * (N * S) + (size_t)z * S + h) * 2;
-        pp[0] = r2;
-        pp[1] = fl;
+        double *pp = part + ((size_t)ch * (N * S) + (size_t)z * S + h) * 3;
+        pp[0] = v3[0];
+        pp[1] = v3[1];
+        pp[2] = v3[2];
     }
 }
 
@@ -528,6 +644,7 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(const T *__restrict__ e, const 
     if (PHI ? !st->eq_pending[lc] : st->done[lc]) return;
     const double *lut = PHI ? prm->k : prm->dk;
     const T d0 = (T)lut[0], d1 = (T)lut[1], d2 = (T)lut[2];
+    const T tm = PHI ? (T)0 : (T)st->tau_mean[ch];
     const T *eb = e + (size_t)ch * N * NN + (size_t)z * NN + (size_t)y0 * N;
     const uint8_t *pb = ph + (size_t)z * NN + (size_t)y0 * N;
     for (int idx = tid; idx < G * N / V; idx += NT) {
@@ -538,8 +655,8 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(const T *__restrict__ e, const 
         pload<V>(pb + y * N + x, p);
 #pragma unroll
         for (int i = 0; i < V; i += 2)
-            rows[y * RS + (x + i) / 2] = Cx<T>{pick<T>(p[i], d0, d1, d2) * a[i],
-                                               pick<T>(p[i + 1], d0, d1, d2) * a[i + 1]};
+            rows[y * RS + (x + i) / 2] = Cx<T>{pick<T>(p[i], d0, d1, d2) * a[i] - tm,
+                                               pick<T>(p[i + 1], d0, d1, d2) * a[i + 1] - tm};
     }
     __syncthreads();
     fft_lds<T, H, false, G, 1, NT, N, SeqStride<RS>>(rows, tw, tid);
@@ -628,12 +745,13 @@ __global__ __launch_bounds__(NT) void k_inv_rows(T *__restrict__ e, const uint8_
                                                  const DevState *__restrict__ st, double *__restrict__ part) {
     constexpr int H = N / 2, RS = H + 1, V = VecOf<T>::V, NN = N * N, GP = N / G;
     __shared__ Cx<T> rows[G * RS];
-    __shared__ double red[2 * (NT / 64)];
+    __shared__ double red[3 * (NT / 64)];
     const int tid = threadIdx.x;
     const int ch = blockIdx.x / (N * GP), rem = blockIdx.x - ch * (N * GP);
     const int z = rem / GP, yg = rem - z * GP, y0 = yg * G;
     const int lc = ch / 3;
     if (st->done[lc]) return;
+    const T ec = (ch % 4 == 0) ? (T)1 : (T)0;
     const Cx<T> *sb = spec + (((size_t)ch * N + z) * N + y0) * H;
     const Cx<T> *nb = nyq + ((size_t)ch * N + z) * N + y0;
     for (int idx = tid; idx < G * RS; idx += NT) {
@@ -651,7 +769,7 @@ __global__ __launch_bounds__(NT) void k_inv_rows(T *__restrict__ e, const uint8_
     const double k0d = prm->k[0], k1d = prm->k[1], k2d = prm->k[2];
     T *eb = e + (size_t)ch * N * NN + (size_t)z * NN + (size_t)y0 * N;
     const uint8_t *pb = ph + (size_t)z * NN + (size_t)y0 * N;
-    double r2 = 0.0, fl = 0.0;
+    double r2 = 0.0, fl = 0.0, se = 0.0;
     for (int idx = tid; idx < G * N / V; idx += NT) {
         const int y = idx / (N / V), x = (idx - y * (N / V)) * V;
         T a[V], c[V];
@@ -664,14 +782,16 @@ __global__ __launch_bounds__(NT) void k_inv_rows(T *__restrict__ e, const uint8_
             c[i] = zz.x;
             c[i + 1] = zz.y;
         }
-        em_update<T, V>(a, c, p, w0, w1, w2, k0d, k1d, k2d, r2, fl);
+        em_update<T, V>(a, c, p, w0, w1, w2, k0d, k1d, k2d, ec, r2, fl, se);
         vstore<T>(eb + y * N + x, a);
     }
-    block_sum2<NT>(r2, fl, red);
+    double v3[3] = {r2, fl, se};
+    block_sum<NT, 3>(v3, red);
     if (tid == 0) {
-        double *pp = part + ((size_t)ch * (N * GP) + (size_t)z * GP + yg) * 2;
-        pp[0] = r2;
-        pp[1] = fl;
+        double *pp = part + ((size_t)ch * (N * GP) + (size_t)z * GP + yg) * 3;
+        pp[0] = v3[0];
+        pp[1] = v3[1];
+        pp[2] = v3[2];
     }
 }
 
@@ -699,7 +819,10 @@ __global__ void k_init(T *__restrict__ e, size_t M, const DevParams *__restrict_
             st->best[lc] = 1e308;
             st->eps_eq[lc] = -1.0;
         }
-        for (int i = 0; i < 9; ++i) st->K[i] = 0.0;
+        for (int i = 0; i < 9; ++i) {
+            st->K[i] = 0.0;
+            st->tau_mean[i] = 0.0;
+        }
         st->all_done = all;
     }
 }

@@ -35,6 +35,10 @@ struct DevState {
     double res[3];
     double best[3];
     double eps_eq[3];
+    // per channel mean of tau = (k - k0) e for the next forward pass; it is
+    // subtracted there (the mean mode of tau is replaced by E anyway), which
+    // keeps the FFT's rounding error relative to the fluctuation only
+    double tau_mean[9];
 };
 
 enum : int { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_STALLED = 2, ST_NONFINITE = -5 };

@@ -135,3 +135,22 @@ def test_server_results_match_alone():
             alone = rh.homogenize(r, q[5], q[6], precision=0)
         assert np.array_equal(res.K, alone.K)
         assert np.array_equal(res.iters, alone.iters)
+
+
+def test_kernel_timing_does_not_change_results():
+    """Events recorded inside the replayed graphs: same tensor, one timed
+    launch per working iteration, positive durations."""
+    print("\n[case] kernel timing", flush=True)
+    ph, _, _ = geom.generate(48, 10, 0.25, 0.2, 8)
+    with rh.rve_create_from_phases(ph) as r:
+        plain = rh.homogenize(r, K3, 1e-6, precision=0)
+        timed = rh.homogenize(r, K3, 1e-6, precision=0, timing=True)
+        kt = rh.rve_get_kernel_times(r)
+        only = rh.homogenize(r, K3, 1e-6, precision=0, timing=4)
+        kt4 = rh.rve_get_kernel_times(r)
+    assert np.array_equal(plain.K, timed.K) and np.array_equal(plain.K, only.K)
+    for name in ("fwd_plane", "zgreen", "inv_plane", "reduce"):
+        assert kt[name]["launches"] == int(plain.iters.max())
+        assert kt[name]["total_ms"] > 0
+    assert kt4["inv_plane"]["launches"] == int(plain.iters.max())
+    assert kt4["fwd_plane"]["launches"] == 0
