@@ -91,8 +91,18 @@ template <typename T, int N> struct Instance {
                                a.prm, (const DevState *)a.st, a.part);
         } else {
             hipLaunchKernelGGL((k_inv_plane<T, N, SP, NTP>), dim3(9 * N * SP), dim3(NTP), 0, s, (T *)a.e,
-                               a.ph, (const Cx<T> *)a.spec, (const Cx<T> *)a.nyq, (const Cx<T> *)a.tw,
+                               a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw,
                                a.prm, (const DevState *)a.st, a.part);
+        }
+    }
+    // fused inverse + next forward pass (whole planes in LDS; not where the
+    // fused kernel would spill registers heavily: FP32 96^3)
+    static constexpr bool FUSED = !FIVE && S == 1 && !(sizeof(T) == 4 && N == 96);
+    static void inv_fwd(const LaunchArgs &a, hipStream_t s) {
+        if constexpr (FUSED) {
+            hipLaunchKernelGGL((k_inv_plane<T, N, 1, NTP, true>), dim3(9 * N), dim3(NTP), 0, s, (T *)a.e, a.ph,
+                               (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
+                               (const DevState *)a.st, a.part);
         }
     }
     static void init(const LaunchArgs &a, size_t M, hipStream_t s) {
@@ -129,6 +139,8 @@ template <typename T, int N> struct Instance {
             {9.0 * M * rb + 9.0 * M + spec_b + extra, 2.0 * spec_b,
              spec_b + 2.0 * 9.0 * M * rb + 9.0 * M + extra},
             ZTiles<N, W>::PER_LC,
+            FUSED ? 2.0 * spec_b + 2.0 * 9.0 * M * rb + 9.0 * M : 0.0,
+            FUSED ? &inv_fwd : nullptr,
             &fwd,
             &fwd_phi,
             &zeq,

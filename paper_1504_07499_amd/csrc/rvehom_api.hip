@@ -455,6 +455,15 @@ int Solver::begin(const uint8_t *d_phase, const double k[3], double tol, const S
     slot = 0;
     launches.clear();
     eq_check = o.eq_check != 0;
+    {
+        const char *f = getenv("RVEHOM_FUSED");
+        fused = ops->inv_fwd != nullptr && !eq_check && !(f && f[0] == '0');
+    }
+    if (fused) {
+        // the first forward pass; every later one is fused into the inverse pass
+        ops->fwd(a, s);
+        HIP_CHECK(hipGetLastError());
+    }
     return RVE_OK;
 }
 
@@ -466,12 +475,13 @@ int Solver::launch_iteration(const LaunchArgs &a, hipStream_t s, int mask, hipEv
     // "external" records become event-record nodes when captured into a graph
     // (a plain record under capture is only an ordering marker, with no time)
     for (int kk = 0; kk < 4; ++kk) {
+        if (fused && kk == 0) continue;  // the forward pass is inside the inverse one
         const bool timed = (mask >> kk) & 1;
         if (timed) HIP_CHECK(hipEventRecordWithFlags(ev[used], s, hipEventRecordExternal));
         switch (kk) {
         case 0: ops->fwd(a, s); break;
         case 1: ops->zgreen(a, s); break;
-        case 2: ops->inv(a, s); break;
+        case 2: fused ? ops->inv_fwd(a, s) : ops->inv(a, s); break;
         default: launch_reduce(a, ops->nper, s); break;
         }
         if (timed) {
@@ -489,9 +499,12 @@ int Solver::launch_iteration(const LaunchArgs &a, hipStream_t s, int mask, hipEv
 
 static int popcount4(int m) { return (m & 1) + ((m >> 1) & 1) + ((m >> 2) & 1) + ((m >> 3) & 1); }
 
+// kernels actually launched per iteration (the forward pass is fused away)
+static int live_mask(int mask, bool fused) { return fused ? (mask & ~1) : mask; }
+
 // Capture kChunk iterations into a graph on the solver's own stream.
 int Solver::ensure_graph(const uint8_t *d_phase) {
-    if (gexec && g_ws == ws && g_ph == d_phase && g_eq == eq_check) return RVE_OK;
+    if (gexec && g_ws == ws && g_ph == d_phase && g_eq == eq_check && g_fused == fused) return RVE_OK;
     drop_graphs();
     LaunchArgs a = args(d_phase);
     hipGraph_t g = nullptr;
@@ -512,6 +525,7 @@ int Solver::ensure_graph(const uint8_t *d_phase) {
     g_ws = ws;
     g_ph = d_phase;
     g_eq = eq_check;
+    g_fused = fused;
     return RVE_OK;
 }
 
@@ -555,7 +569,7 @@ int Solver::enqueue(const uint8_t *d_phase, int count, int max_iter, int timing,
     LaunchArgs a = args(d_phase);
     SlotInfo &si = slots[slot];
     si.first_iter = issued;
-    si.mask = timing & 15;
+    si.mask = live_mask(timing & 15, fused);
     const int per = 2 * popcount4(si.mask);
     if (use_graphs && count == kChunk && issued + kChunk <= max_iter) {
         int rc = si.mask ? ensure_timed_graphs(d_phase, si.mask) : ensure_graph(d_phase);
@@ -664,6 +678,7 @@ int Solver::collect(const SolverOpts &o, hipStream_t s, rve_result *out, double 
         static const char *names[4] = {"fwd_plane", "zgreen", "inv_plane", "reduce"};
         std::memset(kt, 0, sizeof(*kt));
         for (int q = 0; q < 4; ++q) kt->name[q] = names[q];
+        if (fused) kt->name[2] = "inv_fwd_plane";
         int maxit = 0;
         for (int j = 0; j < 3; ++j) maxit = std::max(maxit, hs->iters[j]);
         while (!inflight.empty()) {  // stream drained: remaining slots are complete
@@ -678,7 +693,8 @@ int Solver::collect(const SolverOpts &o, hipStream_t s, rve_result *out, double 
             for (int j = 0; j < 3; ++j) active += (hs->iters[j] > it) ? 1 : 0;
             kt->total_ms[kk] += ms;
             kt->launches[kk] += 1;
-            kt->total_bytes[kk] += (kk < 3) ? ops->bytes[kk] * active / 3.0 : 0.0;
+            const double b = (kk == 2 && fused) ? ops->bytes_fused : (kk < 3 ? ops->bytes[kk] : 0.0);
+            kt->total_bytes[kk] += b * active / 3.0;
         }
     }
     return RVE_OK;

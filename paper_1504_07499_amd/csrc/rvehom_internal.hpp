@@ -73,6 +73,7 @@ struct Solver {
     std::deque<int> inflight;
     std::vector<LaunchRec> launches;
     bool eq_check = false;
+    bool fused = false;  // iterations run zgreen + fused inverse/forward + reduce
     const uint8_t *d_phase_last = nullptr;
     // captured graph of kChunk iterations (kernels only; all parameters are
     // read from device memory, so one graph serves every call on this workspace)
@@ -80,6 +81,7 @@ struct Solver {
     const void *g_ws = nullptr;
     const uint8_t *g_ph = nullptr;
     bool g_eq = false;
+    bool g_fused = false;
     bool use_graphs = true;
     // timed variants: one graph per poll slot (its own events), per mask
     hipGraphExec_t tgexec[kPollSlots] = {};

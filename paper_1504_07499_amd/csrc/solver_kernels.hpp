@@ -177,6 +177,15 @@ __device__ __forceinline__ void em_update(T *a, const T *c, const int *p, T w0, 
     }
 }
 
+// Waves per SIMD asked of the plane kernels: as many workgroups per CU as
+// their LDS plane allows, capped at 4 waves per SIMD (at most 128 VGPRs).
+template <typename T, int N, int S, int NT> constexpr int plane_min_waves() {
+    constexpr size_t lds = (size_t)(N / S) * (N / 2 + 1) * sizeof(Cx<T>) + 512;
+    constexpr int per_cu = (int)((160 * 1024) / lds);
+    constexpr int waves = per_cu * (NT / 256);
+    return waves < 1 ? 1 : (waves > 4 ? 4 : waves);
+}
+
 // Block index -> (channel, z, parity).  For S = 2 the two parities of one
 // plane are 8 blocks apart, so that both run on the same XCD (blocks are
 // dealt round-robin to the 8 XCDs) and the second read of the plane hits L2.
@@ -199,7 +208,7 @@ template <int N, int S> __device__ __forceinline__ void plane_of_block(int b, in
 // With PHI the same pass transforms the flux k e for the equilibrium check.
 // ---------------------------------------------------------------------------
 template <typename T, int N, int S, int NT, bool PHI = false>
-__global__ __launch_bounds__(NT) void k_fwd_plane(const T *__restrict__ e, const uint8_t *__restrict__ ph,
+__global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_plane(const T *__restrict__ e, const uint8_t *__restrict__ ph,
                                                   Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
                                                   const Cx<T> *__restrict__ tw,
                                                   const DevParams *__restrict__ prm,
@@ -503,14 +512,21 @@ __global__ __launch_bounds__(NT) void k_zeq(const Cx<T> *__restrict__ spec, cons
 // ---------------------------------------------------------------------------
 // P3: 2D C2R of the (ch, z) plane, then steps 6-7 and the flux, fused.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int S, int NT>
-__global__ __launch_bounds__(NT) void k_inv_plane(T *__restrict__ e, const uint8_t *__restrict__ ph,
-                                                  const Cx<T> *__restrict__ spec,
-                                                  const Cx<T> *__restrict__ nyq,
+// FWD (S = 1 only): the same workgroup then forms tau = (k - k0) e+ of the
+// next iteration from the updated values it holds, runs the forward 2D R2C
+// of pass 1 and overwrites this plane's spectrum -- one read and one write
+// of the plane per iteration instead of two of each.  The mean subtracted
+// from tau is the previous iteration's (any constant is exact: the mean
+// mode of tau is replaced by E).
+template <typename T, int N, int S, int NT, bool FWD = false>
+__global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_plane(T *__restrict__ e, const uint8_t *__restrict__ ph,
+                                                  Cx<T> *__restrict__ spec,
+                                                  Cx<T> *__restrict__ nyq,
                                                   const Cx<T> *__restrict__ tw,
                                                   const DevParams *__restrict__ prm,
                                                   const DevState *__restrict__ st,
                                                   double *__restrict__ part) {
+    static_assert(!FWD || S == 1, "the fused inverse/forward pass needs a whole plane");
     constexpr int H = N / 2, RS = H + 1, ROWS = N / S, V = VecOf<T>::V, NN = N * N;
     __shared__ Cx<T> plane[ROWS * RS];
     __shared__ double red[3 * (NT / 64)];
@@ -576,6 +592,9 @@ __global__ __launch_bounds__(NT) void k_inv_plane(T *__restrict__ e, const uint8
 
     const T w0 = (T)prm->w[0], w1 = (T)prm->w[1], w2 = (T)prm->w[2];
     const double k0d = prm->k[0], k1d = prm->k[1], k2d = prm->k[2];
+    const T d0 = (T)prm->dk[0], d1 = (T)prm->dk[1], d2 = (T)prm->dk[2];
+    const T tm = (T)st->tau_mean[ch];
+    (void)d0, (void)d1, (void)d2, (void)tm;
     T *eb = e + (size_t)ch * N * NN + (size_t)z * NN;
     const uint8_t *pb = ph + (size_t)z * NN;
     double r2 = 0.0, fl = 0.0, se = 0.0;
@@ -607,6 +626,14 @@ __global__ __launch_bounds__(NT) void k_inv_plane(T *__restrict__ e, const uint8
                 }
                 em_update<T, V>(a[i], c, p[i], w0, w1, w2, k0d, k1d, k2d, ec, r2, fl, se);
                 vstore<T>(eb + y * N + x, a[i]);
+                if constexpr (FWD) {
+                    // next iteration's tau, packed in place of the c values just read
+#pragma unroll
+                    for (int j = 0; j < V; j += 2)
+                        plane[m * RS + (x + j) / 2] =
+                            Cx<T>{pick<T>(p[i][j], d0, d1, d2) * a[i][j] - tm,
+                                  pick<T>(p[i][j + 1], d0, d1, d2) * a[i][j + 1] - tm};
+                }
             }
         }
     }
@@ -617,6 +644,23 @@ __global__ __launch_bounds__(NT) void k_inv_plane(T *__restrict__ e, const uint8
         pp[0] = v3[0];
         pp[1] = v3[1];
         pp[2] = v3[2];
+    }
+    if constexpr (FWD) {
+        __syncthreads();
+        fft_lds<T, H, false, ROWS, 1, NT, N, SeqStride<RS>>(plane, tw, tid);
+        for (int idx = tid; idx < ROWS * (H / 2 + 1); idx += NT) {
+            const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
+            r2c_unpack<T, N, false>(plane + y * RS, k, tw, Cx<T>{(T)1, (T)0});
+        }
+        __syncthreads();
+        fft_lds<T, ROWS, false, RS, RS, NT, N, SeqStride<1>>(plane, tw, tid);
+        Cx<T> *so = spec + ((size_t)ch * N + z) * N * H;
+        for (int idx = tid; idx < ROWS * H / 2; idx += NT) {
+            const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
+            gstore2<T>(so + (size_t)m * H + kx, plane[m * RS + kx], plane[m * RS + kx + 1]);
+        }
+        Cx<T> *no = nyq + ((size_t)ch * N + z) * N;
+        for (int m = tid; m < ROWS; m += NT) no[m] = plane[m * RS + H];
     }
 }
 

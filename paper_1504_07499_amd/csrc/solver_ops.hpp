@@ -38,6 +38,9 @@ struct SolverOps {
     int threads[3];      // threads per block of P1, P2, P3
     double bytes[3];     // algorithmic HBM bytes of one launch of P1, P2, P3 (all 3 load cases)
     int eq_tiles;        // k_zeq blocks per load case
+    double bytes_fused;  // algorithmic bytes of one fused inverse + forward launch
+    // fused inverse pass + next forward pass, or nullptr where planes are split
+    void (*inv_fwd)(const LaunchArgs &, hipStream_t);
     void (*fwd)(const LaunchArgs &, hipStream_t);
     void (*fwd_phi)(const LaunchArgs &, hipStream_t);
     void (*zeq)(const LaunchArgs &, hipStream_t);
