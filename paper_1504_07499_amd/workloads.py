@@ -1,0 +1,197 @@
+"""Seeded synthetic workloads beyond the single-RVE benchmark, run through the
+C ABI: the batched realizations, the serving trace and the 256^3 contrast
+sweep.  All parameters are drawn from seeded generators; the RVE geometry
+follows Sec. 2 of arXiv:1504.07499 (RSA spheres, coating layer l), the solve
+follows the Algorithm of Sec. 3.
+
+Command line (GPU):
+  python -m paper_1504_07499_amd.workloads batch  [--count 64]
+  python -m paper_1504_07499_amd.workloads serve  [--rate 200 --requests 2000]
+  python -m paper_1504_07499_amd.workloads sweep256
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import threading
+import time
+
+import numpy as np
+
+from . import (homogenize, homogenize_batch, rve_create, rve_server_create, rve_server_destroy,
+               rve_server_drain, rve_server_poll, rve_server_submit)
+
+K_BENCH = (0.2, 0.3, 400.0)  # matrix, inclusion, coating
+
+
+# --------------------------------------------------------------------------- batch
+def batch_specs(count=64, seed=4):
+    """count RVEs: N uniform on {64, 96, 128}, 20-100 spheres, volume fraction
+    U[0.10, 0.40], layer U[0.05, 0.30]; RVE seeds 1000 + i."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(count):
+        specs.append((int(rng.choice([64, 96, 128])), int(rng.integers(20, 101)),
+                      float(rng.uniform(0.10, 0.40)), float(rng.uniform(0.05, 0.30)), 1000 + i))
+    return specs
+
+
+def run_batch(count=64, seed=4, precision=0, tol=1e-6, check_alone=4):
+    specs = batch_specs(count, seed)
+    rves = [rve_create(*s) for s in specs]
+    try:
+        homogenize_batch(rves[:2], K_BENCH, tol, precision=precision)  # warm-up (graphs, workspaces)
+        t0 = time.perf_counter()
+        res = homogenize_batch(rves, K_BENCH, tol, precision=precision)
+        wall = time.perf_counter() - t0
+        Ks = np.array([r.K for r in res])
+        vox = sum(s[0] ** 3 * int(r.iters.sum()) for s, r in zip(specs, res))
+        same = True
+        for i in range(min(check_alone, count)):
+            a = homogenize(rves[i], K_BENCH, tol, precision=precision)
+            same &= bool(np.array_equal(a.K, res[i].K))
+        t1 = time.perf_counter()
+        for r in rves:
+            homogenize(r, K_BENCH, tol, precision=precision)
+        seq = time.perf_counter() - t1
+    finally:
+        for r in rves:
+            r.close()
+    return {"workload": f"batch of {count} RVEs, N in {{64,96,128}}, seed {seed}",
+            "precision": "fp32" if precision == 0 else "fp64", "tol": tol,
+            "wall_s": wall, "solves_per_s": count / wall, "voxel_iters_per_s_per_lc": vox / wall,
+            "sequential_wall_s": seq, "batch_speedup_vs_sequential": seq / wall,
+            "K_mean": Ks.mean(0).tolist(), "K_var": Ks.var(0, ddof=1).tolist(),
+            "k_iso_mean": float(np.mean([np.trace(k) / 3 for k in Ks])),
+            "status_counts": {str(s): int(sum(1 for r in res if r.status == s)) for s in set(r.status for r in res)},
+            "alone_equals_batched": same}
+
+
+# --------------------------------------------------------------------------- serve
+def serve_trace(requests=2000, rate=200.0, seed=5):
+    """Poisson arrivals at `rate` per second; N uniform on {32, 64, 128, 256};
+    10-100 spheres; contrast log-uniform in [10, 1e4] (coating 0.2 c);
+    volume fraction U[0.10, 0.30]; layer U[0.05, 0.30]."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=requests))
+    out = []
+    for i in range(requests):
+        c = 10.0 ** rng.uniform(1.0, 4.0)
+        out.append({"t": float(t[i]), "n": int(rng.choice([32, 64, 128, 256])),
+                    "n_spheres": int(rng.integers(10, 101)), "f": float(rng.uniform(0.10, 0.30)),
+                    "layer": float(rng.uniform(0.05, 0.30)), "seed": 5000 + i,
+                    "k": (0.2, 0.3, 0.2 * c), "contrast": c})
+    return out
+
+
+def _pct(a, q):
+    return float(np.percentile(np.asarray(a), q)) if len(a) else None
+
+
+def run_serve(trace, precision=0, tol=1e-6, budget_bytes=64 << 30, slots=16):
+    """Continuous batching: submit each request at its arrival time; the
+    library admits requests by footprint and slot while others iterate."""
+    srv = rve_server_create(budget_bytes, slots, precision)
+    tickets = [None] * len(trace)
+    t0 = time.perf_counter()
+
+    def submitter():
+        for i, r in enumerate(trace):
+            dt = t0 + r["t"] - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            tickets[i] = rve_server_submit(srv, r["n"], r["n_spheres"], r["f"], r["layer"], r["seed"],
+                                           r["k"], tol)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    rve_server_drain(srv)
+    makespan = time.perf_counter() - t0
+    lat, results = [], []
+    for tk in tickets:
+        res, l = rve_server_poll(srv, tk)
+        lat.append(l)
+        results.append(res)
+    rve_server_destroy(srv)
+    return {"mode": "served (continuous batching)", "precision": "fp32" if precision == 0 else "fp64",
+            "requests": len(trace), "makespan_s": makespan, "solves_per_s": len(trace) / makespan,
+            "p50_latency_s": _pct(lat, 50), "p99_latency_s": _pct(lat, 99),
+            "status_counts": {str(s): int(sum(1 for r in results if r.status == s))
+                              for s in set(r.status for r in results)}}, results
+
+
+def run_sequential(trace, precision=1, tol=1e-6):
+    """The plain single-RVE path: one request at a time, in arrival order."""
+    t0 = time.perf_counter()
+    lat, results = [], []
+    for r in trace:
+        now = time.perf_counter() - t0
+        if now < r["t"]:
+            time.sleep(r["t"] - now)
+        with rve_create(r["n"], r["n_spheres"], r["f"], r["layer"], r["seed"]) as h:
+            res = homogenize(h, r["k"], tol, precision=precision)
+        lat.append(time.perf_counter() - t0 - r["t"])
+        results.append(res)
+    makespan = time.perf_counter() - t0
+    return {"mode": "sequential single-RVE", "precision": "fp32" if precision == 0 else "fp64",
+            "requests": len(trace), "makespan_s": makespan, "solves_per_s": len(trace) / makespan,
+            "p50_latency_s": _pct(lat, 50), "p99_latency_s": _pct(lat, 99)}, results
+
+
+def tensor_err(K, Kref):
+    return float(np.abs(K - Kref).max() / np.abs(Kref).max())
+
+
+# --------------------------------------------------------------------------- sweep
+def run_sweep256(layers=(0.05, 0.1, 0.2), contrasts=(1e2, 1e3, 1e4), n_spheres=100, f=0.40, seed=3,
+                 tol=1e-6):
+    """256^3, the same sphere centres for every (l, c); FP32 against FP64:
+    iteration counts and per-entry tensor error."""
+    rows = []
+    for layer in layers:
+        with rve_create(256, n_spheres, f, layer, seed) as h:
+            for c in contrasts:
+                k = (0.2, 0.3, 0.2 * c)
+                r64 = homogenize(h, k, tol, precision=1)
+                r32 = homogenize(h, k, tol, precision=0)
+                rows.append({"layer": layer, "contrast": c, "iters_fp64": r64.iters.tolist(),
+                             "iters_fp32": r32.iters.tolist(), "status_fp32": r32.lc_status.tolist(),
+                             "ms_fp64": r64.solve_ms, "ms_fp32": r32.solve_ms,
+                             "k_iso_fp64": float(np.trace(r64.K) / 3),
+                             "err_fp32_vs_fp64": tensor_err(r32.K, r64.K)})
+                print(json.dumps(rows[-1]), flush=True)
+    return rows
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    b = sub.add_parser("batch")
+    b.add_argument("--count", type=int, default=64)
+    b.add_argument("--precision", type=int, default=0)
+    s = sub.add_parser("serve")
+    s.add_argument("--requests", type=int, default=2000)
+    s.add_argument("--rate", type=float, default=200.0)
+    s.add_argument("--slots", type=int, default=16)
+    s.add_argument("--baseline", type=int, default=0, help="also run the sequential FP64 path")
+    sub.add_parser("sweep256")
+    a = ap.parse_args(argv)
+    if a.cmd == "batch":
+        print(json.dumps(run_batch(a.count, precision=a.precision)), flush=True)
+    elif a.cmd == "serve":
+        tr = serve_trace(a.requests, a.rate)
+        out, served = run_serve(tr, slots=a.slots)
+        print(json.dumps(out), flush=True)
+        if a.baseline:
+            seq, ref = run_sequential(tr, precision=1)
+            seq["max_err_served_fp32_vs_fp64"] = max(tensor_err(x.K, y.K) for x, y in zip(served, ref))
+            print(json.dumps(seq), flush=True)
+    else:
+        run_sweep256()
+
+
+if __name__ == "__main__":
+    sys.exit(main())
