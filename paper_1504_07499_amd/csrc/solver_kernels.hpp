@@ -73,15 +73,15 @@ template <> __device__ __forceinline__ void vstore<float>(float *p, const float 
 template <> __device__ __forceinline__ void vstore<double>(double *p, const double *i) {
     *reinterpret_cast<double2 *>(p) = make_double2(i[0], i[1]);
 }
-template <int V> __device__ __forceinline__ void pload(const uint8_t *p, int *o);
-template <> __device__ __forceinline__ void pload<4>(const uint8_t *p, int *o) {
-    uchar4 v = *reinterpret_cast<const uchar4 *>(p);
-    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+// V phase ids (one byte each) kept packed in one register; ph_at extracts id j.
+template <int V> __device__ __forceinline__ unsigned pload(const uint8_t *p);
+template <> __device__ __forceinline__ unsigned pload<4>(const uint8_t *p) {
+    return *reinterpret_cast<const unsigned *>(p);
 }
-template <> __device__ __forceinline__ void pload<2>(const uint8_t *p, int *o) {
-    uchar2 v = *reinterpret_cast<const uchar2 *>(p);
-    o[0] = v.x; o[1] = v.y;
+template <> __device__ __forceinline__ unsigned pload<2>(const uint8_t *p) {
+    return *reinterpret_cast<const unsigned short *>(p);
 }
+__device__ __forceinline__ int ph_at(unsigned pk, int j) { return (int)((pk >> (8 * j)) & 0xffu); }
 
 // Two consecutive complex values as one 16-byte global access (FP32) or two
 // (FP64); dst/src must be aligned to 2 complex values.
@@ -112,18 +112,24 @@ template <typename T> __device__ __forceinline__ T pick(int p, T a0, T a1, T a2)
 // R2C unpack, item k in [0, N/4] of one row: the length-N/2 FFT Z of the
 // packed even/odd samples becomes X[k] and X[N/2 - k] of the real-input
 // spectrum (X[0] and X[N/2] for k = 0), optionally times a row factor.
-template <typename T, int N, bool ROT>
+// P0: the two real values X[0] and X[N/2] go to row[0] as X[0] + i X[N/2]
+// (the y transform then handles both columns as one complex column).
+template <typename T, int N, bool ROT, bool P0 = false>
 __device__ __forceinline__ void r2c_unpack(Cx<T> *row, int k, const Cx<T> *__restrict__ tw, Cx<T> rot) {
     constexpr int H = N / 2;
     if (k == 0) {
         const Cx<T> z0 = row[0];
-        Cx<T> x0 = {z0.x + z0.y, (T)0}, xh = {z0.x - z0.y, (T)0};
-        if (ROT) {
-            x0 = x0 * rot;
-            xh = xh * rot;
+        if constexpr (P0) {
+            row[0] = Cx<T>{z0.x + z0.y, z0.x - z0.y};
+        } else {
+            Cx<T> x0 = {z0.x + z0.y, (T)0}, xh = {z0.x - z0.y, (T)0};
+            if (ROT) {
+                x0 = x0 * rot;
+                xh = xh * rot;
+            }
+            row[0] = x0;
+            row[H] = xh;
         }
-        row[0] = x0;
-        row[H] = xh;
     } else {
         const Cx<T> a = row[k], b = conj(row[H - k]);
         const Cx<T> A = scale(a + b, (T)0.5);
@@ -142,11 +148,12 @@ __device__ __forceinline__ void r2c_unpack(Cx<T> *row, int k, const Cx<T> *__res
 
 // C2R pack, item k in [0, N/4]: Hermitian half row X[0..N/2] -> the
 // length-N/2 sequence whose inverse FFT holds the even/odd output samples.
-template <typename T, int N>
+// P0: X[0] and X[N/2] arrive packed in row[0] as X[0] + i X[N/2].
+template <typename T, int N, bool P0 = false>
 __device__ __forceinline__ void c2r_pack(Cx<T> *row, int k, const Cx<T> *__restrict__ tw) {
     constexpr int H = N / 2;
     if (k == 0) {
-        const T x0 = row[0].x, xh = row[H].x;
+        const T x0 = row[0].x, xh = P0 ? row[0].y : row[H].x;
         row[0] = Cx<T>{x0 + xh, x0 - xh};
     } else {
         const Cx<T> a = row[k], b = conj(row[H - k]);
@@ -157,12 +164,56 @@ __device__ __forceinline__ void c2r_pack(Cx<T> *row, int k, const Cx<T> *__restr
     }
 }
 
+// Unpack / pack loops over the rows of a plane: per row the items k and
+// N/4 share one thread (N/4 is its own partner), N/4 items per row.
+template <typename T, int N, int ROWS, int NT, bool P0>
+__device__ __forceinline__ void r2c_unpack_rows(Cx<T> *plane, const Cx<T> *__restrict__ tw, int tid) {
+    constexpr int H = N / 2, RS = H + 1, Q = H / 2;
+    for (int idx = tid; idx < ROWS * Q; idx += NT) {
+        const int y = idx / Q, k = idx - y * Q;
+        r2c_unpack<T, N, false, P0>(plane + y * RS, k, tw, Cx<T>{(T)1, (T)0});
+        if (k == 0) r2c_unpack<T, N, false, P0>(plane + y * RS, Q, tw, Cx<T>{(T)1, (T)0});
+    }
+}
+template <typename T, int N, int ROWS, int NT, bool P0>
+__device__ __forceinline__ void c2r_pack_rows(Cx<T> *plane, const Cx<T> *__restrict__ tw, int tid) {
+    constexpr int H = N / 2, RS = H + 1, Q = H / 2;
+    for (int idx = tid; idx < ROWS * Q; idx += NT) {
+        const int y = idx / Q, k = idx - y * Q;
+        c2r_pack<T, N, P0>(plane + y * RS, k, tw);
+        if (k == 0) c2r_pack<T, N, P0>(plane + y * RS, Q, tw);
+    }
+}
+
+// Store the y-transformed plane (S = 1) as spectrum rows ky.  P0: column 0
+// holds Z = Y0 + i YH, the y transforms of the two real columns kx = 0 and
+// kx = N/2; by Hermitian symmetry Y0 = (Z[ky] + conj Z[-ky]) / 2 and
+// YH = (Z[ky] - conj Z[-ky]) / (2 i).
+template <typename T, int N, int NT, bool P0>
+__device__ __forceinline__ void store_plane(const Cx<T> *plane, Cx<T> *sb, Cx<T> *nb, int tid) {
+    constexpr int H = N / 2, RS = H + 1;
+    for (int idx = tid; idx < N * H / 2; idx += NT) {
+        const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
+        Cx<T> v0 = plane[m * RS + kx];
+        const Cx<T> v1 = plane[m * RS + kx + 1];
+        if (P0 && kx == 0) {
+            const Cx<T> b = conj(plane[(m == 0 ? 0 : N - m) * RS]);
+            const Cx<T> d = scale(v0 - b, (T)0.5);
+            nb[m] = Cx<T>{d.y, -d.x};
+            v0 = scale(v0 + b, (T)0.5);
+        }
+        gstore2<T>(sb + (size_t)m * H + kx, v0, v1);
+    }
+    if constexpr (!P0)
+        for (int m = tid; m < N; m += NT) nb[m] = plane[m * RS + H];
+}
+
 // Steps 6-7 and the flux on V voxels of one row: e+ = e + w (c - e),
 // r2 += |e - c|^2, fl += k e+ (FP64 accumulation).
 // c arrives without its mean E (added here).  Also sums e+ (its mean gives
 // the mean of tau for the next forward pass).
 template <typename T, int V>
-__device__ __forceinline__ void em_update(T *a, const T *c, const int *p, T w0, T w1, T w2, double k0d,
+__device__ __forceinline__ void em_update(T *a, const T *c, unsigned p, T w0, T w1, T w2, double k0d,
                                           double k1d, double k2d, T ec, double &r2, double &fl,
                                           double &se) {
 #pragma unroll
@@ -170,11 +221,20 @@ __device__ __forceinline__ void em_update(T *a, const T *c, const int *p, T w0, 
         const T ci = c[i] + ec;
         const T d = a[i] - ci;
         r2 += (double)d * (double)d;
-        const T wi = pick<T>(p[i], w0, w1, w2);
+        const int pi = ph_at(p, i);
+        const T wi = pick<T>(pi, w0, w1, w2);
         a[i] = a[i] + wi * (ci - a[i]);
-        fl += pick<double>(p[i], k0d, k1d, k2d) * (double)a[i];
+        fl += pick<double>(pi, k0d, k1d, k2d) * (double)a[i];
         se += (double)a[i];
     }
+}
+
+// The same pointer, opaque to the optimiser: loads through it are not merged
+// with earlier loads of the same addresses (keeps the inverse pass's twiddles
+// from being held in registers through the update of the fused pass).
+template <typename P> __device__ __forceinline__ P opaque_ptr(P p) {
+    asm volatile("" : "+s"(p));
+    return p;
 }
 
 // Waves per SIMD asked of the plane kernels: as many workgroups per CU as
@@ -235,17 +295,17 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
 #pragma unroll
     for (int i0 = 0; i0 < PERL; i0 += BL) {
         T a[BL][V], b[BL][V];
-        int p[BL][V], q[BL][V];
+        unsigned p[BL], q[BL];
 #pragma unroll
         for (int i = 0; i < BL; ++i) {
             const int idx = tid + (i0 + i) * NT;
             if (i0 + i < PERL && (TOTL % NT == 0 || idx < TOTL)) {
                 const int y = idx / (N / V), x = (idx - y * (N / V)) * V;
                 vload<T>(eb + y * N + x, a[i]);
-                pload<V>(pb + y * N + x, p[i]);
+                p[i] = pload<V>(pb + y * N + x);
                 if constexpr (S == 2) {
                     vload<T>(eb + (y + ROWS) * N + x, b[i]);
-                    pload<V>(pb + (y + ROWS) * N + x, q[i]);
+                    q[i] = pload<V>(pb + (y + ROWS) * N + x);
                 }
             }
         }
@@ -257,9 +317,9 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
                 T u[V];
 #pragma unroll
                 for (int j = 0; j < V; ++j) {
-                    u[j] = pick<T>(p[i][j], d0, d1, d2) * a[i][j] - tm;
+                    u[j] = pick<T>(ph_at(p[i], j), d0, d1, d2) * a[i][j] - tm;
                     if constexpr (S == 2) {
-                        const T t2 = pick<T>(q[i][j], d0, d1, d2) * b[i][j] - tm;
+                        const T t2 = pick<T>(ph_at(q[i], j), d0, d1, d2) * b[i][j] - tm;
                         u[j] = h ? u[j] - t2 : u[j] + t2;
                     }
                 }
@@ -272,26 +332,29 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
     // x: complex FFT of length N/2 of the packed even/odd samples
     fft_lds<T, H, false, ROWS, 1, NT, N, SeqStride<RS>>(plane, tw, tid);
     // unpack to the real-input spectrum X[0..N/2]
-    for (int idx = tid; idx < ROWS * (H / 2 + 1); idx += NT) {
-        const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
-        if constexpr (S == 2) {
-            if (h) {
-                r2c_unpack<T, N, true>(plane + y * RS, k, tw, tw[y]);  // w_N^y of the parity split
-                continue;
-            }
-        }
-        r2c_unpack<T, N, false>(plane + y * RS, k, tw, Cx<T>{(T)1, (T)0});
-    }
-    __syncthreads();
-    // y: complex FFT of length N/S down the N/2 + 1 columns
-    fft_lds<T, ROWS, false, RS, RS, NT, N, SeqStride<1>>(plane, tw, tid);
     Cx<T> *sb = spec + ((size_t)ch * N + z) * N * H;
-    for (int idx = tid; idx < ROWS * H / 2; idx += NT) {
-        const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
-        gstore2<T>(sb + (size_t)(S * m + h) * H + kx, plane[m * RS + kx], plane[m * RS + kx + 1]);
-    }
     Cx<T> *nb = nyq + ((size_t)ch * N + z) * N;
-    for (int m = tid; m < ROWS; m += NT) nb[S * m + h] = plane[m * RS + H];
+    if constexpr (S == 1) {
+        // whole plane: columns kx = 0 and N/2 are real, one complex column
+        r2c_unpack_rows<T, N, ROWS, NT, true>(plane, tw, tid);
+        __syncthreads();
+        fft_lds<T, ROWS, false, H, RS, NT, N, SeqStride<1>>(plane, tw, tid);
+        store_plane<T, N, NT, true>(plane, sb, nb, tid);
+    } else {
+        for (int idx = tid; idx < ROWS * (H / 2 + 1); idx += NT) {
+            const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
+            if (h) r2c_unpack<T, N, true>(plane + y * RS, k, tw, tw[y]);  // w_N^y of the parity split
+            else r2c_unpack<T, N, false>(plane + y * RS, k, tw, Cx<T>{(T)1, (T)0});
+        }
+        __syncthreads();
+        // y: complex FFT of length N/S down the N/2 + 1 columns
+        fft_lds<T, ROWS, false, RS, RS, NT, N, SeqStride<1>>(plane, tw, tid);
+        for (int idx = tid; idx < ROWS * H / 2; idx += NT) {
+            const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
+            gstore2<T>(sb + (size_t)(S * m + h) * H + kx, plane[m * RS + kx], plane[m * RS + kx + 1]);
+        }
+        for (int m = tid; m < ROWS; m += NT) nb[S * m + h] = plane[m * RS + H];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -528,6 +591,10 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
                                                   double *__restrict__ part) {
     static_assert(!FWD || S == 1, "the fused inverse/forward pass needs a whole plane");
     constexpr int H = N / 2, RS = H + 1, ROWS = N / S, V = VecOf<T>::V, NN = N * N;
+    // S = 1 (P0): column kx = 0 becomes Y0 + i YH with YH the kx = N/2 column,
+    // one complex column for the y transform (both are transforms of real
+    // columns, so the inverse separates them exactly)
+    constexpr bool P0 = (S == 1);
     __shared__ Cx<T> plane[ROWS * RS];
     __shared__ double red[3 * (NT / 64)];
     const int tid = threadIdx.x;
@@ -581,11 +648,23 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
         }
     }
     __syncthreads();
-    fft_lds<T, ROWS, true, RS, RS, NT, N, SeqStride<1>>(plane, tw, tid);
-    // pack the Hermitian half row into a length-N/2 complex sequence
-    for (int idx = tid; idx < ROWS * (H / 2 + 1); idx += NT) {
-        const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
-        c2r_pack<T, N>(plane + y * RS, k, tw);
+    if constexpr (P0) {
+        for (int m = tid; m < ROWS; m += NT) {
+            const Cx<T> y0 = plane[m * RS], yh = plane[m * RS + H];
+            plane[m * RS] = Cx<T>{y0.x - yh.y, y0.y + yh.x};
+        }
+        __syncthreads();
+    }
+    if constexpr (S == 1) {
+        fft_lds<T, ROWS, true, H, RS, NT, N, SeqStride<1>>(plane, tw, tid);
+        c2r_pack_rows<T, N, ROWS, NT, true>(plane, tw, tid);
+    } else {
+        fft_lds<T, ROWS, true, RS, RS, NT, N, SeqStride<1>>(plane, tw, tid);
+        // pack the Hermitian half row into a length-N/2 complex sequence
+        for (int idx = tid; idx < ROWS * (H / 2 + 1); idx += NT) {
+            const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
+            c2r_pack<T, N>(plane + y * RS, k, tw);
+        }
     }
     __syncthreads();
     fft_lds<T, H, true, ROWS, 1, NT, N, SeqStride<RS>>(plane, tw, tid);
@@ -602,14 +681,14 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
 #pragma unroll
     for (int i0 = 0; i0 < PERL; i0 += BL) {
         T a[BL][V];
-        int p[BL][V];
+        unsigned p[BL];
 #pragma unroll
         for (int i = 0; i < BL; ++i) {
             const int idx = tid + (i0 + i) * NT;
             if (i0 + i < PERL && (TOTL % NT == 0 || idx < TOTL)) {
                 const int m = idx / (N / V), x = (idx - m * (N / V)) * V, y = S * m + h;
                 vload<T>(eb + y * N + x, a[i]);
-                pload<V>(pb + y * N + x, p[i]);
+                p[i] = pload<V>(pb + y * N + x);
             }
         }
 #pragma unroll
@@ -631,8 +710,8 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
 #pragma unroll
                     for (int j = 0; j < V; j += 2)
                         plane[m * RS + (x + j) / 2] =
-                            Cx<T>{pick<T>(p[i][j], d0, d1, d2) * a[i][j] - tm,
-                                  pick<T>(p[i][j + 1], d0, d1, d2) * a[i][j + 1] - tm};
+                            Cx<T>{pick<T>(ph_at(p[i], j), d0, d1, d2) * a[i][j] - tm,
+                                  pick<T>(ph_at(p[i], j + 1), d0, d1, d2) * a[i][j + 1] - tm};
                 }
             }
         }
@@ -647,20 +726,13 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
     }
     if constexpr (FWD) {
         __syncthreads();
-        fft_lds<T, H, false, ROWS, 1, NT, N, SeqStride<RS>>(plane, tw, tid);
-        for (int idx = tid; idx < ROWS * (H / 2 + 1); idx += NT) {
-            const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
-            r2c_unpack<T, N, false>(plane + y * RS, k, tw, Cx<T>{(T)1, (T)0});
-        }
+        const Cx<T> *twf = opaque_ptr(tw);
+        fft_lds<T, H, false, ROWS, 1, NT, N, SeqStride<RS>>(plane, twf, tid);
+        r2c_unpack_rows<T, N, ROWS, NT, true>(plane, twf, tid);
         __syncthreads();
-        fft_lds<T, ROWS, false, RS, RS, NT, N, SeqStride<1>>(plane, tw, tid);
-        Cx<T> *so = spec + ((size_t)ch * N + z) * N * H;
-        for (int idx = tid; idx < ROWS * H / 2; idx += NT) {
-            const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
-            gstore2<T>(so + (size_t)m * H + kx, plane[m * RS + kx], plane[m * RS + kx + 1]);
-        }
-        Cx<T> *no = nyq + ((size_t)ch * N + z) * N;
-        for (int m = tid; m < ROWS; m += NT) no[m] = plane[m * RS + H];
+        fft_lds<T, ROWS, false, H, RS, NT, N, SeqStride<1>>(plane, twf, tid);
+        store_plane<T, N, NT, true>(plane, spec + ((size_t)ch * N + z) * N * H, nyq + ((size_t)ch * N + z) * N,
+                                    tid);
     }
 }
 
@@ -694,13 +766,12 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(const T *__restrict__ e, const 
     for (int idx = tid; idx < G * N / V; idx += NT) {
         const int y = idx / (N / V), x = (idx - y * (N / V)) * V;
         T a[V];
-        int p[V];
         vload<T>(eb + y * N + x, a);
-        pload<V>(pb + y * N + x, p);
+        const unsigned p = pload<V>(pb + y * N + x);
 #pragma unroll
         for (int i = 0; i < V; i += 2)
-            rows[y * RS + (x + i) / 2] = Cx<T>{pick<T>(p[i], d0, d1, d2) * a[i] - tm,
-                                               pick<T>(p[i + 1], d0, d1, d2) * a[i + 1] - tm};
+            rows[y * RS + (x + i) / 2] = Cx<T>{pick<T>(ph_at(p, i), d0, d1, d2) * a[i] - tm,
+                                               pick<T>(ph_at(p, i + 1), d0, d1, d2) * a[i + 1] - tm};
     }
     __syncthreads();
     fft_lds<T, H, false, G, 1, NT, N, SeqStride<RS>>(rows, tw, tid);
@@ -817,9 +888,8 @@ __global__ __launch_bounds__(NT) void k_inv_rows(T *__restrict__ e, const uint8_
     for (int idx = tid; idx < G * N / V; idx += NT) {
         const int y = idx / (N / V), x = (idx - y * (N / V)) * V;
         T a[V], c[V];
-        int p[V];
         vload<T>(eb + y * N + x, a);
-        pload<V>(pb + y * N + x, p);
+        const unsigned p = pload<V>(pb + y * N + x);
 #pragma unroll
         for (int i = 0; i < V; i += 2) {
             const Cx<T> zz = rows[y * RS + (x + i) / 2];
