@@ -187,6 +187,8 @@ __device__ __forceinline__ void fft_stage(Cx<T> *buf, const Cx<T> *__restrict__ 
     // Butterfly b = j * NSEQ + q: neighbouring threads take the same butterfly
     // of neighbouring sequences, so they share one twiddle (a broadcast load)
     // and, for sequences side by side in LDS, touch consecutive addresses.
+    // Reads, twiddles and the radix-R DFT all happen before the barrier (the
+    // twiddle loads' latency overlaps the wait); only the writes follow it.
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int b = tid + i * NT;
@@ -197,6 +199,24 @@ __device__ __forceinline__ void fft_stage(Cx<T> *buf, const Cx<T> *__restrict__ 
             for (int r = 0; r < R; ++r) v[i][r] = buf[off + (j + r * NB) * ES];
         }
     }
+    if (NS > 1) {
+        Cx<T> w[PER][R];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int b = tid + i * NT;
+            if (TOT % NT == 0 || b < TOT) {
+                const int k = (b / NSEQ) % NS;
+#pragma unroll
+                for (int r = 1; r < R; ++r) w[i][r] = tw[r * k * TWS];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PER; ++i)
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[i][r] = twmul<T, INV>(v[i][r], w[i][r]);
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) dft<T, R, INV>(v[i]);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
@@ -204,11 +224,6 @@ __device__ __forceinline__ void fft_stage(Cx<T> *buf, const Cx<T> *__restrict__ 
         if (TOT % NT == 0 || b < TOT) {
             const int j = b / NSEQ, q = b - j * NSEQ;
             const int k = j % NS;
-            if (NS > 1) {
-#pragma unroll
-                for (int r = 1; r < R; ++r) v[i][r] = twmul<T, INV>(v[i][r], tw[r * k * TWS]);
-            }
-            dft<T, R, INV>(v[i]);
             const int off = Seq::base(q);
             const int d = (j - k) * R + k;
 #pragma unroll

@@ -9,11 +9,13 @@ namespace rvehom {
 
 constexpr size_t kLdsBytes = 160 * 1024;
 
-// Row-parity split of the xy-plane so that N/S rows x (N/2 + 1) columns fit in LDS.
+// Row-parity split of the xy-plane so that N/S rows x (N/2 + 1) columns, the
+// twiddle table (N complex) and the reduction scratch fit in LDS.
 template <typename T, int N> constexpr int plane_split() {
-    return ((size_t)N * (N / 2 + 1) * sizeof(Cx<T>) + 1024 <= kLdsBytes)           ? 1
-           : ((size_t)(N / 2) * (N / 2 + 1) * sizeof(Cx<T>) + 1024 <= kLdsBytes) ? 2
-                                                                                   : 0;
+    constexpr size_t extra = (size_t)N * sizeof(Cx<T>) + 1024;
+    return ((size_t)N * (N / 2 + 1) * sizeof(Cx<T>) + extra <= kLdsBytes)           ? 1
+           : ((size_t)(N / 2) * (N / 2 + 1) * sizeof(Cx<T>) + extra <= kLdsBytes) ? 2
+                                                                                    : 0;
 }
 
 // z-tile width: largest W <= 16 dividing N/2 and N with 3 N W complex in

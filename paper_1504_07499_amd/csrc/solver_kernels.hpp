@@ -229,18 +229,26 @@ __device__ __forceinline__ void em_update(T *a, const T *c, unsigned p, T w0, T 
     }
 }
 
+// Copy a table of L complex values from global memory into LDS (the caller
+// synchronises before the first read).
+template <typename T, int L, int NT>
+__device__ __forceinline__ void table_to_lds(Cx<T> *dst, const Cx<T> *__restrict__ src, int tid) {
+    for (int i = tid; i < L; i += NT) dst[i] = src[i];
+}
+
 // The same pointer, opaque to the optimiser: loads through it are not merged
 // with earlier loads of the same addresses (keeps the inverse pass's twiddles
 // from being held in registers through the update of the fused pass).
-template <typename P> __device__ __forceinline__ P opaque_ptr(P p) {
-    asm volatile("" : "+s"(p));
-    return p;
+template <typename E> __device__ __forceinline__ const E *opaque_ptr(const E *p) {
+    int zero = 0;  // an offset the optimiser cannot see through (p stays a global pointer)
+    asm volatile("" : "+s"(zero));
+    return p + zero;
 }
 
 // Waves per SIMD asked of the plane kernels: as many workgroups per CU as
 // their LDS plane allows, capped at 4 waves per SIMD (at most 128 VGPRs).
 template <typename T, int N, int S, int NT> constexpr int plane_min_waves() {
-    constexpr size_t lds = (size_t)(N / S) * (N / 2 + 1) * sizeof(Cx<T>) + 512;
+    constexpr size_t lds = (size_t)(N / S) * (N / 2 + 1) * sizeof(Cx<T>) + (size_t)N * sizeof(Cx<T>) + 512;
     constexpr int per_cu = (int)((160 * 1024) / lds);
     constexpr int waves = per_cu * (NT / 256);
     return waves < 1 ? 1 : (waves > 4 ? 4 : waves);
@@ -270,7 +278,7 @@ template <int N, int S> __device__ __forceinline__ void plane_of_block(int b, in
 template <typename T, int N, int S, int NT, bool PHI = false>
 __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_plane(const T *__restrict__ e, const uint8_t *__restrict__ ph,
                                                   Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
-                                                  const Cx<T> *__restrict__ tw,
+                                                  const Cx<T> *__restrict__ twg,
                                                   const DevParams *__restrict__ prm,
                                                   const DevState *__restrict__ st) {
     constexpr int H = N / 2, RS = H + 1, ROWS = N / S, V = VecOf<T>::V, NN = N * N;
@@ -328,6 +336,10 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
             }
         }
     }
+    // twiddle table (length N) in LDS: short-latency loads inside the stages
+    __shared__ Cx<T> tws[N];
+    table_to_lds<T, N, NT>(tws, twg, tid);
+    const Cx<T> *tw = tws;
     __syncthreads();
     // x: complex FFT of length N/2 of the packed even/odd samples
     fft_lds<T, H, false, ROWS, 1, NT, N, SeqStride<RS>>(plane, tw, tid);
@@ -371,7 +383,7 @@ template <int N, int W> struct ZTiles {
 
 template <typename T, int N, int W, int NT>
 __global__ __launch_bounds__(NT) void k_zgreen(Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
-                                               const Cx<T> *__restrict__ tw,
+                                               const Cx<T> *__restrict__ twg,
                                                const DevParams *__restrict__ prm,
                                                const DevState *__restrict__ st) {
     using TL = ZTiles<N, W>;
@@ -424,6 +436,10 @@ __global__ __launch_bounds__(NT) void k_zgreen(Cx<T> *__restrict__ spec, Cx<T> *
             }
         }
     }
+    // twiddle table (length N) in LDS: short-latency loads inside the stages
+    __shared__ Cx<T> tws[N];
+    table_to_lds<T, N, NT>(tws, twg, tid);
+    const Cx<T> *tw = tws;
     __syncthreads();
     fft_lds<T, N, false, 3 * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
     const T sc = (T)prm->inv_k0M;
@@ -500,7 +516,7 @@ template <int NT> __device__ __forceinline__ void block_sum2(double &a, double &
 // mode 0.  Partials: peq[lc][tile] = {num, den}.
 template <typename T, int N, int W, int NT>
 __global__ __launch_bounds__(NT) void k_zeq(const Cx<T> *__restrict__ spec, const Cx<T> *__restrict__ nyq,
-                                            const Cx<T> *__restrict__ tw, const DevState *__restrict__ st,
+                                            const Cx<T> *__restrict__ twg, const DevState *__restrict__ st,
                                             double *__restrict__ peq) {
     using TL = ZTiles<N, W>;
     constexpr int H = N / 2, NW = N * W;
@@ -534,6 +550,10 @@ __global__ __launch_bounds__(NT) void k_zeq(const Cx<T> *__restrict__ spec, cons
         const int c = idx / NW, r = idx - c * NW, zz = r / W, w = r - zz * W;
         buf[idx] = base[c * cstride + zz * zstride + w];
     }
+    // twiddle table (length N) in LDS: short-latency loads inside the stages
+    __shared__ Cx<T> tws[N];
+    table_to_lds<T, N, NT>(tws, twg, tid);
+    const Cx<T> *tw = tws;
     __syncthreads();
     fft_lds<T, N, false, 3 * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
     double num = 0.0, den = 0.0;
@@ -585,7 +605,7 @@ template <typename T, int N, int S, int NT, bool FWD = false>
 __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_plane(T *__restrict__ e, const uint8_t *__restrict__ ph,
                                                   Cx<T> *__restrict__ spec,
                                                   Cx<T> *__restrict__ nyq,
-                                                  const Cx<T> *__restrict__ tw,
+                                                  const Cx<T> *__restrict__ twg,
                                                   const DevParams *__restrict__ prm,
                                                   const DevState *__restrict__ st,
                                                   double *__restrict__ part) {
@@ -629,7 +649,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
                     const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
                     Cx<T> a0 = va[i], a1 = vb[i];
                     if constexpr (S == 2) {
-                        const Cx<T> r = conj(tw[m]);
+                        const Cx<T> r = conj(twg[m]);
                         a0 = h ? (a0 - ua[i]) * r : a0 + ua[i];
                         a1 = h ? (a1 - ub[i]) * r : a1 + ub[i];
                     }
@@ -642,11 +662,15 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
             Cx<T> v = nb[m];
             if constexpr (S == 2) {
                 const Cx<T> u = nb[m + ROWS];
-                v = h ? (v - u) * conj(tw[m]) : v + u;
+                v = h ? (v - u) * conj(twg[m]) : v + u;
             }
             plane[m * RS + H] = v;
         }
     }
+    // twiddle table (length N) in LDS: short-latency loads inside the stages
+    __shared__ Cx<T> tws[N];
+    table_to_lds<T, N, NT>(tws, twg, tid);
+    const Cx<T> *tw = tws;
     __syncthreads();
     if constexpr (P0) {
         for (int m = tid; m < ROWS; m += NT) {
@@ -748,7 +772,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
 template <typename T, int N, int G, int NT, bool PHI = false>
 __global__ __launch_bounds__(NT) void k_fwd_rows(const T *__restrict__ e, const uint8_t *__restrict__ ph,
                                                  Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
-                                                 const Cx<T> *__restrict__ tw,
+                                                 const Cx<T> *__restrict__ twg,
                                                  const DevParams *__restrict__ prm,
                                                  const DevState *__restrict__ st) {
     constexpr int H = N / 2, RS = H + 1, V = VecOf<T>::V, NN = N * N, GP = N / G;
@@ -773,6 +797,10 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(const T *__restrict__ e, const 
             rows[y * RS + (x + i) / 2] = Cx<T>{pick<T>(ph_at(p, i), d0, d1, d2) * a[i] - tm,
                                                pick<T>(ph_at(p, i + 1), d0, d1, d2) * a[i + 1] - tm};
     }
+    // twiddle table (length N) in LDS: short-latency loads inside the stages
+    __shared__ Cx<T> tws[N];
+    table_to_lds<T, N, NT>(tws, twg, tid);
+    const Cx<T> *tw = tws;
     __syncthreads();
     fft_lds<T, H, false, G, 1, NT, N, SeqStride<RS>>(rows, tw, tid);
     for (int idx = tid; idx < G * (H / 2 + 1); idx += NT) {
@@ -800,7 +828,7 @@ template <int N, int W> struct ColTiles {
 // ones still iterating.
 template <typename T, int N, int W, int NT, bool INV, bool GATE_EQ = false>
 __global__ __launch_bounds__(NT) void k_cols(Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
-                                             const Cx<T> *__restrict__ tw, const DevState *__restrict__ st) {
+                                             const Cx<T> *__restrict__ twg, const DevState *__restrict__ st) {
     using TL = ColTiles<N, W>;
     constexpr int H = N / 2, NW = N * W;
     __shared__ Cx<T> buf[NW];  // [ky][w]
@@ -837,6 +865,10 @@ __global__ __launch_bounds__(NT) void k_cols(Cx<T> *__restrict__ spec, Cx<T> *__
             buf[ky * W + w] = base[(size_t)w * ss + ky];
         }
     }
+    // twiddle table (length N) in LDS: short-latency loads inside the stages
+    __shared__ Cx<T> tws[N];
+    table_to_lds<T, N, NT>(tws, twg, tid);
+    const Cx<T> *tw = tws;
     __syncthreads();
     fft_lds<T, N, INV, W, W, NT, N, SeqStride<1>>(buf, tw, tid);
     if (ss == 1) {
@@ -855,7 +887,7 @@ __global__ __launch_bounds__(NT) void k_cols(Cx<T> *__restrict__ spec, Cx<T> *__
 template <typename T, int N, int G, int NT>
 __global__ __launch_bounds__(NT) void k_inv_rows(T *__restrict__ e, const uint8_t *__restrict__ ph,
                                                  const Cx<T> *__restrict__ spec, const Cx<T> *__restrict__ nyq,
-                                                 const Cx<T> *__restrict__ tw,
+                                                 const Cx<T> *__restrict__ twg,
                                                  const DevParams *__restrict__ prm,
                                                  const DevState *__restrict__ st, double *__restrict__ part) {
     constexpr int H = N / 2, RS = H + 1, V = VecOf<T>::V, NN = N * N, GP = N / G;
@@ -873,6 +905,10 @@ __global__ __launch_bounds__(NT) void k_inv_rows(T *__restrict__ e, const uint8_
         const int y = idx / RS, kx = idx - y * RS;
         rows[idx] = (kx < H) ? sb[(size_t)y * H + kx] : nb[y];
     }
+    // twiddle table (length N) in LDS: short-latency loads inside the stages
+    __shared__ Cx<T> tws[N];
+    table_to_lds<T, N, NT>(tws, twg, tid);
+    const Cx<T> *tw = tws;
     __syncthreads();
     for (int idx = tid; idx < G * (H / 2 + 1); idx += NT) {
         const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
