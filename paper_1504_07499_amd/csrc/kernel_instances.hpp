@@ -79,10 +79,11 @@ template <typename T, int N> struct Instance {
                            (const Cx<T> *)a.spec, (const Cx<T> *)a.nyq, (const Cx<T> *)a.tw,
                            (const DevState *)a.st, a.peq);
     }
-    static void zgreen(const LaunchArgs &a, hipStream_t s) {
-        hipLaunchKernelGGL((k_zgreen<T, N, W, NTZ>), dim3(3 * ZTiles<N, W>::PER_LC), dim3(NTZ), 0, s,
-                           (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
-                           (const DevState *)a.st);
+    // red_nper > 0: one extra workgroup reduces the previous inverse pass
+    static void zgreen(const LaunchArgs &a, hipStream_t s, int red_nper) {
+        hipLaunchKernelGGL((k_zgreen<T, N, W, NTZ>), dim3(3 * ZTiles<N, W>::PER_LC + (red_nper > 0 ? 1 : 0)),
+                           dim3(NTZ), 0, s, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, a.st,
+                           (const double *)a.part, red_nper, a.hist);
     }
     static void inv(const LaunchArgs &a, hipStream_t s) {
         if constexpr (FIVE) {

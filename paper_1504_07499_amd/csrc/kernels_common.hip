@@ -2,107 +2,17 @@
 // reduction) and the list of grid sizes compiled into this build.
 #include <hip/hip_runtime.h>
 
+#include "reduce_block.hpp"
 #include "solver_ops.hpp"
 #include "solver_state.hpp"
 
 namespace rvehom {
 
-// ---------------------------------------------------------------------------
-// Fixed-order FP64 reduction of the partials, steps 6 / 1 convergence test,
-// <phi> of the updated field (L_hom column), per-load-case freeze.
-// One workgroup of 256 threads.
-// ---------------------------------------------------------------------------
+// Standalone form of the reduction (one workgroup of 256 threads).
 __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ part, int nper,
                                                 const DevParams *__restrict__ prm,
                                                 DevState *__restrict__ st, double *__restrict__ hist) {
-    // per load case {sum |e - c|^2, flux x, flux y, flux z}, and per channel
-    // sum e+.  Every thread adds its strided share of all nine channels
-    // (loads issued together), then a fixed-order wave and block reduction.
-    __shared__ double red[4][21];
-    __shared__ double tot[21];
-    const int tid = threadIdx.x;
-    double v[21];
-#pragma unroll
-    for (int q = 0; q < 21; ++q) v[q] = 0.0;
-    for (int b = tid; b < nper; b += 256) {
-        double r[9], f[9], m[9];
-#pragma unroll
-        for (int ch = 0; ch < 9; ++ch) {
-            const double *pc = part + ((size_t)ch * nper + b) * 3;
-            r[ch] = pc[0];
-            f[ch] = pc[1];
-            m[ch] = pc[2];
-        }
-#pragma unroll
-        for (int ch = 0; ch < 9; ++ch) {
-            v[4 * (ch / 3)] += r[ch];
-            v[4 * (ch / 3) + 1 + ch % 3] += f[ch];
-            v[12 + ch] += m[ch];
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < 21; ++q)
-        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_down(v[q], o, 64);
-    const int lane = tid & 63, wv = tid >> 6;
-    if (lane == 0)
-        for (int q = 0; q < 21; ++q) red[wv][q] = v[q];
-    __syncthreads();
-    if (tid < 21) tot[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-    __syncthreads();
-    if (tid != 0) return;
-    const int it = st->iter;
-    int all = 1;
-    for (int lc = 0; lc < 3; ++lc) {
-        if (st->done[lc]) continue;
-        const double eps = sqrt(tot[4 * lc] * prm->invM);  // |E| = 1
-        st->res[lc] = eps;
-        for (int c = 0; c < 3; ++c) {
-            const double F = tot[4 * lc + 1 + c] * prm->invM;  // <k e+_c>
-            st->K[3 * c + lc] = F;
-            // mean of tau = (k - k0) e+ for the next forward pass
-            st->tau_mean[3 * lc + c] = F - prm->k0 * tot[12 + 3 * lc + c] * prm->invM;
-        }
-        if (it < prm->hist_cap) hist[lc * prm->hist_cap + it] = eps;
-        int fin = 0, status = ST_NOT_CONVERGED;
-        if (!(eps == eps) || eps > 1e300) {
-            fin = 1;
-            status = ST_NONFINITE;
-        } else if (eps < prm->tol) {
-            if (prm->eq_check) {
-                // step 1, second stage: the equilibrium error decides (k_eq_reduce)
-                st->eq_pending[lc] = 1;
-                if (it + 1 >= prm->max_iter) fin = 1;
-            } else {
-                fin = 1;
-                status = ST_OK;
-            }
-        } else {
-            if (eps < st->best[lc]) {
-                st->best[lc] = eps;
-                st->best_it[lc] = it;
-            } else if (prm->stall_window > 0 && it - st->best_it[lc] >= prm->stall_window) {
-                fin = 1;
-                status = ST_STALLED;
-            }
-            // FP32 rounding floor: within 100 tol, less than 5 % progress in
-            // 10 iterations (the contraction gives far more) also stalls
-            if (!fin && prm->stall_window > 0 && it >= 10 && it - 10 < prm->hist_cap &&
-                eps < 100.0 * prm->tol && eps > 0.95 * hist[lc * prm->hist_cap + it - 10]) {
-                fin = 1;
-                status = ST_STALLED;
-            }
-            if (!fin && it + 1 >= prm->max_iter) fin = 1;
-        }
-        if (fin) {
-            st->done[lc] = 1;
-            st->status[lc] = status;
-            st->iters[lc] = it + 1;
-        } else {
-            all = 0;
-        }
-    }
-    st->iter = it + 1;
-    st->all_done = all;
+    reduce_block(part, nper, prm, st, hist, threadIdx.x);
 }
 
 // Equilibrium error of the load cases marked eq_pending: fixed-order sum of

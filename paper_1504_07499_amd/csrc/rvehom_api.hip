@@ -459,6 +459,10 @@ int Solver::begin(const uint8_t *d_phase, const double k[3], double tol, const S
         const char *f = getenv("RVEHOM_FUSED");
         fused = ops->inv_fwd != nullptr && !eq_check && !(f && f[0] == '0');
     }
+    {
+        const char *f = getenv("RVEHOM_MERGE");
+        merge = !eq_check && !(f && f[0] == '0');
+    }
     if (fused) {
         // the first forward pass; every later one is fused into the inverse pass
         ops->fwd(a, s);
@@ -470,17 +474,21 @@ int Solver::begin(const uint8_t *d_phase, const double k[3], double tol, const S
 // One iteration: the three passes, the reduction and (two-stage stop only)
 // the equilibrium check.  Every kernel exits at once for frozen load cases.
 // Kernels whose bit is set in mask are bracketed by the next two events of ev.
-int Solver::launch_iteration(const LaunchArgs &a, hipStream_t s, int mask, hipEvent_t *ev) {
+// red_in_z: the z pass also reduces the previous iteration's partials;
+// defer_red: this iteration's reduction is left to the next z pass.
+int Solver::launch_iteration(const LaunchArgs &a, hipStream_t s, int mask, hipEvent_t *ev, bool red_in_z,
+                             bool defer_red) {
     int used = 0;
     // "external" records become event-record nodes when captured into a graph
     // (a plain record under capture is only an ordering marker, with no time)
     for (int kk = 0; kk < 4; ++kk) {
         if (fused && kk == 0) continue;  // the forward pass is inside the inverse one
+        if (defer_red && kk == 3) continue;
         const bool timed = (mask >> kk) & 1;
         if (timed) HIP_CHECK(hipEventRecordWithFlags(ev[used], s, hipEventRecordExternal));
         switch (kk) {
         case 0: ops->fwd(a, s); break;
-        case 1: ops->zgreen(a, s); break;
+        case 1: ops->zgreen(a, s, red_in_z ? ops->nper : 0); break;
         case 2: fused ? ops->inv_fwd(a, s) : ops->inv(a, s); break;
         default: launch_reduce(a, ops->nper, s); break;
         }
@@ -499,17 +507,32 @@ int Solver::launch_iteration(const LaunchArgs &a, hipStream_t s, int mask, hipEv
 
 static int popcount4(int m) { return (m & 1) + ((m >> 1) & 1) + ((m >> 2) & 1) + ((m >> 3) & 1); }
 
+// count consecutive iterations; with merging, every reduction but the last
+// one of the batch runs inside the following z pass (the last stays a kernel
+// of its own, so the batch ends with the convergence flags up to date).
+// Not when the reduction itself is timed.
+int Solver::launch_batch(const LaunchArgs &a, hipStream_t s, int count, int mask, hipEvent_t *ev) {
+    const bool m = merge && !(mask & 8);
+    const int per = 2 * popcount4(mask);
+    for (int i = 0; i < count; ++i) {
+        int rc = launch_iteration(a, s, mask, ev ? ev + i * per : nullptr, m && i > 0, m && i + 1 < count);
+        if (rc != RVE_OK) return rc;
+    }
+    return RVE_OK;
+}
+
 // kernels actually launched per iteration (the forward pass is fused away)
 static int live_mask(int mask, bool fused) { return fused ? (mask & ~1) : mask; }
 
 // Capture kChunk iterations into a graph on the solver's own stream.
 int Solver::ensure_graph(const uint8_t *d_phase) {
-    if (gexec && g_ws == ws && g_ph == d_phase && g_eq == eq_check && g_fused == fused) return RVE_OK;
+    if (gexec && g_ws == ws && g_ph == d_phase && g_eq == eq_check && g_fused == fused && g_merge == merge)
+        return RVE_OK;
     drop_graphs();
     LaunchArgs a = args(d_phase);
     hipGraph_t g = nullptr;
     HIP_CHECK(hipStreamBeginCapture(own_stream, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < kChunk; ++i) launch_iteration(a, own_stream);
+    (void)launch_batch(a, own_stream, kChunk, 0, nullptr);
     hipError_t cap = hipStreamEndCapture(own_stream, &g);
     if (cap != hipSuccess) {
         set_error("graph capture failed: %s", hipGetErrorString(cap));
@@ -526,6 +549,7 @@ int Solver::ensure_graph(const uint8_t *d_phase) {
     g_ph = d_phase;
     g_eq = eq_check;
     g_fused = fused;
+    g_merge = merge;
     return RVE_OK;
 }
 
@@ -544,7 +568,7 @@ int Solver::ensure_timed_graphs(const uint8_t *d_phase, int mask) {
     for (int sl = 0; sl < kPollSlots; ++sl) {
         hipGraph_t g = nullptr;
         HIP_CHECK(hipStreamBeginCapture(own_stream, hipStreamCaptureModeThreadLocal));
-        for (int i = 0; i < kChunk; ++i) launch_iteration(a, own_stream, mask, slots[sl].ev.data() + i * per);
+        (void)launch_batch(a, own_stream, kChunk, mask, slots[sl].ev.data());
         hipError_t cap = hipStreamEndCapture(own_stream, &g);
         if (cap != hipSuccess) {
             set_error("graph capture failed: %s", hipGetErrorString(cap));
@@ -570,7 +594,6 @@ int Solver::enqueue(const uint8_t *d_phase, int count, int max_iter, int timing,
     SlotInfo &si = slots[slot];
     si.first_iter = issued;
     si.mask = live_mask(timing & 15, fused);
-    const int per = 2 * popcount4(si.mask);
     if (use_graphs && count == kChunk && issued + kChunk <= max_iter) {
         int rc = si.mask ? ensure_timed_graphs(d_phase, si.mask) : ensure_graph(d_phase);
         if (rc != RVE_OK) return rc;
@@ -578,9 +601,11 @@ int Solver::enqueue(const uint8_t *d_phase, int count, int max_iter, int timing,
         issued += kChunk;
         si.count = kChunk;
     } else {
-        si.count = 0;
-        for (int i = 0; i < count && issued < max_iter; ++i, ++issued, ++si.count)
-            launch_iteration(a, s, si.mask, si.ev.data() + i * per);
+        si.count = count < max_iter - issued ? count : max_iter - issued;
+        if (si.count < 0) si.count = 0;
+        int rc = launch_batch(a, s, si.count, si.mask, si.ev.data());
+        if (rc != RVE_OK) return rc;
+        issued += si.count;
     }
     HIP_CHECK(hipGetLastError());
     int *flags = (int *)((char *)h_pinned + kFlagsOffset);

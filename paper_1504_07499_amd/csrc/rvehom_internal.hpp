@@ -74,6 +74,7 @@ struct Solver {
     std::vector<LaunchRec> launches;
     bool eq_check = false;
     bool fused = false;  // iterations run zgreen + fused inverse/forward + reduce
+    bool merge = false;  // each reduction runs inside the next iteration's z pass
     const uint8_t *d_phase_last = nullptr;
     // captured graph of kChunk iterations (kernels only; all parameters are
     // read from device memory, so one graph serves every call on this workspace)
@@ -82,6 +83,7 @@ struct Solver {
     const uint8_t *g_ph = nullptr;
     bool g_eq = false;
     bool g_fused = false;
+    bool g_merge = false;
     bool use_graphs = true;
     // timed variants: one graph per poll slot (its own events), per mask
     hipGraphExec_t tgexec[kPollSlots] = {};
@@ -94,7 +96,9 @@ struct Solver {
     int ensure_twiddles(hipStream_t s);
     int begin(const uint8_t *d_phase, const double k[3], double tol, const SolverOpts &o, hipStream_t s);
     int enqueue(const uint8_t *d_phase, int count, int max_iter, int timing, hipStream_t s);
-    int launch_iteration(const LaunchArgs &a, hipStream_t s, int mask = 0, hipEvent_t *ev = nullptr);
+    int launch_iteration(const LaunchArgs &a, hipStream_t s, int mask, hipEvent_t *ev, bool red_in_z,
+                         bool defer_red);
+    int launch_batch(const LaunchArgs &a, hipStream_t s, int count, int mask, hipEvent_t *ev);
     int ensure_graph(const uint8_t *d_phase);
     int ensure_timed_graphs(const uint8_t *d_phase, int mask);
     int read_slot_times(int sl);

@@ -41,6 +41,7 @@
 #include <stdint.h>
 
 #include "fft_lds.hpp"
+#include "reduce_block.hpp"
 #include "solver_state.hpp"
 
 namespace rvehom {
@@ -381,18 +382,30 @@ template <int N, int W> struct ZTiles {
     static constexpr int PER_LC = MAIN + NYQ;
 };
 
+// With red_nper > 0 the first workgroup instead runs the reduction of the
+// previous inverse pass's partials (nper per channel) while the others do
+// the tiles.  The tiles then read the convergence flags as of the iteration
+// before: a load case that has just converged may be transformed once more,
+// which is harmless (its spectrum is not used again).
 template <typename T, int N, int W, int NT>
 __global__ __launch_bounds__(NT) void k_zgreen(Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
                                                const Cx<T> *__restrict__ twg,
                                                const DevParams *__restrict__ prm,
-                                               const DevState *__restrict__ st) {
+                                               DevState *__restrict__ st, const double *__restrict__ part,
+                                               int red_nper, double *__restrict__ hist) {
     using TL = ZTiles<N, W>;
     constexpr int H = N / 2, NW = N * W;
     static_assert(H % W == 0 && N % W == 0 && W % 2 == 0, "tile width must be even and divide N/2");
+    static_assert(NT == 256, "the merged reduction runs on a 256-thread workgroup");
     __shared__ Cx<T> buf[3 * NW];
     const int tid = threadIdx.x;
-    const int lc = blockIdx.x / TL::PER_LC, t = blockIdx.x - lc * TL::PER_LC;
-    if (st->done[lc]) return;
+    if (red_nper > 0 && blockIdx.x == 0) {
+        reduce_block(part, red_nper, prm, st, hist, tid);
+        return;
+    }
+    const int bt = blockIdx.x - (red_nper > 0 ? 1 : 0);
+    const int lc = bt / TL::PER_LC, t = bt - lc * TL::PER_LC;
+    if (__hip_atomic_load(&st->done[lc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     Cx<T> *base;
     size_t cstride, zstride;
     int kx0, ky0, dkx, dky;  // kx(w) = kx0 + dkx*w, ky(w) = ky0 + dky*w

@@ -44,7 +44,7 @@ struct SolverOps {
     void (*fwd)(const LaunchArgs &, hipStream_t);
     void (*fwd_phi)(const LaunchArgs &, hipStream_t);
     void (*zeq)(const LaunchArgs &, hipStream_t);
-    void (*zgreen)(const LaunchArgs &, hipStream_t);
+    void (*zgreen)(const LaunchArgs &, hipStream_t, int red_nper);
     void (*inv)(const LaunchArgs &, hipStream_t);
     void (*init)(const LaunchArgs &, size_t M, hipStream_t);
     void (*from_f64)(void *e, const double *src, size_t count, hipStream_t);
