@@ -69,7 +69,9 @@ typedef struct {
     int lc_mask;            /* load cases to solve, bit j = e_(j+1); 0 = all three */
     int timing;             /* bitmask of kernels to time with HIP events: 1 fwd_plane,
                                2 zgreen, 4 inv_plane, 8 reduce (15 = all); the events are
-                               recorded inside the replayed iteration graphs */
+                               recorded inside the replayed iteration graphs.  + 16
+                               (sampled): only one batch of iterations in four is
+                               timed, which keeps the events' own cost low */
     void *stream;           /* hipStream_t for all work, NULL = the handle's own */
     const double *init_field; /* host, 9 N^3 FP64 start field, NULL = E */
     double *out_field;      /* host, 9 N^3 FP64 final field, NULL = not returned */

@@ -267,7 +267,7 @@ def _opts(max_iter=0, precision=0, equilibrium_check=False, stall_window=-1, lc_
     o.stall_window = int(stall_window)
     o.lc_mask = int(lc_mask)
     # timing: True = all four kernels, or a bitmask (1 fwd_plane, 2 zgreen,
-    # 4 inv_plane, 8 reduce)
+    # 4 inv_plane, 8 reduce; + 16 = time one batch of iterations in four)
     o.timing = 15 if timing is True else int(timing)
     o.stream = _stream_handle(stream)
     o.init_field = _dptr(init_field) if init_field is not None else None

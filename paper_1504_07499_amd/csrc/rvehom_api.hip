@@ -416,7 +416,7 @@ SolverOpts resolve_opts(const rve_opts *opts) {
     int sw = opts ? opts->stall_window : -1;
     o.stall_window = sw < 0 ? (o.precision == 0 ? 50 : 0) : sw;
     o.lc_mask = (opts && (opts->lc_mask & 7)) ? (opts->lc_mask & 7) : 7;
-    o.timing = opts ? (opts->timing & 15) : 0;
+    o.timing = opts ? (opts->timing & 31) : 0;
     o.stream = opts ? (hipStream_t)opts->stream : nullptr;
     o.init_field = opts ? opts->init_field : nullptr;
     o.out_field = opts ? opts->out_field : nullptr;
@@ -593,7 +593,8 @@ int Solver::enqueue(const uint8_t *d_phase, int count, int max_iter, int timing,
     LaunchArgs a = args(d_phase);
     SlotInfo &si = slots[slot];
     si.first_iter = issued;
-    si.mask = live_mask(timing & 15, fused);
+    // sampled timing (bit 16): events only in the batches of poll slot 0
+    si.mask = ((timing & 16) && slot != 0) ? 0 : live_mask(timing & 15, fused);
     if (use_graphs && count == kChunk && issued + kChunk <= max_iter) {
         int rc = si.mask ? ensure_timed_graphs(d_phase, si.mask) : ensure_graph(d_phase);
         if (rc != RVE_OK) return rc;

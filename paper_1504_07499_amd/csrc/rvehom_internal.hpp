@@ -30,7 +30,7 @@ struct SolverOpts {
     int stall_window = 0;
     int lc_mask = 7;
     int scheme = 0;
-    int timing = 0;  // bitmask of timed kernels: 1 fwd, 2 zgreen, 4 inv, 8 reduce
+    int timing = 0;  // bitmask of timed kernels: 1 fwd, 2 zgreen, 4 inv, 8 reduce; 16 sampled
     hipStream_t stream = nullptr;
     const double *init_field = nullptr;
     double *out_field = nullptr;

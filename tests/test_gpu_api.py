@@ -148,7 +148,13 @@ def test_kernel_timing_does_not_change_results():
         kt = rh.rve_get_kernel_times(r)
         only = rh.homogenize(r, K3, 1e-6, precision=0, timing=4)
         kt4 = rh.rve_get_kernel_times(r)
+        sampled = rh.homogenize(r, K3, 1e-6, precision=0, timing=4 | 16)
+        kts = rh.rve_get_kernel_times(r)
     assert np.array_equal(plain.K, timed.K) and np.array_equal(plain.K, only.K)
+    assert np.array_equal(plain.K, sampled.K)
+    # sampled: one batch of iterations in four carries events
+    assert 0 < kts[list(kts)[2]]["launches"] < int(plain.iters.max())
+    assert kts[list(kts)[2]]["total_ms"] > 0
     names = list(kt)
     assert names[1] == "zgreen" and names[3] == "reduce"
     for name in names[1:]:
