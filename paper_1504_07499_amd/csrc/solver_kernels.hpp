@@ -246,6 +246,27 @@ template <typename E> __device__ __forceinline__ const E *opaque_ptr(const E *p)
     return p + zero;
 }
 
+// Steps 6-7 as em_update, and the next iteration's tau = (k - k0) e+ - tm
+// (tm: a constant the mean mode absorbs).  Instead of the flux, fl collects
+// sum tau in FP64: k e+ = (tau + tm) + k0 e+, so the caller adds
+// count * tm + k0 * (sum e+) -- no per-voxel FP64 conductivity lookup.
+// lut[phase] = {w, k - k0} (LDS).
+template <typename T, int V>
+__device__ __forceinline__ void em_update_tau(T *a, const T *c, unsigned p, const Cx<T> *lut, T tm, T ec,
+                                              double &r2, double &st, double &se, T *tau) {
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+        const T ci = c[i] + ec;
+        const T d = a[i] - ci;
+        r2 += (double)d * (double)d;
+        const Cx<T> wd = lut[ph_at(p, i)];
+        a[i] = a[i] + wd.x * (ci - a[i]);
+        tau[i] = wd.y * a[i] - tm;
+        st += (double)tau[i];
+        se += (double)a[i];
+    }
+}
+
 // Waves per SIMD asked of the plane kernels: as many workgroups per CU as
 // their LDS plane allows, capped at 4 waves per SIMD (at most 128 VGPRs).
 template <typename T, int N, int S, int NT> constexpr int plane_min_waves() {
@@ -684,6 +705,9 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
     __shared__ Cx<T> tws[N];
     table_to_lds<T, N, NT>(tws, twg, tid);
     const Cx<T> *tw = tws;
+    // per-phase {w, k - k0} of the update (fused form)
+    __shared__ Cx<T> lut[3];
+    if (FWD && tid < 3) lut[tid] = Cx<T>{(T)prm->w[tid], (T)prm->dk[tid]};
     __syncthreads();
     if constexpr (P0) {
         for (int m = tid; m < ROWS; m += NT) {
@@ -740,18 +764,26 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
                     c[j] = zz.x;
                     c[j + 1] = zz.y;
                 }
-                em_update<T, V>(a[i], c, p[i], w0, w1, w2, k0d, k1d, k2d, ec, r2, fl, se);
-                vstore<T>(eb + y * N + x, a[i]);
                 if constexpr (FWD) {
-                    // next iteration's tau, packed in place of the c values just read
+                    // next iteration's tau, packed in place of the c values just
+                    // read; fl collects sum tau here (the flux follows below)
+                    T tau[V];
+                    em_update_tau<T, V>(a[i], c, p[i], lut, tm, ec, r2, fl, se, tau);
+                    vstore<T>(eb + y * N + x, a[i]);
 #pragma unroll
-                    for (int j = 0; j < V; j += 2)
-                        plane[m * RS + (x + j) / 2] =
-                            Cx<T>{pick<T>(ph_at(p[i], j), d0, d1, d2) * a[i][j] - tm,
-                                  pick<T>(ph_at(p[i], j + 1), d0, d1, d2) * a[i][j + 1] - tm};
+                    for (int j = 0; j < V; j += 2) plane[m * RS + (x + j) / 2] = Cx<T>{tau[j], tau[j + 1]};
+                } else {
+                    em_update<T, V>(a[i], c, p[i], w0, w1, w2, k0d, k1d, k2d, ec, r2, fl, se);
+                    vstore<T>(eb + y * N + x, a[i]);
                 }
             }
         }
+    }
+    if constexpr (FWD) {
+        // flux k e+ = (k - k0) e+ + k0 e+ = (tau + tm) + k0 e+ per voxel, summed
+        // over the voxels of this thread (V per item idx = tid + i NT < TOTL)
+        const int items = tid < TOTL ? (TOTL - 1 - tid) / NT + 1 : 0;
+        fl += (double)(items * V) * (double)tm + prm->k0 * se;
     }
     double v3[3] = {r2, fl, se};
     block_sum<NT, 3>(v3, red);
