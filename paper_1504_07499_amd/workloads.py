@@ -8,6 +8,7 @@ Command line (GPU):
   python -m paper_1504_07499_amd.workloads batch  [--count 64]
   python -m paper_1504_07499_amd.workloads serve  [--rate 200 --requests 2000]
   python -m paper_1504_07499_amd.workloads sweep256
+  python -m paper_1504_07499_amd.workloads rates  [--requests 200 --rate 200]
 """
 from __future__ import annotations
 
@@ -166,6 +167,35 @@ def run_sweep256(layers=(0.05, 0.1, 0.2), contrasts=(1e2, 1e3, 1e4), n_spheres=1
     return rows
 
 
+def run_rate_sweep(requests=200, overload_rate=200.0, fractions=(0.5, 0.8), slots=16, check=20, seed=5):
+    """Serving capacity and latency: the trace at an overload rate gives the
+    capacity (served solves/s); the same request mix is then replayed at the
+    given fractions of that capacity.  The first `check` requests of the
+    overload run are also solved alone in FP64 and compared."""
+    rows = []
+    trace = serve_trace(requests, overload_rate, seed)
+    out, served = run_serve(trace, slots=slots)
+    cap = out["solves_per_s"]
+    out.update({"rate": overload_rate, "fraction_of_capacity": overload_rate / cap})
+    if check:
+        errs = []
+        for r, x in zip(trace[:check], served[:check]):
+            with rve_create(r["n"], r["n_spheres"], r["f"], r["layer"], r["seed"]) as h:
+                ref = homogenize(h, r["k"], 1e-6, precision=1)
+            errs.append(tensor_err(x.K, ref.K))
+        out["max_err_vs_fp64_first_%d" % check] = max(errs)
+    rows.append(out)
+    print(json.dumps(out), flush=True)
+    for frac in fractions:
+        rate = frac * cap
+        tr = serve_trace(requests, rate, seed)
+        o, _ = run_serve(tr, slots=slots)
+        o.update({"rate": rate, "fraction_of_capacity": frac})
+        rows.append(o)
+        print(json.dumps(o), flush=True)
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -178,6 +208,9 @@ def main(argv=None):
     s.add_argument("--slots", type=int, default=16)
     s.add_argument("--baseline", type=int, default=0, help="also run the sequential FP64 path")
     sub.add_parser("sweep256")
+    rs = sub.add_parser("rates")
+    rs.add_argument("--requests", type=int, default=200)
+    rs.add_argument("--rate", type=float, default=200.0)
     a = ap.parse_args(argv)
     if a.cmd == "batch":
         print(json.dumps(run_batch(a.count, precision=a.precision)), flush=True)
@@ -189,6 +222,8 @@ def main(argv=None):
             seq, ref = run_sequential(tr, precision=1)
             seq["max_err_served_fp32_vs_fp64"] = max(tensor_err(x.K, y.K) for x, y in zip(served, ref))
             print(json.dumps(seq), flush=True)
+    elif a.cmd == "rates":
+        run_rate_sweep(a.requests, a.rate)
     else:
         run_sweep256()
 
