@@ -9,6 +9,7 @@ Command line (GPU):
   python -m paper_1504_07499_amd.workloads serve  [--rate 200 --requests 2000]
   python -m paper_1504_07499_amd.workloads sweep256
   python -m paper_1504_07499_amd.workloads rates  [--requests 200 --rate 200]
+  python -m paper_1504_07499_amd.workloads run512
 """
 from __future__ import annotations
 
@@ -196,6 +197,24 @@ def run_rate_sweep(requests=200, overload_rate=200.0, fractions=(0.5, 0.8), slot
     return rows
 
 
+def run_512(n_spheres=100, f=0.30, layer=0.2, seed=7, k=K_BENCH, tol=1e-6):
+    """One 512^3 RVE on one GPU in both precisions (the paper needed a
+    cluster for 512^3, Sec. 4): iterations, solve time, FP32 against FP64."""
+    t0 = time.perf_counter()
+    with rve_create(512, n_spheres, f, layer, seed) as h:
+        setup = time.perf_counter() - t0
+        r32 = homogenize(h, k, tol, precision=0)
+        r64 = homogenize(h, k, tol, precision=1)
+    out = {"n": 512, "n_spheres": n_spheres, "f": f, "layer": layer, "seed": seed, "setup_s": setup,
+           "iters_fp32": r32.iters.tolist(), "iters_fp64": r64.iters.tolist(),
+           "status_fp32": r32.lc_status.tolist(), "ms_fp32": r32.solve_ms, "ms_fp64": r64.solve_ms,
+           "voxel_iters_per_s_per_lc_fp32": 512 ** 3 * int(r32.iters.sum()) / (r32.solve_ms * 1e-3),
+           "voxel_iters_per_s_per_lc_fp64": 512 ** 3 * int(r64.iters.sum()) / (r64.solve_ms * 1e-3),
+           "k_iso_fp64": float(np.trace(r64.K) / 3), "err_fp32_vs_fp64": tensor_err(r32.K, r64.K)}
+    print(json.dumps(out), flush=True)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -208,6 +227,7 @@ def main(argv=None):
     s.add_argument("--slots", type=int, default=16)
     s.add_argument("--baseline", type=int, default=0, help="also run the sequential FP64 path")
     sub.add_parser("sweep256")
+    sub.add_parser("run512")
     rs = sub.add_parser("rates")
     rs.add_argument("--requests", type=int, default=200)
     rs.add_argument("--rate", type=float, default=200.0)
@@ -222,6 +242,8 @@ def main(argv=None):
             seq, ref = run_sequential(tr, precision=1)
             seq["max_err_served_fp32_vs_fp64"] = max(tensor_err(x.K, y.K) for x, y in zip(served, ref))
             print(json.dumps(seq), flush=True)
+    elif a.cmd == "run512":
+        run_512()
     elif a.cmd == "rates":
         run_rate_sweep(a.requests, a.rate)
     else:

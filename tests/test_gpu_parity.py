@@ -178,7 +178,7 @@ def test_five_pass_256_fp64_vs_oracle():
     assert tensor_err(g.K[:, 0], ref.K[:, 0]) <= 1e-11
 
 
-@pytest.mark.parametrize("n,precision", [(512, 0), (256, 1)])
+@pytest.mark.parametrize("n,precision", [(512, 0), (256, 1), (512, 1)])
 def test_large_grid_laminate_exact(n, precision):
     """Closed form at sizes the oracle cannot run in a test: a laminate
     normal to y with odd layer widths gives K = diag(<k>, 1/<1/k>, <k>)."""
