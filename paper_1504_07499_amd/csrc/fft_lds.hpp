@@ -233,20 +233,188 @@ __device__ __forceinline__ void fft_stage(Cx<T> *buf, const Cx<T> *__restrict__ 
     __syncthreads();
 }
 
-template <typename T, int L, int S, int NST, bool INV, int NSEQ, int ES, int NT, int TW, class Seq>
+// Two neighbouring complex values in LDS as one 16-byte access (FP32; the
+// address must be 16-byte aligned) or two (FP64).
+template <typename T> __device__ __forceinline__ void lds_ld2(const Cx<T> *p, Cx<T> &a, Cx<T> &b) {
+    if constexpr (sizeof(T) == 4) {
+        const float4 t = *reinterpret_cast<const float4 *>(p);
+        a = Cx<T>{t.x, t.y};
+        b = Cx<T>{t.z, t.w};
+    } else {
+        a = p[0];
+        b = p[1];
+    }
+}
+template <typename T> __device__ __forceinline__ void lds_st2(Cx<T> *p, Cx<T> a, Cx<T> b) {
+    if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4 *>(p) = make_float4(a.x, a.y, b.x, b.y);
+    } else {
+        p[0] = a;
+        p[1] = b;
+    }
+}
+
+// Paired stages: each thread owns two butterflies whose data sit side by
+// side in LDS, so every LDS access moves two complex values.
+//  * PairSeq: the same butterfly of sequences 2p and 2p + 1, which must be
+//    adjacent (Seq::base(2p + 1) = Seq::base(2p) + 1, base even, ES even).
+//  * PairElem: butterflies 2p and 2p + 1 of one sequence whose elements are
+//    contiguous (ES = 1, Seq::base even); needs R and NB even.  A first stage
+//    (NS = 1) writes each butterfly's R outputs contiguously (pairs along r);
+//    later stages write the two butterflies' outputs side by side.
+enum PairMode { kPairNone = 0, kPairSeq = 1, kPairElem = 2 };
+
+template <typename T, int L, int S, bool INV, int NSEQ, int ES, int NT, int TW, class Seq>
+__device__ __forceinline__ void fft_stage_pseq(Cx<T> *buf, const Cx<T> *__restrict__ tw, int tid) {
+    constexpr int R = radix_of(L, S);
+    constexpr int NS = ns_before(L, S);
+    constexpr int NB = L / R;
+    constexpr int NP = NSEQ / 2;
+    constexpr int TOT = NP * NB;
+    constexpr int PER = (TOT + NT - 1) / NT;
+    constexpr int TWS = TW / (NS * R);
+    static_assert(NSEQ % 2 == 0 && ES % 2 == 0, "sequence pairs need an even count and an even stride");
+    Cx<T> v[PER][2][R];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int u = tid + i * NT;
+        if (TOT % NT == 0 || u < TOT) {
+            const int j = u / NP, qp = u - j * NP;
+            const int off = Seq::base(2 * qp);
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds_ld2<T>(buf + off + (j + r * NB) * ES, v[i][0][r], v[i][1][r]);
+        }
+    }
+    if (NS > 1) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int u = tid + i * NT;
+            if (TOT % NT == 0 || u < TOT) {
+                const int k = (u / NP) % NS;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    const Cx<T> w = tw[r * k * TWS];
+                    v[i][0][r] = twmul<T, INV>(v[i][0][r], w);
+                    v[i][1][r] = twmul<T, INV>(v[i][1][r], w);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        dft<T, R, INV>(v[i][0]);
+        dft<T, R, INV>(v[i][1]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int u = tid + i * NT;
+        if (TOT % NT == 0 || u < TOT) {
+            const int j = u / NP, qp = u - j * NP;
+            const int k = j % NS;
+            const int off = Seq::base(2 * qp);
+            const int d = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds_st2<T>(buf + off + (d + r * NS) * ES, v[i][0][r], v[i][1][r]);
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int L, int S, bool INV, int NSEQ, int NT, int TW, class Seq>
+__device__ __forceinline__ void fft_stage_pelem(Cx<T> *buf, const Cx<T> *__restrict__ tw, int tid) {
+    constexpr int R = radix_of(L, S);
+    constexpr int NS = ns_before(L, S);
+    constexpr int NB = L / R;
+    constexpr int NBP = NB / 2;
+    constexpr int TOT = NSEQ * NBP;
+    constexpr int PER = (TOT + NT - 1) / NT;
+    constexpr int TWS = TW / (NS * R);
+    static_assert(R % 2 == 0 && NB % 2 == 0 && (NS == 1 || NS % 2 == 0), "element pairs need even R, NB, NS");
+    Cx<T> v[PER][2][R];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int u = tid + i * NT;
+        if (TOT % NT == 0 || u < TOT) {
+            const int jp = u / NSEQ, q = u - jp * NSEQ;
+            const int off = Seq::base(q) + 2 * jp;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds_ld2<T>(buf + off + r * NB, v[i][0][r], v[i][1][r]);
+        }
+    }
+    if (NS > 1) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int u = tid + i * NT;
+            if (TOT % NT == 0 || u < TOT) {
+                const int k0 = (2 * (u / NSEQ)) % NS;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    v[i][0][r] = twmul<T, INV>(v[i][0][r], tw[r * k0 * TWS]);
+                    v[i][1][r] = twmul<T, INV>(v[i][1][r], tw[r * (k0 + 1) * TWS]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        dft<T, R, INV>(v[i][0]);
+        dft<T, R, INV>(v[i][1]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int u = tid + i * NT;
+        if (TOT % NT == 0 || u < TOT) {
+            const int jp = u / NSEQ, q = u - jp * NSEQ;
+            const int j0 = 2 * jp;
+            const int base = Seq::base(q);
+            if constexpr (NS == 1) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int r = 0; r < R; r += 2) lds_st2<T>(buf + base + (j0 + h) * R + r, v[i][h][r], v[i][h][r + 1]);
+            } else {
+                const int k0 = j0 % NS;
+                const int d = (j0 - k0) * R + k0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds_st2<T>(buf + base + d + r * NS, v[i][0][r], v[i][1][r]);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// stage S with pairing where its radix allows it
+template <typename T, int L, int S, bool INV, int NSEQ, int ES, int NT, int TW, class Seq, int PM>
+__device__ __forceinline__ void fft_stage_any(Cx<T> *buf, const Cx<T> *__restrict__ tw, int tid) {
+    constexpr int R = radix_of(L, S);
+    constexpr int NB = L / R;
+    constexpr int NS = ns_before(L, S);
+    if constexpr (PM == kPairSeq) {
+        fft_stage_pseq<T, L, S, INV, NSEQ, ES, NT, TW, Seq>(buf, tw, tid);
+    } else if constexpr (PM == kPairElem && ES == 1 && R % 2 == 0 && NB % 2 == 0 && (NS == 1 || NS % 2 == 0)) {
+        fft_stage_pelem<T, L, S, INV, NSEQ, NT, TW, Seq>(buf, tw, tid);
+    } else {
+        fft_stage<T, L, S, INV, NSEQ, ES, NT, TW, Seq>(buf, tw, tid);
+    }
+}
+
+template <typename T, int L, int S, int NST, bool INV, int NSEQ, int ES, int NT, int TW, class Seq, int PM>
 __device__ __forceinline__ void fft_stages(Cx<T> *buf, const Cx<T> *__restrict__ tw, int tid) {
     if constexpr (S < NST) {
-        fft_stage<T, L, S, INV, NSEQ, ES, NT, TW, Seq>(buf, tw, tid);
-        fft_stages<T, L, S + 1, NST, INV, NSEQ, ES, NT, TW, Seq>(buf, tw, tid);
+        fft_stage_any<T, L, S, INV, NSEQ, ES, NT, TW, Seq, PM>(buf, tw, tid);
+        fft_stages<T, L, S + 1, NST, INV, NSEQ, ES, NT, TW, Seq, PM>(buf, tw, tid);
     }
 }
 
 // Full length-L transform of NSEQ sequences in LDS (caller syncs before).
-template <typename T, int L, bool INV, int NSEQ, int ES, int NT, int TW, class Seq>
+// PM selects paired stages (the layout must meet that mode's conditions).
+template <typename T, int L, bool INV, int NSEQ, int ES, int NT, int TW, class Seq, int PM = kPairNone>
 __device__ __forceinline__ void fft_lds(Cx<T> *buf, const Cx<T> *__restrict__ tw, int tid) {
     static_assert(plan_ok(L), "no radix plan for this length");
     static_assert(TW % L == 0, "twiddle table length must be a multiple of L");
-    fft_stages<T, L, 0, num_stages(L), INV, NSEQ, ES, NT, TW, Seq>(buf, tw, tid);
+    fft_stages<T, L, 0, num_stages(L), INV, NSEQ, ES, NT, TW, Seq, PM>(buf, tw, tid);
 }
 
 // Sequence placements

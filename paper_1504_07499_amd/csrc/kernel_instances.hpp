@@ -9,11 +9,12 @@ namespace rvehom {
 
 constexpr size_t kLdsBytes = 160 * 1024;
 
-// Row-parity split of the xy-plane so that N/S rows x (N/2 + 1) columns, the
-// twiddle table (N complex) and the reduction scratch fit in LDS.
+// Row-parity split of the xy-plane so that its rows (pitch N/2 + 2 complex for
+// a whole plane, N/2 + 1 for a half), the twiddle table (N complex) and the
+// reduction scratch fit in LDS.
 template <typename T, int N> constexpr int plane_split() {
     constexpr size_t extra = (size_t)N * sizeof(Cx<T>) + 1024;
-    return ((size_t)N * (N / 2 + 1) * sizeof(Cx<T>) + extra <= kLdsBytes)           ? 1
+    return ((size_t)N * (N / 2 + 2) * sizeof(Cx<T>) + extra <= kLdsBytes)           ? 1
            : ((size_t)(N / 2) * (N / 2 + 1) * sizeof(Cx<T>) + extra <= kLdsBytes) ? 2
                                                                                     : 0;
 }
@@ -42,7 +43,7 @@ template <typename T, int N> constexpr int col_tile() {
 // many registers to hold one Stockham stage.
 template <typename T, int N> constexpr int plane_threads() {
     constexpr int S = plane_split<T, N>();
-    constexpr size_t elems = (size_t)(N / (S ? S : 1)) * (N / 2 + 1);
+    constexpr size_t elems = (size_t)(N / (S ? S : 1)) * (N / 2 + (S == 1 ? 2 : 1));
     return (elems * sizeof(Cx<T>) > 48 * 1024) ? 512 : 256;
 }
 

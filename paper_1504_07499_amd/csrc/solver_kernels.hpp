@@ -110,6 +110,26 @@ template <typename T> __device__ __forceinline__ T pick(int p, T a0, T a1, T a2)
     return p == 0 ? a0 : (p == 1 ? a1 : a2);
 }
 
+// Two neighbouring complex values of a plane row: one 16-byte LDS access
+// when the pair is 16-byte aligned (even row pitch), else two.
+template <typename T, bool ALIGNED>
+__device__ __forceinline__ void ld_pair(const Cx<T> *p, Cx<T> &a, Cx<T> &b) {
+    if constexpr (ALIGNED) {
+        lds_ld2<T>(p, a, b);
+    } else {
+        a = p[0];
+        b = p[1];
+    }
+}
+template <typename T, bool ALIGNED> __device__ __forceinline__ void st_pair(Cx<T> *p, Cx<T> a, Cx<T> b) {
+    if constexpr (ALIGNED) {
+        lds_st2<T>(p, a, b);
+    } else {
+        p[0] = a;
+        p[1] = b;
+    }
+}
+
 // R2C unpack, item k in [0, N/4] of one row: the length-N/2 FFT Z of the
 // packed even/odd samples becomes X[k] and X[N/2 - k] of the real-input
 // spectrum (X[0] and X[N/2] for k = 0), optionally times a row factor.
@@ -167,18 +187,18 @@ __device__ __forceinline__ void c2r_pack(Cx<T> *row, int k, const Cx<T> *__restr
 
 // Unpack / pack loops over the rows of a plane: per row the items k and
 // N/4 share one thread (N/4 is its own partner), N/4 items per row.
-template <typename T, int N, int ROWS, int NT, bool P0>
+template <typename T, int N, int ROWS, int NT, bool P0, int RS>
 __device__ __forceinline__ void r2c_unpack_rows(Cx<T> *plane, const Cx<T> *__restrict__ tw, int tid) {
-    constexpr int H = N / 2, RS = H + 1, Q = H / 2;
+    constexpr int H = N / 2, Q = H / 2;
     for (int idx = tid; idx < ROWS * Q; idx += NT) {
         const int y = idx / Q, k = idx - y * Q;
         r2c_unpack<T, N, false, P0>(plane + y * RS, k, tw, Cx<T>{(T)1, (T)0});
         if (k == 0) r2c_unpack<T, N, false, P0>(plane + y * RS, Q, tw, Cx<T>{(T)1, (T)0});
     }
 }
-template <typename T, int N, int ROWS, int NT, bool P0>
+template <typename T, int N, int ROWS, int NT, bool P0, int RS>
 __device__ __forceinline__ void c2r_pack_rows(Cx<T> *plane, const Cx<T> *__restrict__ tw, int tid) {
-    constexpr int H = N / 2, RS = H + 1, Q = H / 2;
+    constexpr int H = N / 2, Q = H / 2;
     for (int idx = tid; idx < ROWS * Q; idx += NT) {
         const int y = idx / Q, k = idx - y * Q;
         c2r_pack<T, N, P0>(plane + y * RS, k, tw);
@@ -190,13 +210,13 @@ __device__ __forceinline__ void c2r_pack_rows(Cx<T> *plane, const Cx<T> *__restr
 // holds Z = Y0 + i YH, the y transforms of the two real columns kx = 0 and
 // kx = N/2; by Hermitian symmetry Y0 = (Z[ky] + conj Z[-ky]) / 2 and
 // YH = (Z[ky] - conj Z[-ky]) / (2 i).
-template <typename T, int N, int NT, bool P0>
+template <typename T, int N, int NT, bool P0, int RS>
 __device__ __forceinline__ void store_plane(const Cx<T> *plane, Cx<T> *sb, Cx<T> *nb, int tid) {
-    constexpr int H = N / 2, RS = H + 1;
+    constexpr int H = N / 2;
     for (int idx = tid; idx < N * H / 2; idx += NT) {
         const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
-        Cx<T> v0 = plane[m * RS + kx];
-        const Cx<T> v1 = plane[m * RS + kx + 1];
+        Cx<T> v0, v1;
+        ld_pair<T, RS % 2 == 0>(plane + m * RS + kx, v0, v1);
         if (P0 && kx == 0) {
             const Cx<T> b = conj(plane[(m == 0 ? 0 : N - m) * RS]);
             const Cx<T> d = scale(v0 - b, (T)0.5);
@@ -270,7 +290,7 @@ __device__ __forceinline__ void em_update_tau(T *a, const T *c, unsigned p, cons
 // Waves per SIMD asked of the plane kernels: as many workgroups per CU as
 // their LDS plane allows, capped at 4 waves per SIMD (at most 128 VGPRs).
 template <typename T, int N, int S, int NT> constexpr int plane_min_waves() {
-    constexpr size_t lds = (size_t)(N / S) * (N / 2 + 1) * sizeof(Cx<T>) + (size_t)N * sizeof(Cx<T>) + 512;
+    constexpr size_t lds = (size_t)(N / S) * (N / 2 + (S == 1 ? 2 : 1)) * sizeof(Cx<T>) + (size_t)N * sizeof(Cx<T>) + 512;
     constexpr int per_cu = (int)((160 * 1024) / lds);
     constexpr int waves = per_cu * (NT / 256);
     return waves < 1 ? 1 : (waves > 4 ? 4 : waves);
@@ -303,7 +323,13 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
                                                   const Cx<T> *__restrict__ twg,
                                                   const DevParams *__restrict__ prm,
                                                   const DevState *__restrict__ st) {
-    constexpr int H = N / 2, RS = H + 1, ROWS = N / S, V = VecOf<T>::V, NN = N * N;
+    // row pitch: even for whole planes (16-byte pair accesses, paired FFT
+    // stages), N/2 + 1 for split planes
+    constexpr int H = N / 2, RS = (S == 1) ? H + 2 : H + 1, ROWS = N / S, V = VecOf<T>::V, NN = N * N;
+    // paired FFT stages: FP32 whole planes (an FP64 complex already fills a
+    // 16-byte access, and pairs would double the registers of a butterfly)
+    constexpr int PMX = (S == 1 && sizeof(T) == 4) ? kPairElem : kPairNone;
+    constexpr int PMY = (S == 1 && sizeof(T) == 4) ? kPairSeq : kPairNone;
     static_assert(N % 4 == 0 && (S == 1 || S == 2), "plane kernel needs N % 4 == 0");
     __shared__ Cx<T> plane[ROWS * RS];
     const int tid = threadIdx.x;
@@ -353,8 +379,12 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
                         u[j] = h ? u[j] - t2 : u[j] + t2;
                     }
                 }
+                if constexpr (V == 4) {
+                    st_pair<T, RS % 2 == 0>(plane + y * RS + x / 2, Cx<T>{u[0], u[1]}, Cx<T>{u[2], u[3]});
+                } else {
 #pragma unroll
-                for (int j = 0; j < V; j += 2) plane[y * RS + (x + j) / 2] = Cx<T>{u[j], u[j + 1]};
+                    for (int j = 0; j < V; j += 2) plane[y * RS + (x + j) / 2] = Cx<T>{u[j], u[j + 1]};
+                }
             }
         }
     }
@@ -364,16 +394,16 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
     const Cx<T> *tw = tws;
     __syncthreads();
     // x: complex FFT of length N/2 of the packed even/odd samples
-    fft_lds<T, H, false, ROWS, 1, NT, N, SeqStride<RS>>(plane, tw, tid);
+    fft_lds<T, H, false, ROWS, 1, NT, N, SeqStride<RS>, PMX>(plane, tw, tid);
     // unpack to the real-input spectrum X[0..N/2]
     Cx<T> *sb = spec + ((size_t)ch * N + z) * N * H;
     Cx<T> *nb = nyq + ((size_t)ch * N + z) * N;
     if constexpr (S == 1) {
         // whole plane: columns kx = 0 and N/2 are real, one complex column
-        r2c_unpack_rows<T, N, ROWS, NT, true>(plane, tw, tid);
+        r2c_unpack_rows<T, N, ROWS, NT, true, RS>(plane, tw, tid);
         __syncthreads();
-        fft_lds<T, ROWS, false, H, RS, NT, N, SeqStride<1>>(plane, tw, tid);
-        store_plane<T, N, NT, true>(plane, sb, nb, tid);
+        fft_lds<T, ROWS, false, H, RS, NT, N, SeqStride<1>, PMY>(plane, tw, tid);
+        store_plane<T, N, NT, true, RS>(plane, sb, nb, tid);
     } else {
         for (int idx = tid; idx < ROWS * (H / 2 + 1); idx += NT) {
             const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
@@ -644,7 +674,13 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
                                                   const DevState *__restrict__ st,
                                                   double *__restrict__ part) {
     static_assert(!FWD || S == 1, "the fused inverse/forward pass needs a whole plane");
-    constexpr int H = N / 2, RS = H + 1, ROWS = N / S, V = VecOf<T>::V, NN = N * N;
+    // row pitch: even for whole planes (16-byte pair accesses, paired FFT
+    // stages), N/2 + 1 for split planes
+    constexpr int H = N / 2, RS = (S == 1) ? H + 2 : H + 1, ROWS = N / S, V = VecOf<T>::V, NN = N * N;
+    // paired FFT stages: FP32 whole planes (an FP64 complex already fills a
+    // 16-byte access, and pairs would double the registers of a butterfly)
+    constexpr int PMX = (S == 1 && sizeof(T) == 4) ? kPairElem : kPairNone;
+    constexpr int PMY = (S == 1 && sizeof(T) == 4) ? kPairSeq : kPairNone;
     // S = 1 (P0): column kx = 0 becomes Y0 + i YH with YH the kx = N/2 column,
     // one complex column for the y transform (both are transforms of real
     // columns, so the inverse separates them exactly)
@@ -687,8 +723,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
                         a0 = h ? (a0 - ua[i]) * r : a0 + ua[i];
                         a1 = h ? (a1 - ub[i]) * r : a1 + ub[i];
                     }
-                    plane[m * RS + kx] = a0;
-                    plane[m * RS + kx + 1] = a1;
+                    st_pair<T, RS % 2 == 0>(plane + m * RS + kx, a0, a1);
                 }
             }
         }
@@ -717,8 +752,8 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
         __syncthreads();
     }
     if constexpr (S == 1) {
-        fft_lds<T, ROWS, true, H, RS, NT, N, SeqStride<1>>(plane, tw, tid);
-        c2r_pack_rows<T, N, ROWS, NT, true>(plane, tw, tid);
+        fft_lds<T, ROWS, true, H, RS, NT, N, SeqStride<1>, PMY>(plane, tw, tid);
+        c2r_pack_rows<T, N, ROWS, NT, true, RS>(plane, tw, tid);
     } else {
         fft_lds<T, ROWS, true, RS, RS, NT, N, SeqStride<1>>(plane, tw, tid);
         // pack the Hermitian half row into a length-N/2 complex sequence
@@ -728,7 +763,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
         }
     }
     __syncthreads();
-    fft_lds<T, H, true, ROWS, 1, NT, N, SeqStride<RS>>(plane, tw, tid);
+    fft_lds<T, H, true, ROWS, 1, NT, N, SeqStride<RS>, PMX>(plane, tw, tid);
 
     const T w0 = (T)prm->w[0], w1 = (T)prm->w[1], w2 = (T)prm->w[2];
     const double k0d = prm->k[0], k1d = prm->k[1], k2d = prm->k[2];
@@ -758,11 +793,17 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
             if (i0 + i < PERL && (TOTL % NT == 0 || idx < TOTL)) {
                 const int m = idx / (N / V), x = (idx - m * (N / V)) * V, y = S * m + h;
                 T c[V];
+                if constexpr (V == 4) {
+                    Cx<T> z0, z1;
+                    ld_pair<T, RS % 2 == 0>(plane + m * RS + x / 2, z0, z1);
+                    c[0] = z0.x, c[1] = z0.y, c[2] = z1.x, c[3] = z1.y;
+                } else {
 #pragma unroll
-                for (int j = 0; j < V; j += 2) {
-                    const Cx<T> zz = plane[m * RS + (x + j) / 2];
-                    c[j] = zz.x;
-                    c[j + 1] = zz.y;
+                    for (int j = 0; j < V; j += 2) {
+                        const Cx<T> zz = plane[m * RS + (x + j) / 2];
+                        c[j] = zz.x;
+                        c[j + 1] = zz.y;
+                    }
                 }
                 if constexpr (FWD) {
                     // next iteration's tau, packed in place of the c values just
@@ -770,8 +811,12 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
                     T tau[V];
                     em_update_tau<T, V>(a[i], c, p[i], lut, tm, ec, r2, fl, se, tau);
                     vstore<T>(eb + y * N + x, a[i]);
+                    if constexpr (V == 4) {
+                        st_pair<T, RS % 2 == 0>(plane + m * RS + x / 2, Cx<T>{tau[0], tau[1]}, Cx<T>{tau[2], tau[3]});
+                    } else {
 #pragma unroll
-                    for (int j = 0; j < V; j += 2) plane[m * RS + (x + j) / 2] = Cx<T>{tau[j], tau[j + 1]};
+                        for (int j = 0; j < V; j += 2) plane[m * RS + (x + j) / 2] = Cx<T>{tau[j], tau[j + 1]};
+                    }
                 } else {
                     em_update<T, V>(a[i], c, p[i], w0, w1, w2, k0d, k1d, k2d, ec, r2, fl, se);
                     vstore<T>(eb + y * N + x, a[i]);
@@ -796,11 +841,11 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
     if constexpr (FWD) {
         __syncthreads();
         const Cx<T> *twf = opaque_ptr(tw);
-        fft_lds<T, H, false, ROWS, 1, NT, N, SeqStride<RS>>(plane, twf, tid);
-        r2c_unpack_rows<T, N, ROWS, NT, true>(plane, twf, tid);
+        fft_lds<T, H, false, ROWS, 1, NT, N, SeqStride<RS>, PMX>(plane, twf, tid);
+        r2c_unpack_rows<T, N, ROWS, NT, true, RS>(plane, twf, tid);
         __syncthreads();
-        fft_lds<T, ROWS, false, H, RS, NT, N, SeqStride<1>>(plane, twf, tid);
-        store_plane<T, N, NT, true>(plane, spec + ((size_t)ch * N + z) * N * H, nyq + ((size_t)ch * N + z) * N,
+        fft_lds<T, ROWS, false, H, RS, NT, N, SeqStride<1>, PMY>(plane, twf, tid);
+        store_plane<T, N, NT, true, RS>(plane, spec + ((size_t)ch * N + z) * N * H, nyq + ((size_t)ch * N + z) * N,
                                     tid);
     }
 }
@@ -915,7 +960,8 @@ __global__ __launch_bounds__(NT) void k_cols(Cx<T> *__restrict__ spec, Cx<T> *__
     table_to_lds<T, N, NT>(tws, twg, tid);
     const Cx<T> *tw = tws;
     __syncthreads();
-    fft_lds<T, N, INV, W, W, NT, N, SeqStride<1>>(buf, tw, tid);
+    fft_lds<T, N, INV, W, W, NT, N, SeqStride<1>, (W % 2 == 0 && sizeof(T) == 4) ? kPairSeq : kPairNone>(buf, tw,
+                                                                                                           tid);
     if (ss == 1) {
         for (int idx = tid; idx < NW; idx += NT) {
             const int ky = idx / W, w = idx - ky * W;
