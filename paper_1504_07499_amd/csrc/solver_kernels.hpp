@@ -433,6 +433,19 @@ template <int N, int W> struct ZTiles {
     static constexpr int PER_LC = MAIN + NYQ;
 };
 
+// Tile of the t-th workgroup of a load case.  When a tile row is shorter than
+// a 128-byte line, the two tiles that share each line (neighbouring kx chunks
+// of one ky, or neighbouring ky groups of the kx = N/2 column) go to
+// workgroups 8 apart: workgroups are dealt round-robin to the 8 XCDs, so both
+// run on one XCD and the second read of the line hits its L2.
+template <typename T, int N, int W> __device__ __forceinline__ int ztile_of(int t) {
+    using TL = ZTiles<N, W>;
+    constexpr bool PAIR = W * (int)sizeof(Cx<T>) < 128 && TL::MAIN % 16 == 0 && TL::NYQ % 16 == 0 &&
+                          (TL::H / W) % 2 == 0;
+    if constexpr (PAIR) return (t & ~15) | ((t & 7) << 1) | ((t >> 3) & 1);
+    return t;
+}
+
 // With red_nper > 0 the first workgroup instead runs the reduction of the
 // previous inverse pass's partials (nper per channel) while the others do
 // the tiles.  The tiles then read the convergence flags as of the iteration
@@ -455,7 +468,7 @@ __global__ __launch_bounds__(NT) void k_zgreen(Cx<T> *__restrict__ spec, Cx<T> *
         return;
     }
     const int bt = blockIdx.x - (red_nper > 0 ? 1 : 0);
-    const int lc = bt / TL::PER_LC, t = bt - lc * TL::PER_LC;
+    const int lc = bt / TL::PER_LC, t = ztile_of<T, N, W>(bt - lc * TL::PER_LC);
     if (__hip_atomic_load(&st->done[lc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     Cx<T> *base;
     size_t cstride, zstride;
@@ -587,7 +600,7 @@ __global__ __launch_bounds__(NT) void k_zeq(const Cx<T> *__restrict__ spec, cons
     __shared__ Cx<T> buf[3 * NW];
     __shared__ double red[2 * (NT / 64)];
     const int tid = threadIdx.x;
-    const int lc = blockIdx.x / TL::PER_LC, t = blockIdx.x - lc * TL::PER_LC;
+    const int lc = blockIdx.x / TL::PER_LC, t = ztile_of<T, N, W>(blockIdx.x - lc * TL::PER_LC);
     if (!st->eq_pending[lc]) return;
     const Cx<T> *base;
     size_t cstride, zstride;
