@@ -451,8 +451,15 @@ template <typename T, int N, int W> __device__ __forceinline__ int ztile_of(int 
 // the tiles.  The tiles then read the convergence flags as of the iteration
 // before: a load case that has just converged may be transformed once more,
 // which is harmless (its spectrum is not used again).
+// Waves per SIMD asked of the z pass: six for FP32 128^3 (8-column tiles,
+// six workgroups per CU fit in LDS; measured faster despite a few spills),
+// otherwise no bound.
+template <typename T, int N, int W> constexpr int zpass_min_waves() {
+    return (sizeof(T) == 4 && N == 128 && W == 8) ? 6 : 1;
+}
+
 template <typename T, int N, int W, int NT>
-__global__ __launch_bounds__(NT) void k_zgreen(Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
+__global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
                                                const Cx<T> *__restrict__ twg,
                                                const DevParams *__restrict__ prm,
                                                DevState *__restrict__ st, const double *__restrict__ part,
