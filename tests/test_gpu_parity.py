@@ -27,7 +27,7 @@ def field_err(a, b):
 
 
 @pytest.mark.parametrize("precision", [1, 0])
-@pytest.mark.parametrize("n", [8, 12, 16, 24, 32, 48, 64])
+@pytest.mark.parametrize("n", [8, 12, 16, 24, 32, 48, 64, 96, 128])
 def test_field_after_fixed_iterations(n, precision):
     """Three iterations from E on an i.i.d. phase image: every voxel of every
     channel matches the oracle (steps 2-7 of the Algorithm end to end)."""
