@@ -62,7 +62,12 @@ template <typename T, int N> struct Instance {
     static constexpr int NTR = 256;
     static constexpr int NPER = FIVE ? N * (N / G) : N * S;
 
-    template <bool PHI> static void fwd_t(const LaunchArgs &a, hipStream_t s) {
+    // lc_sel < 0: all three load cases; else only load case lc_sel (plane and
+    // z grids of that load case alone; the five-pass form launches all and
+    // relies on the frozen-load-case early exit)
+    static int pgrid(int lc_sel) { return (lc_sel < 0 ? 9 : 3) * N * SP; }
+    static int ch0(int lc_sel) { return lc_sel < 0 ? 0 : 3 * lc_sel; }
+    template <bool PHI> static void fwd_t(const LaunchArgs &a, hipStream_t s, int lc_sel) {
         if constexpr (FIVE) {
             hipLaunchKernelGGL((k_fwd_rows<T, N, G, NTR, PHI>), dim3(9 * N * (N / G)), dim3(NTR), 0, s,
                                (const T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq,
@@ -71,25 +76,26 @@ template <typename T, int N> struct Instance {
                                s, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw,
                                (const DevState *)a.st);
         } else {
-            hipLaunchKernelGGL((k_fwd_plane<T, N, SP, NTP, PHI>), dim3(9 * N * SP), dim3(NTP), 0, s,
+            hipLaunchKernelGGL((k_fwd_plane<T, N, SP, NTP, PHI>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s,
                                (const T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq,
-                               (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st);
+                               (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st, ch0(lc_sel));
         }
     }
-    static void fwd(const LaunchArgs &a, hipStream_t s) { fwd_t<false>(a, s); }
-    static void fwd_phi(const LaunchArgs &a, hipStream_t s) { fwd_t<true>(a, s); }
+    static void fwd(const LaunchArgs &a, hipStream_t s, int lc_sel) { fwd_t<false>(a, s, lc_sel); }
+    static void fwd_phi(const LaunchArgs &a, hipStream_t s) { fwd_t<true>(a, s, -1); }
     static void zeq(const LaunchArgs &a, hipStream_t s) {
         hipLaunchKernelGGL((k_zeq<T, N, W, NTZ>), dim3(3 * ZTiles<N, W>::PER_LC), dim3(NTZ), 0, s,
                            (const Cx<T> *)a.spec, (const Cx<T> *)a.nyq, (const Cx<T> *)a.tw,
                            (const DevState *)a.st, a.peq);
     }
     // red_nper > 0: one extra workgroup reduces the previous inverse pass
-    static void zgreen(const LaunchArgs &a, hipStream_t s, int red_nper) {
-        hipLaunchKernelGGL((k_zgreen<T, N, W, NTZ>), dim3(3 * ZTiles<N, W>::PER_LC + (red_nper > 0 ? 1 : 0)),
+    static void zgreen(const LaunchArgs &a, hipStream_t s, int red_nper, int lc_sel) {
+        const int lcs = FIVE || lc_sel < 0 ? 3 : 1;
+        hipLaunchKernelGGL((k_zgreen<T, N, W, NTZ>), dim3(lcs * ZTiles<N, W>::PER_LC + (red_nper > 0 ? 1 : 0)),
                            dim3(NTZ), 0, s, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, a.st,
-                           (const double *)a.part, red_nper, a.hist);
+                           (const double *)a.part, red_nper, a.hist, lcs == 3 ? 0 : lc_sel);
     }
-    static void inv(const LaunchArgs &a, hipStream_t s) {
+    static void inv(const LaunchArgs &a, hipStream_t s, int lc_sel) {
         if constexpr (FIVE) {
             hipLaunchKernelGGL((k_cols<T, N, WC, NTR, true>), dim3(ColTiles<N, WC>::ALL), dim3(NTR), 0, s,
                                (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, (const DevState *)a.st);
@@ -97,19 +103,19 @@ template <typename T, int N> struct Instance {
                                a.ph, (const Cx<T> *)a.spec, (const Cx<T> *)a.nyq, (const Cx<T> *)a.tw,
                                a.prm, (const DevState *)a.st, a.part);
         } else {
-            hipLaunchKernelGGL((k_inv_plane<T, N, SP, NTP>), dim3(9 * N * SP), dim3(NTP), 0, s, (T *)a.e,
+            hipLaunchKernelGGL((k_inv_plane<T, N, SP, NTP>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s, (T *)a.e,
                                a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw,
-                               a.prm, (const DevState *)a.st, a.part);
+                               a.prm, (const DevState *)a.st, a.part, ch0(lc_sel));
         }
     }
     // fused inverse + next forward pass (whole planes in LDS; not where the
     // fused kernel would spill registers heavily: FP32 96^3)
     static constexpr bool FUSED = !FIVE && S == 1 && !(sizeof(T) == 4 && N == 96);
-    static void inv_fwd(const LaunchArgs &a, hipStream_t s) {
+    static void inv_fwd(const LaunchArgs &a, hipStream_t s, int lc_sel) {
         if constexpr (FUSED) {
-            hipLaunchKernelGGL((k_inv_plane<T, N, 1, NTP, true>), dim3(9 * N), dim3(NTP), 0, s, (T *)a.e, a.ph,
-                               (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
-                               (const DevState *)a.st, a.part);
+            hipLaunchKernelGGL((k_inv_plane<T, N, 1, NTP, true>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s, (T *)a.e,
+                               a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
+                               (const DevState *)a.st, a.part, ch0(lc_sel));
         }
     }
     static void init(const LaunchArgs &a, size_t M, hipStream_t s) {

@@ -463,9 +463,12 @@ int Solver::begin(const uint8_t *d_phase, const double k[3], double tol, const S
         const char *f = getenv("RVEHOM_MERGE");
         merge = !eq_check && !(f && f[0] == '0');
     }
+    // a single load case: the iteration kernels run that load case's grid only
+    lc_sel = -1;
+    if (!eq_check && (o.lc_mask == 1 || o.lc_mask == 2 || o.lc_mask == 4)) lc_sel = o.lc_mask == 1 ? 0 : (o.lc_mask == 2 ? 1 : 2);
     if (fused) {
         // the first forward pass; every later one is fused into the inverse pass
-        ops->fwd(a, s);
+        ops->fwd(a, s, lc_sel);
         HIP_CHECK(hipGetLastError());
     }
     return RVE_OK;
@@ -487,9 +490,9 @@ int Solver::launch_iteration(const LaunchArgs &a, hipStream_t s, int mask, hipEv
         const bool timed = (mask >> kk) & 1;
         if (timed) HIP_CHECK(hipEventRecordWithFlags(ev[used], s, hipEventRecordExternal));
         switch (kk) {
-        case 0: ops->fwd(a, s); break;
-        case 1: ops->zgreen(a, s, red_in_z ? ops->nper : 0); break;
-        case 2: fused ? ops->inv_fwd(a, s) : ops->inv(a, s); break;
+        case 0: ops->fwd(a, s, lc_sel); break;
+        case 1: ops->zgreen(a, s, red_in_z ? ops->nper : 0, lc_sel); break;
+        case 2: fused ? ops->inv_fwd(a, s, lc_sel) : ops->inv(a, s, lc_sel); break;
         default: launch_reduce(a, ops->nper, s); break;
         }
         if (timed) {
@@ -526,7 +529,8 @@ static int live_mask(int mask, bool fused) { return fused ? (mask & ~1) : mask; 
 
 // Capture kChunk iterations into a graph on the solver's own stream.
 int Solver::ensure_graph(const uint8_t *d_phase) {
-    if (gexec && g_ws == ws && g_ph == d_phase && g_eq == eq_check && g_fused == fused && g_merge == merge)
+    if (gexec && g_ws == ws && g_ph == d_phase && g_eq == eq_check && g_fused == fused && g_merge == merge &&
+        g_lc == lc_sel)
         return RVE_OK;
     drop_graphs();
     LaunchArgs a = args(d_phase);
@@ -550,6 +554,7 @@ int Solver::ensure_graph(const uint8_t *d_phase) {
     g_eq = eq_check;
     g_fused = fused;
     g_merge = merge;
+    g_lc = lc_sel;
     return RVE_OK;
 }
 
@@ -735,6 +740,94 @@ rve_status worst_status(const rve_result &r, int lc_mask) {
     return (rve_status)worst;
 }
 
+// The three load cases of a solve are independent (Algorithm of Sec. 3 per
+// E = e_j).  Where the iteration kernels can be restricted to one load case
+// (whole or split planes), a full solve runs as three single-load-case solves,
+// each with its own workspace, stream and iteration graph: their kernels
+// overlap on the device (one's memory-bound phases beside another's compute
+// and launch ramps).  The arithmetic per load case is unchanged, so the
+// results equal those of the single-stream solve.
+static bool use_chains(const SolverOps *ops, const SolverOpts &o) {
+    const char *f = getenv("RVEHOM_CHAINS");
+    if (f && f[0] == '0') return false;
+    return ops->split > 0 && o.lc_mask == 7 && !o.eq_check && !o.init_field && !o.out_field && !o.workspace;
+}
+
+struct ChainItem {
+    Solver *sv;
+    const uint8_t *d_phase;
+    hipStream_t stream;
+    int max_iter;
+    int lc;
+    SolverOpts opts;
+    int timing;
+};
+
+static rve_status solve_chains(rve_s *r, const SolverOps *ops, const double k[3], double tol, const SolverOpts &o,
+                               rve_result *out, double *hist, int hist_cap) {
+    Solver &c0 = r->chain[o.precision][0];
+    for (int lc = 0; lc < 3; ++lc) {
+        int rc = r->chain[o.precision][lc].prepare(ops, nullptr, 0);
+        if (rc != RVE_OK) return (rve_status)rc;
+    }
+    hipStream_t s = o.stream ? o.stream : c0.own_stream;
+    HIP_CHECK(hipEventRecord(c0.run_ev[0], s));
+    std::vector<ChainItem> act;
+    for (int lc = 0; lc < 3; ++lc) {
+        Solver &cs = r->chain[o.precision][lc];
+        SolverOpts co = o;
+        co.lc_mask = 1 << lc;
+        co.stream = nullptr;
+        if (cs.own_stream != s) HIP_CHECK(hipStreamWaitEvent(cs.own_stream, c0.run_ev[0], 0));
+        int rc = cs.begin(r->d_phase, k, tol, co, cs.own_stream);
+        if (rc != RVE_OK) return (rve_status)rc;
+        act.push_back({&cs, r->d_phase, cs.own_stream, o.max_iter, lc, co, o.timing});
+    }
+    rve_result res{};
+    rve_kernel_times kt_sum{};
+    std::vector<double> hrow(hist && hist_cap > 0 ? (size_t)3 * hist_cap : 0);
+    int rc = drive(act, [&](ChainItem &a) {
+        rve_result rl{};
+        rve_kernel_times kt{};
+        int c = a.sv->collect(a.opts, a.stream, &rl, hrow.empty() ? nullptr : hrow.data(), hist_cap,
+                              o.timing ? &kt : nullptr);
+        if (c != RVE_OK) return c;
+        const int j = a.lc;
+        for (int i = 0; i < 3; ++i) res.K[3 * i + j] = rl.K[3 * i + j];  // column j = load case e_j
+        res.iters[j] = rl.iters[j];
+        res.status[j] = rl.status[j];
+        res.final_residual[j] = rl.final_residual[j];
+        res.eps_eq[j] = rl.eps_eq[j];
+        if (!hrow.empty())
+            std::memcpy(hist + (size_t)j * hist_cap, hrow.data() + (size_t)j * hist_cap, hist_cap * sizeof(double));
+        if (o.timing) {
+            for (int q = 0; q < 4; ++q) {
+                kt_sum.name[q] = kt.name[q];
+                kt_sum.total_ms[q] += kt.total_ms[q];
+                kt_sum.launches[q] += kt.launches[q];
+                kt_sum.total_bytes[q] += kt.total_bytes[q];
+            }
+        }
+        return (int)RVE_OK;
+    });
+    if (rc != RVE_OK) return (rve_status)rc;
+    // join: the caller's stream continues after every load case's work
+    for (int lc = 0; lc < 3; ++lc) {
+        Solver &cs = r->chain[o.precision][lc];
+        if (cs.own_stream == s) continue;
+        HIP_CHECK(hipEventRecord(cs.run_ev[1], cs.own_stream));
+        HIP_CHECK(hipStreamWaitEvent(s, cs.run_ev[1], 0));
+    }
+    HIP_CHECK(hipEventRecord(c0.run_ev[1], s));
+    HIP_CHECK(hipEventSynchronize(c0.run_ev[1]));
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, c0.run_ev[0], c0.run_ev[1]));
+    res.solve_ms = ms;
+    if (o.timing) r->times = kt_sum;
+    if (out) *out = res;
+    return worst_status(res, o.lc_mask);
+}
+
 // One RVE, start to finish, on stream s.
 rve_status solve_one(rve_s *r, const double k[3], double tol, const SolverOpts &o, rve_result *out,
                      double *hist, int hist_cap) {
@@ -746,6 +839,11 @@ rve_status solve_one(rve_s *r, const double k[3], double tol, const SolverOpts &
     int cur = 0;
     HIP_CHECK(hipGetDevice(&cur));
     if (cur != r->device) HIP_CHECK(hipSetDevice(r->device));
+    if (use_chains(ops, o)) {
+        rve_status st = solve_chains(r, ops, k, tol, o, out, hist, hist_cap);
+        if (cur != r->device) HIP_CHECK(hipSetDevice(cur));
+        return st;
+    }
     Solver &sv = r->sol[o.precision];
     int rc = sv.prepare(ops, o.workspace, o.workspace_bytes);
     if (rc != RVE_OK) return (rve_status)rc;

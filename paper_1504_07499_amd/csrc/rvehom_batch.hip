@@ -26,50 +26,6 @@
 
 namespace rvehom {
 
-// Drive already-begun solvers to completion, interleaving their chunks.
-// done_cb(i) is called once per finished solver (after its results are in).
-template <class Active, class Finish>
-static int drive(std::vector<Active> &act, Finish finish) {
-    while (!act.empty()) {
-        for (auto &a : act) {
-            Solver &sv = *a.sv;
-            if ((int)sv.inflight.size() < kLookahead && sv.issued < a.max_iter) {
-                int rc = sv.enqueue(a.d_phase, kChunk, a.max_iter, 0, a.stream);
-                if (rc != RVE_OK) return rc;
-            }
-        }
-        bool any = false;
-        for (size_t i = 0; i < act.size();) {
-            int rc = act[i].sv->poll(false, act[i].max_iter);
-            if (rc < 0) return rc;
-            if (rc == 1) {
-                rc = finish(act[i]);
-                if (rc != RVE_OK) return rc;
-                act.erase(act.begin() + i);
-                any = true;
-            } else {
-                ++i;
-            }
-        }
-        if (!any && !act.empty()) {
-            // every solver is ahead by kLookahead chunks: wait for the oldest
-            bool all_full = true;
-            for (auto &a : act)
-                if ((int)a.sv->inflight.size() < kLookahead && a.sv->issued < a.max_iter) all_full = false;
-            if (all_full) {
-                int rc = act[0].sv->poll(true, act[0].max_iter);
-                if (rc < 0) return rc;
-                if (rc == 1) {
-                    rc = finish(act[0]);
-                    if (rc != RVE_OK) return rc;
-                    act.erase(act.begin());
-                }
-            }
-        }
-    }
-    return RVE_OK;
-}
-
 struct BatchItem {
     Solver *sv;
     const uint8_t *d_phase;
@@ -77,6 +33,7 @@ struct BatchItem {
     int max_iter;
     int index;
     SolverOpts opts;
+    int timing;  // kernel timing mask (none in batches)
 };
 
 rve_status batch_solve(int count, const rve_t *rves, const double *k, const double *tol, const SolverOpts &o,
@@ -89,7 +46,7 @@ rve_status batch_solve(int count, const rve_t *rves, const double *k, const doub
         if (rc != RVE_OK) return (rve_status)rc;
         rc = sv.begin(r->d_phase, k + 3 * i, tol[i], o, sv.own_stream);
         if (rc != RVE_OK) return (rve_status)rc;
-        act.push_back({&sv, r->d_phase, sv.own_stream, o.max_iter, i, o});
+        act.push_back({&sv, r->d_phase, sv.own_stream, o.max_iter, i, o, 0});
     }
     rve_status worst = RVE_OK;
     int rc = drive(act, [&](BatchItem &a) {

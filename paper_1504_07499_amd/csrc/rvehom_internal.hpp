@@ -75,6 +75,7 @@ struct Solver {
     bool eq_check = false;
     bool fused = false;  // iterations run zgreen + fused inverse/forward + reduce
     bool merge = false;  // each reduction runs inside the next iteration's z pass
+    int lc_sel = -1;     // -1: all load cases; else the only load case iterated
     const uint8_t *d_phase_last = nullptr;
     // captured graph of kChunk iterations (kernels only; all parameters are
     // read from device memory, so one graph serves every call on this workspace)
@@ -84,6 +85,7 @@ struct Solver {
     bool g_eq = false;
     bool g_fused = false;
     bool g_merge = false;
+    int g_lc = -1;
     bool use_graphs = true;
     // timed variants: one graph per poll slot (its own events), per mask
     hipGraphExec_t tgexec[kPollSlots] = {};
@@ -119,6 +121,50 @@ rve_status solve_one(struct ::rve_s *r, const double k[3], double tol, const Sol
 rve_status batch_solve(int count, const rve_t *rves, const double *k, const double *tol, const SolverOpts &o,
                        rve_result *out);
 
+// Drive already-begun solvers to completion, interleaving their chunks.
+// finish(item) is called once per finished solver.
+template <class Active, class Finish>
+inline int drive(std::vector<Active> &act, Finish finish) {
+    while (!act.empty()) {
+        for (auto &a : act) {
+            Solver &sv = *a.sv;
+            if ((int)sv.inflight.size() < kLookahead && sv.issued < a.max_iter) {
+                int rc = sv.enqueue(a.d_phase, kChunk, a.max_iter, a.timing, a.stream);
+                if (rc != RVE_OK) return rc;
+            }
+        }
+        bool any = false;
+        for (size_t i = 0; i < act.size();) {
+            int rc = act[i].sv->poll(false, act[i].max_iter);
+            if (rc < 0) return rc;
+            if (rc == 1) {
+                rc = finish(act[i]);
+                if (rc != RVE_OK) return rc;
+                act.erase(act.begin() + i);
+                any = true;
+            } else {
+                ++i;
+            }
+        }
+        if (!any && !act.empty()) {
+            // every solver is ahead by kLookahead chunks: wait for the oldest
+            bool all_full = true;
+            for (auto &a : act)
+                if ((int)a.sv->inflight.size() < kLookahead && a.sv->issued < a.max_iter) all_full = false;
+            if (all_full) {
+                int rc = act[0].sv->poll(true, act[0].max_iter);
+                if (rc < 0) return rc;
+                if (rc == 1) {
+                    rc = finish(act[0]);
+                    if (rc != RVE_OK) return rc;
+                    act.erase(act.begin());
+                }
+            }
+        }
+    }
+    return RVE_OK;
+}
+
 }  // namespace rvehom
 
 struct rve_s {
@@ -131,5 +177,8 @@ struct rve_s {
     double layer = 0.0;
     int method = -1;
     rvehom::Solver sol[2];
+    // per precision, one solver per load case: a full solve runs as three
+    // concurrent single-load-case solves on their own streams
+    rvehom::Solver chain[2][3];
     rve_kernel_times times{};
 };

@@ -322,7 +322,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
                                                   Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
                                                   const Cx<T> *__restrict__ twg,
                                                   const DevParams *__restrict__ prm,
-                                                  const DevState *__restrict__ st) {
+                                                  const DevState *__restrict__ st, int ch0) {
     // row pitch: even for whole planes (16-byte pair accesses, paired FFT
     // stages), N/2 + 1 for split planes
     constexpr int H = N / 2, RS = (S == 1) ? H + 2 : H + 1, ROWS = N / S, V = VecOf<T>::V, NN = N * N;
@@ -335,6 +335,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
     const int tid = threadIdx.x;
     int ch, z, h;
     plane_of_block<N, S>(blockIdx.x, ch, z, h);
+    ch += ch0;  // the grid covers channels ch0 .. (all nine, or one load case's three)
     const int lc = ch / 3;
     // PHI: the flux k e of the equilibrium check (step 1); else tau = (k - k0) e
     if (PHI ? !st->eq_pending[lc] : st->done[lc]) return;
@@ -463,7 +464,7 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
                                                const Cx<T> *__restrict__ twg,
                                                const DevParams *__restrict__ prm,
                                                DevState *__restrict__ st, const double *__restrict__ part,
-                                               int red_nper, double *__restrict__ hist) {
+                                               int red_nper, double *__restrict__ hist, int lc0) {
     using TL = ZTiles<N, W>;
     constexpr int H = N / 2, NW = N * W;
     static_assert(H % W == 0 && N % W == 0 && W % 2 == 0, "tile width must be even and divide N/2");
@@ -475,7 +476,8 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
         return;
     }
     const int bt = blockIdx.x - (red_nper > 0 ? 1 : 0);
-    const int lc = bt / TL::PER_LC, t = ztile_of<T, N, W>(bt - lc * TL::PER_LC);
+    const int lt = bt / TL::PER_LC, t = ztile_of<T, N, W>(bt - lt * TL::PER_LC);
+    const int lc = lc0 + lt;  // the grid covers load cases lc0 .. (all three, or one)
     if (__hip_atomic_load(&st->done[lc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     Cx<T> *base;
     size_t cstride, zstride;
@@ -692,7 +694,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
                                                   const Cx<T> *__restrict__ twg,
                                                   const DevParams *__restrict__ prm,
                                                   const DevState *__restrict__ st,
-                                                  double *__restrict__ part) {
+                                                  double *__restrict__ part, int ch0) {
     static_assert(!FWD || S == 1, "the fused inverse/forward pass needs a whole plane");
     // row pitch: even for whole planes (16-byte pair accesses, paired FFT
     // stages), N/2 + 1 for split planes
@@ -710,6 +712,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
     const int tid = threadIdx.x;
     int ch, z, h;
     plane_of_block<N, S>(blockIdx.x, ch, z, h);
+    ch += ch0;  // the grid covers channels ch0 .. (all nine, or one load case's three)
     const int lc = ch / 3;
     if (st->done[lc]) return;
     const T ec = (ch % 4 == 0) ? (T)1 : (T)0;  // E_comp of this channel (ch = 3 lc + comp)

@@ -40,12 +40,13 @@ struct SolverOps {
     int eq_tiles;        // k_zeq blocks per load case
     double bytes_fused;  // algorithmic bytes of one fused inverse + forward launch
     // fused inverse pass + next forward pass, or nullptr where planes are split
-    void (*inv_fwd)(const LaunchArgs &, hipStream_t);
-    void (*fwd)(const LaunchArgs &, hipStream_t);
+    // lc_sel: -1 = all three load cases, else the one load case to iterate
+    void (*inv_fwd)(const LaunchArgs &, hipStream_t, int lc_sel);
+    void (*fwd)(const LaunchArgs &, hipStream_t, int lc_sel);
     void (*fwd_phi)(const LaunchArgs &, hipStream_t);
     void (*zeq)(const LaunchArgs &, hipStream_t);
-    void (*zgreen)(const LaunchArgs &, hipStream_t, int red_nper);
-    void (*inv)(const LaunchArgs &, hipStream_t);
+    void (*zgreen)(const LaunchArgs &, hipStream_t, int red_nper, int lc_sel);
+    void (*inv)(const LaunchArgs &, hipStream_t, int lc_sel);
     void (*init)(const LaunchArgs &, size_t M, hipStream_t);
     void (*from_f64)(void *e, const double *src, size_t count, hipStream_t);
     void (*to_f64)(double *dst, const void *e, size_t count, hipStream_t);

@@ -139,19 +139,28 @@ def test_server_results_match_alone():
 
 def test_kernel_timing_does_not_change_results():
     """Events recorded inside the replayed graphs: same tensor, one timed
-    launch per working iteration, positive durations."""
+    launch per working iteration (single stream), positive durations; with
+    the three load-case chains each chain times its own launches."""
+    import os
+
     print("\n[case] kernel timing", flush=True)
     ph, _, _ = geom.generate(48, 10, 0.25, 0.2, 8)
     with rh.rve_create_from_phases(ph) as r:
-        plain = rh.homogenize(r, K3, 1e-6, precision=0)
-        timed = rh.homogenize(r, K3, 1e-6, precision=0, timing=True)
-        kt = rh.rve_get_kernel_times(r)
-        only = rh.homogenize(r, K3, 1e-6, precision=0, timing=4)
-        kt4 = rh.rve_get_kernel_times(r)
-        sampled = rh.homogenize(r, K3, 1e-6, precision=0, timing=4 | 16)
-        kts = rh.rve_get_kernel_times(r)
+        os.environ["RVEHOM_CHAINS"] = "0"
+        try:
+            plain = rh.homogenize(r, K3, 1e-6, precision=0)
+            timed = rh.homogenize(r, K3, 1e-6, precision=0, timing=True)
+            kt = rh.rve_get_kernel_times(r)
+            only = rh.homogenize(r, K3, 1e-6, precision=0, timing=4)
+            kt4 = rh.rve_get_kernel_times(r)
+            sampled = rh.homogenize(r, K3, 1e-6, precision=0, timing=4 | 16)
+            kts = rh.rve_get_kernel_times(r)
+        finally:
+            os.environ.pop("RVEHOM_CHAINS", None)
+        chained = rh.homogenize(r, K3, 1e-6, precision=0, timing=True)
+        ktc = rh.rve_get_kernel_times(r)
     assert np.array_equal(plain.K, timed.K) and np.array_equal(plain.K, only.K)
-    assert np.array_equal(plain.K, sampled.K)
+    assert np.array_equal(plain.K, sampled.K) and np.array_equal(plain.K, chained.K)
     # sampled: one batch of iterations in four carries events
     assert 0 < kts[list(kts)[2]]["launches"] < int(plain.iters.max())
     assert kts[list(kts)[2]]["total_ms"] > 0
@@ -160,6 +169,9 @@ def test_kernel_timing_does_not_change_results():
     for name in names[1:]:
         assert kt[name]["launches"] == int(plain.iters.max())
         assert kt[name]["total_ms"] > 0
+        # chains: every load case launches its own kernels
+        assert ktc[name]["launches"] == int(plain.iters.sum())
+        assert ktc[name]["total_ms"] > 0
     assert kt4[names[2]]["launches"] == int(plain.iters.max())
     assert kt4["zgreen"]["launches"] == 0
 
@@ -180,3 +192,30 @@ def test_fused_pass_matches_separate_passes():
             os.environ.pop("RVEHOM_FUSED", None)
     assert np.array_equal(fused.iters, sep.iters)
     assert np.abs(fused.K - sep.K).max() <= 1e-12 * np.abs(sep.K).max()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_load_case_chains_match_single_stream(precision):
+    """A full solve runs as three concurrent single-load-case solves (own
+    streams and graphs); tensor, iteration counts and histories equal those
+    of the single-stream solve of all three load cases."""
+    import os
+
+    print(f"\n[case] chains vs single stream precision={precision}", flush=True)
+    ph, _, _ = geom.generate(64, 12, 0.3, 0.2, 23)
+    with rh.rve_create_from_phases(ph) as r:
+        chained = rh.homogenize(r, K3, 1e-6, precision=precision, hist_cap=512)
+        os.environ["RVEHOM_CHAINS"] = "0"
+        try:
+            single = rh.homogenize(r, K3, 1e-6, precision=precision, hist_cap=512)
+        finally:
+            os.environ.pop("RVEHOM_CHAINS", None)
+        one = rh.homogenize(r, K3, 1e-6, precision=precision, lc_mask=2)
+    assert np.array_equal(chained.K, single.K)
+    assert np.array_equal(chained.iters, single.iters)
+    assert np.array_equal(chained.lc_status, single.lc_status)
+    for j in range(3):
+        n = int(single.iters[j])
+        np.testing.assert_array_equal(chained.history[j][:n], single.history[j][:n])
+    # a single load case (its own grid) gives that column exactly
+    assert np.array_equal(one.K[:, 1], single.K[:, 1]) and int(one.iters[1]) == int(single.iters[1])
