@@ -128,7 +128,13 @@ rve_status rve_get_spheres(rve_t rve, double *xyzr, int cap, int *count, double 
 /* Grid size of an RVE. */
 int rve_n(rve_t rve);
 
-/* Device workspace bytes homogenize needs for this RVE and precision. */
+/* Device workspace bytes homogenize needs for this RVE and precision (one
+ * workspace: a caller-provided one, or one solve of a single load case).  A
+ * solve of all three load cases without a caller workspace, without the
+ * two-stage stop and without a start or final field, on a grid whose
+ * xy-planes fit in LDS (whole or split; not FP64 256^3 or 512^3), runs the
+ * load cases as three concurrent chains and allocates three such workspaces
+ * (cached on the handle until rve_destroy); the results are the same. */
 size_t rve_workspace_size(rve_t rve, int precision);
 
 /* The Algorithm of Sec. 3 for the three load cases, on the GPU.
