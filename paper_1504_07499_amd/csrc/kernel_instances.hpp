@@ -34,6 +34,18 @@ template <typename T, int N> constexpr int ztile() {
     return ztile_cap<T, N>(64 * 1024) >= 8 ? ztile_cap<T, N>(64 * 1024) : ztile_cap<T, N>(96 * 1024);
 }
 
+// The other z-tile width the autotuner tries: half the default where that
+// still divides N/2 (even, >= 2), else double it where that fits; the
+// default itself if neither exists.  The z transform of a pencil does not
+// depend on how many pencils a tile holds, so both give identical results.
+template <typename T, int N> constexpr int ztile_alt() {
+    constexpr int W = ztile<T, N>();
+    if constexpr (W / 2 >= 2 && (W / 2) % 2 == 0 && (N / 2) % (W / 2) == 0) return W / 2;
+    if constexpr (2 * W <= 16 && (N / 2) % (2 * W) == 0 && (size_t)3 * N * 2 * W * sizeof(Cx<T>) <= 96 * 1024)
+        return 2 * W;
+    return W;
+}
+
 // Five-pass form: rows per block of the x passes, columns per block of the y passes.
 template <typename T, int N> constexpr int row_group() { return N >= 16 ? 16 : N; }
 template <typename T, int N> constexpr int col_tile() {
@@ -55,6 +67,7 @@ template <typename T, int N> struct Instance {
     static constexpr bool FIVE = (S == 0);  // plane does not fit in LDS
     static constexpr int SP = FIVE ? 1 : S;
     static constexpr int W = ztile<T, N>();
+    static constexpr int W2 = ztile_alt<T, N>();
     static constexpr int NTP = plane_threads<T, N>();
     static constexpr int NTZ = 256;
     static constexpr int G = row_group<T, N>();
@@ -89,11 +102,17 @@ template <typename T, int N> struct Instance {
                            (const DevState *)a.st, a.peq);
     }
     // red_nper > 0: one extra workgroup reduces the previous inverse pass
-    static void zgreen(const LaunchArgs &a, hipStream_t s, int red_nper, int lc_sel) {
+    template <int WV> static void zgreen_w(const LaunchArgs &a, hipStream_t s, int red_nper, int lc_sel) {
         const int lcs = FIVE || lc_sel < 0 ? 3 : 1;
-        hipLaunchKernelGGL((k_zgreen<T, N, W, NTZ>), dim3(lcs * ZTiles<N, W>::PER_LC + (red_nper > 0 ? 1 : 0)),
+        hipLaunchKernelGGL((k_zgreen<T, N, WV, NTZ>), dim3(lcs * ZTiles<N, WV>::PER_LC + (red_nper > 0 ? 1 : 0)),
                            dim3(NTZ), 0, s, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, a.st,
                            (const double *)a.part, red_nper, a.hist, lcs == 3 ? 0 : lc_sel);
+    }
+    static void zgreen(const LaunchArgs &a, hipStream_t s, int red_nper, int lc_sel) {
+        zgreen_w<W>(a, s, red_nper, lc_sel);
+    }
+    static void zgreen_alt(const LaunchArgs &a, hipStream_t s, int red_nper, int lc_sel) {
+        zgreen_w<W2>(a, s, red_nper, lc_sel);
     }
     static void inv(const LaunchArgs &a, hipStream_t s, int lc_sel) {
         if constexpr (FIVE) {
@@ -158,6 +177,8 @@ template <typename T, int N> struct Instance {
             &fwd_phi,
             &zeq,
             &zgreen,
+            W2,
+            W2 != W ? &zgreen_alt : nullptr,
             &inv,
             &init,
             &from_f64,

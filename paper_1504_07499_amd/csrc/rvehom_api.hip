@@ -15,6 +15,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -427,6 +429,51 @@ SolverOpts resolve_opts(const rve_opts *opts) {
 }
 
 // Enqueue init (and optional warm start) on s.
+// Autotuner: the first solve of each (precision, N) in the process times the
+// z pass at its two tile widths on this workspace (before the first forward
+// pass overwrites the spectrum) and keeps the faster; differences under 3 %
+// keep the default.  The z transform of a pencil does not depend on the tile
+// width, so the choice never changes a result.  RVEHOM_ZTILE=0 / 1 forces the
+// default / the other width.
+static std::mutex g_tune_mu;
+static std::map<const SolverOps *, int> g_ztune;
+
+int Solver::tune_zpass(const LaunchArgs &a, hipStream_t s) {
+    zvar = 0;
+    if (!ops->zgreen_alt) return RVE_OK;
+    const char *f = getenv("RVEHOM_ZTILE");
+    if (f && (f[0] == '0' || f[0] == '1')) {
+        zvar = f[0] - '0';
+        return RVE_OK;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_ztune.find(ops);
+        if (it != g_ztune.end()) {
+            zvar = it->second;
+            return RVE_OK;
+        }
+    }
+    hipEvent_t ev[3];
+    for (auto &e : ev) HIP_CHECK(hipEventCreate(&e));
+    constexpr int reps = 6;
+    ops->zgreen(a, s, 0, -1);  // first launches (code load) outside the timing
+    ops->zgreen_alt(a, s, 0, -1);
+    HIP_CHECK(hipEventRecord(ev[0], s));
+    for (int i = 0; i < reps; ++i) ops->zgreen(a, s, 0, -1);
+    HIP_CHECK(hipEventRecord(ev[1], s));
+    for (int i = 0; i < reps; ++i) ops->zgreen_alt(a, s, 0, -1);
+    HIP_CHECK(hipEventRecord(ev[2], s));
+    HIP_CHECK(hipEventSynchronize(ev[2]));
+    float t0 = 0.f, t1 = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&t0, ev[0], ev[1]));
+    HIP_CHECK(hipEventElapsedTime(&t1, ev[1], ev[2]));
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    zvar = g_ztune.emplace(ops, t1 < 0.97f * t0 ? 1 : 0).first->second;
+    return RVE_OK;
+}
+
 int Solver::begin(const uint8_t *d_phase, const double k[3], double tol, const SolverOpts &o, hipStream_t s) {
     d_phase_last = d_phase;
     int rc = ensure_twiddles(s);
@@ -438,6 +485,8 @@ int Solver::begin(const uint8_t *d_phase, const double k[3], double tol, const S
     const size_t M = (size_t)ops->n * ops->n * ops->n;
     ops->init(a, M, s);
     HIP_CHECK(hipGetLastError());
+    rc = tune_zpass(a, s);
+    if (rc != RVE_OK) return rc;
     if (o.init_field) {
         // stage the FP64 field through the spectrum buffer region if it fits,
         // else through a temporary device buffer
@@ -491,7 +540,7 @@ int Solver::launch_iteration(const LaunchArgs &a, hipStream_t s, int mask, hipEv
         if (timed) HIP_CHECK(hipEventRecordWithFlags(ev[used], s, hipEventRecordExternal));
         switch (kk) {
         case 0: ops->fwd(a, s, lc_sel); break;
-        case 1: ops->zgreen(a, s, red_in_z ? ops->nper : 0, lc_sel); break;
+        case 1: (zvar ? ops->zgreen_alt : ops->zgreen)(a, s, red_in_z ? ops->nper : 0, lc_sel); break;
         case 2: fused ? ops->inv_fwd(a, s, lc_sel) : ops->inv(a, s, lc_sel); break;
         default: launch_reduce(a, ops->nper, s); break;
         }
@@ -530,7 +579,7 @@ static int live_mask(int mask, bool fused) { return fused ? (mask & ~1) : mask; 
 // Capture kChunk iterations into a graph on the solver's own stream.
 int Solver::ensure_graph(const uint8_t *d_phase) {
     if (gexec && g_ws == ws && g_ph == d_phase && g_eq == eq_check && g_fused == fused && g_merge == merge &&
-        g_lc == lc_sel)
+        g_lc == lc_sel && g_zvar == zvar)
         return RVE_OK;
     drop_graphs();
     LaunchArgs a = args(d_phase);
@@ -555,6 +604,7 @@ int Solver::ensure_graph(const uint8_t *d_phase) {
     g_fused = fused;
     g_merge = merge;
     g_lc = lc_sel;
+    g_zvar = zvar;
     return RVE_OK;
 }
 

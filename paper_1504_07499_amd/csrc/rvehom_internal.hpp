@@ -76,6 +76,7 @@ struct Solver {
     bool fused = false;  // iterations run zgreen + fused inverse/forward + reduce
     bool merge = false;  // each reduction runs inside the next iteration's z pass
     int lc_sel = -1;     // -1: all load cases; else the only load case iterated
+    int zvar = 0;        // z-pass tile width: 0 default, 1 the other (autotuned)
     const uint8_t *d_phase_last = nullptr;
     // captured graph of kChunk iterations (kernels only; all parameters are
     // read from device memory, so one graph serves every call on this workspace)
@@ -86,6 +87,7 @@ struct Solver {
     bool g_fused = false;
     bool g_merge = false;
     int g_lc = -1;
+    int g_zvar = 0;
     bool use_graphs = true;
     // timed variants: one graph per poll slot (its own events), per mask
     hipGraphExec_t tgexec[kPollSlots] = {};
@@ -97,6 +99,7 @@ struct Solver {
     LaunchArgs args(const uint8_t *d_phase) const;
     int ensure_twiddles(hipStream_t s);
     int begin(const uint8_t *d_phase, const double k[3], double tol, const SolverOpts &o, hipStream_t s);
+    int tune_zpass(const LaunchArgs &a, hipStream_t s);
     int enqueue(const uint8_t *d_phase, int count, int max_iter, int timing, hipStream_t s);
     int launch_iteration(const LaunchArgs &a, hipStream_t s, int mask, hipEvent_t *ev, bool red_in_z,
                          bool defer_red);

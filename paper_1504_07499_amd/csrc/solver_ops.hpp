@@ -46,6 +46,8 @@ struct SolverOps {
     void (*fwd_phi)(const LaunchArgs &, hipStream_t);
     void (*zeq)(const LaunchArgs &, hipStream_t);
     void (*zgreen)(const LaunchArgs &, hipStream_t, int red_nper, int lc_sel);
+    int ztile_alt;  // the other z-tile width the autotuner tries
+    void (*zgreen_alt)(const LaunchArgs &, hipStream_t, int red_nper, int lc_sel);  // or nullptr
     void (*inv)(const LaunchArgs &, hipStream_t, int lc_sel);
     void (*init)(const LaunchArgs &, size_t M, hipStream_t);
     void (*from_f64)(void *e, const double *src, size_t count, hipStream_t);

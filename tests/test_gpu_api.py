@@ -219,3 +219,24 @@ def test_load_case_chains_match_single_stream(precision):
         np.testing.assert_array_equal(chained.history[j][:n], single.history[j][:n])
     # a single load case (its own grid) gives that column exactly
     assert np.array_equal(one.K[:, 1], single.K[:, 1]) and int(one.iters[1]) == int(single.iters[1])
+
+
+@pytest.mark.parametrize("n,precision", [(64, 0), (128, 0), (64, 1)])
+def test_z_tile_widths_give_identical_results(n, precision):
+    """The autotuner picks one of two z-tile widths per grid size; both give
+    bitwise the same result (the z transform of a pencil does not depend on
+    how many pencils a tile holds)."""
+    import os
+
+    print(f"\n[case] z tile widths n={n} precision={precision}", flush=True)
+    ph, _, _ = geom.generate(n, 12, 0.3, 0.2, 31)
+    out = []
+    with rh.rve_create_from_phases(ph) as r:
+        for v in ("0", "1"):
+            os.environ["RVEHOM_ZTILE"] = v
+            try:
+                out.append(rh.homogenize(r, K3, 1e-6, precision=precision, max_iter=60))
+            finally:
+                os.environ.pop("RVEHOM_ZTILE", None)
+    assert np.array_equal(out[0].K, out[1].K)
+    assert np.array_equal(out[0].iters, out[1].iters)
