@@ -271,20 +271,26 @@ template <typename E> __device__ __forceinline__ const E *opaque_ptr(const E *p)
 // sum tau in FP64: k e+ = (tau + tm) + k0 e+, so the caller adds
 // count * tm + k0 * (sum e+) -- no per-voxel FP64 conductivity lookup.
 // lut[phase] = {w, k - k0} (LDS).
+// The V neighbouring voxels' terms are summed in the working precision, then
+// accumulated in FP64 (a V-term FP32 sum adds ~1e-7 relative error).
 template <typename T, int V>
 __device__ __forceinline__ void em_update_tau(T *a, const T *c, unsigned p, const Cx<T> *lut, T tm, T ec,
                                               double &r2, double &st, double &se, T *tau) {
+    T r2v = (T)0, stv = (T)0, sev = (T)0;
 #pragma unroll
     for (int i = 0; i < V; ++i) {
         const T ci = c[i] + ec;
         const T d = a[i] - ci;
-        r2 += (double)d * (double)d;
+        r2v += d * d;
         const Cx<T> wd = lut[ph_at(p, i)];
         a[i] = a[i] + wd.x * (ci - a[i]);
         tau[i] = wd.y * a[i] - tm;
-        st += (double)tau[i];
-        se += (double)a[i];
+        stv += tau[i];
+        sev += a[i];
     }
+    r2 += (double)r2v;
+    st += (double)stv;
+    se += (double)sev;
 }
 
 // Waves per SIMD asked of the plane kernels: as many workgroups per CU as
