@@ -85,10 +85,11 @@ __device__ __forceinline__ void reduce_block(const double *__restrict__ part, in
                 fin = 1;
                 status = ST_STALLED;
             }
-            // FP32 rounding floor: within 100 tol, less than 5 % progress in
-            // 10 iterations (the contraction gives far more) also stalls
-            if (!fin && prm->stall_window > 0 && it >= 10 && it - 10 < prm->hist_cap &&
-                eps < 100.0 * prm->tol && eps > 0.95 * hist[lc * prm->hist_cap + it - 10]) {
+            // FP32 rounding floor: within 100 tol, the last 10 iterations
+            // gained less than a quarter of the least progress the scheme's
+            // contraction bound allows (1 - rho^10)
+            if (!fin && prm->stall_window > 0 && it >= 10 && it - 10 < prm->hist_cap && eps < 100.0 * prm->tol &&
+                eps > (1.0 - 0.25 * prm->prog10) * hist[lc * prm->hist_cap + it - 10]) {
                 fin = 1;
                 status = ST_STALLED;
             }

@@ -400,6 +400,11 @@ void fill_params(DevParams &p, const double k[3], double tol, int n, const Solve
         p.w[i] = o.scheme == 1 ? 1.0 : 2.0 * k0 / (k[i] + k0);
     }
     p.k0 = k0;
+    // contraction bound of the scheme at contrast c = kmax / kmin: Eyre-Milton
+    // (sqrt c - 1) / (sqrt c + 1), basic scheme (c - 1) / (c + 1)
+    const double c = kmax / kmin;
+    const double rho = o.scheme == 1 ? (c - 1.0) / (c + 1.0) : (std::sqrt(c) - 1.0) / (std::sqrt(c) + 1.0);
+    p.prog10 = 1.0 - std::pow(rho, 10.0);
     p.inv_k0M = 1.0 / (k0 * M);
     p.tol = tol;
     p.invM = 1.0 / M;

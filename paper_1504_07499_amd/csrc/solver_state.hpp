@@ -13,6 +13,7 @@ struct DevParams {
     double inv_k0M;  // 1 / (k0 M): Green scale with the 1/M of the inverse folded in
     double tol;
     double invM;
+    double prog10;  // 1 - rho^10: least progress of 10 iterations the scheme's contraction bound allows
     int max_iter;
     int stall_window;  // 0 = off
     int hist_cap;
