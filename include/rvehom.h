@@ -104,7 +104,7 @@ typedef struct {
     double total_bytes[4];
 } rve_kernel_times;
 
-/* Grid sizes N this build supports for a precision (0 FP32, 1 FP64).
+/* Grid sizes N the library supports for a precision (0 FP32, 1 FP64).
  * out: up to cap ints; count receives the number. */
 rve_status rve_supported_n(int precision, int *out, int cap, int *count);
 

@@ -1,5 +1,5 @@
 // kernels_common.hip -- precision-independent kernels (the FP64 convergence
-// reduction) and the list of grid sizes compiled into this build.
+// reduction) and the list of grid sizes compiled into the library.
 #include <hip/hip_runtime.h>
 
 #include "reduce_block.hpp"

@@ -60,7 +60,7 @@ void launch_reduce(const LaunchArgs &a, int nper, hipStream_t s);
 void launch_eq_reduce(const LaunchArgs &a, int per_lc, int final, hipStream_t s);
 void launch_eq_request(const LaunchArgs &a, hipStream_t s);
 
-// Sizes compiled into this build (ascending), per precision.
+// Grid sizes compiled into the library (ascending), per precision.
 int supported_sizes(int precision, const int **list);
 
 }  // namespace rvehom
