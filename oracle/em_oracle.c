@@ -314,7 +314,23 @@ void orc_set_threads(int t)
  *             K column, iters and residual zero
  *  scheme     0 = the accelerated scheme of the Algorithm (k0 of Sec. 5);
  *             1 = the basic scheme named in Sec. 3 as an alternative:
- *             e+ = grad theta_comp, with k0 = (min k + max k) / 2
+ *             e+ = grad theta_comp, with k0 = (min k + max k) / 2;
+ *             2 = the augmented-Lagrangian scheme named in Sec. 3 (k0 of
+ *             Sec. 5), for this linear problem the alternating minimisation
+ *             of  1/2 <d.k d> + <lam.(e - d)> + k0/2 <|e - d|^2>  over the
+ *             local field d, the compatible field e (mean E) and the
+ *             multiplier lam:
+ *                 d    = (lam + k0 e) / (k + k0)
+ *                 e+   = E + P(d - lam / k0)     (P: projection on gradients,
+ *                                                 the Green operator times k0)
+ *                 lam+ = lam + k0 (e+ - d)
+ *             from d = e = E, lam = k E (the first transform is then that of
+ *             the accelerated scheme); per iteration the compatible step,
+ *             the residual sqrt(<|e+ - d|^2>), the multiplier step and the
+ *             local step of the new pair (lam+, e+), whose flux <k d+> is the
+ *             tensor column; out_field returns d.  eq_check is not used.
+ *             Parity unpinned against the cited work (its equations are not
+ *             in the paper); pinned by the same closed forms as the others.
  */
 int orc_homogenize(int n, const uint8_t *phase, const double kph[3], double tol,
                    int max_iter, int eq_check, const double *init_field,
@@ -329,7 +345,7 @@ int orc_homogenize(int n, const uint8_t *phase, const double kph[3], double tol,
     for (size_t v = 0; v < M; ++v)
         if (phase[v] > 2) return ORC_ERR_ARG;
 
-    if (scheme != 0 && scheme != 1) return ORC_ERR_ARG;
+    if (scheme < 0 || scheme > 2) return ORC_ERR_ARG;
     /* Sec. 5: L0 = -sqrt(min k * max k) I over the three given k (R1);
      * the basic scheme takes the arithmetic mean of the extremes. */
     double kmin = fmin(kph[0], fmin(kph[1], kph[2]));
@@ -339,8 +355,11 @@ int orc_homogenize(int n, const uint8_t *phase, const double kph[3], double tol,
     double *kvox = malloc(sizeof(double) * M);
     double *e = malloc(sizeof(double) * 3 * M);
     cplx *t = malloc(sizeof(cplx) * 3 * M);
-    if (!kvox || !e || !t) {
-        free(kvox); free(e); free(t);
+    /* augmented Lagrangian: the local field d and the multiplier lam */
+    double *d = scheme == 2 ? malloc(sizeof(double) * 3 * M) : NULL;
+    double *lam = scheme == 2 ? malloc(sizeof(double) * 3 * M) : NULL;
+    if (!kvox || !e || !t || (scheme == 2 && (!d || !lam))) {
+        free(kvox); free(e); free(t); free(d); free(lam);
         return ORC_ERR_ARG;
     }
     for (size_t v = 0; v < M; ++v) kvox[v] = kph[phase[v]];
@@ -367,7 +386,49 @@ int orc_homogenize(int n, const uint8_t *phase, const double kph[3], double tol,
 
         double F[3] = {0.0, 0.0, 0.0}, r = 0.0, eq = -1.0;
         int st = ORC_NOT_CONVERGED, it = 0;
-        while (it < max_iter) {
+        if (scheme == 2)
+            for (int i = 0; i < 3; ++i)
+                for (size_t v = 0; v < M; ++v) {
+                    d[i * M + v] = e[i * M + v];                 /* d^0 = e^0 */
+                    lam[i * M + v] = kvox[v] * e[i * M + v];     /* lam^0 = k e^0 */
+                }
+        while (scheme == 2 && it < max_iter) {
+            /* compatible step: e+ = E + P(d - lam/k0) = E - Gamma0 * (lam - k0 d),
+             * through the transform, the Green operator and the inverse */
+            for (int i = 0; i < 3; ++i)
+                for (size_t v = 0; v < M; ++v) t[i * M + v] = lam[i * M + v] - k0 * d[i * M + v];
+            for (int i = 0; i < 3; ++i) orc_fft3(n, (double *)(t + i * M), -1);
+            orc_green_apply(n, k0, E, (const double *)t, (double *)t);
+            for (int i = 0; i < 3; ++i) orc_fft3(n, (double *)(t + i * M), +1);
+            /* residual sqrt(<|e+ - d|^2>); multiplier step lam+ = lam + k0 (e+ - d);
+             * local step d+ = (lam+ + k0 e+) / (k + k0); flux <k d+> */
+            double r2 = 0.0;
+            for (int i = 0; i < 3; ++i) {
+                double s = 0.0;
+                for (size_t v = 0; v < M; ++v) {
+                    double c = creal(t[i * M + v]) / (double)M;
+                    double g = c - d[i * M + v];
+                    r2 += g * g;
+                    lam[i * M + v] += k0 * g;
+                    d[i * M + v] = (lam[i * M + v] + k0 * c) / (kvox[v] + k0);
+                    e[i * M + v] = c;
+                    s += kvox[v] * d[i * M + v];
+                }
+                F[i] = s / (double)M;
+            }
+            r = sqrt(r2 / (double)M);
+            if (hist && it < hist_cap) hist[lc * hist_cap + it] = r;
+            ++it;
+            if (!isfinite(r)) {
+                st = ORC_ERR_NONFINITE;
+                break;
+            }
+            if (r < tol) {
+                st = ORC_OK;
+                break;
+            }
+        }
+        while (scheme != 2 && it < max_iter) {
             eq = -1.0;
             /* step 2: tau = (k - k0) e */
             for (int i = 0; i < 3; ++i)
@@ -428,10 +489,12 @@ int orc_homogenize(int n, const uint8_t *phase, const double kph[3], double tol,
         if (status) status[lc] = st;
         if (final_res) final_res[lc] = r;
         if (eps_eq) eps_eq[lc] = (eq >= 0.0) ? eq : equilibrium_error(n, kvox, e, t);
-        if (out_field) memcpy(out_field + (size_t)lc * 3 * M, e, sizeof(double) * 3 * M);
+        if (out_field) memcpy(out_field + (size_t)lc * 3 * M, scheme == 2 ? d : e, sizeof(double) * 3 * M);
     }
     free(kvox);
     free(e);
     free(t);
+    free(d);
+    free(lam);
     return ORC_OK;
 }

@@ -86,12 +86,14 @@ def test_green_reproduces_compatible_fields(n):
 
 
 # ----------------------------------------------------------- exact solutions
+@pytest.mark.parametrize("scheme", [0, 2])
 @pytest.mark.parametrize("n", [8, 9])
 @pytest.mark.parametrize("kv", [1.0, 2.0, 400.0])
-def test_homogeneous_medium_exact(n, kv):
-    """One phase everywhere (k = k0 or not): K = k I after one iteration."""
+def test_homogeneous_medium_exact(n, kv, scheme):
+    """One phase everywhere (k = k0 or not): K = k I after one iteration
+    (accelerated and augmented-Lagrangian schemes)."""
     ph = np.zeros((n, n, n), np.uint8)
-    r = oracle.homogenize(ph, [kv, 0.2, 400.0], tol=1e-12)
+    r = oracle.homogenize(ph, [kv, 0.2, 400.0], tol=1e-12, scheme=scheme)
     np.testing.assert_allclose(r.K, kv * np.eye(3), atol=1e-13 * kv)
     assert list(r.iters) == [1, 1, 1]
     assert np.all(r.final_residual <= 1e-14)
@@ -112,13 +114,14 @@ def _laminate(n, axis, widths, phases):
     (12, [5, 1, 6], [2, 0, 1]),      # a one-voxel layer
 ])
 @pytest.mark.parametrize("axis", [0, 1, 2])
-def test_laminate_exact(n, widths, phases, axis):
+@pytest.mark.parametrize("scheme", [0, 2])
+def test_laminate_exact(n, widths, phases, axis, scheme):
     """Layered laminate: normal entry = harmonic mean, tangential entries =
     arithmetic mean, off-diagonals 0 (series / parallel result)."""
     k = K_PAPER
     ph = _laminate(n, axis, widths, phases)
     kv = k[ph]
-    r = oracle.homogenize(ph, k, tol=1e-13, max_iter=20000)
+    r = oracle.homogenize(ph, k, tol=1e-13, max_iter=20000, scheme=scheme)
     assert np.all(r.status == 0)
     Kex = np.eye(3) * kv.mean()
     Kex[axis, axis] = 1.0 / (1.0 / kv).mean()
@@ -147,13 +150,15 @@ def _spectral_direct_solve(ph, k):
 
 
 @pytest.mark.parametrize("n,seed", [(5, 1), (7, 2)])
-def test_odd_grid_matches_direct_spectral_solve(n, seed):
+@pytest.mark.parametrize("scheme", [0, 2])
+def test_odd_grid_matches_direct_spectral_solve(n, seed, scheme):
     """For odd N the fixed point of the Algorithm is the Galerkin spectral
-    solution of div(k (E + grad u)) = 0, independent of k0."""
+    solution of div(k (E + grad u)) = 0, independent of k0 (and the same for
+    the augmented-Lagrangian scheme, whose fixed point has d = e, lam = k e)."""
     ph = geom.random_phases(n, seed)
     k = np.array([1.0, 0.2, 40.0])
     ref = _spectral_direct_solve(ph, k)
-    r = oracle.homogenize(ph, k, tol=1e-13, max_iter=20000)
+    r = oracle.homogenize(ph, k, tol=1e-13, max_iter=20000, scheme=scheme)
     assert np.all(r.status == 0)
     np.testing.assert_allclose(r.K, ref, atol=1e-10 * np.abs(ref).max())
 
@@ -173,11 +178,14 @@ def _sign_averaged_symbol(n, kk):
     return acc / cnt
 
 
-def test_even_grid_fixed_point_dense_solve():
+@pytest.mark.parametrize("scheme", [0, 2])
+def test_even_grid_fixed_point_dense_solve(scheme):
     """Even N: the converged iterate solves the discrete Lippmann-Schwinger
     equation e = E - (1/k0) IDFT(G DFT((k - k0) e)), assembled with dense DFT
     matrices (not the oracle's FFT) and solved directly.  This pins the
-    iteration (steps 2-7 reach the fixed point), with G the Nyquist reading."""
+    iteration (steps 2-7 reach the fixed point), with G the Nyquist reading.
+    The augmented-Lagrangian fixed point (d = e, lam = k e) is the same
+    equation with the same k0."""
     n = 4
     ph = geom.random_phases(n, 11)
     k = np.array([1.0, 0.2, 40.0])
@@ -196,7 +204,7 @@ def test_even_grid_fixed_point_dense_solve():
         for j in range(3):
             blk = np.real(F3i @ (G[i, j][:, None] * F3)) * (kv - k0)[None, :] / k0
             L[i * M:(i + 1) * M, j * M:(j + 1) * M] += blk
-    r = oracle.homogenize(ph, k, tol=1e-14, max_iter=50000)
+    r = oracle.homogenize(ph, k, tol=1e-14, max_iter=50000, scheme=scheme)
     for j in range(3):
         rhs = np.zeros(3 * M)
         rhs[j * M:(j + 1) * M] = 1.0
@@ -360,3 +368,26 @@ def test_basic_scheme_same_fixed_point_odd_grid():
     assert rate <= (c - 1) / (c + 1) * 1.02
     acc = oracle.homogenize(ph, k, tol=1e-13, max_iter=50000)
     assert acc.iters[0] < r.iters[0]
+
+
+@pytest.mark.parametrize("n,seed,k", [(5, 1, [1.0, 0.2, 4.0]), (9, 1, [1.0, 0.2, 40.0]),
+                                      (12, 2, [1.0, 0.2, 400.0])])
+def test_augmented_lagrangian_rate_and_field(n, seed, k):
+    """The augmented-Lagrangian scheme named in Sec. 3 (alternating local
+    step, compatible step and multiplier step, k0 of Sec. 5) is the
+    Douglas-Rachford averaging (I + T) / 2 of the accelerated scheme's
+    operator T, whose contraction factor is rho = (sqrt c - 1)/(sqrt c + 1):
+    its asymptotic rate is at most (1 + rho) / 2.  Its final local field is
+    the accelerated scheme's converged field."""
+    ph = geom.random_phases(n, seed)
+    k = np.array(k)
+    al = oracle.homogenize(ph, k, tol=1e-12, max_iter=20000, scheme=2, want_field=True)
+    em = oracle.homogenize(ph, k, tol=1e-13, max_iter=20000, want_field=True)
+    assert np.all(al.status == 0) and np.all(em.status == 0)
+    c = k.max() / k.min()
+    rho = (np.sqrt(c) - 1) / (np.sqrt(c) + 1)
+    for h in al.history:
+        rate = (h[-1] / h[-21]) ** (1.0 / 20)
+        assert rate <= (1 + rho) / 2 * 1.01
+    np.testing.assert_allclose(al.K, em.K, atol=1e-10 * k.max())
+    assert np.abs(al.field - em.field).max() <= 1e-9 * np.abs(em.field).max()
