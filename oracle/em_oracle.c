@@ -325,10 +325,14 @@ void orc_set_threads(int t)
  *                                                 the Green operator times k0)
  *                 lam+ = lam + k0 (e+ - d)
  *             from d = e = E, lam = k E (the first transform is then that of
- *             the accelerated scheme); per iteration the compatible step,
- *             the residual sqrt(<|e+ - d|^2>), the multiplier step and the
- *             local step of the new pair (lam+, e+), whose flux <k d+> is the
- *             tensor column; out_field returns d.  eq_check is not used.
+ *             the accelerated scheme; a start field replaces E in d and e);
+ *             per iteration the compatible step, the multiplier step and
+ *             the local step.  The residual is the gap sqrt(<|e+ - d+|^2>)
+ *             between the compatible and the local field of the same
+ *             iteration, the tensor column their common limit's flux
+ *             <k d+>.  out_field returns lam - k0 d, the input of the next
+ *             compatible step ((k - k0) e at the fixed point, where d = e
+ *             and lam = k e).  eq_check is not used.
  *             Parity unpinned against the cited work (its equations are not
  *             in the paper); pinned by the same closed forms as the others.
  */
@@ -400,17 +404,18 @@ int orc_homogenize(int n, const uint8_t *phase, const double kph[3], double tol,
             for (int i = 0; i < 3; ++i) orc_fft3(n, (double *)(t + i * M), -1);
             orc_green_apply(n, k0, E, (const double *)t, (double *)t);
             for (int i = 0; i < 3; ++i) orc_fft3(n, (double *)(t + i * M), +1);
-            /* residual sqrt(<|e+ - d|^2>); multiplier step lam+ = lam + k0 (e+ - d);
-             * local step d+ = (lam+ + k0 e+) / (k + k0); flux <k d+> */
+            /* multiplier step lam+ = lam + k0 (e+ - d); local step
+             * d+ = (lam+ + k0 e+) / (k + k0); residual sqrt(<|e+ - d+|^2>);
+             * flux <k d+> */
             double r2 = 0.0;
             for (int i = 0; i < 3; ++i) {
                 double s = 0.0;
                 for (size_t v = 0; v < M; ++v) {
                     double c = creal(t[i * M + v]) / (double)M;
+                    lam[i * M + v] += k0 * (c - d[i * M + v]);
+                    d[i * M + v] = (lam[i * M + v] + k0 * c) / (kvox[v] + k0);
                     double g = c - d[i * M + v];
                     r2 += g * g;
-                    lam[i * M + v] += k0 * g;
-                    d[i * M + v] = (lam[i * M + v] + k0 * c) / (kvox[v] + k0);
                     e[i * M + v] = c;
                     s += kvox[v] * d[i * M + v];
                 }
@@ -489,7 +494,12 @@ int orc_homogenize(int n, const uint8_t *phase, const double kph[3], double tol,
         if (status) status[lc] = st;
         if (final_res) final_res[lc] = r;
         if (eps_eq) eps_eq[lc] = (eq >= 0.0) ? eq : equilibrium_error(n, kvox, e, t);
-        if (out_field) memcpy(out_field + (size_t)lc * 3 * M, scheme == 2 ? d : e, sizeof(double) * 3 * M);
+        if (out_field && scheme == 2)
+            for (int i = 0; i < 3; ++i)
+                for (size_t v = 0; v < M; ++v)
+                    out_field[(size_t)(lc * 3 + i) * M + v] = lam[i * M + v] - k0 * d[i * M + v];
+        else if (out_field)
+            memcpy(out_field + (size_t)lc * 3 * M, e, sizeof(double) * 3 * M);
     }
     free(kvox);
     free(e);
