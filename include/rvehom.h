@@ -80,7 +80,16 @@ typedef struct {
     size_t workspace_bytes;
     int scheme;             /* 0 = accelerated (Eyre-Milton, Sec. 3 Algorithm, k0 of Sec. 5);
                                1 = basic scheme named in Sec. 3 (e+ = c, the compatible
-                               field, with k0 = (min k + max k) / 2) */
+                               field, with k0 = (min k + max k) / 2);
+                               2 = augmented-Lagrangian scheme named in Sec. 3 (k0 of
+                               Sec. 5): local step d = (lam + k0 e) / (k + k0), compatible
+                               step e+ = E - Gamma0 (lam - k0 d), multiplier step
+                               lam+ = lam + k0 (e+ - d), from d = e = E (or init_field)
+                               and lam = k d; final_residual is sqrt<|e+ - d+|^2>, K the
+                               flux <k d+>, out_field the state lam - k0 d.  Built
+                               for the grids whose xy-plane pass is one kernel
+                               (N <= 128 except FP32 N = 96); other N, and
+                               equilibrium_check, give RVE_ERR_ARG */
 } rve_opts;
 
 typedef struct {

@@ -253,7 +253,7 @@ def _to_result(rc: int, r: _Result, hist=None, hist_cap=0, fld=None) -> HomResul
                      history, fld)
 
 
-SCHEMES = {"accelerated": 0, "basic": 1}
+SCHEMES = {"accelerated": 0, "basic": 1, "augmented_lagrangian": 2}
 
 
 def _opts(max_iter=0, precision=0, equilibrium_check=False, stall_window=-1, lc_mask=7,
@@ -285,9 +285,11 @@ def homogenize(rve: RVE, k_phases, tol: float = 1e-6, *, max_iter: int = 0, prec
                scheme="accelerated") -> HomResult:
     """The Algorithm of Sec. 3 for E = e_1, e_2, e_3 on the device.
 
-    scheme: "accelerated" (Eyre-Milton, the paper's choice) or "basic" (the
+    scheme: "accelerated" (Eyre-Milton, the paper's choice), "basic" (the
     basic scheme the paper names as an alternative: e+ = c, k0 = mean of the
-    extreme conductivities)."""
+    extreme conductivities) or "augmented_lagrangian" (also named there; k0
+    of Sec. 5; the field returned is its state lam - k0 d; N <= 128 except
+    FP32 N = 96, no equilibrium check)."""
     k = np.ascontiguousarray(k_phases, dtype=np.float64)
     if k.shape != (3,):
         raise RveError(RVE_ERR_ARG, "k_phases must hold 3 conductivities")

@@ -130,13 +130,15 @@ template <typename T, int N> struct Instance {
     // fused inverse + next forward pass (whole planes in LDS; not where the
     // fused kernel would spill registers heavily: FP32 96^3)
     static constexpr bool FUSED = !FIVE && S == 1 && !(sizeof(T) == 4 && N == 96);
-    static void inv_fwd(const LaunchArgs &a, hipStream_t s, int lc_sel) {
+    template <bool AL> static void inv_fwd_t(const LaunchArgs &a, hipStream_t s, int lc_sel) {
         if constexpr (FUSED) {
-            hipLaunchKernelGGL((k_inv_plane<T, N, 1, NTP, true>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s, (T *)a.e,
-                               a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
+            hipLaunchKernelGGL((k_inv_plane<T, N, 1, NTP, true, AL>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s,
+                               (T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
                                (const DevState *)a.st, a.part, ch0(lc_sel));
         }
     }
+    static void inv_fwd(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_fwd_t<false>(a, s, lc_sel); }
+    static void inv_fwd_al(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_fwd_t<true>(a, s, lc_sel); }
     static void init(const LaunchArgs &a, size_t M, hipStream_t s) {
         hipLaunchKernelGGL((k_init<T>), dim3(1024), dim3(256), 0, s, (T *)a.e, M, a.prm, a.st);
     }
@@ -183,6 +185,7 @@ template <typename T, int N> struct Instance {
             &init,
             &from_f64,
             &to_f64,
+            FUSED ? &inv_fwd_al : nullptr,
         };
         return &o;
     }

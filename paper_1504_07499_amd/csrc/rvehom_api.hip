@@ -390,7 +390,8 @@ void fill_params(DevParams &p, const double k[3], double tol, int n, const Solve
     const double kmin = std::min(k[0], std::min(k[1], k[2]));
     const double kmax = std::max(k[0], std::max(k[1], k[2]));
     // Sec. 5: L0 = -sqrt(min k * max k) I over the three given conductivities
-    // (accelerated scheme); the basic scheme uses the arithmetic mean.
+    // (accelerated and augmented-Lagrangian schemes); the basic scheme uses
+    // the arithmetic mean.
     const double k0 = o.scheme == 1 ? 0.5 * (kmin + kmax) : std::sqrt(kmin * kmax);
     const double M = (double)n * n * n;
     for (int i = 0; i < 3; ++i) {
@@ -398,12 +399,17 @@ void fill_params(DevParams &p, const double k[3], double tol, int n, const Solve
         p.dk[i] = k[i] - k0;
         // step 7: e+ = e + 2 k0 / (k + k0) (c - e); basic scheme: e+ = c
         p.w[i] = o.scheme == 1 ? 1.0 : 2.0 * k0 / (k[i] + k0);
+        p.gam[i] = 1.0 / (k[i] + k0);
     }
     p.k0 = k0;
+    p.scheme = o.scheme;
     // contraction bound of the scheme at contrast c = kmax / kmin: Eyre-Milton
-    // (sqrt c - 1) / (sqrt c + 1), basic scheme (c - 1) / (c + 1)
+    // (sqrt c - 1) / (sqrt c + 1), basic scheme (c - 1) / (c + 1); the
+    // augmented Lagrangian averages the Eyre-Milton operator with the
+    // identity (Douglas-Rachford form): (1 + rho_EM) / 2
     const double c = kmax / kmin;
-    const double rho = o.scheme == 1 ? (c - 1.0) / (c + 1.0) : (std::sqrt(c) - 1.0) / (std::sqrt(c) + 1.0);
+    const double rem = (std::sqrt(c) - 1.0) / (std::sqrt(c) + 1.0);
+    const double rho = o.scheme == 1 ? (c - 1.0) / (c + 1.0) : (o.scheme == 2 ? 0.5 * (1.0 + rem) : rem);
     p.prog10 = 1.0 - std::pow(rho, 10.0);
     p.inv_k0M = 1.0 / (k0 * M);
     p.tol = tol;
@@ -509,9 +515,11 @@ int Solver::begin(const uint8_t *d_phase, const double k[3], double tol, const S
     slot = 0;
     launches.clear();
     eq_check = o.eq_check != 0;
+    al = o.scheme == 2;
     {
+        // (the augmented-Lagrangian update exists only in the fused pass)
         const char *f = getenv("RVEHOM_FUSED");
-        fused = ops->inv_fwd != nullptr && !eq_check && !(f && f[0] == '0');
+        fused = ops->inv_fwd != nullptr && !eq_check && (al || !(f && f[0] == '0'));
     }
     {
         const char *f = getenv("RVEHOM_MERGE");
@@ -546,7 +554,7 @@ int Solver::launch_iteration(const LaunchArgs &a, hipStream_t s, int mask, hipEv
         switch (kk) {
         case 0: ops->fwd(a, s, lc_sel); break;
         case 1: (zvar ? ops->zgreen_alt : ops->zgreen)(a, s, red_in_z ? ops->nper : 0, lc_sel); break;
-        case 2: fused ? ops->inv_fwd(a, s, lc_sel) : ops->inv(a, s, lc_sel); break;
+        case 2: fused ? (al ? ops->inv_fwd_al : ops->inv_fwd)(a, s, lc_sel) : ops->inv(a, s, lc_sel); break;
         default: launch_reduce(a, ops->nper, s); break;
         }
         if (timed) {
@@ -584,7 +592,7 @@ static int live_mask(int mask, bool fused) { return fused ? (mask & ~1) : mask; 
 // Capture kChunk iterations into a graph on the solver's own stream.
 int Solver::ensure_graph(const uint8_t *d_phase) {
     if (gexec && g_ws == ws && g_ph == d_phase && g_eq == eq_check && g_fused == fused && g_merge == merge &&
-        g_lc == lc_sel && g_zvar == zvar)
+        g_lc == lc_sel && g_zvar == zvar && g_al == al)
         return RVE_OK;
     drop_graphs();
     LaunchArgs a = args(d_phase);
@@ -610,6 +618,7 @@ int Solver::ensure_graph(const uint8_t *d_phase) {
     g_merge = merge;
     g_lc = lc_sel;
     g_zvar = zvar;
+    g_al = al;
     return RVE_OK;
 }
 
@@ -883,6 +892,24 @@ static rve_status solve_chains(rve_s *r, const SolverOps *ops, const double k[3]
     return worst_status(res, o.lc_mask);
 }
 
+// The scheme option against what the grid size's kernels provide.
+int check_scheme(const SolverOpts &o, const SolverOps *ops) {
+    if (o.scheme < 0 || o.scheme > 2) {
+        set_error("scheme must be 0 (accelerated), 1 (basic) or 2 (augmented Lagrangian)");
+        return RVE_ERR_ARG;
+    }
+    if (o.scheme == 2 && o.eq_check) {
+        set_error("the augmented-Lagrangian scheme has no equilibrium check");
+        return RVE_ERR_ARG;
+    }
+    if (o.scheme == 2 && !ops->inv_fwd_al) {
+        set_error("the augmented-Lagrangian scheme is built for whole-plane grids only (not N = %d in %s)", ops->n,
+                  ops->precision ? "FP64" : "FP32");
+        return RVE_ERR_ARG;
+    }
+    return RVE_OK;
+}
+
 // One RVE, start to finish, on stream s.
 rve_status solve_one(rve_s *r, const double k[3], double tol, const SolverOpts &o, rve_result *out,
                      double *hist, int hist_cap) {
@@ -891,6 +918,7 @@ rve_status solve_one(rve_s *r, const double k[3], double tol, const SolverOpts &
         set_error("grid size %d is not built for precision %d", r->n, o.precision);
         return RVE_ERR_ARG;
     }
+    if (check_scheme(o, ops) != RVE_OK) return RVE_ERR_ARG;
     int cur = 0;
     HIP_CHECK(hipGetDevice(&cur));
     if (cur != r->device) HIP_CHECK(hipSetDevice(r->device));
@@ -948,10 +976,6 @@ extern "C" rve_status homogenize(rve_t r, const double k_phases[3], double tol, 
         set_error("precision must be 0 (FP32) or 1 (FP64)");
         return RVE_ERR_ARG;
     }
-    if (opts && (opts->scheme != 0 && opts->scheme != 1)) {
-        set_error("scheme must be 0 (accelerated) or 1 (basic)");
-        return RVE_ERR_ARG;
-    }
     if (hist_cap < 0 || (hist_cap > 0 && !residual_history)) {
         set_error("residual_history is NULL but hist_cap > 0");
         return RVE_ERR_ARG;
@@ -997,6 +1021,7 @@ extern "C" rve_status homogenize_batch(int count, const rve_t *rves, const doubl
             set_error("grid size %d is not built for precision %d", rves[i]->n, o.precision);
             return RVE_ERR_ARG;
         }
+        if (check_scheme(o, lookup_ops(o.precision, rves[i]->n)) != RVE_OK) return RVE_ERR_ARG;
         for (int j = 0; j < i; ++j)
             if (rves[j] == rves[i]) {
                 set_error("homogenize_batch: rve %d appears twice", i);

@@ -77,6 +77,7 @@ struct Solver {
     bool merge = false;  // each reduction runs inside the next iteration's z pass
     int lc_sel = -1;     // -1: all load cases; else the only load case iterated
     int zvar = 0;        // z-pass tile width: 0 default, 1 the other (autotuned)
+    bool al = false;     // augmented-Lagrangian update in the fused pass
     const uint8_t *d_phase_last = nullptr;
     // captured graph of kChunk iterations (kernels only; all parameters are
     // read from device memory, so one graph serves every call on this workspace)
@@ -88,6 +89,7 @@ struct Solver {
     bool g_merge = false;
     int g_lc = -1;
     int g_zvar = 0;
+    bool g_al = false;
     bool use_graphs = true;
     // timed variants: one graph per poll slot (its own events), per mask
     hipGraphExec_t tgexec[kPollSlots] = {};

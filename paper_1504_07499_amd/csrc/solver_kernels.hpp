@@ -293,6 +293,41 @@ __device__ __forceinline__ void em_update_tau(T *a, const T *c, unsigned p, cons
     se += (double)sev;
 }
 
+// The augmented-Lagrangian scheme (named in Sec. 3 beside the accelerated
+// one; k0 of Sec. 5) in the variable tau = lam - k0 d that its compatible step
+// transforms (d: local field, lam: multiplier).  With c = e+ the compatible
+// field, the multiplier step gives lam+ = tau + k0 c and the local step
+// d+ = (lam+ + k0 c) / (k + k0), so that
+//     g    = c - d+ = ((k - k0) c - tau) / (k + k0)   (residual),
+//     tau+ = lam+ - k0 d+ = tau + k0 g,
+//     k d+ = tau+ + k0 c                               (flux).
+// tau is the one field carried between iterations: the buffer that holds e
+// for the accelerated scheme holds tau here.  The first pass finds e^0 there
+// (the start field, E by default) and takes tau^0 = (k - k0) e^0 (first).
+// lut[phase] = {k - k0, 1 / (k + k0)} (LDS).  As em_update_tau, st collects
+// sum (tau+ - tm) and se sum c, so that the caller's
+// count * tm + k0 * (sum c) completes the flux.
+template <typename T, int V>
+__device__ __forceinline__ void al_update_tau(T *a, const T *c, unsigned p, const Cx<T> *lut, T k0, T tm, T ec,
+                                              bool first, double &r2, double &st, double &se, T *tau) {
+    T r2v = (T)0, stv = (T)0, sev = (T)0;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+        const T ci = c[i] + ec;
+        const Cx<T> dg = lut[ph_at(p, i)];
+        const T ti = first ? dg.x * a[i] : a[i];
+        const T g = (dg.x * ci - ti) * dg.y;
+        r2v += g * g;
+        a[i] = ti + k0 * g;
+        tau[i] = a[i] - tm;
+        stv += tau[i];
+        sev += ci;
+    }
+    r2 += (double)r2v;
+    st += (double)stv;
+    se += (double)sev;
+}
+
 // Waves per SIMD asked of the plane kernels: as many workgroups per CU as
 // their LDS plane allows, capped at 4 waves per SIMD (at most 128 VGPRs).
 template <typename T, int N, int S, int NT> constexpr int plane_min_waves() {
@@ -693,7 +728,7 @@ __global__ __launch_bounds__(NT) void k_zeq(const Cx<T> *__restrict__ spec, cons
 // of the plane per iteration instead of two of each.  The mean subtracted
 // from tau is the previous iteration's (any constant is exact: the mean
 // mode of tau is replaced by E).
-template <typename T, int N, int S, int NT, bool FWD = false>
+template <typename T, int N, int S, int NT, bool FWD = false, bool AL = false>
 __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_plane(T *__restrict__ e, const uint8_t *__restrict__ ph,
                                                   Cx<T> *__restrict__ spec,
                                                   Cx<T> *__restrict__ nyq,
@@ -702,6 +737,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
                                                   const DevState *__restrict__ st,
                                                   double *__restrict__ part, int ch0) {
     static_assert(!FWD || S == 1, "the fused inverse/forward pass needs a whole plane");
+    static_assert(!AL || FWD, "the augmented-Lagrangian update is built into the fused pass");
     // row pitch: even for whole planes (16-byte pair accesses, paired FFT
     // stages), N/2 + 1 for split planes
     constexpr int H = N / 2, RS = (S == 1) ? H + 2 : H + 1, ROWS = N / S, V = VecOf<T>::V, NN = N * N;
@@ -769,9 +805,11 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
     __shared__ Cx<T> tws[N];
     table_to_lds<T, N, NT>(tws, twg, tid);
     const Cx<T> *tw = tws;
-    // per-phase {w, k - k0} of the update (fused form)
+    // per-phase {w, k - k0} of the update (fused form; augmented Lagrangian:
+    // {k - k0, 1 / (k + k0)})
     __shared__ Cx<T> lut[3];
-    if (FWD && tid < 3) lut[tid] = Cx<T>{(T)prm->w[tid], (T)prm->dk[tid]};
+    if (FWD && tid < 3)
+        lut[tid] = AL ? Cx<T>{(T)prm->dk[tid], (T)prm->gam[tid]} : Cx<T>{(T)prm->w[tid], (T)prm->dk[tid]};
     __syncthreads();
     if constexpr (P0) {
         for (int m = tid; m < ROWS; m += NT) {
@@ -798,7 +836,9 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
     const double k0d = prm->k[0], k1d = prm->k[1], k2d = prm->k[2];
     const T d0 = (T)prm->dk[0], d1 = (T)prm->dk[1], d2 = (T)prm->dk[2];
     const T tm = (T)st->tau_mean[ch];
-    (void)d0, (void)d1, (void)d2, (void)tm;
+    const bool first = AL && st->iter == 0;  // the buffer still holds e^0
+    const T k0t = (T)prm->k0;
+    (void)d0, (void)d1, (void)d2, (void)tm, (void)first, (void)k0t;
     T *eb = e + (size_t)ch * N * NN + (size_t)z * NN;
     const uint8_t *pb = ph + (size_t)z * NN;
     double r2 = 0.0, fl = 0.0, se = 0.0;
@@ -838,7 +878,10 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
                     // next iteration's tau, packed in place of the c values just
                     // read; fl collects sum tau here (the flux follows below)
                     T tau[V];
-                    em_update_tau<T, V>(a[i], c, p[i], lut, tm, ec, r2, fl, se, tau);
+                    if constexpr (AL)
+                        al_update_tau<T, V>(a[i], c, p[i], lut, k0t, tm, ec, first, r2, fl, se, tau);
+                    else
+                        em_update_tau<T, V>(a[i], c, p[i], lut, tm, ec, r2, fl, se, tau);
                     vstore<T>(eb + y * N + x, a[i]);
                     if constexpr (V == 4) {
                         st_pair<T, RS % 2 == 0>(plane + m * RS + x / 2, Cx<T>{tau[0], tau[1]}, Cx<T>{tau[2], tau[3]});

@@ -52,6 +52,9 @@ struct SolverOps {
     void (*init)(const LaunchArgs &, size_t M, hipStream_t);
     void (*from_f64)(void *e, const double *src, size_t count, hipStream_t);
     void (*to_f64)(double *dst, const void *e, size_t count, hipStream_t);
+    // the fused pass with the augmented-Lagrangian update (nullptr where
+    // there is no fused pass)
+    void (*inv_fwd_al)(const LaunchArgs &, hipStream_t, int lc_sel);
 };
 
 const SolverOps *ops_f32(int n);

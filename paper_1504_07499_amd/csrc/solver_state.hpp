@@ -14,12 +14,14 @@ struct DevParams {
     double tol;
     double invM;
     double prog10;  // 1 - rho^10: least progress of 10 iterations the scheme's contraction bound allows
+    double gam[3];  // 1 / (k + k0) (augmented-Lagrangian local step)
     int max_iter;
     int stall_window;  // 0 = off
     int hist_cap;
     int eq_check;
     int lc_mask;  // bit lc set = solve that load case
-    int pad_[3];
+    int scheme;   // 0 accelerated, 1 basic, 2 augmented Lagrangian
+    int pad_[2];
 };
 
 // Solver state, in device memory; written only by k_reduce / k_init.

@@ -91,18 +91,20 @@ def test_torch_workspace_and_stream():
     assert "torch interop ok" in out.stdout
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_batch_equals_alone(precision):
+@pytest.mark.parametrize("precision,scheme", [(0, "accelerated"), (1, "accelerated"),
+                                              (0, "augmented_lagrangian")])
+def test_batch_equals_alone(precision, scheme):
     """Mixed grid sizes in one batched solve: each result is bitwise the
     result of solving that RVE alone."""
-    print(f"\n[case] batch precision={precision}", flush=True)
+    print(f"\n[case] batch precision={precision} scheme={scheme}", flush=True)
     specs = [(16, 3, 0.2, 0.2, 1), (24, 5, 0.25, 0.1, 2), (32, 8, 0.2, 0.1, 3),
              (48, 10, 0.3, 0.2, 4), (32, 4, 0.1, 0.3, 5)]
     rves = [rh.rve_create(*s) for s in specs]
     ks = np.array([K3, [1.0, 0.2, 400.0], K3, [0.2, 0.3, 20.0], K3])
     tols = np.array([1e-6, 1e-6, 1e-5, 1e-6, 1e-6])
-    alone = [rh.homogenize(r, kk, t, precision=precision) for r, kk, t in zip(rves, ks, tols)]
-    mixed = rh.homogenize_batch(rves, ks, tols, precision=precision)
+    alone = [rh.homogenize(r, kk, t, precision=precision, scheme=scheme)
+             for r, kk, t in zip(rves, ks, tols)]
+    mixed = rh.homogenize_batch(rves, ks, tols, precision=precision, scheme=scheme)
     for a, b in zip(alone, mixed):
         assert np.array_equal(a.K, b.K)
         assert np.array_equal(a.iters, b.iters)

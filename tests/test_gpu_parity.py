@@ -225,3 +225,92 @@ def test_basic_scheme_fp64_vs_oracle():
         g = rh.homogenize(r, K_PAPER_CFG, 0.0, max_iter=5, precision=1, want_field=True,
                           scheme="basic")
     assert field_err(g.field, ref.field) <= 1e-11
+
+
+AL = "augmented_lagrangian"
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("n", [8, 12, 24, 48, 64, 128])
+def test_augmented_lagrangian_fixed_iterations(n, precision):
+    """Augmented-Lagrangian scheme (named in Sec. 3; k0 of Sec. 5): after
+    four iterations from E, the state lam - k0 d of every voxel of every
+    channel, the tensor <k d> and the residual history match the oracle."""
+    print(f"\n[case] augmented lagrangian n={n} precision={precision}", flush=True)
+    ph = geom.random_phases(n, seed=300 + n)
+    ref = oracle.homogenize(ph, K_PAPER_CFG, tol=0.0, max_iter=4, want_field=True, scheme=2)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize(r, K_PAPER_CFG, 0.0, max_iter=4, precision=precision,
+                          want_field=True, hist_cap=8, scheme=AL)
+    bar = 1e-11 if precision == 1 else 3e-5
+    assert field_err(g.field, ref.field) <= bar
+    assert tensor_err(g.K, ref.K) <= bar
+    assert list(g.iters) == [4, 4, 4]
+    for j in range(3):
+        np.testing.assert_allclose(g.history[j], ref.history[j], rtol=bar * 10)
+
+
+def test_augmented_lagrangian_start_field():
+    """A start field takes the place of E in d and e (lam = k d): three
+    iterations from the field of two accelerated iterations, voxel by voxel."""
+    print("\n[case] augmented lagrangian start field", flush=True)
+    ph = geom.random_phases(24, 91)
+    init = oracle.homogenize(ph, K_PAPER_CFG, tol=0.0, max_iter=2, want_field=True).field
+    ref = oracle.homogenize(ph, K_PAPER_CFG, tol=0.0, max_iter=3, want_field=True,
+                            init_field=init, scheme=2)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize(r, K_PAPER_CFG, 0.0, max_iter=3, precision=1, want_field=True,
+                          init_field=init, scheme=AL)
+    assert field_err(g.field, ref.field) <= 1e-11
+    assert tensor_err(g.K, ref.K) <= 1e-11
+
+
+def test_augmented_lagrangian_converged_fp64_vs_oracle():
+    """32^3, 8 RSA spheres, f = 0.2, l = 0.1, seed 1, tol 1e-6, FP64: the
+    augmented-Lagrangian tensor within 1e-9 of the oracle's, same iteration
+    counts and residual histories."""
+    print("\n[case] augmented lagrangian converged fp64", flush=True)
+    ph, _, _ = geom.generate(32, 8, 0.2, 0.1, 1)
+    ref = oracle.homogenize(ph, K_PAPER_CFG, tol=1e-6, scheme=2)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=1, hist_cap=1000, scheme=AL)
+    assert g.status == rh.RVE_OK
+    assert list(g.iters) == list(ref.iters)
+    assert tensor_err(g.K, ref.K) <= 1e-9
+    for j in range(3):
+        np.testing.assert_allclose(g.history[j], ref.history[j], rtol=1e-9)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_augmented_lagrangian_config2_128(precision):
+    """The benchmark workload with the augmented-Lagrangian scheme (in the
+    load-case chains bench.py uses): the same discrete solution as the stored
+    oracle tensor of the accelerated scheme, within the FP32 bar (FP64:
+    1e-5, the two stop at tol 1e-6 on different residuals), after more
+    iterations than the accelerated scheme."""
+    print(f"\n[case] augmented lagrangian config2 128 precision={precision}", flush=True)
+    ref = _golden("rve128_50sph_f0.30_l0.20_seed2")
+    g0 = ref["geometry"]
+    with rh.rve_create(g0["n"], g0["n_spheres"], g0["volume_fraction"], g0["layer"],
+                       g0["seed"]) as r:
+        g = rh.homogenize(r, ref["k_phases"], ref["tol"], precision=precision, scheme=AL)
+    assert g.status in ((rh.RVE_OK, rh.RVE_STALLED) if precision == 0 else (rh.RVE_OK,))
+    assert tensor_err(g.K, np.array(ref["K"])) <= (1e-4 if precision == 0 else 1e-5)
+    assert int(min(g.iters)) > max(ref["iters"])
+
+
+def test_augmented_lagrangian_rejected_where_not_built():
+    """Grids without a whole-plane pass, the equilibrium check and unknown
+    schemes are refused before any work."""
+    print("\n[case] augmented lagrangian rejections", flush=True)
+    for n, prec in ((96, 0), (256, 0), (256, 1)):
+        with rh.rve_create_from_phases(np.zeros((n, n, n), np.uint8)) as r:
+            with pytest.raises(rh.RveError):
+                rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=prec, scheme=AL)
+    with rh.rve_create_from_phases(geom.random_phases(16, 5)) as r:
+        with pytest.raises(rh.RveError):
+            rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=1, scheme=AL, equilibrium_check=True)
+        with pytest.raises(rh.RveError):
+            rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=1, scheme=3)
+        ok = rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=1, scheme=AL)
+        assert ok.status == rh.RVE_OK
