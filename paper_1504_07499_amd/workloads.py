@@ -10,6 +10,7 @@ Command line (GPU):
   python -m paper_1504_07499_amd.workloads sweep256
   python -m paper_1504_07499_amd.workloads rates  [--requests 200 --rate 200]
   python -m paper_1504_07499_amd.workloads run512
+  python -m paper_1504_07499_amd.workloads schemes [--precision 1]
 """
 from __future__ import annotations
 
@@ -215,6 +216,37 @@ def run_512(n_spheres=100, f=0.30, layer=0.2, seed=7, k=K_BENCH, tol=1e-6):
     return out
 
 
+# -------------------------------------------------------------------- schemes
+def run_schemes(coatings=(1.0, 4.0, 20.0, 80.0, 400.0), n=128, n_spheres=50, f=0.30, layer=0.2, seed=2,
+                tol=1e-6, precision=1, max_iter=20000):
+    """Iterations against contrast for the schemes Sec. 3 names (basic,
+    augmented Lagrangian, accelerated) on one RVE: matrix 1, inclusion 0.2,
+    coating from 1 to 400 (contrast 5 to 2000, the range of Sec. 3), with
+    the contraction bound of each scheme and the iterations it predicts."""
+    rows = []
+    with rve_create(n, n_spheres, f, layer, seed) as h:
+        for kc in coatings:
+            k = (1.0, 0.2, kc)
+            c = max(k) / min(k)
+            rho = (math.sqrt(c) - 1) / (math.sqrt(c) + 1)
+            bounds = {"accelerated": rho, "augmented_lagrangian": 0.5 * (1 + rho),
+                      "basic": (c - 1) / (c + 1)}
+            ref = None
+            for sch in ("accelerated", "augmented_lagrangian", "basic"):
+                r = homogenize(h, k, tol, precision=precision, scheme=sch, max_iter=max_iter)
+                if ref is None:
+                    ref = r
+                row = {"contrast": c, "scheme": sch, "iters": r.iters.tolist(),
+                       "status": r.lc_status.tolist(), "ms": r.solve_ms,
+                       "ms_per_iter": r.solve_ms / max(1, int(r.iters.max())),
+                       "rate_bound": bounds[sch],
+                       "iters_bound": math.ceil(math.log(tol) / math.log(bounds[sch])),
+                       "k_iso": float(np.trace(r.K) / 3), "err_vs_accelerated": tensor_err(r.K, ref.K)}
+                rows.append(row)
+                print(json.dumps(row), flush=True)
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -228,6 +260,8 @@ def main(argv=None):
     s.add_argument("--baseline", type=int, default=0, help="also run the sequential FP64 path")
     sub.add_parser("sweep256")
     sub.add_parser("run512")
+    sc = sub.add_parser("schemes")
+    sc.add_argument("--precision", type=int, default=1)
     rs = sub.add_parser("rates")
     rs.add_argument("--requests", type=int, default=200)
     rs.add_argument("--rate", type=float, default=200.0)
@@ -244,6 +278,8 @@ def main(argv=None):
             print(json.dumps(seq), flush=True)
     elif a.cmd == "run512":
         run_512()
+    elif a.cmd == "schemes":
+        run_schemes(precision=a.precision)
     elif a.cmd == "rates":
         run_rate_sweep(a.requests, a.rate)
     else:
