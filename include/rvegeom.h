@@ -1,7 +1,8 @@
 /*
  * rvegeom.h -- seeded input generator: random sequential adsorption (RSA) of
- * identical non-overlapping spheres in the periodic unit cell, and voxel-centre
- * classification into the three phases (matrix, inclusion, coating).
+ * identical non-overlapping spheres (or aligned fibres) in the periodic unit
+ * cell, and voxel-centre classification into the three phases (matrix,
+ * inclusion, coating).
  *
  * This is setup, not the homogenization method: it holds none of the scheme's
  * arithmetic.  It serves both the GPU library (rve_create) and the tests that
@@ -58,6 +59,23 @@ int rvegeom_voxelize(int n, int n_spheres, const double *centers, double radius,
 /* Both steps: placement, then voxelization.  centers may be NULL. */
 int rvegeom_generate(int n, int n_spheres, double volume_fraction, double layer,
                      uint64_t seed, uint8_t *phases, double *centers, int *method);
+
+/* Aligned coated fibres: the cylindrical inclusions Sec. 6 names as the next
+ * geometry, as infinite circular cylinders along z (the image is invariant
+ * along z).  Same conventions as the spheres in the xy cross-section: radius
+ * r = (f / (pi n))^(1/2) (coating included; f is the area fraction of the
+ * cross-section, hence the volume fraction), RSA of the axes in the periodic
+ * unit square from std::mt19937_64(seed) (x then y per attempt), minimum
+ * axis distance 2 r, Monte Carlo shaking if the budget runs out, voxel
+ * classification by the centre ((i+.5)/N, (j+.5)/N) of each column.
+ * centers: 2 doubles (x, y) per fibre. */
+double rvegeom_fiber_radius(int n_fibers, double volume_fraction);
+int rvegeom_place_fibers(int n_fibers, double volume_fraction, uint64_t seed,
+                         double *centers, int *method);
+int rvegeom_voxelize_fibers(int n, int n_fibers, const double *centers, double radius,
+                            double layer, uint8_t *phases);
+int rvegeom_generate_fibers(int n, int n_fibers, double volume_fraction, double layer,
+                            uint64_t seed, uint8_t *phases, double *centers, int *method);
 
 #ifdef __cplusplus
 }

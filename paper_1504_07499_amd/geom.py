@@ -1,4 +1,5 @@
-"""Seeded input generator (RSA spheres + voxelization), ctypes binding.
+"""Seeded input generator (RSA spheres or aligned fibres + voxelization),
+ctypes binding.
 
 Wraps ``librvegeom.so`` (``geom/rve_geom.cpp``, declared in
 ``include/rvegeom.h``).  Paper: arXiv:1504.07499, Sec. 2 (RSA of identical
@@ -41,6 +42,16 @@ def _load():
     lib.rvegeom_generate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_uint64, u8p, dp, ip]
     lib.rvegeom_generate.restype = ctypes.c_int
+    lib.rvegeom_fiber_radius.argtypes = [ctypes.c_int, ctypes.c_double]
+    lib.rvegeom_fiber_radius.restype = ctypes.c_double
+    lib.rvegeom_place_fibers.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_uint64, dp, ip]
+    lib.rvegeom_place_fibers.restype = ctypes.c_int
+    lib.rvegeom_voxelize_fibers.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_double,
+                                            ctypes.c_double, u8p]
+    lib.rvegeom_voxelize_fibers.restype = ctypes.c_int
+    lib.rvegeom_generate_fibers.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_uint64, u8p, dp, ip]
+    lib.rvegeom_generate_fibers.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -94,6 +105,55 @@ def generate(n: int, n_spheres: int, volume_fraction: float, layer: float, seed:
         raise RuntimeError("sphere placement exhausted its attempt budget (jammed)")
     if rc != 0:
         raise ValueError("invalid geometry arguments")
+    return out, c, int(m.value)
+
+
+def fiber_radius(n_fibers: int, volume_fraction: float) -> float:
+    """r = (f / (pi n))^(1/2), coating included: aligned fibres along z."""
+    return float(_load().rvegeom_fiber_radius(int(n_fibers), float(volume_fraction)))
+
+
+def place_fibers(n_fibers: int, volume_fraction: float, seed: int):
+    """RSA fibre axes (n, 2) in the unit square and the method used."""
+    lib = _load()
+    c = np.zeros((int(n_fibers), 2))
+    m = ctypes.c_int(-1)
+    rc = lib.rvegeom_place_fibers(int(n_fibers), float(volume_fraction), int(seed),
+                                  c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(m))
+    if rc == -2:
+        raise RuntimeError("fibre placement exhausted its attempt budget (jammed)")
+    if rc != 0:
+        raise ValueError("invalid fibre placement arguments")
+    return c, int(m.value)
+
+
+def voxelize_fibers(n: int, centers: np.ndarray, r: float, layer: float) -> np.ndarray:
+    """Phase image (n, n, n) uint8 of coated fibres along z."""
+    lib = _load()
+    c = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 2)
+    out = np.zeros((n, n, n), dtype=np.uint8)
+    rc = lib.rvegeom_voxelize_fibers(int(n), int(c.shape[0]),
+                                     c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     float(r), float(layer),
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    if rc != 0:
+        raise ValueError("invalid fibre voxelization arguments")
+    return out
+
+
+def generate_fibers(n: int, n_fibers: int, volume_fraction: float, layer: float, seed: int):
+    """Aligned coated fibres along z: (phases (n,n,n) uint8, axes (n_f, 2), method)."""
+    lib = _load()
+    out = np.zeros((n, n, n), dtype=np.uint8)
+    c = np.zeros((int(n_fibers), 2))
+    m = ctypes.c_int(-1)
+    rc = lib.rvegeom_generate_fibers(int(n), int(n_fibers), float(volume_fraction), float(layer),
+                                     int(seed), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                     c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(m))
+    if rc == -2:
+        raise RuntimeError("fibre placement exhausted its attempt budget (jammed)")
+    if rc != 0:
+        raise ValueError("invalid fibre geometry arguments")
     return out, c, int(m.value)
 
 

@@ -11,6 +11,7 @@ Command line (GPU):
   python -m paper_1504_07499_amd.workloads rates  [--requests 200 --rate 200]
   python -m paper_1504_07499_amd.workloads run512
   python -m paper_1504_07499_amd.workloads schemes [--precision 1]
+  python -m paper_1504_07499_amd.workloads fibers
 """
 from __future__ import annotations
 
@@ -23,8 +24,9 @@ import time
 
 import numpy as np
 
-from . import (homogenize, homogenize_batch, rve_create, rve_server_create, rve_server_destroy,
-               rve_server_drain, rve_server_poll, rve_server_submit)
+from . import (homogenize, homogenize_batch, rve_create, rve_create_from_phases, rve_server_create,
+               rve_server_destroy, rve_server_drain, rve_server_poll, rve_server_submit)
+from .geom import generate_fibers
 
 K_BENCH = (0.2, 0.3, 400.0)  # matrix, inclusion, coating
 
@@ -247,6 +249,28 @@ def run_schemes(coatings=(1.0, 4.0, 20.0, 80.0, 400.0), n=128, n_spheres=50, f=0
     return rows
 
 
+# --------------------------------------------------------------------- fibres
+def run_fibers(layers=(0.02, 0.05, 0.1, 0.2, 0.4, 0.8), n=128, n_fibers=40, f=0.40, seeds=(1, 2, 3),
+               k=(1.0, 0.2, 400.0), tol=1e-6, precision=0):
+    """Aligned coated fibres along z (the cylindrical inclusions Sec. 6 names
+    next), the paper's conductivities: transverse and axial conductivity
+    against the coating layer l, over a few seeded realizations."""
+    rows = []
+    for layer in layers:
+        for seed in seeds:
+            ph, _, _ = generate_fibers(n, n_fibers, f, layer, seed)
+            with rve_create_from_phases(ph) as h:
+                r = homogenize(h, k, tol, precision=precision)
+            kv = np.asarray(k)[ph]
+            row = {"layer": layer, "seed": seed, "iters": r.iters.tolist(), "status": r.lc_status.tolist(),
+                   "ms": r.solve_ms, "k_transverse": float(0.5 * (r.K[0, 0] + r.K[1, 1])),
+                   "k_axial": float(r.K[2, 2]), "k_mean": float(kv.mean()),
+                   "k_harmonic": float(1.0 / (1.0 / kv).mean())}
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -260,6 +284,7 @@ def main(argv=None):
     s.add_argument("--baseline", type=int, default=0, help="also run the sequential FP64 path")
     sub.add_parser("sweep256")
     sub.add_parser("run512")
+    sub.add_parser("fibers")
     sc = sub.add_parser("schemes")
     sc.add_argument("--precision", type=int, default=1)
     rs = sub.add_parser("rates")
@@ -278,6 +303,8 @@ def main(argv=None):
             print(json.dumps(seq), flush=True)
     elif a.cmd == "run512":
         run_512()
+    elif a.cmd == "fibers":
+        run_fibers()
     elif a.cmd == "schemes":
         run_schemes(precision=a.precision)
     elif a.cmd == "rates":

@@ -94,3 +94,43 @@ def test_generator_rejects_bad_input():
         geom.generate(32, 1, 0.9, 0.1, 1)  # radius >= 0.5
     with pytest.raises(ValueError):
         geom.generate(32, 5, 0.2, 1.5, 1)
+
+
+# ------------------------------------------------------------ aligned fibres
+def _min_pair_distance_2d(c):
+    d = c[:, None, :] - c[None, :, :]
+    d -= np.round(d)
+    dist = np.sqrt((d ** 2).sum(-1))
+    dist[np.diag_indices(len(c))] = np.inf
+    return dist.min()
+
+
+@pytest.mark.parametrize("n,f", [(20, 0.3), (50, 0.5)])
+def test_fiber_rsa_non_overlap_and_determinism(n, f):
+    """Fibre axes: periodic minimum distance >= 2 r, seeded, in the unit square."""
+    c1, m1 = geom.place_fibers(n, f, 17)
+    c2, m2 = geom.place_fibers(n, f, 17)
+    c3, _ = geom.place_fibers(n, f, 18)
+    assert np.array_equal(c1, c2) and m1 == m2
+    assert not np.array_equal(c1, c3)
+    assert np.all((c1 >= 0) & (c1 < 1))
+    assert _min_pair_distance_2d(c1) >= 2 * geom.fiber_radius(n, f) * (1 - 1e-12)
+
+
+def test_fiber_image_is_invariant_along_z_and_fills_f():
+    """The image of fibres along z repeats one cross-section on every z plane;
+    the voxel fraction of fibre (core + coating) approaches f, that of the
+    core (1 - l)^2 f."""
+    ph, c, _ = geom.generate_fibers(96, 12, 0.35, 0.25, 4)
+    assert np.array_equal(ph, np.broadcast_to(ph[0], ph.shape))
+    frac = np.bincount(ph.ravel(), minlength=3) / ph.size
+    assert abs(frac[1] + frac[2] - 0.35) <= 0.01 * 0.35
+    assert abs(frac[1] - 0.75 ** 2 * 0.35) <= 0.02 * 0.35
+    assert np.array_equal(ph, geom.voxelize_fibers(96, c, geom.fiber_radius(12, 0.35), 0.25))
+
+
+def test_fiber_generator_rejects_bad_input():
+    with pytest.raises(ValueError):
+        geom.generate_fibers(32, 1, 0.9, 0.1, 1)  # radius >= 0.5
+    with pytest.raises(ValueError):
+        geom.generate_fibers(32, 5, 0.2, 1.5, 1)

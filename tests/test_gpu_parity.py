@@ -314,3 +314,35 @@ def test_augmented_lagrangian_rejected_where_not_built():
             rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=1, scheme=3)
         ok = rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=1, scheme=AL)
         assert ok.status == rh.RVE_OK
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_fibers_fixed_iterations_vs_oracle(precision):
+    """Aligned coated fibres (cylindrical inclusions, Sec. 6): three
+    iterations from E, voxel by voxel against the oracle."""
+    print(f"\n[case] fibres fixed iterations precision={precision}", flush=True)
+    ph, _, _ = geom.generate_fibers(48, 10, 0.35, 0.2, 6)
+    ref = oracle.homogenize(ph, K_PAPER_CFG, tol=0.0, max_iter=3, want_field=True)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize(r, K_PAPER_CFG, 0.0, max_iter=3, precision=precision, want_field=True)
+    bar = 1e-11 if precision == 1 else 3e-5
+    assert field_err(g.field, ref.field) <= bar
+    assert tensor_err(g.K, ref.K) <= bar
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_fibers_128_axial_exact(precision):
+    """128^3, 40 coated fibres along z, f = 0.4, l = 0.2: the axial load case
+    converges in one iteration to K_33 = <k> (closed form), K_13 = K_23 = 0;
+    the transverse tensor agrees between precisions within the FP32 bar."""
+    print(f"\n[case] fibres 128 axial precision={precision}", flush=True)
+    ph, _, _ = geom.generate_fibers(128, 40, 0.4, 0.2, 8)
+    k = np.array([1.0, 0.2, 400.0])
+    kmean = k[ph].mean()
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize(r, k, 1e-6, precision=precision)
+        g64 = g if precision == 1 else rh.homogenize(r, k, 1e-6, precision=1)
+    assert int(g.iters[2]) == 1
+    assert abs(g.K[2, 2] - kmean) <= (1e-12 if precision == 1 else 1e-6) * kmean
+    assert np.abs(g.K[:2, 2]).max() <= 1e-6 * kmean
+    assert tensor_err(g.K, g64.K) <= 1e-4

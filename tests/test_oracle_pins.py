@@ -393,3 +393,42 @@ def test_augmented_lagrangian_rate_and_field(n, seed, k):
     k0 = np.sqrt(k.min() * k.max())
     ref = (k[ph] - k0)[None, None] * em.field
     assert np.abs(al.field - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------ aligned fibres
+def test_fibers_axial_load_exact():
+    """Fibres along z (cylindrical inclusions, Sec. 6): the microstructure does
+    not vary along z, so for E = e_3 the uniform field is compatible and its
+    flux k E divergence-free: K_33 = <k> after one iteration, K_13 = K_23 = 0;
+    the transverse entries stay within the Wiener bounds."""
+    ph, _, _ = geom.generate_fibers(16, 6, 0.3, 0.2, 3)
+    r = oracle.homogenize(ph, K_PAPER, tol=1e-10)
+    kv = K_PAPER[ph]
+    assert int(r.iters[2]) == 1
+    np.testing.assert_allclose(r.K[2, 2], kv.mean(), rtol=1e-13)
+    assert np.abs(r.K[:2, 2]).max() <= 1e-12 and np.abs(r.K[2, :2]).max() <= 1e-9
+    lam = np.linalg.eigvalsh(0.5 * (r.K[:2, :2] + r.K[:2, :2].T))
+    assert lam.min() >= 1.0 / (1.0 / kv).mean() and lam.max() <= kv.mean()
+
+
+def _maxwell_garnett_2d(km, ki, kc, f, phi):
+    """Coated cylinder (composite cylinder) in a dilute Maxwell-Garnett matrix,
+    transverse conductivity: textbook result, not from the paper."""
+    keq = kc * ((ki + kc) + phi * (ki - kc)) / ((ki + kc) - phi * (ki - kc))
+    return km * ((keq + km) + f * (keq - km)) / ((keq + km) - f * (keq - km))
+
+
+def test_dilute_coated_fiber_maxwell_garnett():
+    """One coated fibre at the cell centre (f = 0.05, l = 0.3): transverse
+    K_11 = K_22 (the cross-section is symmetric under x <-> y) and within
+    1.5 % of the dilute composite-cylinder estimate (its increment over the
+    matrix within 12 %)."""
+    n, f, layer = 32, 0.05, 0.3
+    ph = geom.voxelize_fibers(n, np.array([[0.5, 0.5]]), geom.fiber_radius(1, f), layer)
+    cnt = np.bincount(ph.ravel(), minlength=3) / ph.size
+    fa = cnt[1] + cnt[2]
+    kmg = _maxwell_garnett_2d(*K_PAPER, fa, cnt[1] / fa)
+    res = oracle.homogenize(ph, K_PAPER, tol=1e-8, lc_mask=3)
+    assert abs(res.K[0, 0] - res.K[1, 1]) <= 1e-10 * res.K[0, 0]
+    assert abs(res.K[0, 0] - kmg) / kmg <= 0.015
+    assert abs((res.K[0, 0] - 1.0) - (kmg - 1.0)) <= 0.12 * (kmg - 1.0)
