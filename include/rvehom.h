@@ -86,10 +86,8 @@ typedef struct {
                                step e+ = E - Gamma0 (lam - k0 d), multiplier step
                                lam+ = lam + k0 (e+ - d), from d = e = E (or init_field)
                                and lam = k d; final_residual is sqrt<|e+ - d+|^2>, K the
-                               flux <k d+>, out_field the state lam - k0 d.  Built
-                               for the grids whose xy-plane pass is one kernel
-                               (N <= 128 except FP32 N = 96); other N, and
-                               equilibrium_check, give RVE_ERR_ARG */
+                               flux <k d+>, out_field the state lam - k0 d; with
+                               equilibrium_check: RVE_ERR_ARG */
 } rve_opts;
 
 typedef struct {

@@ -288,8 +288,8 @@ def homogenize(rve: RVE, k_phases, tol: float = 1e-6, *, max_iter: int = 0, prec
     scheme: "accelerated" (Eyre-Milton, the paper's choice), "basic" (the
     basic scheme the paper names as an alternative: e+ = c, k0 = mean of the
     extreme conductivities) or "augmented_lagrangian" (also named there; k0
-    of Sec. 5; the field returned is its state lam - k0 d; N <= 128 except
-    FP32 N = 96, no equilibrium check)."""
+    of Sec. 5; the field returned is its state lam - k0 d; no equilibrium
+    check)."""
     k = np.ascontiguousarray(k_phases, dtype=np.float64)
     if k.shape != (3,):
         raise RveError(RVE_ERR_ARG, "k_phases must hold 3 conductivities")

@@ -114,18 +114,23 @@ template <typename T, int N> struct Instance {
     static void zgreen_alt(const LaunchArgs &a, hipStream_t s, int red_nper, int lc_sel) {
         zgreen_w<W2>(a, s, red_nper, lc_sel);
     }
-    static void inv(const LaunchArgs &a, hipStream_t s, int lc_sel) {
+    template <bool AL> static void inv_t(const LaunchArgs &a, hipStream_t s, int lc_sel) {
         if constexpr (FIVE) {
             hipLaunchKernelGGL((k_cols<T, N, WC, NTR, true>), dim3(ColTiles<N, WC>::ALL), dim3(NTR), 0, s,
                                (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, (const DevState *)a.st);
-            hipLaunchKernelGGL((k_inv_rows<T, N, G, NTR>), dim3(9 * N * (N / G)), dim3(NTR), 0, s, (T *)a.e,
+            hipLaunchKernelGGL((k_inv_rows<T, N, G, NTR, AL>), dim3(9 * N * (N / G)), dim3(NTR), 0, s, (T *)a.e,
                                a.ph, (const Cx<T> *)a.spec, (const Cx<T> *)a.nyq, (const Cx<T> *)a.tw,
                                a.prm, (const DevState *)a.st, a.part);
         } else {
-            hipLaunchKernelGGL((k_inv_plane<T, N, SP, NTP>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s, (T *)a.e,
-                               a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw,
-                               a.prm, (const DevState *)a.st, a.part, ch0(lc_sel));
+            hipLaunchKernelGGL((k_inv_plane<T, N, SP, NTP, false, AL>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s,
+                               (T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
+                               (const DevState *)a.st, a.part, ch0(lc_sel));
         }
+    }
+    static void inv(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_t<false>(a, s, lc_sel); }
+    static void inv_al(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_t<true>(a, s, lc_sel); }
+    static void to_tau(const LaunchArgs &a, size_t M, hipStream_t s) {
+        hipLaunchKernelGGL((k_to_tau<T>), dim3(1024), dim3(256), 0, s, (T *)a.e, a.ph, M, a.prm);
     }
     // fused inverse + next forward pass (whole planes in LDS; not where the
     // fused kernel would spill registers heavily: FP32 96^3)
@@ -186,6 +191,8 @@ template <typename T, int N> struct Instance {
             &from_f64,
             &to_f64,
             FUSED ? &inv_fwd_al : nullptr,
+            &inv_al,
+            &to_tau,
         };
         return &o;
     }

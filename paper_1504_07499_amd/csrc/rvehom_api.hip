@@ -516,10 +516,14 @@ int Solver::begin(const uint8_t *d_phase, const double k[3], double tol, const S
     launches.clear();
     eq_check = o.eq_check != 0;
     al = o.scheme == 2;
+    if (al) {
+        // the augmented-Lagrangian state: tau^0 = (k - k0) e^0 in the field buffer
+        ops->to_tau(a, M, s);
+        HIP_CHECK(hipGetLastError());
+    }
     {
-        // (the augmented-Lagrangian update exists only in the fused pass)
         const char *f = getenv("RVEHOM_FUSED");
-        fused = ops->inv_fwd != nullptr && !eq_check && (al || !(f && f[0] == '0'));
+        fused = ops->inv_fwd != nullptr && !eq_check && !(f && f[0] == '0');
     }
     {
         const char *f = getenv("RVEHOM_MERGE");
@@ -554,7 +558,7 @@ int Solver::launch_iteration(const LaunchArgs &a, hipStream_t s, int mask, hipEv
         switch (kk) {
         case 0: ops->fwd(a, s, lc_sel); break;
         case 1: (zvar ? ops->zgreen_alt : ops->zgreen)(a, s, red_in_z ? ops->nper : 0, lc_sel); break;
-        case 2: fused ? (al ? ops->inv_fwd_al : ops->inv_fwd)(a, s, lc_sel) : ops->inv(a, s, lc_sel); break;
+        case 2: (fused ? (al ? ops->inv_fwd_al : ops->inv_fwd) : (al ? ops->inv_al : ops->inv))(a, s, lc_sel); break;
         default: launch_reduce(a, ops->nper, s); break;
         }
         if (timed) {
@@ -892,19 +896,15 @@ static rve_status solve_chains(rve_s *r, const SolverOps *ops, const double k[3]
     return worst_status(res, o.lc_mask);
 }
 
-// The scheme option against what the grid size's kernels provide.
+// The scheme option against the other options.
 int check_scheme(const SolverOpts &o, const SolverOps *ops) {
+    (void)ops;
     if (o.scheme < 0 || o.scheme > 2) {
         set_error("scheme must be 0 (accelerated), 1 (basic) or 2 (augmented Lagrangian)");
         return RVE_ERR_ARG;
     }
     if (o.scheme == 2 && o.eq_check) {
         set_error("the augmented-Lagrangian scheme has no equilibrium check");
-        return RVE_ERR_ARG;
-    }
-    if (o.scheme == 2 && !ops->inv_fwd_al) {
-        set_error("the augmented-Lagrangian scheme is built for whole-plane grids only (not N = %d in %s)", ops->n,
-                  ops->precision ? "FP64" : "FP32");
         return RVE_ERR_ARG;
     }
     return RVE_OK;

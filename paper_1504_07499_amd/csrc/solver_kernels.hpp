@@ -302,23 +302,22 @@ __device__ __forceinline__ void em_update_tau(T *a, const T *c, unsigned p, cons
 //     tau+ = lam+ - k0 d+ = tau + k0 g,
 //     k d+ = tau+ + k0 c                               (flux).
 // tau is the one field carried between iterations: the buffer that holds e
-// for the accelerated scheme holds tau here.  The first pass finds e^0 there
-// (the start field, E by default) and takes tau^0 = (k - k0) e^0 (first).
+// for the accelerated scheme holds tau here (k_to_tau writes
+// tau^0 = (k - k0) e^0 from the start field before the first pass).
 // lut[phase] = {k - k0, 1 / (k + k0)} (LDS).  As em_update_tau, st collects
 // sum (tau+ - tm) and se sum c, so that the caller's
 // count * tm + k0 * (sum c) completes the flux.
 template <typename T, int V>
 __device__ __forceinline__ void al_update_tau(T *a, const T *c, unsigned p, const Cx<T> *lut, T k0, T tm, T ec,
-                                              bool first, double &r2, double &st, double &se, T *tau) {
+                                              double &r2, double &st, double &se, T *tau) {
     T r2v = (T)0, stv = (T)0, sev = (T)0;
 #pragma unroll
     for (int i = 0; i < V; ++i) {
         const T ci = c[i] + ec;
         const Cx<T> dg = lut[ph_at(p, i)];
-        const T ti = first ? dg.x * a[i] : a[i];
-        const T g = (dg.x * ci - ti) * dg.y;
+        const T g = (dg.x * ci - a[i]) * dg.y;
         r2v += g * g;
-        a[i] = ti + k0 * g;
+        a[i] = a[i] + k0 * g;
         tau[i] = a[i] - tm;
         stv += tau[i];
         sev += ci;
@@ -326,6 +325,24 @@ __device__ __forceinline__ void al_update_tau(T *a, const T *c, unsigned p, cons
     r2 += (double)r2v;
     st += (double)stv;
     se += (double)sev;
+}
+
+// The augmented-Lagrangian update of the separate inverse passes: as
+// al_update_tau, with the flux k d+ = tau+ + k0 c summed per voxel in FP64
+// (fl) and se = sum c.
+template <typename T, int V>
+__device__ __forceinline__ void al_update(T *a, const T *c, unsigned p, T dk0, T dk1, T dk2, T gm0, T gm1, T gm2,
+                                          T k0, T ec, double &r2, double &fl, double &se) {
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+        const T ci = c[i] + ec;
+        const int pi = ph_at(p, i);
+        const T g = (pick<T>(pi, dk0, dk1, dk2) * ci - a[i]) * pick<T>(pi, gm0, gm1, gm2);
+        r2 += (double)g * (double)g;
+        a[i] = a[i] + k0 * g;
+        fl += (double)a[i] + (double)k0 * (double)ci;
+        se += (double)ci;
+    }
 }
 
 // Waves per SIMD asked of the plane kernels: as many workgroups per CU as
@@ -379,9 +396,11 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
     ch += ch0;  // the grid covers channels ch0 .. (all nine, or one load case's three)
     const int lc = ch / 3;
     // PHI: the flux k e of the equilibrium check (step 1); else tau = (k - k0) e
+    // (augmented Lagrangian: the buffer already holds tau)
     if (PHI ? !st->eq_pending[lc] : st->done[lc]) return;
     const double *lut = PHI ? prm->k : prm->dk;
-    const T d0 = (T)lut[0], d1 = (T)lut[1], d2 = (T)lut[2];
+    const bool tau_in = !PHI && prm->scheme == 2;
+    const T d0 = tau_in ? (T)1 : (T)lut[0], d1 = tau_in ? (T)1 : (T)lut[1], d2 = tau_in ? (T)1 : (T)lut[2];
     const T tm = PHI ? (T)0 : (T)st->tau_mean[ch];  // only the discarded mean mode changes
     const T *eb = e + (size_t)ch * N * NN + (size_t)z * NN;
     const uint8_t *pb = ph + (size_t)z * NN;
@@ -737,7 +756,6 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
                                                   const DevState *__restrict__ st,
                                                   double *__restrict__ part, int ch0) {
     static_assert(!FWD || S == 1, "the fused inverse/forward pass needs a whole plane");
-    static_assert(!AL || FWD, "the augmented-Lagrangian update is built into the fused pass");
     // row pitch: even for whole planes (16-byte pair accesses, paired FFT
     // stages), N/2 + 1 for split planes
     constexpr int H = N / 2, RS = (S == 1) ? H + 2 : H + 1, ROWS = N / S, V = VecOf<T>::V, NN = N * N;
@@ -836,9 +854,9 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
     const double k0d = prm->k[0], k1d = prm->k[1], k2d = prm->k[2];
     const T d0 = (T)prm->dk[0], d1 = (T)prm->dk[1], d2 = (T)prm->dk[2];
     const T tm = (T)st->tau_mean[ch];
-    const bool first = AL && st->iter == 0;  // the buffer still holds e^0
     const T k0t = (T)prm->k0;
-    (void)d0, (void)d1, (void)d2, (void)tm, (void)first, (void)k0t;
+    const T g0 = (T)prm->gam[0], g1 = (T)prm->gam[1], g2 = (T)prm->gam[2];
+    (void)d0, (void)d1, (void)d2, (void)tm, (void)k0t, (void)g0, (void)g1, (void)g2;
     T *eb = e + (size_t)ch * N * NN + (size_t)z * NN;
     const uint8_t *pb = ph + (size_t)z * NN;
     double r2 = 0.0, fl = 0.0, se = 0.0;
@@ -879,7 +897,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
                     // read; fl collects sum tau here (the flux follows below)
                     T tau[V];
                     if constexpr (AL)
-                        al_update_tau<T, V>(a[i], c, p[i], lut, k0t, tm, ec, first, r2, fl, se, tau);
+                        al_update_tau<T, V>(a[i], c, p[i], lut, k0t, tm, ec, r2, fl, se, tau);
                     else
                         em_update_tau<T, V>(a[i], c, p[i], lut, tm, ec, r2, fl, se, tau);
                     vstore<T>(eb + y * N + x, a[i]);
@@ -890,7 +908,10 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
                         for (int j = 0; j < V; j += 2) plane[m * RS + (x + j) / 2] = Cx<T>{tau[j], tau[j + 1]};
                     }
                 } else {
-                    em_update<T, V>(a[i], c, p[i], w0, w1, w2, k0d, k1d, k2d, ec, r2, fl, se);
+                    if constexpr (AL)
+                        al_update<T, V>(a[i], c, p[i], d0, d1, d2, g0, g1, g2, k0t, ec, r2, fl, se);
+                    else
+                        em_update<T, V>(a[i], c, p[i], w0, w1, w2, k0d, k1d, k2d, ec, r2, fl, se);
                     vstore<T>(eb + y * N + x, a[i]);
                 }
             }
@@ -945,7 +966,8 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(const T *__restrict__ e, const 
     const int lc = ch / 3;
     if (PHI ? !st->eq_pending[lc] : st->done[lc]) return;
     const double *lut = PHI ? prm->k : prm->dk;
-    const T d0 = (T)lut[0], d1 = (T)lut[1], d2 = (T)lut[2];
+    const bool tau_in = !PHI && prm->scheme == 2;  // augmented Lagrangian: the buffer holds tau
+    const T d0 = tau_in ? (T)1 : (T)lut[0], d1 = tau_in ? (T)1 : (T)lut[1], d2 = tau_in ? (T)1 : (T)lut[2];
     const T tm = PHI ? (T)0 : (T)st->tau_mean[ch];
     const T *eb = e + (size_t)ch * N * NN + (size_t)z * NN + (size_t)y0 * N;
     const uint8_t *pb = ph + (size_t)z * NN + (size_t)y0 * N;
@@ -1047,7 +1069,7 @@ __global__ __launch_bounds__(NT) void k_cols(Cx<T> *__restrict__ spec, Cx<T> *__
     }
 }
 
-template <typename T, int N, int G, int NT>
+template <typename T, int N, int G, int NT, bool AL = false>
 __global__ __launch_bounds__(NT) void k_inv_rows(T *__restrict__ e, const uint8_t *__restrict__ ph,
                                                  const Cx<T> *__restrict__ spec, const Cx<T> *__restrict__ nyq,
                                                  const Cx<T> *__restrict__ twg,
@@ -1095,7 +1117,11 @@ __global__ __launch_bounds__(NT) void k_inv_rows(T *__restrict__ e, const uint8_
             c[i] = zz.x;
             c[i + 1] = zz.y;
         }
-        em_update<T, V>(a, c, p, w0, w1, w2, k0d, k1d, k2d, ec, r2, fl, se);
+        if constexpr (AL)
+            al_update<T, V>(a, c, p, (T)prm->dk[0], (T)prm->dk[1], (T)prm->dk[2], (T)prm->gam[0],
+                            (T)prm->gam[1], (T)prm->gam[2], (T)prm->k0, ec, r2, fl, se);
+        else
+            em_update<T, V>(a, c, p, w0, w1, w2, k0d, k1d, k2d, ec, r2, fl, se);
         vstore<T>(eb + y * N + x, a);
     }
     double v3[3] = {r2, fl, se};
@@ -1110,6 +1136,19 @@ __global__ __launch_bounds__(NT) void k_inv_rows(T *__restrict__ e, const uint8_
 
 // e = E_lc for every voxel; solver state reset.  Load cases outside the mask
 // start frozen.
+// Augmented Lagrangian: the start field e^0 becomes tau^0 = (k - k0) e^0 in
+// place, for the load cases being solved (lam^0 = k e^0, d^0 = e^0).
+template <typename T>
+__global__ void k_to_tau(T *__restrict__ e, const uint8_t *__restrict__ ph, size_t M,
+                         const DevParams *__restrict__ prm) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < 9 * M; i += stride) {
+        const int lc = (int)(i / (3 * M));
+        if (!((prm->lc_mask >> lc) & 1)) continue;
+        e[i] = (T)(prm->dk[ph[i % M]] * (double)e[i]);
+    }
+}
+
 template <typename T>
 __global__ void k_init(T *__restrict__ e, size_t M, const DevParams *__restrict__ prm, DevState *__restrict__ st) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;

@@ -52,9 +52,12 @@ struct SolverOps {
     void (*init)(const LaunchArgs &, size_t M, hipStream_t);
     void (*from_f64)(void *e, const double *src, size_t count, hipStream_t);
     void (*to_f64)(double *dst, const void *e, size_t count, hipStream_t);
-    // the fused pass with the augmented-Lagrangian update (nullptr where
-    // there is no fused pass)
+    // the augmented-Lagrangian update: fused pass (nullptr where there is no
+    // fused pass), separate inverse pass, and the start field's conversion to
+    // tau^0 = (k - k0) e^0
     void (*inv_fwd_al)(const LaunchArgs &, hipStream_t, int lc_sel);
+    void (*inv_al)(const LaunchArgs &, hipStream_t, int lc_sel);
+    void (*to_tau)(const LaunchArgs &, size_t M, hipStream_t);
 };
 
 const SolverOps *ops_f32(int n);
