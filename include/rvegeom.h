@@ -77,6 +77,19 @@ int rvegeom_voxelize_fibers(int n, int n_fibers, const double *centers, double r
 int rvegeom_generate_fibers(int n, int n_fibers, double volume_fraction, double layer,
                             uint64_t seed, uint8_t *phases, double *centers, int *method);
 
+/* Mixed inclusions: coated fibres along z and coated spheres in one cell,
+ * both with coating layer l.  Fibres are placed first (as above, seed), then
+ * spheres by RSA (1e6 attempts, no shaking, a second stream derived from the
+ * seed) against each other and against the fibres: a sphere's centre lies at
+ * least rs + rf from every fibre axis in the cross-section.  The fractions
+ * are those of each shape (coating included); f_spheres + f_fibers < 1.
+ * sphere_centers: 3 n_spheres doubles, fiber_centers: 2 n_fibers. */
+int rvegeom_place_mixed(int n_spheres, double f_spheres, int n_fibers, double f_fibers,
+                        uint64_t seed, double *sphere_centers, double *fiber_centers,
+                        int *method);
+int rvegeom_generate_mixed(int n, int n_spheres, double f_spheres, int n_fibers,
+                           double f_fibers, double layer, uint64_t seed, uint8_t *phases);
+
 #ifdef __cplusplus
 }
 #endif

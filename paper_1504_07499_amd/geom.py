@@ -52,6 +52,12 @@ def _load():
     lib.rvegeom_generate_fibers.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                             ctypes.c_double, ctypes.c_uint64, u8p, dp, ip]
     lib.rvegeom_generate_fibers.restype = ctypes.c_int
+    lib.rvegeom_place_mixed.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                        ctypes.c_uint64, dp, dp, ip]
+    lib.rvegeom_place_mixed.restype = ctypes.c_int
+    lib.rvegeom_generate_mixed.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_uint64, u8p]
+    lib.rvegeom_generate_mixed.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -155,6 +161,37 @@ def generate_fibers(n: int, n_fibers: int, volume_fraction: float, layer: float,
     if rc != 0:
         raise ValueError("invalid fibre geometry arguments")
     return out, c, int(m.value)
+
+
+def place_mixed(n_spheres: int, f_spheres: float, n_fibers: int, f_fibers: float, seed: int):
+    """Fibre axes (n_f, 2) and sphere centres (n_s, 3) of a mixed cell."""
+    lib = _load()
+    cs = np.zeros((int(n_spheres), 3))
+    cf = np.zeros((int(n_fibers), 2))
+    m = ctypes.c_int(-1)
+    rc = lib.rvegeom_place_mixed(int(n_spheres), float(f_spheres), int(n_fibers), float(f_fibers), int(seed),
+                                 cs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 cf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(m))
+    if rc == -2:
+        raise RuntimeError("mixed placement exhausted its attempt budget (jammed)")
+    if rc != 0:
+        raise ValueError("invalid mixed placement arguments")
+    return cs, cf
+
+
+def generate_mixed(n: int, n_spheres: int, f_spheres: float, n_fibers: int, f_fibers: float,
+                   layer: float, seed: int) -> np.ndarray:
+    """Coated spheres and coated fibres along z in one cell: phases (n,n,n) uint8."""
+    lib = _load()
+    out = np.zeros((n, n, n), dtype=np.uint8)
+    rc = lib.rvegeom_generate_mixed(int(n), int(n_spheres), float(f_spheres), int(n_fibers),
+                                    float(f_fibers), float(layer), int(seed),
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    if rc == -2:
+        raise RuntimeError("mixed placement exhausted its attempt budget (jammed)")
+    if rc != 0:
+        raise ValueError("invalid mixed geometry arguments")
+    return out
 
 
 def random_phases(n: int, seed: int, probs=(0.5, 0.3, 0.2)) -> np.ndarray:

@@ -215,3 +215,58 @@ extern "C" int rvegeom_generate_fibers(int n, int n_fibers, double f, double lay
         for (size_t i = 0; i < c.size(); ++i) centers[i] = c[i];
     return 0;
 }
+
+// ------------------------------------------------------ spheres and fibres
+
+extern "C" int rvegeom_place_mixed(int n_spheres, double f_spheres, int n_fibers, double f_fibers, uint64_t seed,
+                                   double *sphere_centers, double *fiber_centers, int *method) {
+    if (n_spheres < 1 || n_fibers < 1 || !(f_spheres > 0.0) || !(f_fibers > 0.0) ||
+        !(f_spheres + f_fibers < 1.0) || !sphere_centers || !fiber_centers)
+        return -1;
+    const double rs = rvegeom_radius(n_spheres, f_spheres), rf = rvegeom_fiber_radius(n_fibers, f_fibers);
+    if (!(rs < 0.5) || !(rf < 0.5)) return -1;
+    // fibres first (RSA of their axes, own seed stream), then spheres by RSA
+    // against the fibres (axis distance in the cross-section >= rs + rf) and
+    // each other; no shaking for the spheres
+    int rc = place_balls<2>(n_fibers, rf, seed, fiber_centers, method);
+    if (rc != 0) return rc;
+    Uniform u(seed ^ 0x9e3779b97f4a7c15ull);
+    std::vector<double> c(3 * (size_t)n_spheres);
+    const double ss2 = 4.0 * rs * rs, sf2 = (rs + rf) * (rs + rf);
+    int placed = 0;
+    const long budget = 1000000;
+    for (long a = 0; a < budget && placed < n_spheres; ++a) {
+        double p[3] = {0.0, 0.0, 0.0};
+        for (int d = 0; d < 3; ++d) p[d] = u.next();
+        bool ok = fits_n<3>(c, placed, p, ss2, -1);
+        for (int i = 0; ok && i < n_fibers; ++i)
+            if (min_image_d2n<2>(fiber_centers + 2 * i, p) < sf2) ok = false;
+        if (ok) {
+            for (int d = 0; d < 3; ++d) c[3 * (size_t)placed + d] = p[d];
+            ++placed;
+        }
+    }
+    if (placed < n_spheres) return -2;
+    for (size_t i = 0; i < c.size(); ++i) sphere_centers[i] = c[i];
+    return 0;
+}
+
+extern "C" int rvegeom_generate_mixed(int n, int n_spheres, double f_spheres, int n_fibers, double f_fibers,
+                                      double layer, uint64_t seed, uint8_t *phases) {
+    if (n < 1 || !phases || !(layer > 0.0 && layer < 1.0)) return -1;
+    if (n_spheres < 1 || n_fibers < 1) return -1;
+    std::vector<double> cs(3 * (size_t)n_spheres), cf(2 * (size_t)n_fibers);
+    int rc = rvegeom_place_mixed(n_spheres, f_spheres, n_fibers, f_fibers, seed, cs.data(), cf.data(), nullptr);
+    if (rc != 0) return rc;
+    const size_t M = (size_t)n * n * n;
+    std::vector<uint8_t> sph(M);
+    rc = rvegeom_voxelize_fibers(n, n_fibers, cf.data(), rvegeom_fiber_radius(n_fibers, f_fibers), layer, phases);
+    if (rc != 0) return rc;
+    rc = rvegeom_voxelize(n, n_spheres, cs.data(), rvegeom_radius(n_spheres, f_spheres), layer, sph.data());
+    if (rc != 0) return rc;
+    // inclusions do not overlap, so a voxel is claimed by at most one shape up
+    // to voxel-centre rounding; an inclusion (core) id wins over a coating id
+    for (size_t v = 0; v < M; ++v)
+        if (sph[v] == 1 || (sph[v] == 2 && phases[v] == 0)) phases[v] = sph[v];
+    return 0;
+}

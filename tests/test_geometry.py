@@ -134,3 +134,22 @@ def test_fiber_generator_rejects_bad_input():
         geom.generate_fibers(32, 1, 0.9, 0.1, 1)  # radius >= 0.5
     with pytest.raises(ValueError):
         geom.generate_fibers(32, 5, 0.2, 1.5, 1)
+
+
+def test_mixed_spheres_and_fibers():
+    """Mixed inclusions: spheres keep rs + rf from every fibre axis and 2 rs
+    from each other; both shapes' voxel fractions approach their targets."""
+    cs, cf = geom.place_mixed(10, 0.1, 8, 0.2, 3)
+    rs, rf = geom.radius(10, 0.1), geom.fiber_radius(8, 0.2)
+    d = cs[:, None, :2] - cf[None, :, :]
+    d -= np.round(d)
+    assert np.sqrt((d ** 2).sum(-1)).min() >= (rs + rf) * (1 - 1e-12)
+    assert _min_pair_distance(cs) >= 2 * rs * (1 - 1e-12)
+    assert _min_pair_distance_2d(cf) >= 2 * rf * (1 - 1e-12)
+    ph = geom.generate_mixed(96, 10, 0.1, 8, 0.2, 0.2, 3)
+    fib = geom.voxelize_fibers(96, cf, rf, 0.2)
+    sph = geom.voxelize(96, cs, rs, 0.2)
+    assert np.array_equal(ph[(fib > 0) & (sph == 0)], fib[(fib > 0) & (sph == 0)])
+    assert np.array_equal(ph[sph == 1], sph[sph == 1])
+    frac = np.bincount(ph.ravel(), minlength=3) / ph.size
+    assert abs(frac[1] + frac[2] - 0.3) <= 0.02 * 0.3
