@@ -8,7 +8,8 @@ nothing from the product path.
 The numerics live in ``em_oracle.c`` (plain C99, own mixed-radix FFT,
 OpenMP over pencils).  This module only marshals numpy arrays through ctypes.
 Paper: arXiv:1504.07499, Sec. 3 (eq. (1), eq. (3), the Green operator, the
-Algorithm of the accelerated scheme, L_hom from <phi>) and Sec. 5 (L0).
+Algorithm of the accelerated scheme, L_hom from <phi>) and Sec. 5 (L0); the
+elastic case that Sec. 6 names as the extension (``homogenize_elastic``).
 """
 from __future__ import annotations
 
@@ -54,6 +55,10 @@ def _load():
         ctypes.c_int, ctypes.c_int, dp, dp, ip, ip, dp, dp, dp, ctypes.c_int, dp,
         ctypes.c_int, ctypes.c_int]
     lib.orc_homogenize.restype = ctypes.c_int
+    lib.orc_homogenize_elastic.argtypes = [
+        ctypes.c_int, ctypes.POINTER(ctypes.c_uint8), dp, ctypes.c_int, dp, ctypes.c_double,
+        ctypes.c_int, dp, ip, ip, dp, dp, ctypes.c_int, dp]
+    lib.orc_homogenize_elastic.restype = ctypes.c_int
     lib.orc_threads.argtypes = []
     lib.orc_threads.restype = ctypes.c_int
     lib.orc_set_threads.argtypes = [ctypes.c_int]
@@ -143,3 +148,49 @@ def homogenize(phases: np.ndarray, k_phases, tol: float = 1e-6, max_iter: int = 
     h = hist.reshape(3, hc)
     history = [h[j, :min(int(iters[j]), hc)].copy() for j in range(3)]
     return OracleResult(K.reshape(3, 3), iters, status, res, eq, history, field)
+
+
+# Tensor components of the elastic fields: 11, 22, 33, 23, 13, 12 (tensor,
+# not engineering, shear components).
+EL_COMPS = ((0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1))
+
+
+@dataclass
+class ElasticResult:
+    S: np.ndarray            # (nlc, 6) mean stress per load case
+    iters: np.ndarray
+    status: np.ndarray
+    final_residual: np.ndarray
+    history: list
+    field: np.ndarray | None  # (nlc, 6, n, n, n) or None
+
+
+def homogenize_elastic(phases: np.ndarray, moduli, E, tol: float = 1e-6, max_iter: int = 10000,
+                       want_field: bool = False, hist_cap: int | None = None) -> ElasticResult:
+    """The accelerated scheme for isotropic elastic phases.  moduli: (3, 2)
+    bulk and shear modulus per phase; E: (nlc, 6) imposed mean strains
+    (components 11, 22, 33, 23, 13, 12 of the tensor)."""
+    lib = _load()
+    ph = np.ascontiguousarray(phases, dtype=np.uint8)
+    n = ph.shape[0]
+    assert ph.shape == (n, n, n)
+    mod = np.ascontiguousarray(moduli, dtype=np.float64).reshape(6)
+    Ev = np.ascontiguousarray(E, dtype=np.float64).reshape(-1, 6)
+    nlc = Ev.shape[0]
+    S = np.zeros((nlc, 6))
+    iters = np.zeros(nlc, dtype=np.int32)
+    status = np.zeros(nlc, dtype=np.int32)
+    res = np.zeros(nlc)
+    hc = int(max_iter if hist_cap is None else hist_cap)
+    hist = np.zeros(nlc * hc)
+    field = np.zeros((nlc, 6, n, n, n)) if want_field else None
+    rc = lib.orc_homogenize_elastic(
+        n, ph.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), _dp(mod), nlc, _dp(Ev), float(tol),
+        int(max_iter), _dp(S), iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+        status.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(res), _dp(hist), hc,
+        _dp(field) if field is not None else None)
+    if rc != 0:
+        raise ValueError(f"oracle rejected its arguments (code {rc})")
+    h = hist.reshape(nlc, hc)
+    history = [h[j, :min(int(iters[j]), hc)].copy() for j in range(nlc)]
+    return ElasticResult(S, iters, status, res, history, field)

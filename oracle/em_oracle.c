@@ -508,3 +508,186 @@ int orc_homogenize(int n, const uint8_t *phase, const double kph[3], double tol,
     free(lam);
     return ORC_OK;
 }
+
+/* ========================================================================
+ * Elastic case.  Sec. 6 names linear elasticity as the extension of the
+ * method; the scheme is the same accelerated iteration with isotropic phases
+ * C = 3 kappa J + 2 mu K (J, K: the hydrostatic and deviatoric projectors)
+ * and the isotropic reference C0 (kappa0, mu0):
+ *   tau   = (C - C0) : e                                      (step 2)
+ *   c^    = -Gamma0(xi) : tau^ for xi != 0, c^(0) = M E       (steps 3-5)
+ *   eps   = sqrt(<|e - c|^2>) / |E|   (Frobenius norm of the full tensor)
+ *   e+    = e + 2 (C + C0)^-1 C0 : (c - e), i.e. the hydrostatic part of
+ *           c - e times 2 kappa0 / (kappa + kappa0), the deviatoric part
+ *           times 2 mu0 / (mu + mu0)                          (step 7)
+ *   column of C_hom: the mean stress <C : e+>
+ * with the Green operator of the isotropic reference medium
+ *   Gamma0_ijkh = (d_ki x_h x_j + d_hi x_k x_j + d_kj x_h x_i + d_hj x_k x_i)
+ *                 / (4 mu0 |x|^2)
+ *               - (lambda0 + mu0) / (mu0 (lambda0 + 2 mu0)) x_i x_j x_k x_h / |x|^4,
+ * lambda0 = kappa0 - 2 mu0 / 3, averaged over the signs of the Nyquist
+ * components as in R3, and kappa0 = sqrt(min kappa max kappa),
+ * mu0 = sqrt(min mu max mu) (the Sec. 5 rule applied to each modulus).
+ * Tensors are stored as the 6 components 11, 22, 33, 23, 13, 12 of the full
+ * symmetric tensor (tensor shear components, not engineering ones).
+ * The equations are not in the paper (they are in the cited elastic work):
+ * parity unpinned against that work; pinned by closed forms and a dense
+ * displacement solve in the tests.
+ * ====================================================================== */
+
+static const int EL_I[6] = {0, 1, 2, 1, 0, 0};
+static const int EL_J[6] = {0, 1, 2, 2, 2, 1};
+
+static int el_comp(int i, int j)
+{
+    if (i == j) return i;
+    int a = i < j ? i : j, b = i < j ? j : i;
+    return (a == 1 && b == 2) ? 3 : (a == 0 && b == 2) ? 4 : 5;
+}
+
+/* Gamma0_ijkh at mode kk, averaged over the Nyquist signs (R3). */
+static void el_green_symbol(int n, const int kk[3], double mu0, double beta, double G[3][3][3][3])
+{
+    double xi[3];
+    int flip = 0;
+    for (int d = 0; d < 3; ++d) {
+        xi[d] = wavenumber(kk[d], n);
+        if (is_nyquist(kk[d], n)) flip |= 1 << d;
+    }
+    memset(G, 0, sizeof(double) * 81);
+    int count = 0;
+    for (int s = 0; s < 8; ++s) {
+        if (s & ~flip) continue;
+        double v[3];
+        for (int d = 0; d < 3; ++d) v[d] = ((s >> d) & 1) ? -xi[d] : xi[d];
+        double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                for (int k = 0; k < 3; ++k)
+                    for (int h = 0; h < 3; ++h) {
+                        double a = ((k == i) * v[h] * v[j] + (h == i) * v[k] * v[j] +
+                                    (k == j) * v[h] * v[i] + (h == j) * v[k] * v[i]) / (4.0 * mu0 * v2);
+                        double b = beta * v[i] * v[j] * v[k] * v[h] / (v2 * v2);
+                        G[i][j][k][h] += a - b;
+                    }
+        ++count;
+    }
+    for (int i = 0; i < 81; ++i) ((double *)G)[i] /= (double)count;
+}
+
+int orc_homogenize_elastic(int n, const uint8_t *phase, const double moduli[6], int nlc,
+                           const double *Elc, double tol, int max_iter, double *S, int *iters,
+                           int *status, double *final_res, double *hist, int hist_cap,
+                           double *out_field)
+{
+    if (n < 1 || nlc < 1 || !Elc || max_iter < 1 || !(tol >= 0.0) || !phase || !moduli || !S)
+        return ORC_ERR_ARG;
+    for (int q = 0; q < 6; ++q)
+        if (!(moduli[q] > 0.0) || !isfinite(moduli[q])) return ORC_ERR_ARG;
+    size_t M = (size_t)n * n * n;
+    for (size_t v = 0; v < M; ++v)
+        if (phase[v] > 2) return ORC_ERR_ARG;
+    double kap[3], mu[3];
+    for (int p = 0; p < 3; ++p) {
+        kap[p] = moduli[2 * p];
+        mu[p] = moduli[2 * p + 1];
+    }
+    double kmin = fmin(kap[0], fmin(kap[1], kap[2])), kmax = fmax(kap[0], fmax(kap[1], kap[2]));
+    double mmin = fmin(mu[0], fmin(mu[1], mu[2])), mmax = fmax(mu[0], fmax(mu[1], mu[2]));
+    double kap0 = sqrt(kmin * kmax), mu0 = sqrt(mmin * mmax);
+    double lam0 = kap0 - 2.0 * mu0 / 3.0;
+    double beta = (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0));
+
+    double *e = malloc(sizeof(double) * 6 * M);
+    cplx *t = malloc(sizeof(cplx) * 6 * M);
+    if (!e || !t) {
+        free(e);
+        free(t);
+        return ORC_ERR_ARG;
+    }
+    for (int lc = 0; lc < nlc; ++lc) {
+        const double *E = Elc + 6 * lc;
+        double E2 = 0.0;
+        for (int q = 0; q < 6; ++q) E2 += (q < 3 ? 1.0 : 2.0) * E[q] * E[q];
+        double Enorm = sqrt(E2);
+        for (int q = 0; q < 6; ++q)
+            for (size_t v = 0; v < M; ++v) e[q * M + v] = E[q];
+        double r = 0.0, Sm[6] = {0, 0, 0, 0, 0, 0};
+        int st = ORC_NOT_CONVERGED, it = 0;
+        while (it < max_iter) {
+            /* tau = (C - C0) : e = 3 (kappa - kappa0) (tr e / 3) I + 2 (mu - mu0) dev e */
+            for (size_t v = 0; v < M; ++v) {
+                int p = phase[v];
+                double tr3 = (e[v] + e[M + v] + e[2 * M + v]) / 3.0;
+                for (int q = 0; q < 6; ++q) {
+                    double dev = e[q * M + v] - (q < 3 ? tr3 : 0.0);
+                    t[q * M + v] = 3.0 * (kap[p] - kap0) * (q < 3 ? tr3 : 0.0) + 2.0 * (mu[p] - mu0) * dev;
+                }
+            }
+            for (int q = 0; q < 6; ++q) orc_fft3(n, (double *)(t + q * M), -1);
+            /* c^ = -Gamma0 : tau^ (sum over the full k, h), c^(0) = M E */
+            #pragma omp parallel for schedule(static)
+            for (long idx = 0; idx < (long)M; ++idx) {
+                int kk[3] = {(int)(idx % n), (int)((idx / n) % n), (int)(idx / ((long)n * n))};
+                if (kk[0] == 0 && kk[1] == 0 && kk[2] == 0) {
+                    for (int q = 0; q < 6; ++q) t[q * M + idx] = (double)M * E[q];
+                    continue;
+                }
+                double G[3][3][3][3];
+                el_green_symbol(n, kk, mu0, beta, G);
+                cplx tv[6], cv[6];
+                for (int q = 0; q < 6; ++q) tv[q] = t[q * M + idx];
+                for (int q = 0; q < 6; ++q) {
+                    cplx acc = 0;
+                    for (int k = 0; k < 3; ++k)
+                        for (int h = 0; h < 3; ++h) acc += G[EL_I[q]][EL_J[q]][k][h] * tv[el_comp(k, h)];
+                    cv[q] = -acc;
+                }
+                for (int q = 0; q < 6; ++q) t[q * M + idx] = cv[q];
+            }
+            for (int q = 0; q < 6; ++q) orc_fft3(n, (double *)(t + q * M), +1);
+            /* residual, update, mean stress */
+            double r2 = 0.0;
+            double acc[6] = {0, 0, 0, 0, 0, 0};
+            for (size_t v = 0; v < M; ++v) {
+                int p = phase[v];
+                double d[6];
+                for (int q = 0; q < 6; ++q) {
+                    d[q] = creal(t[q * M + v]) / (double)M - e[q * M + v];
+                    r2 += (q < 3 ? 1.0 : 2.0) * d[q] * d[q];
+                }
+                double dtr3 = (d[0] + d[1] + d[2]) / 3.0;
+                double wk = 2.0 * kap0 / (kap[p] + kap0), wm = 2.0 * mu0 / (mu[p] + mu0);
+                for (int q = 0; q < 6; ++q) {
+                    double hyd = q < 3 ? dtr3 : 0.0;
+                    e[q * M + v] += wk * hyd + wm * (d[q] - hyd);
+                }
+                double tr3 = (e[v] + e[M + v] + e[2 * M + v]) / 3.0;
+                for (int q = 0; q < 6; ++q) {
+                    double hyd = q < 3 ? tr3 : 0.0;
+                    acc[q] += 3.0 * kap[p] * hyd + 2.0 * mu[p] * (e[q * M + v] - hyd);
+                }
+            }
+            for (int q = 0; q < 6; ++q) Sm[q] = acc[q] / (double)M;
+            r = sqrt(r2 / (double)M) / Enorm;
+            if (hist && it < hist_cap) hist[lc * hist_cap + it] = r;
+            ++it;
+            if (!isfinite(r)) {
+                st = ORC_ERR_NONFINITE;
+                break;
+            }
+            if (r < tol) {
+                st = ORC_OK;
+                break;
+            }
+        }
+        for (int q = 0; q < 6; ++q) S[6 * lc + q] = Sm[q];
+        if (iters) iters[lc] = it;
+        if (status) status[lc] = st;
+        if (final_res) final_res[lc] = r;
+        if (out_field) memcpy(out_field + (size_t)lc * 6 * M, e, sizeof(double) * 6 * M);
+    }
+    free(e);
+    free(t);
+    return ORC_OK;
+}
