@@ -163,6 +163,45 @@ rve_status homogenize_batch(int count, const rve_t *rves, const double *k_phases
 /* Kernel timings of the last homogenize call on this handle. */
 rve_status rve_get_kernel_times(rve_t rve, rve_kernel_times *out);
 
+/* ---- Elastic case: linear elasticity with isotropic phases, which Sec. 6
+ * names as the extension of the method.  The same accelerated iteration:
+ * tau = (C - C0) : e, c^ = -Gamma0 : tau^ with the Green operator of the
+ * isotropic reference medium (its Nyquist modes read as for conductivity),
+ * e+ = e + 2 (C + C0)^-1 C0 : (c - e), the mean stress <C : e+> as the
+ * column of C_hom.  Reference medium: kappa0 = sqrt(min kappa max kappa),
+ * mu0 = sqrt(min mu max mu) (the Sec. 5 rule applied to each modulus).
+ * The six load cases impose E = B_j, the orthonormal basis of symmetric
+ * tensors
+ *   B0 = I / sqrt3,  B1 = (e1e1 - e2e2) / sqrt2,
+ *   B2 = (e1e1 + e2e2 - 2 e3e3) / sqrt6,  B3 = (e2e3 + e3e2) / sqrt2,
+ *   B4 = (e1e3 + e3e1) / sqrt2,  B5 = (e1e2 + e2e1) / sqrt2,
+ * in which an isotropic stiffness is diag(3 kappa, 2 mu, 2 mu, 2 mu, 2 mu,
+ * 2 mu); the residual of load case j is sqrt<|e - c|^2> (|B_j| = 1). */
+typedef struct {
+    double C[36];              /* C_hom, Voigt, row-major: sigma_I = sum_J C[6 I + J] eps_J,
+                                  I, J over 11, 22, 33, 23, 13, 12 with engineering shear
+                                  strains (C[6 I + J] = C_ijkl) */
+    double C_basis[36];        /* C_basis[6 k + l] = B_k : C_hom : B_l (column l: load case B_l) */
+    int iters[6];              /* per load case B_j */
+    int status[6];
+    double final_residual[6];
+    double solve_ms;           /* device time of the iteration phase */
+} rve_elastic_result;
+
+/* moduli: host, (kappa, mu) of matrix, inclusion, coating (bulk and shear
+ * moduli, > 0, finite); tol as in homogenize.  opts may be NULL; honoured:
+ * precision, max_iter, stall_window, stream, init_field and out_field (host,
+ * 36 N^3 doubles, [load case j][component k][z][y][x] in the basis above).
+ * equilibrium_check, scheme != 0, a workspace or a partial lc_mask give
+ * RVE_ERR_ARG, as does a grid size not in rve_supported_n_elastic.
+ * residual_history: host [6][hist_cap] or NULL.  Returns the worst
+ * per-load-case status, as homogenize. */
+rve_status homogenize_elastic(rve_t rve, const double moduli[6], double tol, const rve_opts *opts,
+                              rve_elastic_result *out, double *residual_history, int hist_cap);
+
+/* Grid sizes N the elastic case supports for a precision. */
+rve_status rve_supported_n_elastic(int precision, int *out, int cap, int *count);
+
 /* Serving: a request loop that keeps fields resident on the device,
  * admits requests by device-memory footprint and free slots, and advances
  * all admitted requests together one iteration at a time (continuous

@@ -58,6 +58,12 @@ class _Result(ctypes.Structure):
                 ("eps_eq", ctypes.c_double * 3), ("solve_ms", ctypes.c_double)]
 
 
+class _ElResult(ctypes.Structure):
+    _fields_ = [("C", ctypes.c_double * 36), ("C_basis", ctypes.c_double * 36),
+                ("iters", ctypes.c_int * 6), ("status", ctypes.c_int * 6),
+                ("final_residual", ctypes.c_double * 6), ("solve_ms", ctypes.c_double)]
+
+
 class _KTimes(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p * 4), ("total_ms", ctypes.c_double * 4),
                 ("launches", ctypes.c_int * 4), ("total_bytes", ctypes.c_double * 4)]
@@ -87,6 +93,8 @@ def _load_library():
         "homogenize": (c_int, [c_vp, P(c_double), c_double, P(_Opts), P(_Result), P(c_double), c_int]),
         "homogenize_batch": (c_int, [c_int, P(c_vp), P(c_double), P(c_double), P(_Opts), P(_Result)]),
         "rve_get_kernel_times": (c_int, [c_vp, P(_KTimes)]),
+        "homogenize_elastic": (c_int, [c_vp, P(c_double), c_double, P(_Opts), P(_ElResult), P(c_double), c_int]),
+        "rve_supported_n_elastic": (c_int, [c_int, P(c_int), c_int, P(c_int)]),
         "rve_server_create": (c_int, [c_size_t, c_int, c_int, P(c_vp)]),
         "rve_server_submit": (c_int, [c_vp, P(_Geom), P(c_double), c_double, P(ctypes.c_uint64)]),
         "rve_server_poll": (c_int, [c_vp, ctypes.c_uint64, P(_Result), P(c_double)]),
@@ -307,6 +315,83 @@ def homogenize(rve: RVE, k_phases, tol: float = 1e-6, *, max_iter: int = 0, prec
     rc = _check(_lib.homogenize(rve.handle, _dptr(k), float(tol), ctypes.byref(o), ctypes.byref(res),
                                 _dptr(hist) if hist is not None else None, int(hist_cap)))
     return _to_result(rc, res, hist, hist_cap, fld)
+
+
+@dataclass
+class ElasticResult:
+    status: int
+    C: np.ndarray          # (6, 6) Voigt stiffness (11, 22, 33, 23, 13, 12; engineering shear)
+    C_basis: np.ndarray    # (6, 6) in the orthonormal basis B_0..B_5 of the kernels
+    iters: np.ndarray
+    lc_status: np.ndarray
+    final_residual: np.ndarray
+    solve_ms: float
+    history: list = field(default_factory=list)
+    field: np.ndarray | None = None  # (6 load cases, 6 components, n, n, n), basis components
+
+
+# Orthonormal basis of symmetric tensors of the elastic case (load case j
+# imposes E = B[j]; field components are e : B[k]).
+def _sym_unit(i, j):
+    a = np.zeros((3, 3))
+    a[i, j] = a[j, i] = 1.0
+    return a / np.sqrt(2.0)
+
+
+ELASTIC_BASIS = np.array([
+    np.eye(3) / np.sqrt(3.0),
+    np.diag([1.0, -1.0, 0.0]) / np.sqrt(2.0),
+    np.diag([1.0, 1.0, -2.0]) / np.sqrt(6.0),
+    _sym_unit(1, 2),
+    _sym_unit(0, 2),
+    _sym_unit(0, 1),
+])
+
+
+def moduli_from_young_poisson(young, poisson):
+    """(kappa, mu) per phase from Young's moduli and Poisson ratios."""
+    E = np.asarray(young, dtype=np.float64)
+    nu = np.asarray(poisson, dtype=np.float64)
+    return np.stack([E / (3.0 * (1.0 - 2.0 * nu)), E / (2.0 * (1.0 + nu))], axis=-1)
+
+
+def homogenize_elastic(rve: RVE, moduli, tol: float = 1e-6, *, max_iter: int = 0, precision: int = 0,
+                       stall_window: int = -1, stream=None, init_field: np.ndarray | None = None,
+                       want_field: bool = False, hist_cap: int = 0) -> ElasticResult:
+    """The accelerated scheme for isotropic elastic phases (the elastic case
+    Sec. 6 names as the extension): moduli (3, 2) = (bulk, shear) of matrix,
+    inclusion, coating; six load cases E = B_j."""
+    m = np.ascontiguousarray(moduli, dtype=np.float64).reshape(-1)
+    if m.shape != (6,):
+        raise RveError(RVE_ERR_ARG, "moduli must hold (kappa, mu) of 3 phases")
+    n = rve.n
+    init = None
+    if init_field is not None:
+        init = np.ascontiguousarray(init_field, dtype=np.float64)
+        if init.size != 36 * n ** 3:
+            raise RveError(RVE_ERR_ARG, "init_field must hold 36 n^3 values")
+    fld = np.zeros((6, 6, n, n, n)) if want_field else None
+    o = _opts(max_iter, precision, False, stall_window, 0, False, stream, init, fld, None)
+    res = _ElResult()
+    hist = np.zeros(6 * hist_cap) if hist_cap > 0 else None
+    rc = _check(_lib.homogenize_elastic(rve.handle, _dptr(m), float(tol), ctypes.byref(o), ctypes.byref(res),
+                                        _dptr(hist) if hist is not None else None, int(hist_cap)))
+    iters = np.array(res.iters[:], dtype=np.int64)
+    history = []
+    if hist is not None:
+        h = hist.reshape(6, hist_cap)
+        history = [h[j, :min(int(iters[j]), hist_cap)].copy() for j in range(6)]
+    return ElasticResult(rc, np.array(res.C[:]).reshape(6, 6), np.array(res.C_basis[:]).reshape(6, 6), iters,
+                         np.array(res.status[:]), np.array(res.final_residual[:]), float(res.solve_ms),
+                         history, fld)
+
+
+def rve_supported_n_elastic(precision: int = 0) -> list:
+    """Grid sizes of the elastic case for a precision."""
+    buf = (ctypes.c_int * 64)()
+    cnt = ctypes.c_int(0)
+    _check(_lib.rve_supported_n_elastic(int(precision), buf, 64, ctypes.byref(cnt)))
+    return list(buf[:cnt.value])
 
 
 def homogenize_batch(rves, k_phases, tol, *, max_iter: int = 0, precision: int = 0,

@@ -1,0 +1,252 @@
+// elastic_kernels.hpp -- the elastic case of the accelerated scheme (linear
+// elasticity with isotropic phases, which Sec. 6 names as the extension of
+// the method): the z pass with the isotropic elastic Green operator, and the
+// launcher table of one (T, N).  The plane passes are the conductivity
+// kernels with six components per load case (NC = 6).
+//
+// Components are taken in an orthonormal basis of symmetric tensors,
+//   B0 = I / sqrt3,              B1 = (e1e1 - e2e2) / sqrt2,
+//   B2 = (e1e1 + e2e2 - 2 e3e3) / sqrt6,
+//   B3 = (e2e3 + e3e2) / sqrt2,  B4 = (e1e3 + e3e1) / sqrt2,
+//   B5 = (e1e2 + e2e1) / sqrt2,
+// where an isotropic stiffness is diagonal, diag(3 kappa, 2 mu, ..., 2 mu):
+// the update e+ = e + 2 (C + C0)^-1 C0 (c - e) and tau = (C - C0) e then act
+// on each component alone (hydrostatic channel: 3 kappa, deviatoric ones:
+// 2 mu), exactly as the conductivity update acts on each vector component.
+// Load case j imposes E = Bj; the mean stress component k is C_hom's entry
+// (k, j) in this basis.
+#pragma once
+
+#include "kernel_instances.hpp"
+
+namespace rvehom {
+
+// z-tile width for six components: largest even W <= 16 dividing N/2 with
+// 6 N W complex values in 64 KiB of LDS (96 KiB if that leaves W < 4).
+template <typename T, int N> constexpr int ztile_el_cap(size_t cap) {
+    for (int w = 16; w >= 2; w -= 2)
+        if ((N / 2) % w == 0 && N % w == 0 && (size_t)6 * N * w * sizeof(Cx<T>) <= cap) return w;
+    return 0;
+}
+template <typename T, int N> constexpr int ztile_el() {
+    return ztile_el_cap<T, N>(64 * 1024) >= 4 ? ztile_el_cap<T, N>(64 * 1024) : ztile_el_cap<T, N>(96 * 1024);
+}
+
+// P2 of the elastic case: z FFT of the six components' pencils, the Green
+// operator of the isotropic reference medium (lambda0, mu0),
+//   c^ = -[ sym((T^ xi) (x) xi) / (mu0 |xi|^2)
+//           - beta (xi . T^ xi) xi (x) xi / |xi|^4 ] / M,
+//   beta = (lambda0 + mu0) / (mu0 (lambda0 + 2 mu0)),
+// with T^ = sum_l tau^_l B_l, averaged over the signs of the Nyquist
+// components (the conductivity reading of even grids), c^(0) = 0 (E is added
+// after the inverse transform), inverse z FFT.
+template <typename T, int N, int W, int NT>
+__global__ __launch_bounds__(NT) void k_zgreen_el(Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
+                                                  const Cx<T> *__restrict__ twg,
+                                                  const DevParams *__restrict__ prm,
+                                                  const DevState *__restrict__ st) {
+    using TL = ZTiles<N, W>;
+    constexpr int H = N / 2, NW = N * W, NC = 6;
+    static_assert(H % W == 0 && N % W == 0 && W % 2 == 0, "tile width must be even and divide N/2");
+    __shared__ Cx<T> buf[NC * NW];
+    const int tid = threadIdx.x;
+    const int lc = blockIdx.x / TL::PER_LC, t = ztile_of<T, N, W>(blockIdx.x - lc * TL::PER_LC);
+    if (st->done[lc]) return;
+    Cx<T> *base;
+    size_t cstride, zstride;
+    int kx0, ky0, dkx, dky;
+    if (t < TL::MAIN) {
+        const int ky = t / (H / W);
+        kx0 = (t - ky * (H / W)) * W;
+        ky0 = ky;
+        dkx = 1;
+        dky = 0;
+        base = spec + (size_t)(NC * lc) * N * N * H + (size_t)ky * H + kx0;
+        cstride = (size_t)N * N * H;
+        zstride = (size_t)N * H;
+    } else {
+        kx0 = H;
+        ky0 = (t - TL::MAIN) * W;
+        dkx = 0;
+        dky = 1;
+        base = nyq + (size_t)(NC * lc) * N * N + ky0;
+        cstride = (size_t)N * N;
+        zstride = N;
+    }
+    constexpr int NP = NC * NW / 2;
+    for (int idx = tid; idx < NP; idx += NT) {
+        const int e0 = 2 * idx, c = e0 / NW, r = e0 - c * NW, zz = r / W, w = r - zz * W;
+        Cx<T> a, b;
+        gload2<T>(base + c * cstride + zz * zstride + w, a, b);
+        buf[e0] = a;
+        buf[e0 + 1] = b;
+    }
+    __shared__ Cx<T> tws[N];
+    table_to_lds<T, N, NT>(tws, twg, tid);
+    const Cx<T> *tw = tws;
+    __syncthreads();
+    fft_lds<T, N, false, NC * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
+    const double s2 = 0.70710678118654752440, s3 = 0.57735026918962576451, s6 = 0.40824829046386301637;
+    const T A0 = (T)prm->el_inv_mu0M, B0c = (T)prm->el_betaM;
+    for (int idx = tid; idx < NW; idx += NT) {
+        const int kz = idx / W, w = idx - kz * W;
+        const int ki[3] = {kx0 + dkx * w, ky0 + dky * w, kz};
+        T xi[3];
+        int flip = 0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (ki[d] == H) flip |= 1 << d;
+            xi[d] = (T)(ki[d] <= H ? ki[d] : ki[d] - N);
+        }
+        Cx<T> o[NC];
+        if (ki[0] == 0 && ki[1] == 0 && ki[2] == 0) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) o[c] = Cx<T>{(T)0, (T)0};
+        } else {
+            Cx<T> tv[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) tv[c] = buf[c * NW + idx];
+            // T^ as a symmetric tensor: t[0..2] = 11, 22, 33; t[3..5] = 23, 13, 12
+            Cx<T> tt[6];
+            tt[0] = scale(tv[0], (T)s3) + scale(tv[1], (T)s2) + scale(tv[2], (T)s6);
+            tt[1] = scale(tv[0], (T)s3) - scale(tv[1], (T)s2) + scale(tv[2], (T)s6);
+            tt[2] = scale(tv[0], (T)s3) - scale(tv[2], (T)(2.0 * s6));
+            tt[3] = scale(tv[3], (T)s2);
+            tt[4] = scale(tv[4], (T)s2);
+            tt[5] = scale(tv[5], (T)s2);
+            Cx<T> cc[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) cc[q] = Cx<T>{(T)0, (T)0};
+            int count = 0;
+            for (int sgn = 0; sgn < 8; ++sgn) {
+                if (sgn & ~flip) continue;  // only Nyquist components change sign
+                T v[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) v[d] = ((sgn >> d) & 1) ? -xi[d] : xi[d];
+                const T v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+                // u = T^ v, s = v . u
+                const Cx<T> u0 = scale(tt[0], v[0]) + scale(tt[5], v[1]) + scale(tt[4], v[2]);
+                const Cx<T> u1 = scale(tt[5], v[0]) + scale(tt[1], v[1]) + scale(tt[3], v[2]);
+                const Cx<T> u2 = scale(tt[4], v[0]) + scale(tt[3], v[1]) + scale(tt[2], v[2]);
+                const Cx<T> sv = scale(u0, v[0]) + scale(u1, v[1]) + scale(u2, v[2]);
+                const T a = A0 / v2, b = B0c / (v2 * v2);
+                const Cx<T> bs = scale(sv, b);
+                cc[0] = cc[0] + scale(u0, a * v[0]) - scale(bs, v[0] * v[0]);
+                cc[1] = cc[1] + scale(u1, a * v[1]) - scale(bs, v[1] * v[1]);
+                cc[2] = cc[2] + scale(u2, a * v[2]) - scale(bs, v[2] * v[2]);
+                cc[3] = cc[3] + scale(scale(u1, v[2]) + scale(u2, v[1]), (T)0.5 * a) - scale(bs, v[1] * v[2]);
+                cc[4] = cc[4] + scale(scale(u0, v[2]) + scale(u2, v[0]), (T)0.5 * a) - scale(bs, v[0] * v[2]);
+                cc[5] = cc[5] + scale(scale(u0, v[1]) + scale(u1, v[0]), (T)0.5 * a) - scale(bs, v[0] * v[1]);
+                ++count;
+            }
+            const T f = (T)-1 / (T)count;
+            // back to the basis components: c_k = B_k : C
+            o[0] = scale(cc[0] + cc[1] + cc[2], f * (T)s3);
+            o[1] = scale(cc[0] - cc[1], f * (T)s2);
+            o[2] = scale(cc[0] + cc[1] - scale(cc[2], (T)2), f * (T)s6);
+            o[3] = scale(cc[3], f * (T)(2.0 * s2));
+            o[4] = scale(cc[4], f * (T)(2.0 * s2));
+            o[5] = scale(cc[5], f * (T)(2.0 * s2));
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) buf[c * NW + idx] = o[c];
+    }
+    __syncthreads();
+    fft_lds<T, N, true, NC * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
+    for (int idx = tid; idx < NP; idx += NT) {
+        const int e0 = 2 * idx, c = e0 / NW, r = e0 - c * NW, zz = r / W, w = r - zz * W;
+        gstore2<T>(base + c * cstride + zz * zstride + w, buf[e0], buf[e0 + 1]);
+    }
+}
+
+// Reduction of the elastic partials as a kernel of its own (64 threads).
+__global__ void k_reduce_el(const double *part, int nper, const DevParams *prm, DevState *st, double *hist);
+
+template <typename T, int N> struct ElasticInstance {
+    static constexpr int NC = 6, CH = NC * NC;
+    static constexpr int S = plane_split<T, N>();
+    static_assert(S == 1 || S == 2, "the elastic case needs planes that fit in LDS (whole or split)");
+    static constexpr int W = ztile_el<T, N>();
+    static_assert(W >= 2, "no z tile fits in LDS");
+    static constexpr int NTP = plane_threads<T, N>();
+    static constexpr int NTZ = 256;
+    static constexpr int NPER = N * S;
+    static constexpr bool FUSED = S == 1 && !(sizeof(T) == 4 && N == 96);
+    static constexpr int PGRID = CH * N * S;
+
+    static void fwd(const LaunchArgs &a, hipStream_t s, int) {
+        hipLaunchKernelGGL((k_fwd_plane<T, N, S, NTP, false, NC>), dim3(PGRID), dim3(NTP), 0, s, (const T *)a.e, a.ph,
+                           (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st, 0);
+    }
+    static void zgreen(const LaunchArgs &a, hipStream_t s, int, int) {
+        hipLaunchKernelGGL((k_zgreen_el<T, N, W, NTZ>), dim3(NC * ZTiles<N, W>::PER_LC), dim3(NTZ), 0, s,
+                           (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st);
+    }
+    static void inv(const LaunchArgs &a, hipStream_t s, int) {
+        hipLaunchKernelGGL((k_inv_plane<T, N, S, NTP, false, false, NC>), dim3(PGRID), dim3(NTP), 0, s, (T *)a.e,
+                           a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st,
+                           a.part, 0);
+    }
+    static void inv_fwd(const LaunchArgs &a, hipStream_t s, int) {
+        if constexpr (FUSED) {
+            hipLaunchKernelGGL((k_inv_plane<T, N, 1, NTP, true, false, NC>), dim3(PGRID), dim3(NTP), 0, s, (T *)a.e,
+                               a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
+                               (const DevState *)a.st, a.part, 0);
+        }
+    }
+    static void init(const LaunchArgs &a, size_t M, hipStream_t s) {
+        hipLaunchKernelGGL((k_init<T>), dim3(1024), dim3(256), 0, s, (T *)a.e, M, a.prm, a.st);
+    }
+    static void from_f64(void *e, const double *src, size_t count, hipStream_t s) {
+        hipLaunchKernelGGL((k_from_f64<T>), dim3(1024), dim3(256), 0, s, (T *)e, src, count);
+    }
+    static void to_f64(double *dst, const void *e, size_t count, hipStream_t s) {
+        hipLaunchKernelGGL((k_to_f64<T>), dim3(1024), dim3(256), 0, s, dst, (const T *)e, count);
+    }
+    static void reduce(const LaunchArgs &a, int nper, hipStream_t s) {
+        hipLaunchKernelGGL(k_reduce_el, dim3(1), dim3(64), 0, s, (const double *)a.part, nper, a.prm, a.st, a.hist);
+    }
+
+    static const SolverOps *ops(int precision) {
+        constexpr size_t M = (size_t)N * N * N;
+        constexpr size_t H = N / 2;
+        constexpr double cb = (double)sizeof(Cx<T>);
+        constexpr double rb = (double)sizeof(T);
+        constexpr double spec_b = (double)CH * N * N * (H + 1) * cb;
+        static const SolverOps o = {
+            N,
+            precision,
+            S,
+            W,
+            NPER,
+            sizeof(T),
+            (size_t)CH * N * N * H,
+            (size_t)CH * N * N,
+            {PGRID, NC * ZTiles<N, W>::PER_LC, PGRID},
+            {NTP, NTZ, NTP},
+            {CH * (double)M * rb + CH * (double)M + spec_b, 2.0 * spec_b,
+             spec_b + 2.0 * CH * (double)M * rb + CH * (double)M},
+            0,
+            FUSED ? 2.0 * spec_b + 2.0 * CH * (double)M * rb + CH * (double)M : 0.0,
+            FUSED ? &inv_fwd : nullptr,
+            &fwd,
+            nullptr,
+            nullptr,
+            &zgreen,
+            W,
+            nullptr,
+            &inv,
+            &init,
+            &from_f64,
+            &to_f64,
+            nullptr,
+            nullptr,
+            nullptr,
+            NC,
+            &reduce,
+        };
+        return &o;
+    }
+};
+
+}  // namespace rvehom

@@ -193,6 +193,8 @@ template <typename T, int N> struct Instance {
             FUSED ? &inv_fwd_al : nullptr,
             &inv_al,
             &to_tau,
+            3,
+            &launch_reduce,
         };
         return &o;
     }

@@ -1,5 +1,5 @@
 // kernels_common.hip -- precision-independent kernels (the FP64 convergence
-// reduction) and the list of grid sizes compiled into the library.
+// reductions) and the lists of grid sizes compiled into the library.
 #include <hip/hip_runtime.h>
 
 #include "reduce_block.hpp"
@@ -82,8 +82,26 @@ void launch_reduce(const LaunchArgs &a, int nper, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, a.part, nper, a.prm, a.st, a.hist);
 }
 
+// The elastic case's reduction (one workgroup of 64 threads).
+__global__ __launch_bounds__(64) void k_reduce_el(const double *part, int nper, const DevParams *prm, DevState *st,
+                                                  double *hist) {
+    reduce_block_el(part, nper, prm, st, hist, threadIdx.x);
+}
+
 static const int kSizesF32[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 256, 512};
 static const int kSizesF64[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 256, 512};
+
+static const int kSizesElF32[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 256};
+static const int kSizesElF64[] = {8, 12, 16, 24, 32, 48, 64, 96, 128};
+
+int supported_sizes_el(int precision, const int **list) {
+    if (precision == 0) {
+        *list = kSizesElF32;
+        return (int)(sizeof(kSizesElF32) / sizeof(int));
+    }
+    *list = kSizesElF64;
+    return (int)(sizeof(kSizesElF64) / sizeof(int));
+}
 
 int supported_sizes(int precision, const int **list) {
     if (precision == 0) {

@@ -8,6 +8,52 @@
 
 namespace rvehom {
 
+// Convergence decision of one load case at iteration it with residual eps:
+// history, NaN, tolerance (or the equilibrium stage), stall rules, iteration
+// cap; freezes the load case when it finishes.  Returns 1 when it is done.
+__device__ __forceinline__ int decide_load_case(const DevParams *__restrict__ prm, DevState *__restrict__ st,
+                                                double *__restrict__ hist, int lc, int it, double eps) {
+    st->res[lc] = eps;
+    if (it < prm->hist_cap) hist[lc * prm->hist_cap + it] = eps;
+    int fin = 0, status = ST_NOT_CONVERGED;
+    if (!(eps == eps) || eps > 1e300) {
+        fin = 1;
+        status = ST_NONFINITE;
+    } else if (eps < prm->tol) {
+        if (prm->eq_check) {
+            // step 1, second stage: the equilibrium error decides (k_eq_reduce)
+            st->eq_pending[lc] = 1;
+            if (it + 1 >= prm->max_iter) fin = 1;
+        } else {
+            fin = 1;
+            status = ST_OK;
+        }
+    } else {
+        if (eps < st->best[lc]) {
+            st->best[lc] = eps;
+            st->best_it[lc] = it;
+        } else if (prm->stall_window > 0 && it - st->best_it[lc] >= prm->stall_window) {
+            fin = 1;
+            status = ST_STALLED;
+        }
+        // FP32 rounding floor: within 100 tol, the last 10 iterations
+        // gained less than a quarter of the least progress the scheme's
+        // contraction bound allows (1 - rho^10)
+        if (!fin && prm->stall_window > 0 && it >= 10 && it - 10 < prm->hist_cap && eps < 100.0 * prm->tol &&
+            eps > (1.0 - 0.25 * prm->prog10) * hist[lc * prm->hist_cap + it - 10]) {
+            fin = 1;
+            status = ST_STALLED;
+        }
+        if (!fin && it + 1 >= prm->max_iter) fin = 1;
+    }
+    if (fin) {
+        st->done[lc] = 1;
+        st->status[lc] = status;
+        st->iters[lc] = it + 1;
+    }
+    return fin;
+}
+
 // ---------------------------------------------------------------------------
 // Fixed-order FP64 reduction of the partials, steps 6 / 1 convergence test,
 // <phi> of the updated field (L_hom column), per-load-case freeze.
@@ -56,52 +102,54 @@ __device__ __forceinline__ void reduce_block(const double *__restrict__ part, in
     for (int lc = 0; lc < 3; ++lc) {
         if (st->done[lc]) continue;
         const double eps = sqrt(tot[4 * lc] * prm->invM);  // |E| = 1
-        st->res[lc] = eps;
         for (int c = 0; c < 3; ++c) {
             const double F = tot[4 * lc + 1 + c] * prm->invM;  // <k e+_c>
             st->K[3 * c + lc] = F;
             // mean of tau = (k - k0) e+ for the next forward pass
             st->tau_mean[3 * lc + c] = F - prm->k0 * tot[12 + 3 * lc + c] * prm->invM;
         }
-        if (it < prm->hist_cap) hist[lc * prm->hist_cap + it] = eps;
-        int fin = 0, status = ST_NOT_CONVERGED;
-        if (!(eps == eps) || eps > 1e300) {
-            fin = 1;
-            status = ST_NONFINITE;
-        } else if (eps < prm->tol) {
-            if (prm->eq_check) {
-                // step 1, second stage: the equilibrium error decides (k_eq_reduce)
-                st->eq_pending[lc] = 1;
-                if (it + 1 >= prm->max_iter) fin = 1;
-            } else {
-                fin = 1;
-                status = ST_OK;
-            }
-        } else {
-            if (eps < st->best[lc]) {
-                st->best[lc] = eps;
-                st->best_it[lc] = it;
-            } else if (prm->stall_window > 0 && it - st->best_it[lc] >= prm->stall_window) {
-                fin = 1;
-                status = ST_STALLED;
-            }
-            // FP32 rounding floor: within 100 tol, the last 10 iterations
-            // gained less than a quarter of the least progress the scheme's
-            // contraction bound allows (1 - rho^10)
-            if (!fin && prm->stall_window > 0 && it >= 10 && it - 10 < prm->hist_cap && eps < 100.0 * prm->tol &&
-                eps > (1.0 - 0.25 * prm->prog10) * hist[lc * prm->hist_cap + it - 10]) {
-                fin = 1;
-                status = ST_STALLED;
-            }
-            if (!fin && it + 1 >= prm->max_iter) fin = 1;
+        all &= decide_load_case(prm, st, hist, lc, it, eps);
+    }
+    st->iter = it + 1;
+    st->all_done = all;
+}
+
+// The same for the elastic case (six load cases of six components): thread t
+// < 36 sums channel t's partials in a fixed order, thread 0 forms each load
+// case's residual, mean stress and per-channel mean of tau and decides.
+// Run by one workgroup of at least 64 threads.
+__device__ __forceinline__ void reduce_block_el(const double *__restrict__ part, int nper,
+                                                const DevParams *__restrict__ prm, DevState *__restrict__ st,
+                                                double *__restrict__ hist, int tid) {
+    __shared__ double tot[36][3];
+    if (tid < 36) {
+        double r = 0.0, f = 0.0, m = 0.0;
+        const double *pc = part + (size_t)tid * nper * 3;
+        for (int b = 0; b < nper; ++b) {
+            r += pc[3 * b];
+            f += pc[3 * b + 1];
+            m += pc[3 * b + 2];
         }
-        if (fin) {
-            st->done[lc] = 1;
-            st->status[lc] = status;
-            st->iters[lc] = it + 1;
-        } else {
-            all = 0;
+        tot[tid][0] = r;
+        tot[tid][1] = f;
+        tot[tid][2] = m;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    const int it = st->iter;
+    int all = 1;
+    for (int lc = 0; lc < 6; ++lc) {
+        if (st->done[lc]) continue;
+        double r2 = 0.0;
+        for (int c = 0; c < 6; ++c) r2 += tot[6 * lc + c][0];
+        const double eps = sqrt(r2 * prm->invM);  // |E| = 1 (unit basis tensor)
+        for (int c = 0; c < 6; ++c) {
+            const double F = tot[6 * lc + c][1] * prm->invM;  // mean stress component c
+            st->K[6 * c + lc] = F;
+            const double k0c = c == 0 ? prm->k0 : prm->k0_dev;
+            st->tau_mean[6 * lc + c] = F - k0c * tot[6 * lc + c][2] * prm->invM;
         }
+        all &= decide_load_case(prm, st, hist, lc, it, eps);
     }
     st->iter = it + 1;
     st->all_done = all;

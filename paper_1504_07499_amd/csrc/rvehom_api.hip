@@ -48,6 +48,12 @@ const SolverOps *lookup_ops(int precision, int n) {
     return nullptr;
 }
 
+const SolverOps *lookup_ops_el(int precision, int n) {
+    if (precision == 0) return ops_el_f32(n);
+    if (precision == 1) return ops_el_f64(n);
+    return nullptr;
+}
+
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 WsLayout ws_layout(const SolverOps *o) {
@@ -59,15 +65,16 @@ WsLayout ws_layout(const SolverOps *o) {
         off += align256(bytes);
         return at;
     };
-    L.e = take(9 * M * rb);
+    const size_t ch = (size_t)o->nc * o->nc;  // channels: nc load cases of nc components
+    L.e = take(ch * M * rb);
     L.spec = take(o->spec_elems * 2 * rb);
     L.nyq = take(o->nyq_elems * 2 * rb);
     L.tw = take(n * 2 * rb);
-    L.part = take((size_t)9 * o->nper * 3 * sizeof(double));
+    L.part = take(ch * o->nper * 3 * sizeof(double));
     L.prm = take(sizeof(DevParams));
     L.st = take(sizeof(DevState));
-    L.hist = take((size_t)3 * kHistCap * sizeof(double));
-    L.peq = take((size_t)3 * o->eq_tiles * 2 * sizeof(double));
+    L.hist = take((size_t)o->nc * kHistCap * sizeof(double));
+    L.peq = take((size_t)o->nc * (o->eq_tiles > 0 ? o->eq_tiles : 1) * 2 * sizeof(double));
     L.total = off;
     return L;
 }
@@ -419,6 +426,49 @@ void fill_params(DevParams &p, const double k[3], double tol, int n, const Solve
     p.hist_cap = kHistCap;
     p.eq_check = o.eq_check;
     p.lc_mask = o.lc_mask;
+    p.nc = 3;
+}
+
+// The elastic case: moduli = (kappa, mu) per phase.  Reference medium: the
+// Sec. 5 rule applied to each modulus, kappa0 = sqrt(min kappa max kappa),
+// mu0 = sqrt(min mu max mu).  In the orthonormal basis of the kernels the
+// hydrostatic channel carries 3 kappa, the deviatoric ones 2 mu.
+void fill_params_el(DevParams &p, const double moduli[6], double tol, int n, const SolverOpts &o) {
+    std::memset(&p, 0, sizeof(p));
+    double kap[3], mu[3];
+    for (int i = 0; i < 3; ++i) {
+        kap[i] = moduli[2 * i];
+        mu[i] = moduli[2 * i + 1];
+    }
+    const double kmin = std::min(kap[0], std::min(kap[1], kap[2])), kmax = std::max(kap[0], std::max(kap[1], kap[2]));
+    const double mmin = std::min(mu[0], std::min(mu[1], mu[2])), mmax = std::max(mu[0], std::max(mu[1], mu[2]));
+    const double kap0 = std::sqrt(kmin * kmax), mu0 = std::sqrt(mmin * mmax);
+    const double lam0 = kap0 - 2.0 * mu0 / 3.0;
+    const double M = (double)n * n * n;
+    for (int i = 0; i < 3; ++i) {
+        p.k[i] = 3.0 * kap[i];
+        p.dk[i] = 3.0 * (kap[i] - kap0);
+        p.w[i] = 2.0 * kap0 / (kap[i] + kap0);
+        p.k_dev[i] = 2.0 * mu[i];
+        p.dk_dev[i] = 2.0 * (mu[i] - mu0);
+        p.w_dev[i] = 2.0 * mu0 / (mu[i] + mu0);
+    }
+    p.k0 = 3.0 * kap0;
+    p.k0_dev = 2.0 * mu0;
+    p.el_inv_mu0M = 1.0 / (mu0 * M);
+    p.el_betaM = (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0)) / M;
+    // contraction bound: the larger of the two moduli's Eyre-Milton factors
+    const double ck = kmax / kmin, cm = mmax / mmin;
+    const double rho = std::max((std::sqrt(ck) - 1.0) / (std::sqrt(ck) + 1.0), (std::sqrt(cm) - 1.0) / (std::sqrt(cm) + 1.0));
+    p.prog10 = 1.0 - std::pow(rho, 10.0);
+    p.tol = tol;
+    p.invM = 1.0 / M;
+    p.max_iter = o.max_iter;
+    p.stall_window = o.stall_window;
+    p.hist_cap = kHistCap;
+    p.eq_check = 0;
+    p.lc_mask = 63;
+    p.nc = 6;
 }
 
 SolverOpts resolve_opts(const rve_opts *opts) {
@@ -486,11 +536,23 @@ int Solver::tune_zpass(const LaunchArgs &a, hipStream_t s) {
 }
 
 int Solver::begin(const uint8_t *d_phase, const double k[3], double tol, const SolverOpts &o, hipStream_t s) {
+    fill_params(*(DevParams *)h_pinned, k, tol, ops->n, o);
+    return start(d_phase, o, s);
+}
+
+int Solver::begin_elastic(const uint8_t *d_phase, const double moduli[6], double tol, const SolverOpts &o,
+                          hipStream_t s) {
+    fill_params_el(*(DevParams *)h_pinned, moduli, tol, ops->n, o);
+    return start(d_phase, o, s);
+}
+
+// Upload the parameters (already in the pinned block), initialise the field
+// and the state, and enqueue the first forward pass.
+int Solver::start(const uint8_t *d_phase, const SolverOpts &o, hipStream_t s) {
     d_phase_last = d_phase;
     int rc = ensure_twiddles(s);
     if (rc != RVE_OK) return rc;
     DevParams *hp = (DevParams *)h_pinned;
-    fill_params(*hp, k, tol, ops->n, o);
     LaunchArgs a = args(d_phase);
     HIP_CHECK(hipMemcpyAsync((void *)a.prm, hp, sizeof(DevParams), hipMemcpyHostToDevice, s));
     const size_t M = (size_t)ops->n * ops->n * ops->n;
@@ -502,9 +564,9 @@ int Solver::begin(const uint8_t *d_phase, const double k[3], double tol, const S
         // stage the FP64 field through the spectrum buffer region if it fits,
         // else through a temporary device buffer
         double *tmp = nullptr;
-        HIP_CHECK(hipMalloc(&tmp, 9 * M * sizeof(double)));
-        HIP_CHECK(hipMemcpyAsync(tmp, o.init_field, 9 * M * sizeof(double), hipMemcpyHostToDevice, s));
-        ops->from_f64(a.e, tmp, 9 * M, s);
+        HIP_CHECK(hipMalloc(&tmp, (size_t)ops->nc * ops->nc * M * sizeof(double)));
+        HIP_CHECK(hipMemcpyAsync(tmp, o.init_field, (size_t)ops->nc * ops->nc * M * sizeof(double), hipMemcpyHostToDevice, s));
+        ops->from_f64(a.e, tmp, (size_t)ops->nc * ops->nc * M, s);
         HIP_CHECK(hipGetLastError());
         HIP_CHECK(hipStreamSynchronize(s));
         HIP_CHECK(hipFree(tmp));
@@ -527,7 +589,7 @@ int Solver::begin(const uint8_t *d_phase, const double k[3], double tol, const S
     }
     {
         const char *f = getenv("RVEHOM_MERGE");
-        merge = !eq_check && !(f && f[0] == '0');
+        merge = ops->nc == 3 && !eq_check && !(f && f[0] == '0');
     }
     // a single load case: the iteration kernels run that load case's grid only
     lc_sel = -1;
@@ -559,7 +621,7 @@ int Solver::launch_iteration(const LaunchArgs &a, hipStream_t s, int mask, hipEv
         case 0: ops->fwd(a, s, lc_sel); break;
         case 1: (zvar ? ops->zgreen_alt : ops->zgreen)(a, s, red_in_z ? ops->nper : 0, lc_sel); break;
         case 2: (fused ? (al ? ops->inv_fwd_al : ops->inv_fwd) : (al ? ops->inv_al : ops->inv))(a, s, lc_sel); break;
-        default: launch_reduce(a, ops->nper, s); break;
+        default: ops->reduce(a, ops->nper, s); break;
         }
         if (timed) {
             HIP_CHECK(hipEventRecordWithFlags(ev[used + 1], s, hipEventRecordExternal));
@@ -735,27 +797,30 @@ int Solver::poll(bool wait, int max_iter) {
 
 // Copy results back after the stream has drained.
 int Solver::collect(const SolverOpts &o, hipStream_t s, rve_result *out, double *hist, int hist_cap,
-                    rve_kernel_times *kt) {
+                    rve_kernel_times *kt, rve_elastic_result *eout) {
     LaunchArgs a = args(d_phase_last);
-    // equilibrium error of the final field (step 1 quantity, reported at exit)
-    launch_eq_request(a, s);
-    ops->fwd_phi(a, s);
-    ops->zeq(a, s);
-    launch_eq_reduce(a, ops->eq_tiles, 1, s);
-    HIP_CHECK(hipGetLastError());
+    const int nlc = ops->nc;
+    if (ops->fwd_phi) {
+        // equilibrium error of the final field (step 1 quantity, reported at exit)
+        launch_eq_request(a, s);
+        ops->fwd_phi(a, s);
+        ops->zeq(a, s);
+        launch_eq_reduce(a, ops->eq_tiles, 1, s);
+        HIP_CHECK(hipGetLastError());
+    }
     DevState *hs = (DevState *)((char *)h_pinned + sizeof(DevParams));
     HIP_CHECK(hipMemcpyAsync(hs, a.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
     const size_t M = (size_t)ops->n * ops->n * ops->n;
     double *tmp = nullptr;
     if (o.out_field) {
-        HIP_CHECK(hipMalloc(&tmp, 9 * M * sizeof(double)));
-        ops->to_f64(tmp, a.e, 9 * M, s);
+        HIP_CHECK(hipMalloc(&tmp, (size_t)ops->nc * ops->nc * M * sizeof(double)));
+        ops->to_f64(tmp, a.e, (size_t)ops->nc * ops->nc * M, s);
         HIP_CHECK(hipGetLastError());
-        HIP_CHECK(hipMemcpyAsync(o.out_field, tmp, 9 * M * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(o.out_field, tmp, (size_t)ops->nc * ops->nc * M * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     HIP_CHECK(hipStreamSynchronize(s));
     if (tmp) HIP_CHECK(hipFree(tmp));
-    if (out) {
+    if (out && nlc == 3) {
         for (int i = 0; i < 9; ++i) out->K[i] = hs->K[i];
         for (int j = 0; j < 3; ++j) {
             out->iters[j] = hs->iters[j];
@@ -764,9 +829,17 @@ int Solver::collect(const SolverOpts &o, hipStream_t s, rve_result *out, double 
             out->eps_eq[j] = hs->eps_eq[j];
         }
     }
+    if (eout && nlc == 6) {
+        for (int i = 0; i < 36; ++i) eout->C_basis[i] = hs->K[i];
+        for (int j = 0; j < 6; ++j) {
+            eout->iters[j] = hs->iters[j];
+            eout->status[j] = hs->status[j];
+            eout->final_residual[j] = hs->res[j];
+        }
+    }
     if (hist && hist_cap > 0) {
         const int cap = std::min(hist_cap, kHistCap);
-        for (int j = 0; j < 3; ++j) {
+        for (int j = 0; j < nlc; ++j) {
             const int cnt = std::min(cap, hs->iters[j]);
             if (cnt > 0)
                 HIP_CHECK(hipMemcpy(hist + (size_t)j * hist_cap, a.hist + (size_t)j * kHistCap,
@@ -779,7 +852,7 @@ int Solver::collect(const SolverOpts &o, hipStream_t s, rve_result *out, double 
         for (int q = 0; q < 4; ++q) kt->name[q] = names[q];
         if (fused) kt->name[2] = "inv_fwd_plane";
         int maxit = 0;
-        for (int j = 0; j < 3; ++j) maxit = std::max(maxit, hs->iters[j]);
+        for (int j = 0; j < nlc; ++j) maxit = std::max(maxit, hs->iters[j]);
         while (!inflight.empty()) {  // stream drained: remaining slots are complete
             if (int rc = read_slot_times(inflight.front()); rc != RVE_OK) return rc;
             inflight.pop_front();
@@ -789,11 +862,11 @@ int Solver::collect(const SolverOpts &o, hipStream_t s, rve_result *out, double 
             if (it >= maxit) continue;  // launches after convergence exit at once
             const float ms = launches[i].ms;
             int active = 0;
-            for (int j = 0; j < 3; ++j) active += (hs->iters[j] > it) ? 1 : 0;
+            for (int j = 0; j < nlc; ++j) active += (hs->iters[j] > it) ? 1 : 0;
             kt->total_ms[kk] += ms;
             kt->launches[kk] += 1;
             const double b = (kk == 2 && fused) ? ops->bytes_fused : (kk < 3 ? ops->bytes[kk] : 0.0);
-            kt->total_bytes[kk] += b * active / 3.0;
+            kt->total_bytes[kk] += b * active / (double)nlc;
         }
     }
     return RVE_OK;
@@ -910,6 +983,86 @@ int check_scheme(const SolverOpts &o, const SolverOps *ops) {
     return RVE_OK;
 }
 
+// Iterate a begun solver to completion on stream s, bracketed by its run
+// events.  Poll points every kChunk iterations, at most kLookahead chunks
+// ahead of the host; launches after convergence exit at once on the device
+// flags.
+static int run_solver(Solver &sv, const uint8_t *d_phase, const SolverOpts &o, hipStream_t s) {
+    HIP_CHECK(hipEventRecord(sv.run_ev[0], s));
+    while (true) {
+        if (sv.issued < o.max_iter) {
+            int rc = sv.enqueue(d_phase, kChunk, o.max_iter, o.timing, s);
+            if (rc != RVE_OK) return rc;
+        }
+        const bool must_wait = (int)sv.inflight.size() >= kLookahead || sv.issued >= o.max_iter;
+        if (must_wait) {
+            int rc = sv.poll(true, o.max_iter);
+            if (rc < 0) return rc;
+            if (rc == 1) break;
+        }
+    }
+    HIP_CHECK(hipEventRecord(sv.run_ev[1], s));
+    return RVE_OK;
+}
+
+// The elastic case on one RVE: the six load cases E = B_j in one solver.
+static const double kBasis[6][3][3] = {
+    {{0.57735026918962576451, 0, 0}, {0, 0.57735026918962576451, 0}, {0, 0, 0.57735026918962576451}},
+    {{0.70710678118654752440, 0, 0}, {0, -0.70710678118654752440, 0}, {0, 0, 0}},
+    {{0.40824829046386301637, 0, 0}, {0, 0.40824829046386301637, 0}, {0, 0, -0.81649658092772603273}},
+    {{0, 0, 0}, {0, 0, 0.70710678118654752440}, {0, 0.70710678118654752440, 0}},
+    {{0, 0, 0.70710678118654752440}, {0, 0, 0}, {0.70710678118654752440, 0, 0}},
+    {{0, 0.70710678118654752440, 0}, {0.70710678118654752440, 0, 0}, {0, 0, 0}},
+};
+
+// C_hom in the basis (C_basis[6 k + l] = B_k : C : B_l) to the Voigt matrix
+// C[6 I + J] = C_ijkl with I = (ij), J = (kl) over 11, 22, 33, 23, 13, 12.
+static void basis_to_voigt(const double *Cb, double *Cv) {
+    static const int vi[6] = {0, 1, 2, 1, 0, 0}, vj[6] = {0, 1, 2, 2, 2, 1};
+    for (int I = 0; I < 6; ++I)
+        for (int J = 0; J < 6; ++J) {
+            double acc = 0.0;
+            for (int k = 0; k < 6; ++k)
+                for (int l = 0; l < 6; ++l)
+                    acc += Cb[6 * k + l] * kBasis[k][vi[I]][vj[I]] * kBasis[l][vi[J]][vj[J]];
+            Cv[6 * I + J] = acc;
+        }
+}
+
+static rve_status solve_elastic(rve_s *r, const double moduli[6], double tol, const SolverOpts &o,
+                                rve_elastic_result *out, double *hist, int hist_cap) {
+    const SolverOps *ops = lookup_ops_el(o.precision, r->n);
+    if (!ops) {
+        set_error("grid size %d is not built for the elastic case in precision %d", r->n, o.precision);
+        return RVE_ERR_ARG;
+    }
+    int cur = 0;
+    HIP_CHECK(hipGetDevice(&cur));
+    if (cur != r->device) HIP_CHECK(hipSetDevice(r->device));
+    Solver &sv = r->el[o.precision];
+    int rc = sv.prepare(ops, nullptr, 0);
+    if (rc != RVE_OK) return (rve_status)rc;
+    hipStream_t s = o.stream ? o.stream : sv.own_stream;
+    rc = sv.begin_elastic(r->d_phase, moduli, tol, o, s);
+    if (rc != RVE_OK) return (rve_status)rc;
+    rc = run_solver(sv, r->d_phase, o, s);
+    if (rc != RVE_OK) return (rve_status)rc;
+    rve_elastic_result res{};
+    rc = sv.collect(o, s, nullptr, hist, hist_cap, nullptr, &res);
+    if (rc != RVE_OK) return (rve_status)rc;
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, sv.run_ev[0], sv.run_ev[1]));
+    res.solve_ms = ms;
+    basis_to_voigt(res.C_basis, res.C);
+    *out = res;
+    if (cur != r->device) HIP_CHECK(hipSetDevice(cur));
+    int worst = RVE_OK;
+    auto rank = [](int v) { return v < 0 ? 100 - v : v == RVE_STALLED ? 3 : v == RVE_NOT_CONVERGED ? 2 : 0; };
+    for (int j = 0; j < 6; ++j)
+        if (rank(res.status[j]) > rank(worst)) worst = res.status[j];
+    return (rve_status)worst;
+}
+
 // One RVE, start to finish, on stream s.
 rve_status solve_one(rve_s *r, const double k[3], double tol, const SolverOpts &o, rve_result *out,
                      double *hist, int hist_cap) {
@@ -933,23 +1086,8 @@ rve_status solve_one(rve_s *r, const double k[3], double tol, const SolverOpts &
     hipStream_t s = o.stream ? o.stream : sv.own_stream;
     rc = sv.begin(r->d_phase, k, tol, o, s);
     if (rc != RVE_OK) return (rve_status)rc;
-    HIP_CHECK(hipEventRecord(sv.run_ev[0], s));
-    // Poll points every `chunk` iterations, at most kLookahead chunks ahead of
-    // the host; launches after convergence exit at once on the device flags.
-    const int chunk = kChunk;
-    while (true) {
-        if (sv.issued < o.max_iter) {
-            rc = sv.enqueue(r->d_phase, chunk, o.max_iter, o.timing, s);
-            if (rc != RVE_OK) return (rve_status)rc;
-        }
-        const bool must_wait = (int)sv.inflight.size() >= kLookahead || sv.issued >= o.max_iter;
-        if (must_wait) {
-            rc = sv.poll(true, o.max_iter);
-            if (rc < 0) return (rve_status)rc;
-            if (rc == 1) break;
-        }
-    }
-    HIP_CHECK(hipEventRecord(sv.run_ev[1], s));
+    rc = run_solver(sv, r->d_phase, o, s);
+    if (rc != RVE_OK) return (rve_status)rc;
     rve_result res{};
     rc = sv.collect(o, s, &res, hist, hist_cap, o.timing ? &r->times : nullptr);
     if (rc != RVE_OK) return (rve_status)rc;
@@ -983,6 +1121,54 @@ extern "C" rve_status homogenize(rve_t r, const double k_phases[3], double tol, 
     SolverOpts o = resolve_opts(opts);
     if (o.timing) std::memset(&r->times, 0, sizeof(r->times));
     return solve_one(r, k_phases, tol, o, out, residual_history, hist_cap);
+}
+
+extern "C" rve_status homogenize_elastic(rve_t r, const double moduli[6], double tol, const rve_opts *opts,
+                                         rve_elastic_result *out, double *residual_history, int hist_cap) {
+    clear_error();
+    if (!r || !out || !moduli) {
+        set_error("homogenize_elastic: null rve, moduli or result pointer");
+        return RVE_ERR_ARG;
+    }
+    for (int q = 0; q < 6; ++q)
+        if (!(moduli[q] > 0.0) || !std::isfinite(moduli[q])) {
+            set_error("moduli must be finite and > 0 (entry %d = %g)", q, moduli[q]);
+            return RVE_ERR_ARG;
+        }
+    if (!(tol >= 0.0) || !std::isfinite(tol)) {
+        set_error("tol must be finite and >= 0 (got %g)", tol);
+        return RVE_ERR_ARG;
+    }
+    if (opts && (opts->precision != 0 && opts->precision != 1)) {
+        set_error("precision must be 0 (FP32) or 1 (FP64)");
+        return RVE_ERR_ARG;
+    }
+    if (opts && (opts->equilibrium_check || opts->scheme != 0 || opts->workspace ||
+                 ((opts->lc_mask & 63) != 0 && (opts->lc_mask & 63) != 63))) {
+        set_error("homogenize_elastic: equilibrium_check, scheme, workspace and a partial lc_mask are not supported");
+        return RVE_ERR_ARG;
+    }
+    if (hist_cap < 0 || (hist_cap > 0 && !residual_history)) {
+        set_error("residual_history is NULL but hist_cap > 0");
+        return RVE_ERR_ARG;
+    }
+    SolverOpts o = resolve_opts(opts);
+    o.lc_mask = 63;
+    o.timing = 0;
+    return solve_elastic(r, moduli, tol, o, out, residual_history, hist_cap);
+}
+
+extern "C" rve_status rve_supported_n_elastic(int precision, int *out, int cap, int *count) {
+    clear_error();
+    if ((precision != 0 && precision != 1) || !count || (cap > 0 && !out) || cap < 0) {
+        set_error("rve_supported_n_elastic: bad arguments");
+        return RVE_ERR_ARG;
+    }
+    const int *list = nullptr;
+    const int k = supported_sizes_el(precision, &list);
+    for (int i = 0; i < k && i < cap; ++i) out[i] = list[i];
+    *count = k;
+    return RVE_OK;
 }
 
 extern "C" rve_status rve_get_kernel_times(rve_t r, rve_kernel_times *out) {

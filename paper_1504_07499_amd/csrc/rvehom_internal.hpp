@@ -101,6 +101,9 @@ struct Solver {
     LaunchArgs args(const uint8_t *d_phase) const;
     int ensure_twiddles(hipStream_t s);
     int begin(const uint8_t *d_phase, const double k[3], double tol, const SolverOpts &o, hipStream_t s);
+    int begin_elastic(const uint8_t *d_phase, const double moduli[6], double tol, const SolverOpts &o,
+                      hipStream_t s);
+    int start(const uint8_t *d_phase, const SolverOpts &o, hipStream_t s);
     int tune_zpass(const LaunchArgs &a, hipStream_t s);
     int enqueue(const uint8_t *d_phase, int count, int max_iter, int timing, hipStream_t s);
     int launch_iteration(const LaunchArgs &a, hipStream_t s, int mask, hipEvent_t *ev, bool red_in_z,
@@ -112,10 +115,11 @@ struct Solver {
     void drop_graphs();
     int poll(bool wait, int max_iter);
     int collect(const SolverOpts &o, hipStream_t s, rve_result *out, double *hist, int hist_cap,
-                rve_kernel_times *kt);
+                rve_kernel_times *kt, rve_elastic_result *eout = nullptr);
 };
 
 const SolverOps *lookup_ops(int precision, int n);
+const SolverOps *lookup_ops_el(int precision, int n);
 void set_error(const char *fmt, ...);
 void clear_error();
 int validate_k(const double k[3], double tol);
@@ -185,5 +189,7 @@ struct rve_s {
     // per precision, one solver per load case: a full solve runs as three
     // concurrent single-load-case solves on their own streams
     rvehom::Solver chain[2][3];
+    // per precision, the elastic case's solver (36 channels)
+    rvehom::Solver el[2];
     rve_kernel_times times{};
 };

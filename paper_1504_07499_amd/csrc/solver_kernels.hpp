@@ -375,7 +375,7 @@ template <int N, int S> __device__ __forceinline__ void plane_of_block(int b, in
 // P1: tau = (k - k0) e fused into the load; 2D R2C of the (ch, z) plane.
 // With PHI the same pass transforms the flux k e for the equilibrium check.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int S, int NT, bool PHI = false>
+template <typename T, int N, int S, int NT, bool PHI = false, int NC = 3>
 __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_plane(const T *__restrict__ e, const uint8_t *__restrict__ ph,
                                                   Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
                                                   const Cx<T> *__restrict__ twg,
@@ -394,11 +394,13 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
     int ch, z, h;
     plane_of_block<N, S>(blockIdx.x, ch, z, h);
     ch += ch0;  // the grid covers channels ch0 .. (all nine, or one load case's three)
-    const int lc = ch / 3;
+    const int lc = ch / NC;
     // PHI: the flux k e of the equilibrium check (step 1); else tau = (k - k0) e
-    // (augmented Lagrangian: the buffer already holds tau)
+    // (augmented Lagrangian: the buffer already holds tau; elasticity: the
+    // deviatoric channels take their own table)
     if (PHI ? !st->eq_pending[lc] : st->done[lc]) return;
-    const double *lut = PHI ? prm->k : prm->dk;
+    const bool dev = NC == 6 && ch % NC != 0;
+    const double *lut = PHI ? prm->k : (dev ? prm->dk_dev : prm->dk);
     const bool tau_in = !PHI && prm->scheme == 2;
     const T d0 = tau_in ? (T)1 : (T)lut[0], d1 = tau_in ? (T)1 : (T)lut[1], d2 = tau_in ? (T)1 : (T)lut[2];
     const T tm = PHI ? (T)0 : (T)st->tau_mean[ch];  // only the discarded mean mode changes
@@ -747,7 +749,7 @@ __global__ __launch_bounds__(NT) void k_zeq(const Cx<T> *__restrict__ spec, cons
 // of the plane per iteration instead of two of each.  The mean subtracted
 // from tau is the previous iteration's (any constant is exact: the mean
 // mode of tau is replaced by E).
-template <typename T, int N, int S, int NT, bool FWD = false, bool AL = false>
+template <typename T, int N, int S, int NT, bool FWD = false, bool AL = false, int NC = 3>
 __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_plane(T *__restrict__ e, const uint8_t *__restrict__ ph,
                                                   Cx<T> *__restrict__ spec,
                                                   Cx<T> *__restrict__ nyq,
@@ -773,9 +775,18 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
     int ch, z, h;
     plane_of_block<N, S>(blockIdx.x, ch, z, h);
     ch += ch0;  // the grid covers channels ch0 .. (all nine, or one load case's three)
-    const int lc = ch / 3;
+    const int lc = ch / NC;
     if (st->done[lc]) return;
-    const T ec = (ch % 4 == 0) ? (T)1 : (T)0;  // E_comp of this channel (ch = 3 lc + comp)
+    // E_comp of this channel (ch = NC lc + comp; E of load case lc is the unit
+    // vector or basis tensor lc)
+    const T ec = (ch % (NC + 1) == 0) ? (T)1 : (T)0;
+    // per-phase tables: the conductivities, or (elasticity) those of the
+    // hydrostatic channel or of the deviatoric ones
+    const bool dev = NC == 6 && ch % NC != 0;
+    const double *pk = dev ? prm->k_dev : prm->k;
+    const double *pdk = dev ? prm->dk_dev : prm->dk;
+    const double *pw = dev ? prm->w_dev : prm->w;
+    const double k0c = dev ? prm->k0_dev : prm->k0;
 
     const Cx<T> *sb = spec + ((size_t)ch * N + z) * N * H;
     const Cx<T> *nb = nyq + ((size_t)ch * N + z) * N;
@@ -826,8 +837,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
     // per-phase {w, k - k0} of the update (fused form; augmented Lagrangian:
     // {k - k0, 1 / (k + k0)})
     __shared__ Cx<T> lut[3];
-    if (FWD && tid < 3)
-        lut[tid] = AL ? Cx<T>{(T)prm->dk[tid], (T)prm->gam[tid]} : Cx<T>{(T)prm->w[tid], (T)prm->dk[tid]};
+    if (FWD && tid < 3) lut[tid] = AL ? Cx<T>{(T)pdk[tid], (T)prm->gam[tid]} : Cx<T>{(T)pw[tid], (T)pdk[tid]};
     __syncthreads();
     if constexpr (P0) {
         for (int m = tid; m < ROWS; m += NT) {
@@ -850,11 +860,11 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
     __syncthreads();
     fft_lds<T, H, true, ROWS, 1, NT, N, SeqStride<RS>, PMX>(plane, tw, tid);
 
-    const T w0 = (T)prm->w[0], w1 = (T)prm->w[1], w2 = (T)prm->w[2];
-    const double k0d = prm->k[0], k1d = prm->k[1], k2d = prm->k[2];
-    const T d0 = (T)prm->dk[0], d1 = (T)prm->dk[1], d2 = (T)prm->dk[2];
+    const T w0 = (T)pw[0], w1 = (T)pw[1], w2 = (T)pw[2];
+    const double k0d = pk[0], k1d = pk[1], k2d = pk[2];
+    const T d0 = (T)pdk[0], d1 = (T)pdk[1], d2 = (T)pdk[2];
     const T tm = (T)st->tau_mean[ch];
-    const T k0t = (T)prm->k0;
+    const T k0t = (T)k0c;
     const T g0 = (T)prm->gam[0], g1 = (T)prm->gam[1], g2 = (T)prm->gam[2];
     (void)d0, (void)d1, (void)d2, (void)tm, (void)k0t, (void)g0, (void)g1, (void)g2;
     T *eb = e + (size_t)ch * N * NN + (size_t)z * NN;
@@ -921,7 +931,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
         // flux k e+ = (k - k0) e+ + k0 e+ = (tau + tm) + k0 e+ per voxel, summed
         // over the voxels of this thread (V per item idx = tid + i NT < TOTL)
         const int items = tid < TOTL ? (TOTL - 1 - tid) / NT + 1 : 0;
-        fl += (double)(items * V) * (double)tm + prm->k0 * se;
+        fl += (double)(items * V) * (double)tm + k0c * se;
     }
     double v3[3] = {r2, fl, se};
     block_sum<NT, 3>(v3, red);
@@ -1152,15 +1162,16 @@ __global__ void k_to_tau(T *__restrict__ e, const uint8_t *__restrict__ ph, size
 template <typename T>
 __global__ void k_init(T *__restrict__ e, size_t M, const DevParams *__restrict__ prm, DevState *__restrict__ st) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < 9 * M; i += stride) {
+    const int nc = prm->nc;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)(nc * nc) * M; i += stride) {
         const int ch = (int)(i / M);
-        e[i] = (ch % 4 == 0) ? (T)1 : (T)0;  // ch = 3 lc + comp, comp == lc <=> ch in {0, 4, 8}
+        e[i] = (ch % (nc + 1) == 0) ? (T)1 : (T)0;  // ch = nc lc + comp, comp == lc
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->iter = 0;
         int all = 1;
-        for (int lc = 0; lc < 3; ++lc) {
-            const int on = (prm->lc_mask >> lc) & 1;
+        for (int lc = 0; lc < 6; ++lc) {
+            const int on = lc < nc && ((prm->lc_mask >> lc) & 1);
             st->done[lc] = on ? 0 : 1;
             all &= !on;
             st->status[lc] = on ? ST_NOT_CONVERGED : ST_OK;
@@ -1171,7 +1182,7 @@ __global__ void k_init(T *__restrict__ e, size_t M, const DevParams *__restrict_
             st->best[lc] = 1e308;
             st->eps_eq[lc] = -1.0;
         }
-        for (int i = 0; i < 9; ++i) {
+        for (int i = 0; i < 36; ++i) {
             st->K[i] = 0.0;
             st->tau_mean[i] = 0.0;
         }

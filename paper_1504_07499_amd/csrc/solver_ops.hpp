@@ -58,15 +58,24 @@ struct SolverOps {
     void (*inv_fwd_al)(const LaunchArgs &, hipStream_t, int lc_sel);
     void (*inv_al)(const LaunchArgs &, hipStream_t, int lc_sel);
     void (*to_tau)(const LaunchArgs &, size_t M, hipStream_t);
+    // components per load case = number of load cases: 3 (conductivity) or
+    // 6 (elasticity); the fields hold nc * nc channels
+    int nc;
+    // the reduction of the per-block partials as a launch of its own
+    void (*reduce)(const LaunchArgs &, int nper, hipStream_t);
 };
 
 const SolverOps *ops_f32(int n);
 const SolverOps *ops_f64(int n);
+const SolverOps *ops_el_f32(int n);
+const SolverOps *ops_el_f64(int n);
 void launch_reduce(const LaunchArgs &a, int nper, hipStream_t s);
 void launch_eq_reduce(const LaunchArgs &a, int per_lc, int final, hipStream_t s);
 void launch_eq_request(const LaunchArgs &a, hipStream_t s);
 
-// Grid sizes compiled into the library (ascending), per precision.
+// Grid sizes compiled into the library (ascending), per precision; the
+// elastic case's own list.
 int supported_sizes(int precision, const int **list);
+int supported_sizes_el(int precision, const int **list);
 
 }  // namespace rvehom

@@ -1,0 +1,133 @@
+"""GPU parity of the elastic case (linear elasticity with isotropic phases,
+the extension Sec. 6 names) against the FP64 elastic oracle and closed forms.
+
+The GPU works in the orthonormal basis B_0..B_5 of symmetric tensors with the
+load cases E = B_j; the oracle takes any imposed strain in plain tensor
+components, so it is called with E = B_j and its results are projected on
+the basis here.  Bars as for conductivity: FP64 1e-9 (fields after fixed
+iterations 1e-11), FP32 1e-4 (fields 3e-5).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1504_07499_amd as rh
+from paper_1504_07499_amd import geom
+
+pytestmark = pytest.mark.gpu
+
+B = rh.ELASTIC_BASIS
+# bulk, shear modulus: matrix (epoxy-like), inclusion (glass-like), coating (stiff)
+MOD = np.array([[4.0, 1.5], [40.0, 30.0], [150.0, 100.0]])
+COMPS = oracle.EL_COMPS
+MULT = np.array([1.0, 1.0, 1.0, 2.0, 2.0, 2.0])  # off-diagonal components appear twice
+
+
+def basis_strains():
+    """B_j as the oracle's tensor components (11, 22, 33, 23, 13, 12)."""
+    return np.array([[B[j][a, b] for (a, b) in COMPS] for j in range(6)])
+
+
+def to_basis(t):
+    """Tensor components (..., 6) -> basis components (..., 6)."""
+    P = np.array([[MULT[q] * B[k][COMPS[q]] for q in range(6)] for k in range(6)])
+    return np.tensordot(t, P.T, axes=([-1], [0]))
+
+
+def tensor_err(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("n", [8, 12, 16, 24])
+def test_elastic_fixed_iterations_vs_oracle(n, precision):
+    """Three iterations from E = B_j on an i.i.d. phase image: every voxel of
+    every component, the stiffness and the residual histories."""
+    print(f"\n[case] elastic field n={n} precision={precision}", flush=True)
+    ph = geom.random_phases(n, seed=500 + n)
+    ref = oracle.homogenize_elastic(ph, MOD, basis_strains(), tol=0.0, max_iter=3, want_field=True)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize_elastic(r, MOD, 0.0, max_iter=3, precision=precision, want_field=True, hist_cap=8)
+    bar = 1e-11 if precision == 1 else 3e-5
+    ref_field = to_basis(np.moveaxis(ref.field, 1, -1))  # (lc, z, y, x, k)
+    assert tensor_err(np.moveaxis(g.field, 1, -1), ref_field) <= bar
+    Cb = to_basis(ref.S).T  # column j: stress of load case j in the basis
+    assert tensor_err(g.C_basis, Cb) <= bar
+    assert list(g.iters) == [3] * 6
+    for j in range(6):
+        np.testing.assert_allclose(g.history[j], ref.history[j], rtol=bar * 10)
+
+
+def test_elastic_converged_fp64_vs_oracle():
+    """16^3 RSA coated spheres, tol 1e-8, FP64: C_hom (Voigt) within 1e-9 of
+    the oracle's, built from the same six load cases."""
+    print("\n[case] elastic converged fp64", flush=True)
+    ph, _, _ = geom.generate(16, 4, 0.25, 0.2, 5)
+    ref = oracle.homogenize_elastic(ph, MOD, basis_strains(), tol=1e-8)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize_elastic(r, MOD, 1e-8, precision=1)
+    assert g.status == rh.RVE_OK
+    assert list(g.iters) == list(ref.iters)
+    assert tensor_err(g.C_basis, to_basis(ref.S).T) <= 1e-9
+    assert np.abs(g.C - g.C.T).max() <= 1e-9 * np.abs(g.C).max()
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_elastic_equal_shear_hill_64(precision):
+    """Phases of equal shear modulus on a 64^3 RSA RVE: the hydrostatic load
+    case gives Hill's exact bulk modulus (closed form, any geometry)."""
+    print(f"\n[case] elastic hill 64 precision={precision}", flush=True)
+    mod = np.array([[4.0, 2.0], [40.0, 2.0], [150.0, 2.0]])
+    ph, _, _ = geom.generate(64, 12, 0.3, 0.2, 6)
+    kv = mod[ph, 0]
+    khill = 1.0 / np.mean(1.0 / (kv + 4.0 * 2.0 / 3.0)) - 4.0 * 2.0 / 3.0
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize_elastic(r, mod, 1e-11 if precision else 1e-6, precision=precision)
+    # load case B_0 = I / sqrt3: mean stress 3 kappa* B_0 -> C_basis[0, 0] = 3 kappa*
+    # (exact at the fixed point; the stopping tolerance sets the bar)
+    assert abs(g.C_basis[0, 0] / 3.0 - khill) <= (1e-9 if precision else 1e-5) * khill
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_elastic_laminate_backus_48(precision):
+    """Layers normal to x on a 48^3 grid: the Backus stiffness (closed form)."""
+    print(f"\n[case] elastic laminate precision={precision}", flush=True)
+    prof = np.array([0] * 17 + [1] * 9 + [2] * 22, np.uint8)
+    ph = np.broadcast_to(prof.reshape(1, 1, 48), (48, 48, 48)).copy()
+    kap, mu = MOD[prof, 0], MOD[prof, 1]
+    lam = kap - 2 * mu / 3
+    a = lam + 2 * mu
+    h = np.mean
+    C = np.zeros((6, 6))
+    C11 = 1.0 / h(1 / a)
+    C12 = h(lam / a) * C11
+    C[0, 0] = C11
+    C[0, 1] = C[1, 0] = C[0, 2] = C[2, 0] = C12
+    C[1, 1] = C[2, 2] = h(a - lam ** 2 / a) + h(lam / a) ** 2 * C11
+    C[1, 2] = C[2, 1] = h(lam - lam ** 2 / a) + h(lam / a) ** 2 * C11
+    C[3, 3] = h(mu)
+    C[4, 4] = C[5, 5] = 1.0 / h(1 / mu)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize_elastic(r, MOD, 1e-10 if precision else 1e-6, precision=precision, max_iter=20000)
+    assert tensor_err(g.C, C) <= (1e-9 if precision else 1e-4)
+
+
+def test_elastic_128_fp32_against_fp64():
+    """128^3 RSA coated spheres (50 spheres, f = 0.3, l = 0.2): FP32 stiffness
+    within 1e-4 of FP64, both major-symmetric and near-isotropic."""
+    print("\n[case] elastic 128", flush=True)
+    with rh.rve_create(128, 50, 0.30, 0.2, 2) as r:
+        g32 = rh.homogenize_elastic(r, MOD, 1e-6, precision=0)
+        g64 = rh.homogenize_elastic(r, MOD, 1e-6, precision=1)
+    assert g64.status == rh.RVE_OK and g32.status in (rh.RVE_OK, rh.RVE_STALLED)
+    assert tensor_err(g32.C, g64.C) <= 1e-4
+    for g in (g32, g64):
+        assert np.abs(g.C - g.C.T).max() <= 1e-5 * np.abs(g.C).max()
+
+
+def test_elastic_rejections():
+    print("\n[case] elastic rejections", flush=True)
+    with rh.rve_create_from_phases(geom.random_phases(16, 5)) as r:
+        with pytest.raises(rh.RveError):
+            rh.homogenize_elastic(r, [[1.0, 1.0], [2.0, -1.0], [3.0, 1.0]], 1e-6)
+    assert 512 not in rh.rve_supported_n_elastic(0) and 128 in rh.rve_supported_n_elastic(1)
