@@ -159,7 +159,7 @@ __global__ __launch_bounds__(NT) void k_zgreen_el(Cx<T> *__restrict__ spec, Cx<T
     }
 }
 
-// Reduction of the elastic partials as a kernel of its own (64 threads).
+// Reduction of the elastic partials as a kernel of its own (576 threads).
 __global__ void k_reduce_el(const double *part, int nper, const DevParams *prm, DevState *st, double *hist);
 
 template <typename T, int N> struct ElasticInstance {
@@ -204,7 +204,7 @@ template <typename T, int N> struct ElasticInstance {
         hipLaunchKernelGGL((k_to_f64<T>), dim3(1024), dim3(256), 0, s, dst, (const T *)e, count);
     }
     static void reduce(const LaunchArgs &a, int nper, hipStream_t s) {
-        hipLaunchKernelGGL(k_reduce_el, dim3(1), dim3(64), 0, s, (const double *)a.part, nper, a.prm, a.st, a.hist);
+        hipLaunchKernelGGL(k_reduce_el, dim3(1), dim3(576), 0, s, (const double *)a.part, nper, a.prm, a.st, a.hist);
     }
 
     static const SolverOps *ops(int precision) {

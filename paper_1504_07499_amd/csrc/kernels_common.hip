@@ -82,8 +82,8 @@ void launch_reduce(const LaunchArgs &a, int nper, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, a.part, nper, a.prm, a.st, a.hist);
 }
 
-// The elastic case's reduction (one workgroup of 64 threads).
-__global__ __launch_bounds__(64) void k_reduce_el(const double *part, int nper, const DevParams *prm, DevState *st,
+// The elastic case's reduction (one workgroup of 576 threads).
+__global__ __launch_bounds__(576) void k_reduce_el(const double *part, int nper, const DevParams *prm, DevState *st,
                                                   double *hist) {
     reduce_block_el(part, nper, prm, st, hist, threadIdx.x);
 }

@@ -114,25 +114,32 @@ __device__ __forceinline__ void reduce_block(const double *__restrict__ part, in
     st->all_done = all;
 }
 
-// The same for the elastic case (six load cases of six components): thread t
-// < 36 sums channel t's partials in a fixed order, thread 0 forms each load
-// case's residual, mean stress and per-channel mean of tau and decides.
-// Run by one workgroup of at least 64 threads.
+// The same for the elastic case (six load cases of six components): 16
+// lanes per channel (576 threads) sum channel ch's partials in a fixed order
+// (lane l takes blocks l, l + 16, ...; then a fixed tree over the 16 lanes),
+// and thread 0 forms each load case's residual, mean stress and per-channel
+// mean of tau and decides.
 __device__ __forceinline__ void reduce_block_el(const double *__restrict__ part, int nper,
                                                 const DevParams *__restrict__ prm, DevState *__restrict__ st,
                                                 double *__restrict__ hist, int tid) {
     __shared__ double tot[36][3];
-    if (tid < 36) {
-        double r = 0.0, f = 0.0, m = 0.0;
-        const double *pc = part + (size_t)tid * nper * 3;
-        for (int b = 0; b < nper; ++b) {
-            r += pc[3 * b];
-            f += pc[3 * b + 1];
-            m += pc[3 * b + 2];
+    const int ch = tid >> 4, l = tid & 15;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (ch < 36) {
+        const double *pc = part + (size_t)ch * nper * 3;
+        for (int b = l; b < nper; b += 16) {
+            v[0] += pc[3 * b];
+            v[1] += pc[3 * b + 1];
+            v[2] += pc[3 * b + 2];
         }
-        tot[tid][0] = r;
-        tot[tid][1] = f;
-        tot[tid][2] = m;
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+        for (int o = 8; o > 0; o >>= 1) v[q] += __shfl_down(v[q], o, 16);
+    if (ch < 36 && l == 0) {
+        tot[ch][0] = v[0];
+        tot[ch][1] = v[1];
+        tot[ch][2] = v[2];
     }
     __syncthreads();
     if (tid != 0) return;
