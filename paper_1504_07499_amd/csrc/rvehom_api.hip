@@ -1,11 +1,12 @@
 // rvehom_api.hip -- host side of the C ABI declared in include/rvehom.h:
-// RVE handles, device workspaces, the iteration driver with on-device
-// convergence, batched solves and kernel timing.
+// RVE handles, device workspaces, the iteration loop with on-device
+// convergence, batched solves, the elastic case and kernel timing.
 //
-// Paper: arXiv:1504.07499.  The driver runs the Algorithm of Sec. 3
+// Paper: arXiv:1504.07499.  The host loop runs the Algorithm of Sec. 3
 // (initialise with grad Theta, iterate steps 2-7 until eps_comp < acc, then
 // L_hom from <phi>) for the three unit load cases at once; the reference
-// medium is the one of Sec. 5.
+// medium is the one of Sec. 5.  The elastic case (Sec. 6) runs the same loop
+// over six load cases.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
