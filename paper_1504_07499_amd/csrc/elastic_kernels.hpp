@@ -169,10 +169,10 @@ template <typename T, int N> struct ElasticInstance {
     static constexpr int W = ztile_el<T, N>();
     static_assert(W >= 2, "no z tile fits in LDS");
     static constexpr int NTP = plane_threads<T, N>();
-    // 512-thread z tiles: the six-component tile needs ~128 VGPRs, so the
-    // waves per CU are set by registers, not by LDS (measured 7 % faster
-    // than 256 threads at 128^3 FP32)
-    static constexpr int NTZ = 512;
+    // FP32: 512-thread z tiles (the six-component tile needs ~128 VGPRs, so
+    // the waves per CU are set by registers, not by LDS; measured 7 % faster
+    // than 256 threads at 128^3); FP64: 256 (measured faster)
+    static constexpr int NTZ = sizeof(T) == 4 ? 512 : 256;
     static constexpr int NPER = N * S;
     static constexpr bool FUSED = S == 1 && !(sizeof(T) == 4 && N == 96);
     static constexpr int PGRID = CH * N * S;
