@@ -131,3 +131,36 @@ def test_elastic_rejections():
         with pytest.raises(rh.RveError):
             rh.homogenize_elastic(r, [[1.0, 1.0], [2.0, -1.0], [3.0, 1.0]], 1e-6)
     assert 512 not in rh.rve_supported_n_elastic(0) and 128 in rh.rve_supported_n_elastic(1)
+
+
+def test_elastic_start_field_continues_the_iteration():
+    """The accelerated iteration's state is the strain field alone: one
+    iteration from the field of two equals three iterations from E (FP64)."""
+    print("\n[case] elastic start field", flush=True)
+    ph = geom.random_phases(16, 77)
+    with rh.rve_create_from_phases(ph) as r:
+        g2 = rh.homogenize_elastic(r, MOD, 0.0, max_iter=2, precision=1, want_field=True)
+        g1 = rh.homogenize_elastic(r, MOD, 0.0, max_iter=1, precision=1, want_field=True, init_field=g2.field)
+        g3 = rh.homogenize_elastic(r, MOD, 0.0, max_iter=3, precision=1, want_field=True)
+    assert tensor_err(g1.field, g3.field) <= 1e-12
+    assert tensor_err(g1.C_basis, g3.C_basis) <= 1e-12
+
+
+def test_elastic_homogeneous_and_iteration_cap():
+    """One phase everywhere: C_hom = C after one iteration; an unreachable
+    tolerance with a cap reports NOT_CONVERGED after exactly the cap."""
+    print("\n[case] elastic homogeneous and cap", flush=True)
+    ph = np.full((16, 16, 16), 1, np.uint8)
+    kap, mu = MOD[1]
+    lam = kap - 2 * mu / 3
+    C = np.zeros((6, 6))
+    C[:3, :3] = lam
+    C[np.arange(3), np.arange(3)] = lam + 2 * mu
+    C[np.arange(3, 6), np.arange(3, 6)] = mu
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize_elastic(r, MOD, 1e-10, precision=1)
+        assert list(g.iters) == [1] * 6
+        np.testing.assert_allclose(g.C, C, atol=1e-10 * np.abs(C).max())
+    with rh.rve_create_from_phases(geom.random_phases(16, 3)) as r:
+        c = rh.homogenize_elastic(r, MOD, 1e-30, precision=1, max_iter=7)
+        assert c.status == rh.RVE_NOT_CONVERGED and list(c.iters) == [7] * 6
