@@ -242,3 +242,30 @@ def test_z_tile_widths_give_identical_results(n, precision):
                 os.environ.pop("RVEHOM_ZTILE", None)
     assert np.array_equal(out[0].K, out[1].K)
     assert np.array_equal(out[0].iters, out[1].iters)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_nonfinite_start_field_is_reported(precision):
+    """A NaN in the start field of load case e_2 makes its residual
+    non-finite: the solve reports NONFINITE (as the oracle does for that load
+    case, after one iteration); the other load cases, solved from the same
+    start field, converge as without it."""
+    print(f"\n[case] non-finite start field precision={precision}", flush=True)
+    import oracle
+
+    ph = geom.random_phases(16, 21)
+    init = np.zeros((3, 3, 16, 16, 16))
+    for j in range(3):
+        init[j, j] = 1.0
+    init[1, 0, 3, 4, 5] = np.nan
+    ref = oracle.homogenize(ph, K3, tol=1e-6, init_field=init)
+    assert ref.status[1] == rh.RVE_ERR_NONFINITE and int(ref.iters[1]) == 1
+    with rh.rve_create_from_phases(ph) as r:
+        with pytest.raises(rh.RveError) as err:
+            rh.homogenize(r, K3, 1e-6, precision=precision, init_field=init)
+        assert err.value.status == rh.RVE_ERR_NONFINITE
+        g = rh.homogenize(r, K3, 1e-6, precision=precision, init_field=init, lc_mask=5)
+        clean = rh.homogenize(r, K3, 1e-6, precision=precision, lc_mask=5)
+    for j in (0, 2):
+        assert int(g.lc_status[j]) == int(clean.lc_status[j])
+        np.testing.assert_allclose(g.K[:, j], clean.K[:, j], rtol=1e-12, atol=0)
