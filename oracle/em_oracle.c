@@ -15,8 +15,12 @@
  *           imposed mean gradient), eq. (1) polarization, eq. (3) Fourier
  *           Lippmann-Schwinger equation, the Green operator Gamma^0 and the
  *           Algorithm "FFT-based homogenization scheme for thermal
- *           conductivity case" (steps 1-7), and L_hom from <phi>.
+ *           conductivity case" (steps 1-7), and L_hom from <phi>; the basic
+ *           and augmented-Lagrangian schemes named there as alternatives
+ *           (orc_homogenize, scheme 1 and 2).
  *   Sec. 5  reference medium L0 = -sqrt(min k * max k) I.
+ *   Sec. 6  the elastic case named as the extension (orc_homogenize_elastic,
+ *           at the end of this file).
  *
  * Readings of the paper taken here (each is listed with its reason in the
  * design notes of the repository):
