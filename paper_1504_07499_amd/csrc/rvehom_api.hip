@@ -364,8 +364,13 @@ extern "C" void rve_destroy(rve_t r) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(r->device);
-    r->sol[0].release();
-    r->sol[1].release();
+    // every solver of the handle (thermal, load-case chains, elastic) frees
+    // its workspace, streams and graphs while the handle's device is current
+    for (int p = 0; p < 2; ++p) {
+        r->sol[p].release();
+        for (auto &c : r->chain[p]) c.release();
+        r->el[p].release();
+    }
     if (r->d_phase) (void)hipFree(r->d_phase);
     (void)hipSetDevice(cur);
     delete r;
@@ -873,14 +878,36 @@ int Solver::collect(const SolverOpts &o, hipStream_t s, rve_result *out, double 
     return RVE_OK;
 }
 
-rve_status worst_status(const rve_result &r, int lc_mask) {
+// The worst of count per-load-case statuses (those selected by mask): an
+// error first, then NONFINITE, STALLED, NOT_CONVERGED, OK.
+static rve_status worst_of(const int *status, int count, int mask) {
     int worst = RVE_OK;
     auto rank = [](int s) { return s < 0 ? 100 - s : s == RVE_STALLED ? 3 : s == RVE_NOT_CONVERGED ? 2 : 0; };
-    for (int j = 0; j < 3; ++j)
-        if ((lc_mask >> j) & 1)
-            if (rank(r.status[j]) > rank(worst)) worst = r.status[j];
+    for (int j = 0; j < count; ++j)
+        if ((mask >> j) & 1)
+            if (rank(status[j]) > rank(worst)) worst = status[j];
     return (rve_status)worst;
 }
+
+rve_status worst_status(const rve_result &r, int lc_mask) { return worst_of(r.status, 3, lc_mask); }
+
+// Makes a handle's device current for a scope and restores the caller's
+// device on every exit path.
+struct DeviceScope {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceScope(int dev) {
+        int cur = 0;
+        err = hipGetDevice(&cur);
+        if (err == hipSuccess && cur != dev) {
+            err = hipSetDevice(dev);
+            if (err == hipSuccess) prev = cur;
+        }
+    }
+    ~DeviceScope() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
 
 // The three load cases of a solve are independent (Algorithm of Sec. 3 per
 // E = e_j).  Where the iteration kernels can be restricted to one load case
@@ -1037,9 +1064,8 @@ static rve_status solve_elastic(rve_s *r, const double moduli[6], double tol, co
         set_error("grid size %d is not built for the elastic case in precision %d", r->n, o.precision);
         return RVE_ERR_ARG;
     }
-    int cur = 0;
-    HIP_CHECK(hipGetDevice(&cur));
-    if (cur != r->device) HIP_CHECK(hipSetDevice(r->device));
+    DeviceScope dev(r->device);
+    HIP_CHECK(dev.err);
     Solver &sv = r->el[o.precision];
     int rc = sv.prepare(ops, nullptr, 0);
     if (rc != RVE_OK) return (rve_status)rc;
@@ -1056,12 +1082,7 @@ static rve_status solve_elastic(rve_s *r, const double moduli[6], double tol, co
     res.solve_ms = ms;
     basis_to_voigt(res.C_basis, res.C);
     *out = res;
-    if (cur != r->device) HIP_CHECK(hipSetDevice(cur));
-    int worst = RVE_OK;
-    auto rank = [](int v) { return v < 0 ? 100 - v : v == RVE_STALLED ? 3 : v == RVE_NOT_CONVERGED ? 2 : 0; };
-    for (int j = 0; j < 6; ++j)
-        if (rank(res.status[j]) > rank(worst)) worst = res.status[j];
-    return (rve_status)worst;
+    return worst_of(res.status, 6, 63);
 }
 
 // One RVE, start to finish, on stream s.
@@ -1073,14 +1094,9 @@ rve_status solve_one(rve_s *r, const double k[3], double tol, const SolverOpts &
         return RVE_ERR_ARG;
     }
     if (check_scheme(o, ops) != RVE_OK) return RVE_ERR_ARG;
-    int cur = 0;
-    HIP_CHECK(hipGetDevice(&cur));
-    if (cur != r->device) HIP_CHECK(hipSetDevice(r->device));
-    if (use_chains(ops, o)) {
-        rve_status st = solve_chains(r, ops, k, tol, o, out, hist, hist_cap);
-        if (cur != r->device) HIP_CHECK(hipSetDevice(cur));
-        return st;
-    }
+    DeviceScope dev(r->device);
+    HIP_CHECK(dev.err);
+    if (use_chains(ops, o)) return solve_chains(r, ops, k, tol, o, out, hist, hist_cap);
     Solver &sv = r->sol[o.precision];
     int rc = sv.prepare(ops, o.workspace, o.workspace_bytes);
     if (rc != RVE_OK) return (rve_status)rc;
@@ -1096,7 +1112,6 @@ rve_status solve_one(rve_s *r, const double k[3], double tol, const SolverOpts &
     HIP_CHECK(hipEventElapsedTime(&ms, sv.run_ev[0], sv.run_ev[1]));
     res.solve_ms = ms;
     if (out) *out = res;
-    if (cur != r->device) HIP_CHECK(hipSetDevice(cur));
     return worst_status(res, o.lc_mask);
 }
 
