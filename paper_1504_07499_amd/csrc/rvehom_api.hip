@@ -167,8 +167,11 @@ int Solver::prepare(const SolverOps *o, void *user_ws, size_t user_bytes) {
         poll_ev.resize(kPollSlots);
         for (auto &ev : poll_ev) HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         for (auto &si : slots) {
+            // kernel-timing events: nothing waits on them, so they skip the
+            // system-scope release (a cache writeback that would otherwise be
+            // charged to the bracketed kernel)
             si.ev.resize(2 * kChunk * 4);
-            for (auto &ev : si.ev) HIP_CHECK(hipEventCreate(&ev));
+            for (auto &ev : si.ev) HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableSystemFence));
         }
     }
     if (!run_ev[0]) {
