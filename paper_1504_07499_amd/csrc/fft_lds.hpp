@@ -391,7 +391,9 @@ __device__ __forceinline__ void fft_stage_any(Cx<T> *buf, const Cx<T> *__restric
     constexpr int R = radix_of(L, S);
     constexpr int NB = L / R;
     constexpr int NS = ns_before(L, S);
-    if constexpr (PM == kPairSeq) {
+    // sequence pairs only where they give every thread a butterfly pair (a
+    // radix-16 stage over few sequences would leave half the block idle)
+    if constexpr (PM == kPairSeq && (NSEQ / 2) * NB >= NT) {
         fft_stage_pseq<T, L, S, INV, NSEQ, ES, NT, TW, Seq>(buf, tw, tid);
     } else if constexpr (PM == kPairElem && ES == 1 && R % 2 == 0 && NB % 2 == 0 && (NS == 1 || NS % 2 == 0)) {
         fft_stage_pelem<T, L, S, INV, NSEQ, NT, TW, Seq>(buf, tw, tid);

@@ -206,27 +206,80 @@ __device__ __forceinline__ void c2r_pack_rows(Cx<T> *plane, const Cx<T> *__restr
     }
 }
 
-// Store the y-transformed plane (S = 1) as spectrum rows ky.  P0: column 0
-// holds Z = Y0 + i YH, the y transforms of the two real columns kx = 0 and
-// kx = N/2; by Hermitian symmetry Y0 = (Z[ky] + conj Z[-ky]) / 2 and
-// YH = (Z[ky] - conj Z[-ky]) / (2 i).
-template <typename T, int N, int NT, bool P0, int RS>
-__device__ __forceinline__ void store_plane(const Cx<T> *plane, Cx<T> *sb, Cx<T> *nb, int tid) {
-    constexpr int H = N / 2;
-    for (int idx = tid; idx < N * H / 2; idx += NT) {
-        const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
-        Cx<T> v0, v1;
-        ld_pair<T, RS % 2 == 0>(plane + m * RS + kx, v0, v1);
-        if (P0 && kx == 0) {
-            const Cx<T> b = conj(plane[(m == 0 ? 0 : N - m) * RS]);
-            const Cx<T> d = scale(v0 - b, (T)0.5);
-            nb[m] = Cx<T>{d.y, -d.x};
-            v0 = scale(v0 + b, (T)0.5);
+// Last stage of the forward y transform of a whole plane (S = 1), its outputs
+// stored straight to the spectrum rows ky in global memory instead of going
+// back through LDS: butterfly b = j H + q reads column q as the self-sorting
+// stage does, and row ky = d + r NS of column q leaves as one 8- or 16-byte
+// store (neighbouring threads: neighbouring columns).  Column 0 holds
+// Z = Y0 + i YH, the y transforms of the two real columns kx = 0 and N/2; it
+// also goes to LDS, and after a barrier (which orders the workgroup's two
+// stores to each of its addresses) Y0 = (Z[ky] + conj Z[-ky]) / 2 replaces it
+// and YH = (Z[ky] - conj Z[-ky]) / (2 i) is stored (Hermitian symmetry).
+template <typename T, int N, int NT, int RS>
+__device__ __forceinline__ void y_last_stage_store(Cx<T> *plane, const Cx<T> *__restrict__ tw, Cx<T> *sb, Cx<T> *nb,
+                                                   int tid) {
+    constexpr int H = N / 2, SL = num_stages(N) - 1, R = radix_of(N, SL), NS = ns_before(N, SL), NB = N / R;
+    // FP32: the same butterfly of columns 2p and 2p + 1 per thread (16-byte
+    // accesses) where the pairs still give every thread work
+    constexpr int P = (sizeof(T) == 4 && (H / 2) * NB >= NT) ? 2 : 1, NQ = H / P;
+    constexpr int TOT = NQ * NB, PER = (TOT + NT - 1) / NT, TWS = N / (NS * R);
+    Cx<T> v[PER][P][R];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int b = tid + i * NT;
+        if (TOT % NT == 0 || b < TOT) {
+            const int j = b / NQ, q = (b - j * NQ) * P;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if constexpr (P == 2) lds_ld2<T>(plane + q + (j + r * NB) * RS, v[i][0][r], v[i][1][r]);
+                else v[i][0][r] = plane[q + (j + r * NB) * RS];
+            }
+            if constexpr (NS > 1) {
+                const int k = j % NS;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    const Cx<T> w = tw[r * k * TWS];
+#pragma unroll
+                    for (int u = 0; u < P; ++u) v[i][u][r] = twmul<T, false>(v[i][u][r], w);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < P; ++u) dft<T, R, false>(v[i][u]);
         }
-        gstore2<T>(sb + (size_t)m * H + kx, v0, v1);
     }
-    if constexpr (!P0)
-        for (int m = tid; m < N; m += NT) nb[m] = plane[m * RS + H];
+    __syncthreads();  // every read of the plane is done before column 0 is rewritten
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int b = tid + i * NT;
+        if (TOT % NT == 0 || b < TOT) {
+            const int j = b / NQ, q = (b - j * NQ) * P;
+            const int k = j % NS, d = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {  // column 0: rewritten below
+                if constexpr (P == 2) gstore2<T>(sb + (size_t)(d + r * NS) * H + q, v[i][0][r], v[i][1][r]);
+                else sb[(size_t)(d + r * NS) * H + q] = v[i][0][r];
+            }
+        }
+    }
+    // compiler-only fence: keeps the column-0 LDS stores from being merged
+    // with the global ones into flat stores through a selected pointer
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int b = tid + i * NT;
+        if ((TOT % NT == 0 || b < TOT) && b % NQ == 0) {
+            const int j = b / NQ, k = j % NS, d = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) plane[(d + r * NS) * RS] = v[i][0][r];
+        }
+    }
+    __syncthreads();
+    for (int m = tid; m < N; m += NT) {
+        const Cx<T> a = plane[m * RS], b = conj(plane[(m == 0 ? 0 : N - m) * RS]);
+        const Cx<T> dd = scale(a - b, (T)0.5);
+        nb[m] = Cx<T>{dd.y, -dd.x};
+        sb[(size_t)m * H] = scale(a + b, (T)0.5);
+    }
 }
 
 // Steps 6-7 and the flux on V voxels of one row: e+ = e + w (c - e),
@@ -465,8 +518,8 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
         // whole plane: columns kx = 0 and N/2 are real, one complex column
         r2c_unpack_rows<T, N, ROWS, NT, true, RS>(plane, tw, tid);
         __syncthreads();
-        fft_lds<T, ROWS, false, H, RS, NT, N, SeqStride<1>, PMY>(plane, tw, tid);
-        store_plane<T, N, NT, true, RS>(plane, sb, nb, tid);
+        fft_stages<T, ROWS, 0, num_stages(ROWS) - 1, false, H, RS, NT, N, SeqStride<1>, PMY>(plane, tw, tid);
+        y_last_stage_store<T, N, NT, RS>(plane, tw, sb, nb, tid);
     } else {
         for (int idx = tid; idx < ROWS * (H / 2 + 1); idx += NT) {
             const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
@@ -740,6 +793,51 @@ __global__ __launch_bounds__(NT) void k_zeq(const Cx<T> *__restrict__ spec, cons
     }
 }
 
+// First stage of the inverse y transform of a whole plane (S = 1), its inputs
+// read straight from the spectrum rows in global memory rather than staged
+// through LDS: butterfly b = j H + q takes rows j + r N/R of column q, so
+// neighbouring threads read neighbouring columns (coalesced).  load() issues
+// the reads; finish() (after a barrier that published LDS column H) forms
+// column 0 as Y0 + i YH from the kx = N/2 column held in LDS column H, which
+// no stage writes, runs the radix-R DFTs (stage 0 has no twiddles) and writes
+// the outputs to LDS in the self-sorting order of stage 0.  The caller runs
+// the later stages.
+template <typename T, int N, int NT, int RS> struct YFirstStage {
+    static constexpr int H = N / 2, R = radix_of(N, 0), NB = N / R, TOT = H * NB, PER = (TOT + NT - 1) / NT;
+    Cx<T> v[PER][R];
+    __device__ __forceinline__ void load(const Cx<T> *__restrict__ sb, int tid) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int b = tid + i * NT;
+            if (TOT % NT == 0 || b < TOT) {
+                const int j = b / H, q = b - j * H;
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[i][r] = sb[(size_t)(j + r * NB) * H + q];
+            }
+        }
+    }
+    __device__ __forceinline__ void finish(Cx<T> *plane, int tid) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int b = tid + i * NT;
+            if (TOT % NT == 0 || b < TOT) {
+                const int j = b / H, q = b - j * H;
+                if (q == 0) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const Cx<T> yh = plane[(j + r * NB) * RS + H];
+                        v[i][r] = Cx<T>{v[i][r].x - yh.y, v[i][r].y + yh.x};
+                    }
+                }
+                dft<T, R, true>(v[i]);
+#pragma unroll
+                for (int r = 0; r < R; ++r) plane[(j * R + r) * RS + q] = v[i][r];
+            }
+        }
+        __syncthreads();
+    }
+};
+
 // ---------------------------------------------------------------------------
 // P3: 2D C2R of the (ch, z) plane, then steps 6-7 and the flux, fused.
 // ---------------------------------------------------------------------------
@@ -765,10 +863,9 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
     // 16-byte access, and pairs would double the registers of a butterfly)
     constexpr int PMX = (S == 1 && sizeof(T) == 4) ? kPairElem : kPairNone;
     constexpr int PMY = (S == 1 && sizeof(T) == 4) ? kPairSeq : kPairNone;
-    // S = 1 (P0): column kx = 0 becomes Y0 + i YH with YH the kx = N/2 column,
-    // one complex column for the y transform (both are transforms of real
+    // S = 1: column kx = 0 becomes Y0 + i YH with YH the kx = N/2 column, one
+    // complex column for the y transform (both are transforms of real
     // columns, so the inverse separates them exactly)
-    constexpr bool P0 = (S == 1);
     __shared__ Cx<T> plane[ROWS * RS];
     __shared__ double red[3 * (NT / 64)];
     const int tid = threadIdx.x;
@@ -790,10 +887,16 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
 
     const Cx<T> *sb = spec + ((size_t)ch * N + z) * N * H;
     const Cx<T> *nb = nyq + ((size_t)ch * N + z) * N;
-    {
+    YFirstStage<T, N, NT, RS> y0;
+    if constexpr (S == 1) {
+        // the main columns straight to the registers of the first y stage,
+        // the kx = N/2 column into LDS column H
+        y0.load(sb, tid);
+        for (int m = tid; m < ROWS; m += NT) plane[m * RS + H] = nb[m];
+    } else {
         // main columns, two complex values per access, all loads of a batch
-        // in flight before the LDS stores (S = 2: rows m and m + N/2 combined)
-        constexpr int NP = ROWS * H / 2, PERP = (NP + NT - 1) / NT, BP = S == 2 ? 4 : 8;
+        // in flight before the LDS stores (rows m and m + N/2 combined)
+        constexpr int NP = ROWS * H / 2, PERP = (NP + NT - 1) / NT, BP = 4;
 #pragma unroll
         for (int i0 = 0; i0 < PERP; i0 += BP) {
             Cx<T> va[BP], vb[BP], ua[BP], ub[BP];
@@ -803,7 +906,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
                 if (i0 + i < PERP && (NP % NT == 0 || idx < NP)) {
                     const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
                     gload2<T>(sb + (size_t)m * H + kx, va[i], vb[i]);
-                    if constexpr (S == 2) gload2<T>(sb + (size_t)(m + ROWS) * H + kx, ua[i], ub[i]);
+                    gload2<T>(sb + (size_t)(m + ROWS) * H + kx, ua[i], ub[i]);
                 }
             }
 #pragma unroll
@@ -811,23 +914,16 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
                 const int idx = tid + (i0 + i) * NT;
                 if (i0 + i < PERP && (NP % NT == 0 || idx < NP)) {
                     const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
-                    Cx<T> a0 = va[i], a1 = vb[i];
-                    if constexpr (S == 2) {
-                        const Cx<T> r = conj(twg[m]);
-                        a0 = h ? (a0 - ua[i]) * r : a0 + ua[i];
-                        a1 = h ? (a1 - ub[i]) * r : a1 + ub[i];
-                    }
+                    const Cx<T> r = conj(twg[m]);
+                    const Cx<T> a0 = h ? (va[i] - ua[i]) * r : va[i] + ua[i];
+                    const Cx<T> a1 = h ? (vb[i] - ub[i]) * r : vb[i] + ub[i];
                     st_pair<T, RS % 2 == 0>(plane + m * RS + kx, a0, a1);
                 }
             }
         }
         for (int m = tid; m < ROWS; m += NT) {
-            Cx<T> v = nb[m];
-            if constexpr (S == 2) {
-                const Cx<T> u = nb[m + ROWS];
-                v = h ? (v - u) * conj(twg[m]) : v + u;
-            }
-            plane[m * RS + H] = v;
+            const Cx<T> v = nb[m], u = nb[m + ROWS];
+            plane[m * RS + H] = h ? (v - u) * conj(twg[m]) : v + u;
         }
     }
     // twiddle table (length N) in LDS: short-latency loads inside the stages
@@ -839,15 +935,9 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
     __shared__ Cx<T> lut[3];
     if (FWD && tid < 3) lut[tid] = AL ? Cx<T>{(T)pdk[tid], (T)prm->gam[tid]} : Cx<T>{(T)pw[tid], (T)pdk[tid]};
     __syncthreads();
-    if constexpr (P0) {
-        for (int m = tid; m < ROWS; m += NT) {
-            const Cx<T> y0 = plane[m * RS], yh = plane[m * RS + H];
-            plane[m * RS] = Cx<T>{y0.x - yh.y, y0.y + yh.x};
-        }
-        __syncthreads();
-    }
     if constexpr (S == 1) {
-        fft_lds<T, ROWS, true, H, RS, NT, N, SeqStride<1>, PMY>(plane, tw, tid);
+        y0.finish(plane, tid);
+        fft_stages<T, ROWS, 1, num_stages(ROWS), true, H, RS, NT, N, SeqStride<1>, PMY>(plane, tw, tid);
         c2r_pack_rows<T, N, ROWS, NT, true, RS>(plane, tw, tid);
     } else {
         fft_lds<T, ROWS, true, RS, RS, NT, N, SeqStride<1>>(plane, tw, tid);
@@ -947,9 +1037,9 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
         fft_lds<T, H, false, ROWS, 1, NT, N, SeqStride<RS>, PMX>(plane, twf, tid);
         r2c_unpack_rows<T, N, ROWS, NT, true, RS>(plane, twf, tid);
         __syncthreads();
-        fft_lds<T, ROWS, false, H, RS, NT, N, SeqStride<1>, PMY>(plane, twf, tid);
-        store_plane<T, N, NT, true, RS>(plane, spec + ((size_t)ch * N + z) * N * H, nyq + ((size_t)ch * N + z) * N,
-                                    tid);
+        fft_stages<T, ROWS, 0, num_stages(ROWS) - 1, false, H, RS, NT, N, SeqStride<1>, PMY>(plane, twf, tid);
+        y_last_stage_store<T, N, NT, RS>(plane, twf, spec + ((size_t)ch * N + z) * N * H,
+                                         nyq + ((size_t)ch * N + z) * N, tid);
     }
 }
 
