@@ -562,6 +562,69 @@ template <typename T, int N, int W> __device__ __forceinline__ int ztile_of(int 
     return t;
 }
 
+// First stage of the forward z transform of a tile, its inputs read straight
+// from the pencils in global memory: butterfly b = j 3W + q takes elements
+// kz = j + r N/R of pencil q (component q / W, column q % W), neighbouring
+// threads neighbouring pencils.  finish() runs the radix-R DFTs (stage 0 has
+// no twiddles) and writes the outputs to LDS (pencil q at (q / W) N W + q % W,
+// element stride W) in the self-sorting order of stage 0.
+template <typename T, int N, int W, int NT> struct ZFirstStage {
+    static constexpr int NSEQ = 3 * W, NW = N * W, R = radix_of(N, 0), NB = N / R, TOT = NSEQ * NB,
+                         PER = (TOT + NT - 1) / NT;
+    Cx<T> v[PER][R];
+    __device__ __forceinline__ void load(const Cx<T> *base, size_t cstride, size_t zstride, int tid) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int b = tid + i * NT;
+            if (TOT % NT == 0 || b < TOT) {
+                const int j = b / NSEQ, q = b - j * NSEQ, c = q / W, w = q - c * W;
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[i][r] = base[c * cstride + (j + r * NB) * zstride + w];
+            }
+        }
+    }
+    __device__ __forceinline__ void finish(Cx<T> *buf, int tid) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int b = tid + i * NT;
+            if (TOT % NT == 0 || b < TOT) {
+                const int j = b / NSEQ, q = b - j * NSEQ, c = q / W, w = q - c * W;
+                dft<T, R, false>(v[i]);
+#pragma unroll
+                for (int r = 0; r < R; ++r) buf[c * NW + w + (j * R + r) * W] = v[i][r];
+            }
+        }
+        __syncthreads();
+    }
+};
+
+// Last stage of the inverse z transform of a tile, its outputs stored straight
+// to the pencils in global memory (the layout of ZFirstStage).
+template <typename T, int N, int W, int NT>
+__device__ __forceinline__ void z_last_stage_store(const Cx<T> *buf, const Cx<T> *__restrict__ tw, Cx<T> *base,
+                                                   size_t cstride, size_t zstride, int tid) {
+    constexpr int NSEQ = 3 * W, NW = N * W, SL = num_stages(N) - 1, R = radix_of(N, SL), NS = ns_before(N, SL),
+                  NB = N / R, TOT = NSEQ * NB, PER = (TOT + NT - 1) / NT, TWS = N / (NS * R);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int b = tid + i * NT;
+        if (TOT % NT == 0 || b < TOT) {
+            const int j = b / NSEQ, q = b - j * NSEQ, c = q / W, w = q - c * W;
+            Cx<T> v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = buf[c * NW + w + (j + r * NB) * W];
+            const int k = j % NS, d = (j - k) * R + k;
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[r] = twmul<T, true>(v[r], tw[r * k * TWS]);
+            }
+            dft<T, R, true>(v);
+#pragma unroll
+            for (int r = 0; r < R; ++r) base[c * cstride + (d + r * NS) * zstride + w] = v[r];
+        }
+    }
+}
+
 // With red_nper > 0 the first workgroup instead runs the reduction of the
 // previous inverse pass's partials (nper per channel) while the others do
 // the tiles.  The tiles then read the convergence flags as of the iteration
@@ -615,34 +678,16 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
         cstride = (size_t)N * N;
         zstride = N;
     }
-    // load the three components' pencils, two complex values per access,
-    // every load of a thread in flight before the first LDS store
-    constexpr int NP = 3 * NW / 2, PERP = (NP + NT - 1) / NT;
-    {
-        Cx<T> va[PERP], vb[PERP];
-#pragma unroll
-        for (int i = 0; i < PERP; ++i) {
-            const int idx = tid + i * NT;
-            if (NP % NT == 0 || idx < NP) {
-                const int e0 = 2 * idx, c = e0 / NW, r = e0 - c * NW, zz = r / W, w = r - zz * W;
-                gload2<T>(base + c * cstride + zz * zstride + w, va[i], vb[i]);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < PERP; ++i) {
-            const int idx = tid + i * NT;
-            if (NP % NT == 0 || idx < NP) {
-                buf[2 * idx] = va[i];
-                buf[2 * idx + 1] = vb[i];
-            }
-        }
-    }
+    // the three components' pencils straight to the registers of the first
+    // z stage
+    ZFirstStage<T, N, W, NT> z0;
+    z0.load(base, cstride, zstride, tid);
     // twiddle table (length N) in LDS: short-latency loads inside the stages
     __shared__ Cx<T> tws[N];
     table_to_lds<T, N, NT>(tws, twg, tid);
     const Cx<T> *tw = tws;
-    __syncthreads();
-    fft_lds<T, N, false, 3 * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
+    z0.finish(buf, tid);
+    fft_stages<T, N, 1, num_stages(N), false, 3 * W, W, NT, N, SeqBlocked<W, NW>, kPairNone>(buf, tw, tid);
     const T sc = (T)prm->inv_k0M;
     for (int idx = tid; idx < NW; idx += NT) {
         const int kz = idx / W, w = idx - kz * W;
@@ -676,11 +721,8 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
         buf[2 * NW + idx] = out[2];
     }
     __syncthreads();
-    fft_lds<T, N, true, 3 * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
-    for (int idx = tid; idx < NP; idx += NT) {
-        const int e0 = 2 * idx, c = e0 / NW, r = e0 - c * NW, zz = r / W, w = r - zz * W;
-        gstore2<T>(base + c * cstride + zz * zstride + w, buf[e0], buf[e0 + 1]);
-    }
+    fft_stages<T, N, 0, num_stages(N) - 1, true, 3 * W, W, NT, N, SeqBlocked<W, NW>, kPairNone>(buf, tw, tid);
+    z_last_stage_store<T, N, W, NT>(buf, tw, base, cstride, zstride, tid);
 }
 
 // FP64 block sums of NV values; results valid in thread 0.  red holds
