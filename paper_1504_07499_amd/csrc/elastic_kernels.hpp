@@ -73,19 +73,33 @@ __global__ __launch_bounds__(NT) void k_zgreen_el(Cx<T> *__restrict__ spec, Cx<T
         cstride = (size_t)N * N;
         zstride = N;
     }
+    // the six components' pencils straight to the registers of the first z
+    // stage, and the last inverse stage straight back (measured faster except
+    // for FP64 from 128^3 on, whose 4-column tiles keep the staged form)
+    constexpr bool DIRECT = !(sizeof(T) == 8 && N >= 128);
     constexpr int NP = NC * NW / 2;
-    for (int idx = tid; idx < NP; idx += NT) {
-        const int e0 = 2 * idx, c = e0 / NW, r = e0 - c * NW, zz = r / W, w = r - zz * W;
-        Cx<T> a, b;
-        gload2<T>(base + c * cstride + zz * zstride + w, a, b);
-        buf[e0] = a;
-        buf[e0 + 1] = b;
+    ZFirstStage<T, N, W, NT, NC> z0;
+    if constexpr (DIRECT) {
+        z0.load(base, cstride, zstride, tid);
+    } else {
+        for (int idx = tid; idx < NP; idx += NT) {
+            const int e0 = 2 * idx, c = e0 / NW, r = e0 - c * NW, zz = r / W, w = r - zz * W;
+            Cx<T> a, b;
+            gload2<T>(base + c * cstride + zz * zstride + w, a, b);
+            buf[e0] = a;
+            buf[e0 + 1] = b;
+        }
     }
     __shared__ Cx<T> tws[N];
     table_to_lds<T, N, NT>(tws, twg, tid);
     const Cx<T> *tw = tws;
-    __syncthreads();
-    fft_lds<T, N, false, NC * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
+    if constexpr (DIRECT) {
+        z0.finish(buf, tid);
+        fft_stages<T, N, 1, num_stages(N), false, NC * W, W, NT, N, SeqBlocked<W, NW>, kPairNone>(buf, tw, tid);
+    } else {
+        __syncthreads();
+        fft_lds<T, N, false, NC * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
+    }
     const double s2 = 0.70710678118654752440, s3 = 0.57735026918962576451, s6 = 0.40824829046386301637;
     const T A0 = (T)prm->el_inv_mu0M, B0c = (T)prm->el_betaM;
     for (int idx = tid; idx < NW; idx += NT) {
@@ -152,10 +166,15 @@ __global__ __launch_bounds__(NT) void k_zgreen_el(Cx<T> *__restrict__ spec, Cx<T
         for (int c = 0; c < NC; ++c) buf[c * NW + idx] = o[c];
     }
     __syncthreads();
-    fft_lds<T, N, true, NC * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
-    for (int idx = tid; idx < NP; idx += NT) {
-        const int e0 = 2 * idx, c = e0 / NW, r = e0 - c * NW, zz = r / W, w = r - zz * W;
-        gstore2<T>(base + c * cstride + zz * zstride + w, buf[e0], buf[e0 + 1]);
+    if constexpr (DIRECT) {
+        fft_stages<T, N, 0, num_stages(N) - 1, true, NC * W, W, NT, N, SeqBlocked<W, NW>, kPairNone>(buf, tw, tid);
+        z_last_stage_store<T, N, W, NT, NC>(buf, tw, base, cstride, zstride, tid);
+    } else {
+        fft_lds<T, N, true, NC * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
+        for (int idx = tid; idx < NP; idx += NT) {
+            const int e0 = 2 * idx, c = e0 / NW, r = e0 - c * NW, zz = r / W, w = r - zz * W;
+            gstore2<T>(base + c * cstride + zz * zstride + w, buf[e0], buf[e0 + 1]);
+        }
     }
 }
 

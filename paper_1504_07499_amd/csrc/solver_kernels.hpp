@@ -562,14 +562,15 @@ template <typename T, int N, int W> __device__ __forceinline__ int ztile_of(int 
     return t;
 }
 
-// First stage of the forward z transform of a tile, its inputs read straight
-// from the pencils in global memory: butterfly b = j 3W + q takes elements
-// kz = j + r N/R of pencil q (component q / W, column q % W), neighbouring
-// threads neighbouring pencils.  finish() runs the radix-R DFTs (stage 0 has
-// no twiddles) and writes the outputs to LDS (pencil q at (q / W) N W + q % W,
-// element stride W) in the self-sorting order of stage 0.
-template <typename T, int N, int W, int NT> struct ZFirstStage {
-    static constexpr int NSEQ = 3 * W, NW = N * W, R = radix_of(N, 0), NB = N / R, TOT = NSEQ * NB,
+// First stage of the forward z transform of a tile of NCOMP components, its
+// inputs read straight from the pencils in global memory: butterfly
+// b = j NCOMP W + q takes elements kz = j + r N/R of pencil q (component
+// q / W, column q % W), neighbouring threads neighbouring pencils.  finish()
+// runs the radix-R DFTs (stage 0 has no twiddles) and writes the outputs to
+// LDS (pencil q at (q / W) N W + q % W, element stride W) in the
+// self-sorting order of stage 0.
+template <typename T, int N, int W, int NT, int NCOMP = 3> struct ZFirstStage {
+    static constexpr int NSEQ = NCOMP * W, NW = N * W, R = radix_of(N, 0), NB = N / R, TOT = NSEQ * NB,
                          PER = (TOT + NT - 1) / NT;
     Cx<T> v[PER][R];
     __device__ __forceinline__ void load(const Cx<T> *base, size_t cstride, size_t zstride, int tid) {
@@ -600,10 +601,10 @@ template <typename T, int N, int W, int NT> struct ZFirstStage {
 
 // Last stage of the inverse z transform of a tile, its outputs stored straight
 // to the pencils in global memory (the layout of ZFirstStage).
-template <typename T, int N, int W, int NT>
+template <typename T, int N, int W, int NT, int NCOMP = 3>
 __device__ __forceinline__ void z_last_stage_store(const Cx<T> *buf, const Cx<T> *__restrict__ tw, Cx<T> *base,
                                                    size_t cstride, size_t zstride, int tid) {
-    constexpr int NSEQ = 3 * W, NW = N * W, SL = num_stages(N) - 1, R = radix_of(N, SL), NS = ns_before(N, SL),
+    constexpr int NSEQ = NCOMP * W, NW = N * W, SL = num_stages(N) - 1, R = radix_of(N, SL), NS = ns_before(N, SL),
                   NB = N / R, TOT = NSEQ * NB, PER = (TOT + NT - 1) / NT, TWS = N / (NS * R);
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
