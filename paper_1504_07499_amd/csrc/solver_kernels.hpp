@@ -562,25 +562,27 @@ template <typename T, int N, int W> __device__ __forceinline__ int ztile_of(int 
     return t;
 }
 
-// First stage of the forward z transform of a tile of NCOMP components, its
-// inputs read straight from the pencils in global memory: butterfly
-// b = j NCOMP W + q takes elements kz = j + r N/R of pencil q (component
-// q / W, column q % W), neighbouring threads neighbouring pencils.  finish()
-// runs the radix-R DFTs (stage 0 has no twiddles) and writes the outputs to
-// LDS (pencil q at (q / W) N W + q % W, element stride W) in the
-// self-sorting order of stage 0.
-template <typename T, int N, int W, int NT, int NCOMP = 3> struct ZFirstStage {
+// First stage of a length-N transform (forward, or inverse with INV) of a
+// tile of NCOMP x W pencils, its inputs read straight from global memory:
+// butterfly b = j NCOMP W + q takes elements j + r N/R of pencil q
+// (component q / W at cstride, column q % W at wstride, elements at
+// estride), neighbouring threads neighbouring pencils.  finish() runs the
+// radix-R DFTs (stage 0 has no twiddles) and writes the outputs to LDS
+// (pencil q at (q / W) N W + q % W, element stride W) in the self-sorting
+// order of stage 0.
+template <typename T, int N, int W, int NT, int NCOMP = 3, bool INV = false> struct ZFirstStage {
     static constexpr int NSEQ = NCOMP * W, NW = N * W, R = radix_of(N, 0), NB = N / R, TOT = NSEQ * NB,
                          PER = (TOT + NT - 1) / NT;
     Cx<T> v[PER][R];
-    __device__ __forceinline__ void load(const Cx<T> *base, size_t cstride, size_t zstride, int tid) {
+    __device__ __forceinline__ void load(const Cx<T> *base, size_t cstride, size_t estride, int tid,
+                                         size_t wstride = 1) {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int b = tid + i * NT;
             if (TOT % NT == 0 || b < TOT) {
                 const int j = b / NSEQ, q = b - j * NSEQ, c = q / W, w = q - c * W;
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[i][r] = base[c * cstride + (j + r * NB) * zstride + w];
+                for (int r = 0; r < R; ++r) v[i][r] = base[c * cstride + (j + r * NB) * estride + w * wstride];
             }
         }
     }
@@ -590,7 +592,7 @@ template <typename T, int N, int W, int NT, int NCOMP = 3> struct ZFirstStage {
             const int b = tid + i * NT;
             if (TOT % NT == 0 || b < TOT) {
                 const int j = b / NSEQ, q = b - j * NSEQ, c = q / W, w = q - c * W;
-                dft<T, R, false>(v[i]);
+                dft<T, R, INV>(v[i]);
 #pragma unroll
                 for (int r = 0; r < R; ++r) buf[c * NW + w + (j * R + r) * W] = v[i][r];
             }
@@ -599,11 +601,12 @@ template <typename T, int N, int W, int NT, int NCOMP = 3> struct ZFirstStage {
     }
 };
 
-// Last stage of the inverse z transform of a tile, its outputs stored straight
-// to the pencils in global memory (the layout of ZFirstStage).
-template <typename T, int N, int W, int NT, int NCOMP = 3>
+// Last stage of a length-N transform (inverse, or forward without INV) of a
+// tile of pencils, its outputs stored straight to global memory (the layouts
+// of ZFirstStage).
+template <typename T, int N, int W, int NT, int NCOMP = 3, bool INV = true>
 __device__ __forceinline__ void z_last_stage_store(const Cx<T> *buf, const Cx<T> *__restrict__ tw, Cx<T> *base,
-                                                   size_t cstride, size_t zstride, int tid) {
+                                                   size_t cstride, size_t estride, int tid, size_t wstride = 1) {
     constexpr int NSEQ = NCOMP * W, NW = N * W, SL = num_stages(N) - 1, R = radix_of(N, SL), NS = ns_before(N, SL),
                   NB = N / R, TOT = NSEQ * NB, PER = (TOT + NT - 1) / NT, TWS = N / (NS * R);
 #pragma unroll
@@ -617,11 +620,11 @@ __device__ __forceinline__ void z_last_stage_store(const Cx<T> *buf, const Cx<T>
             const int k = j % NS, d = (j - k) * R + k;
             if constexpr (NS > 1) {
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[r] = twmul<T, true>(v[r], tw[r * k * TWS]);
+                for (int r = 1; r < R; ++r) v[r] = twmul<T, INV>(v[r], tw[r * k * TWS]);
             }
-            dft<T, R, true>(v);
+            dft<T, R, INV>(v);
 #pragma unroll
-            for (int r = 0; r < R; ++r) base[c * cstride + (d + r * NS) * zstride + w] = v[r];
+            for (int r = 0; r < R; ++r) base[c * cstride + (d + r * NS) * estride + w * wstride] = v[r];
         }
     }
 }
@@ -1181,35 +1184,18 @@ __global__ __launch_bounds__(NT) void k_cols(Cx<T> *__restrict__ spec, Cx<T> *__
     }
     const int lc = ch / 3;
     if (GATE_EQ ? !st->eq_pending[lc] : st->done[lc]) return;
-    if (ss == 1) {
-        for (int idx = tid; idx < NW; idx += NT) {
-            const int ky = idx / W, w = idx - ky * W;
-            buf[idx] = base[(size_t)ky * es + w];
-        }
-    } else {
-        for (int idx = tid; idx < NW; idx += NT) {
-            const int w = idx / N, ky = idx - w * N;
-            buf[ky * W + w] = base[(size_t)w * ss + ky];
-        }
-    }
+    // the columns straight to the registers of the first stage, and the last
+    // stage straight back
+    constexpr int PM = (W % 2 == 0 && sizeof(T) == 4) ? kPairSeq : kPairNone;
+    ZFirstStage<T, N, W, NT, 1, INV> c0;
+    c0.load(base, 0, es, tid, ss);
     // twiddle table (length N) in LDS: short-latency loads inside the stages
     __shared__ Cx<T> tws[N];
     table_to_lds<T, N, NT>(tws, twg, tid);
     const Cx<T> *tw = tws;
-    __syncthreads();
-    fft_lds<T, N, INV, W, W, NT, N, SeqStride<1>, (W % 2 == 0 && sizeof(T) == 4) ? kPairSeq : kPairNone>(buf, tw,
-                                                                                                           tid);
-    if (ss == 1) {
-        for (int idx = tid; idx < NW; idx += NT) {
-            const int ky = idx / W, w = idx - ky * W;
-            base[(size_t)ky * es + w] = buf[idx];
-        }
-    } else {
-        for (int idx = tid; idx < NW; idx += NT) {
-            const int w = idx / N, ky = idx - w * N;
-            base[(size_t)w * ss + ky] = buf[ky * W + w];
-        }
-    }
+    c0.finish(buf, tid);
+    fft_stages<T, N, 1, num_stages(N) - 1, INV, W, W, NT, N, SeqStride<1>, PM>(buf, tw, tid);
+    z_last_stage_store<T, N, W, NT, 1, INV>(buf, tw, base, 0, es, tid, ss);
 }
 
 template <typename T, int N, int G, int NT, bool AL = false>
