@@ -74,9 +74,10 @@ __global__ __launch_bounds__(NT) void k_zgreen_el(Cx<T> *__restrict__ spec, Cx<T
         zstride = N;
     }
     // the six components' pencils straight to the registers of the first z
-    // stage, and the last inverse stage straight back (measured faster except
-    // for FP64 from 128^3 on, whose 4-column tiles keep the staged form)
-    constexpr bool DIRECT = !(sizeof(T) == 8 && N >= 128);
+    // stage, and the last inverse stage straight back (measured faster below
+    // 256^3 in FP32 and below 128^3 in FP64; the 4-column tiles of the larger
+    // grids keep the staged form)
+    constexpr bool DIRECT = !(N >= 256 || (sizeof(T) == 8 && N >= 128));
     constexpr int NP = NC * NW / 2;
     ZFirstStage<T, N, W, NT, NC> z0;
     if constexpr (DIRECT) {

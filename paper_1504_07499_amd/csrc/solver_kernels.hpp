@@ -637,6 +637,10 @@ __device__ __forceinline__ void z_last_stage_store(const Cx<T> *buf, const Cx<T>
 // Waves per SIMD asked of the z pass: six for FP32 128^3 (8-column tiles,
 // six workgroups per CU fit in LDS; measured faster despite a few spills),
 // otherwise no bound.
+// z pass with its first and last stages on the pencils in global memory:
+// measured faster at every grid but FP32 256^3 and 512^3 (1-2 %).
+template <typename T, int N> constexpr bool zpass_direct() { return !(sizeof(T) == 4 && N >= 256); }
+
 template <typename T, int N, int W> constexpr int zpass_min_waves() {
     return (sizeof(T) == 4 && N == 128 && W == 8) ? 6 : 1;
 }
@@ -683,15 +687,45 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
         zstride = N;
     }
     // the three components' pencils straight to the registers of the first
-    // z stage
+    // z stage, and the last inverse stage straight back (except FP32 from
+    // 256^3 on, measured faster with the pencils staged through LDS)
+    constexpr bool DIRECT = zpass_direct<T, N>();
+    constexpr int NP = 3 * NW / 2, PERP = (NP + NT - 1) / NT;
     ZFirstStage<T, N, W, NT> z0;
-    z0.load(base, cstride, zstride, tid);
+    if constexpr (DIRECT) {
+        z0.load(base, cstride, zstride, tid);
+    } else {
+        // two complex values per access, every load of a thread in flight
+        // before the first LDS store
+        Cx<T> va[PERP], vb[PERP];
+#pragma unroll
+        for (int i = 0; i < PERP; ++i) {
+            const int idx = tid + i * NT;
+            if (NP % NT == 0 || idx < NP) {
+                const int e0 = 2 * idx, c = e0 / NW, r = e0 - c * NW, zz = r / W, w = r - zz * W;
+                gload2<T>(base + c * cstride + zz * zstride + w, va[i], vb[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PERP; ++i) {
+            const int idx = tid + i * NT;
+            if (NP % NT == 0 || idx < NP) {
+                buf[2 * idx] = va[i];
+                buf[2 * idx + 1] = vb[i];
+            }
+        }
+    }
     // twiddle table (length N) in LDS: short-latency loads inside the stages
     __shared__ Cx<T> tws[N];
     table_to_lds<T, N, NT>(tws, twg, tid);
     const Cx<T> *tw = tws;
-    z0.finish(buf, tid);
-    fft_stages<T, N, 1, num_stages(N), false, 3 * W, W, NT, N, SeqBlocked<W, NW>, kPairNone>(buf, tw, tid);
+    if constexpr (DIRECT) {
+        z0.finish(buf, tid);
+        fft_stages<T, N, 1, num_stages(N), false, 3 * W, W, NT, N, SeqBlocked<W, NW>, kPairNone>(buf, tw, tid);
+    } else {
+        __syncthreads();
+        fft_lds<T, N, false, 3 * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
+    }
     const T sc = (T)prm->inv_k0M;
     for (int idx = tid; idx < NW; idx += NT) {
         const int kz = idx / W, w = idx - kz * W;
@@ -725,8 +759,16 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
         buf[2 * NW + idx] = out[2];
     }
     __syncthreads();
-    fft_stages<T, N, 0, num_stages(N) - 1, true, 3 * W, W, NT, N, SeqBlocked<W, NW>, kPairNone>(buf, tw, tid);
-    z_last_stage_store<T, N, W, NT>(buf, tw, base, cstride, zstride, tid);
+    if constexpr (DIRECT) {
+        fft_stages<T, N, 0, num_stages(N) - 1, true, 3 * W, W, NT, N, SeqBlocked<W, NW>, kPairNone>(buf, tw, tid);
+        z_last_stage_store<T, N, W, NT>(buf, tw, base, cstride, zstride, tid);
+    } else {
+        fft_lds<T, N, true, 3 * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
+        for (int idx = tid; idx < NP; idx += NT) {
+            const int e0 = 2 * idx, c = e0 / NW, r = e0 - c * NW, zz = r / W, w = r - zz * W;
+            gstore2<T>(base + c * cstride + zz * zstride + w, buf[e0], buf[e0 + 1]);
+        }
+    }
 }
 
 // FP64 block sums of NV values; results valid in thread 0.  red holds
