@@ -178,18 +178,23 @@ def test_five_pass_256_fp64_vs_oracle():
     assert tensor_err(g.K[:, 0], ref.K[:, 0]) <= 1e-11
 
 
+@pytest.mark.parametrize("axis", [0, 1, 2])
 @pytest.mark.parametrize("n,precision", [(512, 0), (256, 1), (512, 1)])
-def test_large_grid_laminate_exact(n, precision):
+def test_large_grid_laminate_exact(n, precision, axis):
     """Closed form at sizes the oracle cannot run in a test: a laminate
-    normal to y with odd layer widths gives K = diag(<k>, 1/<1/k>, <k>)."""
-    print(f"\n[case] laminate n={n} precision={precision}", flush=True)
+    normal to direction `axis` (x, y or z, so that each of the x, y and z
+    transforms carries the variation) with odd layer widths gives <k> on the
+    diagonal and 1/<1/k> in the normal direction."""
+    print(f"\n[case] laminate n={n} precision={precision} axis={axis}", flush=True)
     k = np.array([1.0, 0.2, 4.0])
     widths = [n // 2 - 1, 3, n // 2 - 2]
     prof = np.concatenate([np.full(w, p, np.uint8) for w, p in zip(widths, [0, 2, 1])])
-    ph = np.ascontiguousarray(np.broadcast_to(prof.reshape(1, n, 1), (n, n, n)))
+    shape = [1, 1, 1]
+    shape[2 - axis] = n  # the phase image is [z][y][x]
+    ph = np.ascontiguousarray(np.broadcast_to(prof.reshape(shape), (n, n, n)))
     kv = k[prof]
     Kex = np.eye(3) * kv.mean()
-    Kex[1, 1] = 1.0 / (1.0 / kv).mean()
+    Kex[axis, axis] = 1.0 / (1.0 / kv).mean()
     with rh.rve_create_from_phases(ph) as r:
         g = rh.homogenize(r, k, 1e-10 if precision else 1e-6, precision=precision)
     assert tensor_err(g.K, Kex) <= (1e-9 if precision else 2e-5)
