@@ -771,14 +771,36 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
     }
 }
 
+// One DPP step on an FP64 value (both 32-bit halves): lanes the pattern
+// does not feed, or whose row is masked off, receive 0.
+template <int CTRL, int ROWS> __device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Fixed-order sum over a wave of 64 lanes in registers (no LDS traffic):
+// row shifts by 1, 2, 4 and 8 leave each 16-lane row's prefix sums, the
+// broadcasts of lanes 15 and 31 carry them across rows.  The total is in
+// lane 63.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    v += dpp_f64<0x111, 0xf>(v);  // row_shr:1
+    v += dpp_f64<0x112, 0xf>(v);  // row_shr:2
+    v += dpp_f64<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_f64<0x118, 0xf>(v);  // row_shr:8
+    v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 // FP64 block sums of NV values; results valid in thread 0.  red holds
 // NV * (NT / 64) doubles.
 template <int NT, int NV> __device__ __forceinline__ void block_sum(double *v, double *red) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q)
-        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_down(v[q], o, 64);
+    for (int q = 0; q < NV; ++q) v[q] = wave_sum_f64(v[q]);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0)
+    if (lane == 63)
         for (int q = 0; q < NV; ++q) red[NV * wv + q] = v[q];
     __syncthreads();
     if (threadIdx.x == 0) {
