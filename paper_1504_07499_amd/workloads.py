@@ -219,6 +219,24 @@ def run_512(n_spheres=100, f=0.30, layer=0.2, seed=7, k=K_BENCH, tol=1e-6):
     return out
 
 
+# ---------------------------------------------------------------------- solve
+def run_solve(n=256, n_spheres=100, f=0.40, layer=0.2, seed=3, k=K_BENCH, tol=1e-6, precision=0, repeat=2):
+    """Repeated solves of one seeded RVE (RSA spheres, Sec. 2): iterations,
+    time and tensor of each, e.g. to profile one grid size."""
+    rows = []
+    with rve_create(n, n_spheres, f, layer, seed) as h:
+        for _ in range(repeat):
+            r = homogenize(h, k, tol, precision=precision)
+            row = {"n": n, "n_spheres": n_spheres, "f": f, "layer": layer, "seed": seed,
+                   "precision": "fp32" if precision == 0 else "fp64", "iters": r.iters.tolist(),
+                   "status": r.lc_status.tolist(), "ms": r.solve_ms,
+                   "voxel_iters_per_s_per_lc": n ** 3 * int(r.iters.sum()) / (r.solve_ms * 1e-3),
+                   "K": r.K.tolist()}
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+    return rows
+
+
 # -------------------------------------------------------------------- schemes
 def run_schemes(coatings=(1.0, 4.0, 20.0, 80.0, 400.0), n=128, n_spheres=50, f=0.30, layer=0.2, seed=2,
                 tol=1e-6, precision=1, max_iter=20000):
@@ -323,6 +341,14 @@ def main(argv=None):
     s.add_argument("--baseline", type=int, default=0, help="also run the sequential FP64 path")
     sub.add_parser("sweep256")
     sub.add_parser("run512")
+    so = sub.add_parser("solve")
+    so.add_argument("--n", type=int, default=256)
+    so.add_argument("--spheres", type=int, default=100)
+    so.add_argument("--f", type=float, default=0.40)
+    so.add_argument("--layer", type=float, default=0.2)
+    so.add_argument("--seed", type=int, default=3)
+    so.add_argument("--precision", type=int, default=0)
+    so.add_argument("--repeat", type=int, default=2)
     sub.add_parser("fibers")
     sub.add_parser("elastic")
     sc = sub.add_parser("schemes")
@@ -343,6 +369,8 @@ def main(argv=None):
             print(json.dumps(seq), flush=True)
     elif a.cmd == "run512":
         run_512()
+    elif a.cmd == "solve":
+        run_solve(a.n, a.spheres, a.f, a.layer, a.seed, precision=a.precision, repeat=a.repeat)
     elif a.cmd == "fibers":
         run_fibers()
     elif a.cmd == "elastic":
