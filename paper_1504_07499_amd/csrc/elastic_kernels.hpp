@@ -29,6 +29,9 @@ template <typename T, int N> constexpr int ztile_el_cap(size_t cap) {
     return 0;
 }
 template <typename T, int N> constexpr int ztile_el() {
+    // FP32 256^3: 8-column tiles (96 KiB, 64-byte rows) in one 1024-thread
+    // workgroup per CU; measured 7 % faster per solve than 4-column tiles
+    if constexpr (sizeof(T) == 4 && N == 256) return 8;
     return ztile_el_cap<T, N>(64 * 1024) >= 4 ? ztile_el_cap<T, N>(64 * 1024) : ztile_el_cap<T, N>(96 * 1024);
 }
 
@@ -191,8 +194,9 @@ template <typename T, int N> struct ElasticInstance {
     static constexpr int NTP = plane_threads<T, N>();
     // FP32: 512-thread z tiles (the six-component tile needs ~128 VGPRs, so
     // the waves per CU are set by registers, not by LDS; measured 7 % faster
-    // than 256 threads at 128^3); FP64: 256 (measured faster)
-    static constexpr int NTZ = sizeof(T) == 4 ? 512 : 256;
+    // than 256 threads at 128^3), 1024 for the one 96 KiB tile per CU at
+    // 256^3; FP64: 256 (measured faster)
+    static constexpr int NTZ = sizeof(T) == 4 ? (N == 256 ? 1024 : 512) : 256;
     static constexpr int NPER = N * S;
     static constexpr bool FUSED = S == 1 && !(sizeof(T) == 4 && N == 96);
     static constexpr int PGRID = CH * N * S;

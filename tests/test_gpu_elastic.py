@@ -88,25 +88,31 @@ def test_elastic_equal_shear_hill_64(precision):
     assert abs(g.C_basis[0, 0] / 3.0 - khill) <= (1e-9 if precision else 1e-5) * khill
 
 
-@pytest.mark.parametrize("precision", [1, 0])
-def test_elastic_laminate_backus_48(precision):
-    """Layers normal to x on a 48^3 grid: the Backus stiffness (closed form)."""
-    print(f"\n[case] elastic laminate precision={precision}", flush=True)
-    prof = np.array([0] * 17 + [1] * 9 + [2] * 22, np.uint8)
-    ph = np.broadcast_to(prof.reshape(1, 1, 48), (48, 48, 48)).copy()
+@pytest.mark.parametrize("n,precision,axis", [(48, 1, 0), (48, 0, 0), (256, 0, 0), (256, 0, 2)])
+def test_elastic_laminate_backus(n, precision, axis):
+    """Layers normal to x (or z) on an n^3 grid: the Backus stiffness (closed
+    form); 256^3 runs the split-plane passes and the one-per-CU z tiles."""
+    print(f"\n[case] elastic laminate n={n} precision={precision} axis={axis}", flush=True)
+    w0, w1 = round(n * 17 / 48) | 1, round(n * 9 / 48) | 1
+    prof = np.array([0] * w0 + [1] * w1 + [2] * (n - w0 - w1), np.uint8)
+    shape = [1, 1, 1]
+    shape[2 - axis] = n  # the phase image is [z][y][x]
+    ph = np.broadcast_to(prof.reshape(shape), (n, n, n)).copy()
     kap, mu = MOD[prof, 0], MOD[prof, 1]
     lam = kap - 2 * mu / 3
     a = lam + 2 * mu
     h = np.mean
+    b, c = [d for d in range(3) if d != axis]
     C = np.zeros((6, 6))
     C11 = 1.0 / h(1 / a)
     C12 = h(lam / a) * C11
-    C[0, 0] = C11
-    C[0, 1] = C[1, 0] = C[0, 2] = C[2, 0] = C12
-    C[1, 1] = C[2, 2] = h(a - lam ** 2 / a) + h(lam / a) ** 2 * C11
-    C[1, 2] = C[2, 1] = h(lam - lam ** 2 / a) + h(lam / a) ** 2 * C11
-    C[3, 3] = h(mu)
-    C[4, 4] = C[5, 5] = 1.0 / h(1 / mu)
+    C[axis, axis] = C11
+    C[axis, b] = C[b, axis] = C[axis, c] = C[c, axis] = C12
+    C[b, b] = C[c, c] = h(a - lam ** 2 / a) + h(lam / a) ** 2 * C11
+    C[b, c] = C[c, b] = h(lam - lam ** 2 / a) + h(lam / a) ** 2 * C11
+    # Voigt shear index of the plane of two axes: 3 + the third axis
+    C[3 + axis, 3 + axis] = h(mu)
+    C[3 + b, 3 + b] = C[3 + c, 3 + c] = 1.0 / h(1 / mu)
     with rh.rve_create_from_phases(ph) as r:
         g = rh.homogenize_elastic(r, MOD, 1e-10 if precision else 1e-6, precision=precision, max_iter=20000)
     assert tensor_err(g.C, C) <= (1e-9 if precision else 1e-4)
