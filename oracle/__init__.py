@@ -59,6 +59,8 @@ def _load():
         ctypes.c_int, ctypes.POINTER(ctypes.c_uint8), dp, ctypes.c_int, dp, ctypes.c_double,
         ctypes.c_int, dp, ip, ip, dp, dp, ctypes.c_int, dp]
     lib.orc_homogenize_elastic.restype = ctypes.c_int
+    lib.orc_equilibrium_error.argtypes = [ctypes.c_int, dp, dp]
+    lib.orc_equilibrium_error.restype = ctypes.c_double
     lib.orc_threads.argtypes = []
     lib.orc_threads.restype = ctypes.c_int
     lib.orc_set_threads.argtypes = [ctypes.c_int]
@@ -101,6 +103,18 @@ def green_apply(tau_hat: np.ndarray, k0: float, E) -> np.ndarray:
     lib.orc_green_apply(n, float(k0), _dp(Ev), _dp(t.view(np.float64)),
                         _dp(out.view(np.float64)))
     return out
+
+
+def equilibrium_error(kvox: np.ndarray, field: np.ndarray) -> float:
+    """eps_eq of step 1 (the scale-free reading) for one load case: kvox the
+    (n, n, n) voxel conductivities, field the (3, n, n, n) gradient field."""
+    lib = _load()
+    k = np.ascontiguousarray(kvox, dtype=np.float64)
+    n = k.shape[0]
+    assert k.shape == (n, n, n)
+    f = np.ascontiguousarray(field, dtype=np.float64)
+    assert f.shape == (3, n, n, n)
+    return float(lib.orc_equilibrium_error(n, _dp(k), _dp(f)))
 
 
 @dataclass

@@ -279,6 +279,19 @@ static double equilibrium_error(int n, const double *kvox, const double *e3,
     return sqrt(num) / sqrt(den);
 }
 
+/* eps_eq of R4 for one load case: kvox the M voxel conductivities, e3 the
+ * field [comp][z][y][x] (3 M).  Exported so that the tests can pin it on
+ * fields whose flux spectrum is known in closed form. */
+double orc_equilibrium_error(int n, const double *kvox, const double *e3)
+{
+    size_t M = (size_t)n * n * n;
+    cplx *work3 = malloc(sizeof(cplx) * 3 * M);
+    if (!work3) return -1.0;
+    double r = equilibrium_error(n, kvox, e3, work3);
+    free(work3);
+    return r;
+}
+
 int orc_threads(void)
 {
 #ifdef _OPENMP

@@ -25,6 +25,11 @@ CASES = {
     "rve32_8sph_f0.20_l0.10_seed1": (32, 8, 0.2, 0.1, 1, K_CFG, 1e-6, 10000, 7),
     # 128^3, 50 spheres, f = 0.3, l = 0.2, seed 2, tol 1e-6 (full solve)
     "rve128_50sph_f0.30_l0.20_seed2": (128, 50, 0.3, 0.2, 2, K_CFG, 1e-6, 10000, 7),
+    # 256^3, 100 spheres, f = 0.4 (RSA, then the Monte Carlo fallback), seed 3,
+    # the same centres for every layer; k_coating = 0.2 c for contrast c
+    "rve256_100sph_f0.40_l0.10_c1e3_seed3": (256, 100, 0.4, 0.1, 3, [0.2, 0.3, 200.0], 1e-6, 10000, 7),
+    "rve256_100sph_f0.40_l0.20_c1e2_seed3": (256, 100, 0.4, 0.2, 3, [0.2, 0.3, 20.0], 1e-6, 10000, 7),
+    "rve256_100sph_f0.40_l0.05_c1e4_seed3": (256, 100, 0.4, 0.05, 3, [0.2, 0.3, 2000.0], 1e-6, 10000, 7),
 }
 
 

@@ -324,6 +324,133 @@ def test_convergence_rate_at_most_rho():
     assert rate <= rho * 1.02
 
 
+# ------------------------------------------- residual and equilibrium error
+# Closed forms of the first iteration on a laminate.  With the layers normal
+# to axis a and E = e_a, tau = (k - k0) e_a varies along a only, so the Green
+# operator of step 4 acts on the modes along a, where it is the projection on
+# e_a (also at the Nyquist mode: one Nyquist component and nothing else).
+# Hence c = E - (k - <k>) / k0 e_a, the step-6 residual of the first
+# iteration is eps_comp = std(k) / k0, the update of step 7 gives
+# e+ = (1 - 2 (k - <k>) / (k + k0)) e_a, and the flux phi = k e+ varies along
+# a only: its divergence spectrum is xi_a phi^_a, so by Parseval the
+# scale-free eps_eq = std(phi) / |<phi>| (population standard deviations).
+# With E along the layers instead, tau has no component along the variation,
+# c = E, eps_comp = 0 and phi = k E is divergence free: eps_eq = 0.
+LAMINATE_CASES = [
+    (8, [3, 5], [0, 2]),          # odd widths, even N: the Nyquist mode along a is excited
+    (9, [2, 4, 3], [0, 1, 2]),    # odd N, three phases
+    (10, [1, 6, 3], [2, 0, 1]),   # one-voxel coating layer
+]
+
+
+@pytest.mark.parametrize("n,widths,phases", LAMINATE_CASES)
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_first_iteration_residual_and_equilibrium_laminate(n, widths, phases, axis):
+    k = K_PAPER
+    ph = _laminate(n, axis, widths, phases)
+    kv = k[ph].ravel()
+    k0 = np.sqrt(k.min() * k.max())
+    r = oracle.homogenize(ph, k, tol=0.0, max_iter=1, want_field=True)
+    assert list(r.iters) == [1, 1, 1]
+    # normal load case
+    assert r.history[axis][0] == pytest.approx(kv.std() / k0, rel=1e-12)
+    phi = kv * (1.0 - 2.0 * (kv - kv.mean()) / (kv + k0))
+    assert r.eps_eq[axis] == pytest.approx(phi.std() / abs(phi.mean()), rel=1e-10)
+    np.testing.assert_allclose(r.field[axis, axis].ravel(), phi / kv, rtol=1e-12, atol=1e-13)
+    # load cases along the layers
+    for j in range(3):
+        if j != axis:
+            assert r.history[j][0] <= 1e-14
+            assert r.eps_eq[j] <= 1e-13
+
+
+def test_residual_normalised_by_load():
+    """eps_comp is relative to |E|: scaling the field by s scales nothing."""
+    n, axis = 8, 1
+    ph = _laminate(n, axis, [3, 5], [0, 2])
+    k = K_PAPER
+    kv = k[ph].ravel()
+    k0 = np.sqrt(k.min() * k.max())
+    for s in (0.5, 3.0):
+        init = np.zeros((3, 3, n, n, n))
+        for j in range(3):
+            init[j, j] = s
+        r = oracle.homogenize(ph, k, tol=0.0, max_iter=1, init_field=init)
+        # from e = s E the compatible field is E - s (k - <k>)/k0 e_a + (1 - s)... :
+        # c = E - Gamma((k - k0) s E), whose fluctuation is s times that from E
+        c_minus_e = np.sqrt(((1.0 - s) ** 2) + (s * kv.std() / k0) ** 2)
+        assert r.history[axis][0] == pytest.approx(c_minus_e, rel=1e-12)
+
+
+def _trig_field(n, m, d, a, mean, phase=0.0):
+    """Flux field mean + a cos(2 pi m.x / n + phase) d on an (n, n, n) grid."""
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    arg = 2 * np.pi * (m[0] * x + m[1] * y + m[2] * z) / n + phase
+    f = np.empty((3, n, n, n))
+    for i in range(3):
+        f[i] = mean[i] + a * d[i] * np.cos(arg)
+    return f
+
+
+@pytest.mark.parametrize("m,d,phase", [
+    ((1, 2, 0), (1.0, 0.0, 0.0), 0.0),
+    ((3, -2, 1), (0.3, -1.0, 2.0), 0.7),
+    ((0, 0, 1), (0.0, 0.0, 1.0), 1.1),
+    ((2, 1, -3), (1.0, 2.0, -1.0), 0.0),
+])
+def test_equilibrium_error_single_wave(m, d, phase):
+    """phi = <phi> + a cos(2 pi m.x/n + p) d has phi^ = M a d e^(+-ip) / 2 at
+    +-m, so sum |xi.phi^|^2/|xi|^2 = M^2 a^2 (m.d)^2 / (2 |m|^2) and
+    eps_eq = a |m.d| / (sqrt(2) |m| |<phi>|), whatever the sign convention
+    of the wavenumbers."""
+    n, a = 8, 0.37
+    mean = np.array([0.4, -1.2, 0.5])
+    kv = np.ones((n, n, n))
+    f = _trig_field(n, m, d, a, mean, phase)
+    m_ = np.array(m, float)
+    d_ = np.array(d, float)
+    ref = a * abs(m_ @ d_) / (np.sqrt(2.0) * np.linalg.norm(m_) * np.linalg.norm(mean))
+    assert oracle.equilibrium_error(kv, f) == pytest.approx(ref, rel=1e-12)
+    # the conductivity multiplies the field: phi = k e
+    assert oracle.equilibrium_error(2.5 * kv, f / 2.5) == pytest.approx(ref, rel=1e-12)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_equilibrium_error_nyquist_modes(axis):
+    """Even n.  A wave at the Nyquist index of one axis alone (a single real
+    mode, phi^ = M a d) counts fully: eps_eq = a |d_axis| / |<phi>|.  Modes
+    with a Nyquist component and any other nonzero component are outside
+    the sum (the sign-averaged operator is not the projection there), so a
+    wave on them gives 0."""
+    n, a = 8, 0.3
+    mean = np.array([1.0, 0.5, -0.25])
+    d = np.array([0.6, -0.8, 1.5])
+    kv = np.ones((n, n, n))
+    m = [0, 0, 0]
+    m[axis] = n // 2
+    f = _trig_field(n, m, d, a, mean)
+    ref = a * abs(d[axis]) / np.linalg.norm(mean)
+    assert oracle.equilibrium_error(kv, f) == pytest.approx(ref, rel=1e-12)
+    for other in ([1, 0, 0], [0, 2, 0], [0, 0, n // 2]):
+        m2 = [m[i] + other[i] for i in range(3)]
+        if m2[axis] != n // 2 or sum(1 for v in m2 if v % n) < 2:
+            continue
+        f2 = _trig_field(n, m2, d, a, mean)
+        assert oracle.equilibrium_error(kv, f2) <= 1e-13
+
+
+def test_equilibrium_error_vanishes_at_fixed_point():
+    """At the discrete fixed point the flux is divergence free on the modes of
+    the sum (even grid, random phases, all three phases present): eps_eq
+    falls with the residual, while after one iteration it is large."""
+    ph = geom.random_phases(8, 5)
+    one = oracle.homogenize(ph, K_PAPER, tol=0.0, max_iter=1)
+    assert np.all(one.eps_eq > 1e-2)
+    r = oracle.homogenize(ph, K_PAPER, tol=1e-13, max_iter=20000)
+    assert np.all(r.status == 0)
+    assert np.all(r.eps_eq < 1e-10)
+
+
 def test_equilibrium_two_stage_stop():
     """The option of step 1: stop only once eps_eq < tol as well."""
     ph, _, _ = geom.generate(16, 4, 0.2, 0.3, 4)
