@@ -88,6 +88,21 @@ typedef struct {
                                and lam = k d; final_residual is sqrt<|e+ - d+|^2>, K the
                                flux <k d+>, out_field the state lam - k0 d; with
                                equilibrium_check: RVE_ERR_ARG */
+    int fp32_refine;        /* FP32 only.  0 = default: a load case that the FP32 rounding
+                               floor stops above tol (RVE_STALLED by the floor or stall rule)
+                               is continued in FP64 from its FP32 field, with the same scheme
+                               and tol, until eps_comp < tol (step 6); iters then counts both
+                               parts and refine_iters the FP64 ones.  The FP64 workspace of the
+                               grid is allocated on first use and cached on the handle.
+                               -1 = off: the load case ends RVE_STALLED with the last FP32 K. */
+    int path_flags;         /* measurement switches, 0 = the library's choice.  Results do not
+                               depend on them (the same arithmetic in the same order):
+                               1 = launch kernel by kernel instead of replaying iteration graphs,
+                               2 = separate inverse and forward plane passes instead of the
+                                   fused one, 4 = the reduction as a launch of its own instead
+                               of inside the next z pass, 8 = one stream for the three load
+                               cases instead of three concurrent chains, 16 / 32 = the default /
+                               the alternative z-pass tile width instead of the autotuned one */
 } rve_opts;
 
 typedef struct {
@@ -97,6 +112,7 @@ typedef struct {
     double final_residual[3];  /* last eps_comp per load case */
     double eps_eq[3];          /* equilibrium error of the final field (-1 if not computed) */
     double solve_ms;           /* device time of the iteration phase (HIP events) */
+    int refine_iters[3];       /* FP64 iterations of the fp32_refine continuation (0 if none) */
 } rve_result;
 
 /* Per-kernel device time of the last homogenize call with opts.timing != 0,
@@ -204,11 +220,36 @@ rve_status rve_supported_n_elastic(int precision, int *out, int cap, int *count)
 
 /* Serving: a request loop that keeps fields resident on the device,
  * admits requests by device-memory footprint and free slots, and advances
- * all admitted requests together one iteration at a time (continuous
- * batching).  precision as in rve_opts. */
+ * all admitted requests together (continuous batching: chunks of iterations
+ * of every resident request are enqueued round-robin on per-slot streams,
+ * and a request is admitted as soon as a slot and memory free up).
+ * precision as in rve_opts; FP32 requests get the FP64 continuation of
+ * rve_opts.fp32_refine.
+ * rve_server_create reserves hbm_budget_bytes of device memory (one
+ * allocation, freed by rve_server_destroy) and, per slot, a stream, events
+ * and a pinned staging buffer for the largest phase image that fits the
+ * budget.  A request occupies one block of that reservation, of
+ * phase image + workspace (+ for FP32 the FP64 workspace of its
+ * continuation) bytes, from admission to completion; nothing is allocated
+ * or freed per request.  Requests are admitted in submission order while a
+ * slot is free and their block fits.  RVE_ERR_ARG for max_slots outside
+ * 1..256 or a budget below the smallest grid's footprint; RVE_ERR_OOM if
+ * the reservation fails. */
 typedef struct rve_server_s *rve_server_t;
 rve_status rve_server_create(size_t hbm_budget_bytes, int max_slots, int precision,
                              rve_server_t *out);
+typedef struct {
+    size_t arena_bytes;       /* device memory reserved at creation */
+    size_t peak_bytes;        /* largest sum of the blocks of resident requests */
+    int resident_peak;        /* most requests resident at once */
+    uint64_t admitted;        /* requests brought onto the device */
+    uint64_t completed;       /* requests finished (including setup failures) */
+    uint64_t refined;         /* requests that ran the FP64 continuation */
+    uint64_t graph_hits;      /* solves that reused an instantiated iteration graph */
+    uint64_t graph_misses;    /* graphs captured and instantiated */
+} rve_server_stats;
+/* Counters of a server since its creation. */
+rve_status rve_server_get_stats(rve_server_t s, rve_server_stats *out);
 /* Queue one solve; the geometry is generated on a host worker.  ticket out. */
 rve_status rve_server_submit(rve_server_t s, const rve_geom *g, const double k_phases[3],
                              double tol, uint64_t *ticket);

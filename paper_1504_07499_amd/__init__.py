@@ -28,7 +28,7 @@ __all__ = [
     "RveError", "RVE", "HomResult", "rve_supported_n", "rve_create", "rve_create_from_phases",
     "rve_get_phases", "rve_get_spheres", "rve_workspace_size", "homogenize", "homogenize_batch",
     "rve_get_kernel_times", "rve_server_create", "rve_server_submit", "rve_server_poll",
-    "rve_server_drain", "rve_server_destroy", "rve_destroy", "rve_last_error", "library_path",
+    "rve_server_drain", "rve_server_get_stats", "rve_server_destroy", "rve_destroy", "rve_last_error", "library_path",
     "RVE_OK", "RVE_NOT_CONVERGED", "RVE_STALLED", "RVE_PENDING", "RVE_ERR_ARG", "RVE_ERR_JAMMED",
     "RVE_ERR_OOM", "RVE_ERR_DEVICE", "RVE_ERR_NONFINITE",
 ]
@@ -49,19 +49,28 @@ class _Opts(ctypes.Structure):
                 ("lc_mask", ctypes.c_int), ("timing", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("init_field", ctypes.POINTER(ctypes.c_double)),
                 ("out_field", ctypes.POINTER(ctypes.c_double)), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_size_t), ("scheme", ctypes.c_int)]
+                ("workspace_bytes", ctypes.c_size_t), ("scheme", ctypes.c_int),
+                ("fp32_refine", ctypes.c_int), ("path_flags", ctypes.c_int)]
 
 
 class _Result(ctypes.Structure):
     _fields_ = [("K", ctypes.c_double * 9), ("iters", ctypes.c_int * 3),
                 ("status", ctypes.c_int * 3), ("final_residual", ctypes.c_double * 3),
-                ("eps_eq", ctypes.c_double * 3), ("solve_ms", ctypes.c_double)]
+                ("eps_eq", ctypes.c_double * 3), ("solve_ms", ctypes.c_double),
+                ("refine_iters", ctypes.c_int * 3)]
 
 
 class _ElResult(ctypes.Structure):
     _fields_ = [("C", ctypes.c_double * 36), ("C_basis", ctypes.c_double * 36),
                 ("iters", ctypes.c_int * 6), ("status", ctypes.c_int * 6),
                 ("final_residual", ctypes.c_double * 6), ("solve_ms", ctypes.c_double)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t),
+                ("resident_peak", ctypes.c_int), ("admitted", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("refined", ctypes.c_uint64),
+                ("graph_hits", ctypes.c_uint64), ("graph_misses", ctypes.c_uint64)]
 
 
 class _KTimes(ctypes.Structure):
@@ -99,6 +108,7 @@ def _load_library():
         "rve_server_submit": (c_int, [c_vp, P(_Geom), P(c_double), c_double, P(ctypes.c_uint64)]),
         "rve_server_poll": (c_int, [c_vp, ctypes.c_uint64, P(_Result), P(c_double)]),
         "rve_server_drain": (c_int, [c_vp]),
+        "rve_server_get_stats": (c_int, [c_vp, P(_ServerStats)]),
         "rve_server_destroy": (None, [c_vp]),
         "rve_destroy": (None, [c_vp]),
         "rve_last_error": (ctypes.c_char_p, []),
@@ -248,6 +258,7 @@ class HomResult:
     solve_ms: float
     history: list = field(default_factory=list)
     field: np.ndarray | None = None
+    refine_iters: np.ndarray | None = None  # FP64 iterations past the FP32 floor
 
 
 def _to_result(rc: int, r: _Result, hist=None, hist_cap=0, fld=None) -> HomResult:
@@ -258,16 +269,22 @@ def _to_result(rc: int, r: _Result, hist=None, hist_cap=0, fld=None) -> HomResul
         history = [h[j, :min(int(iters[j]), hist_cap)].copy() for j in range(3)]
     return HomResult(rc, np.array(r.K[:]).reshape(3, 3), iters, np.array(r.status[:]),
                      np.array(r.final_residual[:]), np.array(r.eps_eq[:]), float(r.solve_ms),
-                     history, fld)
+                     history, fld, np.array(r.refine_iters[:], dtype=np.int64))
 
 
 SCHEMES = {"accelerated": 0, "basic": 1, "augmented_lagrangian": 2}
 
+# measurement switches of rve_opts.path_flags (results do not depend on them)
+PATH_NO_GRAPHS, PATH_NO_FUSED, PATH_NO_MERGE, PATH_NO_CHAINS = 1, 2, 4, 8
+PATH_ZTILE_DEFAULT, PATH_ZTILE_ALT = 16, 32
+
 
 def _opts(max_iter=0, precision=0, equilibrium_check=False, stall_window=-1, lc_mask=7,
           timing=False, stream=None, init_field=None, out_field=None, workspace=None,
-          scheme="accelerated"):
+          scheme="accelerated", fp32_refine=True, path_flags=0):
     o = _Opts()
+    o.fp32_refine = 0 if fp32_refine else -1
+    o.path_flags = int(path_flags)
     o.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
     o.max_iter = int(max_iter)
     o.precision = int(precision)
@@ -290,14 +307,16 @@ def homogenize(rve: RVE, k_phases, tol: float = 1e-6, *, max_iter: int = 0, prec
                equilibrium_check: bool = False, stall_window: int = -1, lc_mask: int = 7,
                timing=False, stream=None, init_field: np.ndarray | None = None,
                want_field: bool = False, workspace=None, hist_cap: int = 0,
-               scheme="accelerated") -> HomResult:
+               scheme="accelerated", fp32_refine: bool = True, path_flags: int = 0) -> HomResult:
     """The Algorithm of Sec. 3 for E = e_1, e_2, e_3 on the device.
 
     scheme: "accelerated" (Eyre-Milton, the paper's choice), "basic" (the
     basic scheme the paper names as an alternative: e+ = c, k0 = mean of the
     extreme conductivities) or "augmented_lagrangian" (also named there; k0
     of Sec. 5; the field returned is its state lam - k0 d; no equilibrium
-    check)."""
+    check).  fp32_refine (precision 0): continue load cases stopped by the
+    FP32 rounding floor in FP64 until eps_comp < tol.  path_flags: the
+    PATH_* measurement switches."""
     k = np.ascontiguousarray(k_phases, dtype=np.float64)
     if k.shape != (3,):
         raise RveError(RVE_ERR_ARG, "k_phases must hold 3 conductivities")
@@ -309,7 +328,7 @@ def homogenize(rve: RVE, k_phases, tol: float = 1e-6, *, max_iter: int = 0, prec
             raise RveError(RVE_ERR_ARG, "init_field must hold 9 n^3 values")
     fld = np.zeros((3, 3, n, n, n)) if want_field else None
     o = _opts(max_iter, precision, equilibrium_check, stall_window, lc_mask, timing, stream, init,
-              fld, workspace, scheme)
+              fld, workspace, scheme, fp32_refine, path_flags)
     res = _Result()
     hist = np.zeros(3 * hist_cap) if hist_cap > 0 else None
     rc = _check(_lib.homogenize(rve.handle, _dptr(k), float(tol), ctypes.byref(o), ctypes.byref(res),
@@ -396,13 +415,13 @@ def rve_supported_n_elastic(precision: int = 0) -> list:
 
 def homogenize_batch(rves, k_phases, tol, *, max_iter: int = 0, precision: int = 0,
                      stall_window: int = -1, equilibrium_check: bool = False,
-                     scheme="accelerated") -> list:
+                     scheme="accelerated", fp32_refine: bool = True) -> list:
     """Several RVEs (mixed N) solved concurrently; returns one HomResult each."""
     count = len(rves)
     k = np.ascontiguousarray(np.broadcast_to(np.asarray(k_phases, dtype=np.float64), (count, 3)))
     t = np.ascontiguousarray(np.broadcast_to(np.asarray(tol, dtype=np.float64), (count,)))
     hs = (ctypes.c_void_p * max(count, 1))(*[r.handle.value for r in rves])
-    o = _opts(max_iter, precision, equilibrium_check, stall_window, scheme=scheme)
+    o = _opts(max_iter, precision, equilibrium_check, stall_window, scheme=scheme, fp32_refine=fp32_refine)
     out = (_Result * max(count, 1))()
     rc = _check(_lib.homogenize_batch(count, hs, _dptr(k), _dptr(t), ctypes.byref(o), out))
     res = []
@@ -461,6 +480,12 @@ def rve_server_poll(server, ticket: int):
 
 def rve_server_drain(server) -> None:
     _check(_lib.rve_server_drain(server))
+
+
+def rve_server_get_stats(server) -> dict:
+    st = _ServerStats()
+    _check(_lib.rve_server_get_stats(server, ctypes.byref(st)))
+    return {name: int(getattr(st, name)) for name, _ in _ServerStats._fields_}
 
 
 def rve_server_destroy(server) -> None:

@@ -251,10 +251,9 @@ template <typename T, int N> struct ElasticInstance {
             (size_t)CH * N * N,
             {PGRID, NC * ZTiles<N, W>::PER_LC, PGRID},
             {NTP, NTZ, NTP},
-            {CH * (double)M * rb + CH * (double)M + spec_b, 2.0 * spec_b,
-             spec_b + 2.0 * CH * (double)M * rb + CH * (double)M},
+            {CH * (double)M * rb + spec_b, 2.0 * spec_b, spec_b + 2.0 * CH * (double)M * rb},
             0,
-            FUSED ? 2.0 * spec_b + 2.0 * CH * (double)M * rb + CH * (double)M : 0.0,
+            FUSED ? 2.0 * spec_b + 2.0 * CH * (double)M * rb : 0.0,
             FUSED ? &inv_fwd : nullptr,
             &fwd,
             nullptr,
@@ -271,6 +270,7 @@ template <typename T, int N> struct ElasticInstance {
             nullptr,
             NC,
             &reduce,
+            (double)M,
         };
         return &o;
     }

@@ -165,9 +165,11 @@ template <typename T, int N> struct Instance {
         constexpr double cb = (double)sizeof(Cx<T>);
         constexpr double rb = (double)sizeof(T);
         constexpr double spec_b = 9.0 * N * N * (H + 1) * cb;  // spec + nyq
-        // P1: read e + phases once per channel, write spectrum (five-pass:
-        // plus a read and write of the spectrum for y).  P2: read + write
-        // spectrum.  P3: read spectrum, e, phases; write e (five-pass: plus y).
+        // Field bytes (all three load cases; the phase image, read by P1, P3
+        // and the fused pass, is counted once per launch in phase_bytes):
+        // P1: read e, write spectrum (five-pass: plus a read and write of the
+        // spectrum for y).  P2: read + write spectrum.  P3: read spectrum and
+        // e, write e (five-pass: plus y).
         constexpr double extra = FIVE ? 2.0 * spec_b : 0.0;
         static const SolverOps o = {
             N,
@@ -180,10 +182,9 @@ template <typename T, int N> struct Instance {
             (size_t)9 * N * N,
             {FIVE ? 9 * N * (N / G) : 9 * N * S, 3 * ZTiles<N, W>::PER_LC, FIVE ? 9 * N * (N / G) : 9 * N * S},
             {FIVE ? NTR : NTP, NTZ, FIVE ? NTR : NTP},
-            {9.0 * M * rb + 9.0 * M + spec_b + extra, 2.0 * spec_b,
-             spec_b + 2.0 * 9.0 * M * rb + 9.0 * M + extra},
+            {9.0 * M * rb + spec_b + extra, 2.0 * spec_b, spec_b + 2.0 * 9.0 * M * rb + extra},
             ZTiles<N, W>::PER_LC,
-            FUSED ? 2.0 * spec_b + 2.0 * 9.0 * M * rb + 9.0 * M : 0.0,
+            FUSED ? 2.0 * spec_b + 2.0 * 9.0 * M * rb : 0.0,
             FUSED ? &inv_fwd : nullptr,
             &fwd,
             &fwd_phi,
@@ -200,6 +201,7 @@ template <typename T, int N> struct Instance {
             &to_tau,
             3,
             &launch_reduce,
+            (double)M,
         };
         return &o;
     }

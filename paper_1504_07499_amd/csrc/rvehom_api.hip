@@ -89,6 +89,36 @@ WsLayout ws_layout(const SolverOps *o) {
         }                                                                                 \
     } while (0)
 
+GraphCache::Entry *GraphCache::find(const GraphKey &k) {
+    for (auto &e : entries)
+        if (e.key == k) {
+            e.used = ++tick;
+            return &e;
+        }
+    return nullptr;
+}
+
+GraphCache::Entry *GraphCache::put(const GraphKey &k, hipGraphExec_t x) {
+    if (entries.size() >= cap) {
+        // evict the least recently used entry that no solver holds (if every
+        // entry is held the cache grows past cap)
+        auto victim = entries.end();
+        for (auto it = entries.begin(); it != entries.end(); ++it)
+            if (it->refs == 0 && (victim == entries.end() || it->used < victim->used)) victim = it;
+        if (victim != entries.end()) {
+            (void)hipGraphExecDestroy(victim->exec);
+            entries.erase(victim);
+        }
+    }
+    entries.push_back({k, x, 0, ++tick});
+    return &entries.back();
+}
+
+void GraphCache::clear() {
+    for (auto &e : entries) (void)hipGraphExecDestroy(e.exec);
+    entries.clear();
+}
+
 Solver::~Solver() { release(); }
 
 void Solver::release() {
@@ -114,9 +144,9 @@ void Solver::release() {
 }
 
 void Solver::drop_graphs() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    gexec = nullptr;
-    g_ws = nullptr;
+    if (gcur) gcur->refs--;
+    gcur = nullptr;
+    if (graphs == &own_graphs) own_graphs.clear();
     for (auto &g : tgexec) {
         if (g) (void)hipGraphExecDestroy(g);
         g = nullptr;
@@ -124,10 +154,42 @@ void Solver::drop_graphs() {
     tg_mask = 0;
 }
 
-// Allocate (or adopt) the workspace and the per-solver HIP objects.
+// The HIP objects of a solver: its stream, poll and timing events and the
+// pinned host block (parameters, state, poll flags, twiddle staging).
+int Solver::init_objects() {
+    if (!own_stream) HIP_CHECK(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
+    if (poll_ev.empty()) {
+        poll_ev.resize(kPollSlots);
+        for (auto &ev : poll_ev) HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        for (auto &si : slots) {
+            // kernel-timing events: nothing waits on them, so they skip the
+            // system-scope release (a cache writeback that would otherwise be
+            // charged to the bracketed kernel)
+            si.ev.resize(2 * kChunk * 4);
+            for (auto &ev : si.ev) HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableSystemFence));
+        }
+    }
+    if (!run_ev[0]) {
+        HIP_CHECK(hipEventCreate(&run_ev[0]));
+        HIP_CHECK(hipEventCreate(&run_ev[1]));
+    }
+    if (!h_pinned) {
+        // [DevParams | DevState | poll flags | twiddle staging] in one pinned block
+        HIP_CHECK(hipHostMalloc(&h_pinned, kPinnedBytes, hipHostMallocDefault));
+    }
+    return RVE_OK;
+}
+
+// Allocate (or adopt) the workspace and the per-solver HIP objects.  A change
+// of grid size or precision keeps the HIP objects and the graph cache (its
+// keys hold the kernels) and frees only an owned workspace.
 int Solver::prepare(const SolverOps *o, void *user_ws, size_t user_bytes) {
     if (ops != o) {
-        release();
+        if (owned && ws) (void)hipFree(ws);
+        ws = nullptr;
+        owned = false;
+        ws_bytes = 0;
+        tw_ready = false;
         ops = o;
     }
     const WsLayout L = ws_layout(o);
@@ -158,31 +220,7 @@ int Solver::prepare(const SolverOps *o, void *user_ws, size_t user_bytes) {
         tw_ready = false;
     }
     layout = L;
-    {
-        const char *g = getenv("RVEHOM_GRAPHS");
-        use_graphs = !(g && g[0] == '0');
-    }
-    if (!own_stream) HIP_CHECK(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
-    if (poll_ev.empty()) {
-        poll_ev.resize(kPollSlots);
-        for (auto &ev : poll_ev) HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-        for (auto &si : slots) {
-            // kernel-timing events: nothing waits on them, so they skip the
-            // system-scope release (a cache writeback that would otherwise be
-            // charged to the bracketed kernel)
-            si.ev.resize(2 * kChunk * 4);
-            for (auto &ev : si.ev) HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableSystemFence));
-        }
-    }
-    if (!run_ev[0]) {
-        HIP_CHECK(hipEventCreate(&run_ev[0]));
-        HIP_CHECK(hipEventCreate(&run_ev[1]));
-    }
-    if (!h_pinned) {
-        // [DevParams | DevState | poll flags] in one pinned block
-        HIP_CHECK(hipHostMalloc(&h_pinned, 4096, hipHostMallocDefault));
-    }
-    return RVE_OK;
+    return init_objects();
 }
 
 LaunchArgs Solver::args(const uint8_t *d_phase) const {
@@ -204,22 +242,28 @@ LaunchArgs Solver::args(const uint8_t *d_phase) const {
 int Solver::ensure_twiddles(hipStream_t s) {
     if (tw_ready) return RVE_OK;
     const int n = ops->n;
-    std::vector<double> w64(2 * (size_t)n);
+    // exp(-2 pi i m / n) in FP64, rounded once to the working precision,
+    // staged in the pinned block (rewritten only by a later solve on this
+    // solver, after this one has drained) and copied in stream order
+    char *stage = (char *)h_pinned + kTwStageOffset;
+    const bool f32 = ops->real_bytes == sizeof(float);
+    if ((size_t)n * 2 * ops->real_bytes > kPinnedBytes - kTwStageOffset) {
+        set_error("twiddle table of N = %d does not fit the staging block", n);
+        return RVE_ERR_ARG;
+    }
     for (int m = 0; m < n; ++m) {
-        // exp(-2 pi i m / n) in FP64, rounded once to the working precision
         const double a = 2.0 * M_PI * (double)m / (double)n;
-        w64[2 * m] = std::cos(a);
-        w64[2 * m + 1] = -std::sin(a);
+        const double c = std::cos(a), sn = -std::sin(a);
+        if (f32) {
+            ((float *)stage)[2 * m] = (float)c;
+            ((float *)stage)[2 * m + 1] = (float)sn;
+        } else {
+            ((double *)stage)[2 * m] = c;
+            ((double *)stage)[2 * m + 1] = sn;
+        }
     }
     char *dst = (char *)ws + layout.tw;
-    if (ops->real_bytes == sizeof(float)) {
-        std::vector<float> w32(w64.begin(), w64.end());
-        HIP_CHECK(hipMemcpyAsync(dst, w32.data(), w32.size() * sizeof(float), hipMemcpyHostToDevice, s));
-        HIP_CHECK(hipStreamSynchronize(s));
-    } else {
-        HIP_CHECK(hipMemcpyAsync(dst, w64.data(), w64.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        HIP_CHECK(hipStreamSynchronize(s));
-    }
+    HIP_CHECK(hipMemcpyAsync(dst, stage, (size_t)n * 2 * ops->real_bytes, hipMemcpyHostToDevice, s));
     tw_ready = true;
     return RVE_OK;
 }
@@ -495,6 +539,8 @@ SolverOpts resolve_opts(const rve_opts *opts) {
     o.workspace = opts ? opts->workspace : nullptr;
     o.workspace_bytes = opts ? opts->workspace_bytes : 0;
     o.scheme = opts ? opts->scheme : 0;
+    o.fp32_refine = (opts && opts->fp32_refine < 0) ? -1 : 0;
+    o.path_flags = opts ? (opts->path_flags & 63) : 0;
     return o;
 }
 
@@ -503,17 +549,16 @@ SolverOpts resolve_opts(const rve_opts *opts) {
 // z pass at its two tile widths on this workspace (before the first forward
 // pass overwrites the spectrum) and keeps the faster; differences under 3 %
 // keep the default.  The z transform of a pencil does not depend on the tile
-// width, so the choice never changes a result.  RVEHOM_ZTILE=0 / 1 forces the
-// default / the other width.
+// width, so the choice never changes a result.  PF_ZTILE_DEFAULT /
+// PF_ZTILE_ALT force the default / the other width.
 static std::mutex g_tune_mu;
 static std::map<const SolverOps *, int> g_ztune;
 
 int Solver::tune_zpass(const LaunchArgs &a, hipStream_t s) {
     zvar = 0;
     if (!ops->zgreen_alt) return RVE_OK;
-    const char *f = getenv("RVEHOM_ZTILE");
-    if (f && (f[0] == '0' || f[0] == '1')) {
-        zvar = f[0] - '0';
+    if (path_flags & (PF_ZTILE_DEFAULT | PF_ZTILE_ALT)) {
+        zvar = (path_flags & PF_ZTILE_ALT) ? 1 : 0;
         return RVE_OK;
     }
     {
@@ -559,6 +604,9 @@ int Solver::begin_elastic(const uint8_t *d_phase, const double moduli[6], double
 // and the state, and enqueue the first forward pass.
 int Solver::start(const uint8_t *d_phase, const SolverOpts &o, hipStream_t s) {
     d_phase_last = d_phase;
+    path_flags = o.path_flags;
+    use_graphs = !(o.path_flags & PF_NO_GRAPHS);
+    graph_counted = false;
     int rc = ensure_twiddles(s);
     if (rc != RVE_OK) return rc;
     DevParams *hp = (DevParams *)h_pinned;
@@ -569,6 +617,17 @@ int Solver::start(const uint8_t *d_phase, const SolverOpts &o, hipStream_t s) {
     HIP_CHECK(hipGetLastError());
     rc = tune_zpass(a, s);
     if (rc != RVE_OK) return rc;
+    if (o.dev_init_ops) {
+        // continuation: each solved load case starts from its field in another
+        // workspace (FP32 -> working precision)
+        for (int lc = 0; lc < 3; ++lc) {
+            if (!((o.lc_mask >> lc) & 1) || !o.dev_init[lc]) continue;
+            const size_t off = (size_t)3 * lc * M;
+            o.dev_init_ops->to_f64((double *)((char *)a.e + off * ops->real_bytes),
+                                   (const char *)o.dev_init[lc] + off * o.dev_init_ops->real_bytes, 3 * M, s);
+            HIP_CHECK(hipGetLastError());
+        }
+    }
     if (o.init_field) {
         // stage the FP64 field through the spectrum buffer region if it fits,
         // else through a temporary device buffer
@@ -587,19 +646,14 @@ int Solver::start(const uint8_t *d_phase, const SolverOpts &o, hipStream_t s) {
     launches.clear();
     eq_check = o.eq_check != 0;
     al = o.scheme == 2;
-    if (al) {
+    if (al && !o.dev_init_ops) {
         // the augmented-Lagrangian state: tau^0 = (k - k0) e^0 in the field buffer
+        // (a continuation's fields hold tau already)
         ops->to_tau(a, M, s);
         HIP_CHECK(hipGetLastError());
     }
-    {
-        const char *f = getenv("RVEHOM_FUSED");
-        fused = ops->inv_fwd != nullptr && !eq_check && !(f && f[0] == '0');
-    }
-    {
-        const char *f = getenv("RVEHOM_MERGE");
-        merge = ops->nc == 3 && !eq_check && !(f && f[0] == '0');
-    }
+    fused = ops->inv_fwd != nullptr && !eq_check && !(o.path_flags & PF_NO_FUSED);
+    merge = ops->nc == 3 && !eq_check && !(o.path_flags & PF_NO_MERGE);
     // a single load case: the iteration kernels run that load case's grid only
     lc_sel = -1;
     if (!eq_check && (o.lc_mask == 1 || o.lc_mask == 2 || o.lc_mask == 4)) lc_sel = o.lc_mask == 1 ? 0 : (o.lc_mask == 2 ? 1 : 2);
@@ -665,35 +719,51 @@ int Solver::launch_batch(const LaunchArgs &a, hipStream_t s, int count, int mask
 static int live_mask(int mask, bool fused) { return fused ? (mask & ~1) : mask; }
 
 // Capture kChunk iterations into a graph on the solver's own stream.
+GraphKey Solver::graph_key(const uint8_t *d_phase) const {
+    GraphKey k;
+    k.ops = ops;
+    k.ws = ws;
+    k.ph = d_phase;
+    k.eq = eq_check;
+    k.fused = fused;
+    k.merge = merge;
+    k.al = al;
+    k.lc = lc_sel;
+    k.zvar = zvar;
+    return k;
+}
+
 int Solver::ensure_graph(const uint8_t *d_phase) {
-    if (gexec && g_ws == ws && g_ph == d_phase && g_eq == eq_check && g_fused == fused && g_merge == merge &&
-        g_lc == lc_sel && g_zvar == zvar && g_al == al)
+    const GraphKey key = graph_key(d_phase);
+    if (gcur && gcur->key == key) {
+        if (!graph_counted) graphs->hits++;
+        graph_counted = true;
         return RVE_OK;
-    drop_graphs();
-    LaunchArgs a = args(d_phase);
-    hipGraph_t g = nullptr;
-    HIP_CHECK(hipStreamBeginCapture(own_stream, hipStreamCaptureModeThreadLocal));
-    (void)launch_batch(a, own_stream, kChunk, 0, nullptr);
-    hipError_t cap = hipStreamEndCapture(own_stream, &g);
-    if (cap != hipSuccess) {
-        set_error("graph capture failed: %s", hipGetErrorString(cap));
-        return RVE_ERR_DEVICE;
     }
-    hipError_t inst = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (inst != hipSuccess) {
-        gexec = nullptr;
-        set_error("graph instantiation failed: %s", hipGetErrorString(inst));
-        return RVE_ERR_DEVICE;
+    if (gcur) gcur->refs--;
+    gcur = graphs->find(key);
+    if (!graph_counted) (gcur ? graphs->hits : graphs->misses)++;
+    graph_counted = true;
+    if (!gcur) {
+        LaunchArgs a = args(d_phase);
+        hipGraph_t g = nullptr;
+        HIP_CHECK(hipStreamBeginCapture(own_stream, hipStreamCaptureModeThreadLocal));
+        (void)launch_batch(a, own_stream, kChunk, 0, nullptr);
+        hipError_t cap = hipStreamEndCapture(own_stream, &g);
+        if (cap != hipSuccess) {
+            set_error("graph capture failed: %s", hipGetErrorString(cap));
+            return RVE_ERR_DEVICE;
+        }
+        hipGraphExec_t x = nullptr;
+        hipError_t inst = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (inst != hipSuccess) {
+            set_error("graph instantiation failed: %s", hipGetErrorString(inst));
+            return RVE_ERR_DEVICE;
+        }
+        gcur = graphs->put(key, x);
     }
-    g_ws = ws;
-    g_ph = d_phase;
-    g_eq = eq_check;
-    g_fused = fused;
-    g_merge = merge;
-    g_lc = lc_sel;
-    g_zvar = zvar;
-    g_al = al;
+    gcur->refs++;
     return RVE_OK;
 }
 
@@ -702,7 +772,7 @@ int Solver::ensure_graph(const uint8_t *d_phase) {
 int Solver::ensure_timed_graphs(const uint8_t *d_phase, int mask) {
     int rc = ensure_graph(d_phase);
     if (rc != RVE_OK) return rc;
-    if (tgexec[0] && tg_mask == mask) return RVE_OK;
+    if (tgexec[0] && tg_mask == mask && tg_key == gcur->key) return RVE_OK;
     for (auto &g : tgexec) {
         if (g) (void)hipGraphExecDestroy(g);
         g = nullptr;
@@ -727,6 +797,7 @@ int Solver::ensure_timed_graphs(const uint8_t *d_phase, int mask) {
         }
     }
     tg_mask = mask;
+    tg_key = gcur->key;
     return RVE_OK;
 }
 
@@ -742,7 +813,7 @@ int Solver::enqueue(const uint8_t *d_phase, int count, int max_iter, int timing,
     if (use_graphs && count == kChunk && issued + kChunk <= max_iter) {
         int rc = si.mask ? ensure_timed_graphs(d_phase, si.mask) : ensure_graph(d_phase);
         if (rc != RVE_OK) return rc;
-        HIP_CHECK(hipGraphLaunch(si.mask ? tgexec[slot] : gexec, s));
+        HIP_CHECK(hipGraphLaunch(si.mask ? tgexec[slot] : gcur->exec, s));
         issued += kChunk;
         si.count = kChunk;
     } else {
@@ -875,7 +946,7 @@ int Solver::collect(const SolverOpts &o, hipStream_t s, rve_result *out, double 
             kt->total_ms[kk] += ms;
             kt->launches[kk] += 1;
             const double b = (kk == 2 && fused) ? ops->bytes_fused : (kk < 3 ? ops->bytes[kk] : 0.0);
-            kt->total_bytes[kk] += b * active / (double)nlc;
+            kt->total_bytes[kk] += b * active / (double)nlc + ((kk == 0 || kk == 2) ? ops->phase_bytes : 0.0);
         }
     }
     return RVE_OK;
@@ -919,10 +990,95 @@ struct DeviceScope {
 // overlap on the device (one's memory-bound phases beside another's compute
 // and launch ramps).  The arithmetic per load case is unchanged, so the
 // results equal those of the single-stream solve.
+static int run_solver(Solver &sv, const uint8_t *d_phase, const SolverOpts &o, hipStream_t s);
+
 static bool use_chains(const SolverOps *ops, const SolverOpts &o) {
-    const char *f = getenv("RVEHOM_CHAINS");
-    if (f && f[0] == '0') return false;
+    if (o.path_flags & PF_NO_CHAINS) return false;
     return ops->split > 0 && o.lc_mask == 7 && !o.eq_check && !o.init_field && !o.out_field && !o.workspace;
+}
+
+// FP32 floor -> FP64 continuation (fp32_refine).  Load cases that the FP32
+// solve stopped as STALLED (the rounding floor of the FP32 transforms above
+// tol, or no new residual minimum) restart in FP64 from their FP32 fields
+// (src[lc]: base of the 9-channel FP32 field holding load case lc) with the
+// same scheme and tol, and iterate steps 2-7 until eps_comp < tol.  Their K
+// column, status, residual and eps_eq become the FP64 ones; iterations and
+// residual history continue the FP32 ones.
+int refine_mask(const rve_result &res, const SolverOpts &o) {
+    if (o.precision != 0 || o.fp32_refine < 0) return 0;
+    int mask = 0;
+    for (int lc = 0; lc < 3; ++lc)
+        if (((o.lc_mask >> lc) & 1) && res.status[lc] == RVE_STALLED) mask |= 1 << lc;
+    return mask;
+}
+
+SolverOpts refine_opts(const SolverOpts &o, const rve_result &res, int mask, const void *const src[3],
+                       const SolverOps *ops32) {
+    int maxit32 = 0;
+    for (int lc = 0; lc < 3; ++lc)
+        if ((mask >> lc) & 1) maxit32 = std::max(maxit32, res.iters[lc]);
+    SolverOpts o64 = o;
+    o64.precision = 1;
+    o64.lc_mask = mask;
+    o64.stall_window = 0;
+    o64.max_iter = std::max(1, o.max_iter - maxit32);
+    o64.timing = 0;
+    o64.init_field = nullptr;
+    o64.out_field = nullptr;
+    o64.workspace = nullptr;
+    o64.workspace_bytes = 0;
+    o64.path_flags = o.path_flags & ~(PF_ZTILE_DEFAULT | PF_ZTILE_ALT);
+    for (int lc = 0; lc < 3; ++lc) o64.dev_init[lc] = src[lc];
+    o64.dev_init_ops = ops32;
+    return o64;
+}
+
+void refine_merge(rve_result &res, const rve_result &r64, int mask, double *hist, int hist_cap, const double *h64) {
+    res.solve_ms += r64.solve_ms;
+    for (int lc = 0; lc < 3; ++lc) {
+        if (!((mask >> lc) & 1)) continue;
+        for (int i = 0; i < 3; ++i) res.K[3 * i + lc] = r64.K[3 * i + lc];
+        const int it32 = res.iters[lc];
+        for (int i = 0; i < r64.iters[lc] && hist && h64; ++i)
+            if (it32 + i < hist_cap) hist[(size_t)lc * hist_cap + it32 + i] = h64[(size_t)lc * hist_cap + i];
+        res.iters[lc] = it32 + r64.iters[lc];
+        res.refine_iters[lc] = r64.iters[lc];
+        res.status[lc] = r64.status[lc];
+        res.final_residual[lc] = r64.final_residual[lc];
+        res.eps_eq[lc] = r64.eps_eq[lc];
+    }
+}
+
+rve_status refine_fp64(rve_s *r, const SolverOps *ops32, const double k[3], double tol, const SolverOpts &o,
+                       rve_result &res, double *hist, int hist_cap, const void *const src[3], hipStream_t s) {
+    const int mask = refine_mask(res, o);
+    if (!mask) return RVE_OK;
+    const SolverOps *ops64 = lookup_ops(1, r->n);
+    if (!ops64) return RVE_OK;  // no FP64 build of this grid: the load cases stay STALLED
+    Solver &sv = r->sol[1];
+    int rc = sv.prepare(ops64, nullptr, 0);
+    if (rc != RVE_OK) return (rve_status)rc;
+    SolverOpts o64 = refine_opts(o, res, mask, src, ops32);
+    rc = sv.begin(r->d_phase, k, tol, o64, s);
+    if (rc != RVE_OK) return (rve_status)rc;
+    rc = run_solver(sv, r->d_phase, o64, s);
+    if (rc != RVE_OK) return (rve_status)rc;
+    rve_result r64{};
+    std::vector<double> h64(hist && hist_cap > 0 ? (size_t)3 * hist_cap : 0);
+    const size_t M = (size_t)r->n * r->n * r->n;
+    std::vector<double> f64(o.out_field ? 9 * M : 0);
+    o64.out_field = o.out_field ? f64.data() : nullptr;
+    rc = sv.collect(o64, s, &r64, h64.empty() ? nullptr : h64.data(), hist_cap, nullptr);
+    if (rc != RVE_OK) return (rve_status)rc;
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, sv.run_ev[0], sv.run_ev[1]));
+    r64.solve_ms = ms;
+    refine_merge(res, r64, mask, hist, hist_cap, h64.empty() ? nullptr : h64.data());
+    if (o.out_field)
+        for (int lc = 0; lc < 3; ++lc)
+            if ((mask >> lc) & 1)
+                std::memcpy(o.out_field + 3 * lc * M, f64.data() + 3 * lc * M, 3 * M * sizeof(double));
+    return RVE_OK;
 }
 
 struct ChainItem {
@@ -996,6 +1152,13 @@ static rve_status solve_chains(rve_s *r, const SolverOps *ops, const double k[3]
     HIP_CHECK(hipEventElapsedTime(&ms, c0.run_ev[0], c0.run_ev[1]));
     res.solve_ms = ms;
     if (o.timing) r->times = kt_sum;
+    const void *src[3];
+    for (int lc = 0; lc < 3; ++lc) {
+        const Solver &cs = r->chain[o.precision][lc];
+        src[lc] = (const char *)cs.ws + cs.layout.e;
+    }
+    rc = refine_fp64(r, ops, k, tol, o, res, hist, hist_cap, src, s);
+    if (rc != RVE_OK) return (rve_status)rc;
     if (out) *out = res;
     return worst_status(res, o.lc_mask);
 }
@@ -1114,6 +1277,14 @@ rve_status solve_one(rve_s *r, const double k[3], double tol, const SolverOpts &
     float ms = 0.f;
     HIP_CHECK(hipEventElapsedTime(&ms, sv.run_ev[0], sv.run_ev[1]));
     res.solve_ms = ms;
+    if (o.precision == 0 && o.fp32_refine >= 0) {
+        // FP64 continuation of load cases stopped by the FP32 floor (with a
+        // caller workspace the FP64 one is still the handle's own)
+        const void *src[3];
+        for (int lc = 0; lc < 3; ++lc) src[lc] = (const char *)sv.ws + sv.layout.e;
+        rc = refine_fp64(r, ops, k, tol, o, res, hist, hist_cap, src, s);
+        if (rc != RVE_OK) return (rve_status)rc;
+    }
     if (out) *out = res;
     return worst_status(res, o.lc_mask);
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <deque>
+#include <list>
 #include <vector>
 
 #include "rvehom.h"
@@ -17,6 +18,8 @@ constexpr int kChunk = 8;        // iterations between host poll points
 constexpr int kLookahead = 2;    // poll points in flight before the host waits
 constexpr int kPollSlots = 4;
 constexpr size_t kFlagsOffset = 2048;  // poll flags inside the pinned block
+constexpr size_t kTwStageOffset = 4096;  // twiddle staging inside the pinned block
+constexpr size_t kPinnedBytes = 4096 + 8192;  // N <= 512 complex doubles of twiddles
 
 struct WsLayout {
     size_t e, spec, nyq, tw, part, prm, st, hist, peq, total;
@@ -36,7 +39,17 @@ struct SolverOpts {
     double *out_field = nullptr;
     void *workspace = nullptr;
     size_t workspace_bytes = 0;
+    int fp32_refine = 0;  // 0 on, -1 off (rve_opts)
+    int path_flags = 0;   // PF_* measurement switches (rve_opts)
+    // FP64 continuation: start from the FP32 fields on the device (per load
+    // case, the base of a 9-channel FP32 field; channels 3 lc .. 3 lc + 2 are
+    // taken) instead of E; the buffers hold tau already for scheme 2
+    const void *dev_init[3] = {nullptr, nullptr, nullptr};
+    const SolverOps *dev_init_ops = nullptr;
 };
+
+enum : int { PF_NO_GRAPHS = 1, PF_NO_FUSED = 2, PF_NO_MERGE = 4, PF_NO_CHAINS = 8, PF_ZTILE_DEFAULT = 16,
+             PF_ZTILE_ALT = 32 };
 
 struct LaunchRec {
     int kernel;
@@ -51,6 +64,41 @@ struct SlotInfo {
     int count = 0;
     int mask = 0;
     std::vector<hipEvent_t> ev;  // 2 * kChunk * 4
+};
+
+// What a captured iteration graph depends on: the kernels (ops), the
+// pointers baked into their arguments, and the launch-sequence switches.
+struct GraphKey {
+    const SolverOps *ops = nullptr;
+    const void *ws = nullptr;
+    const uint8_t *ph = nullptr;
+    bool eq = false, fused = false, merge = false, al = false;
+    int lc = -1, zvar = 0;
+    bool operator==(const GraphKey &o) const {
+        return ops == o.ops && ws == o.ws && ph == o.ph && eq == o.eq && fused == o.fused && merge == o.merge &&
+               al == o.al && lc == o.lc && zvar == o.zvar;
+    }
+};
+
+// Instantiated iteration graphs, reused across solves whose key matches
+// (a server shares one cache among its slots).  An entry some solver holds
+// as its current graph (refs > 0) is never evicted; any other entry has no
+// launch in flight (a solve drains its stream before its solver moves on).
+struct GraphCache {
+    struct Entry {
+        GraphKey key;
+        hipGraphExec_t exec;
+        int refs;
+        uint64_t used;
+    };
+    std::list<Entry> entries;  // stable addresses: solvers hold pointers to entries
+    size_t cap = 4;
+    uint64_t tick = 0;
+    uint64_t hits = 0, misses = 0;  // solves whose first full chunk found / captured its graph
+    Entry *find(const GraphKey &k);
+    Entry *put(const GraphKey &k, hipGraphExec_t x);
+    void clear();
+    ~GraphCache() { clear(); }
 };
 
 // Device workspace + HIP objects of one (RVE, precision).
@@ -78,26 +126,26 @@ struct Solver {
     int lc_sel = -1;     // -1: all load cases; else the only load case iterated
     int zvar = 0;        // z-pass tile width: 0 default, 1 the other (autotuned)
     bool al = false;     // augmented-Lagrangian update in the fused pass
+    int path_flags = 0;  // PF_* of the current solve
     const uint8_t *d_phase_last = nullptr;
     // captured graph of kChunk iterations (kernels only; all parameters are
-    // read from device memory, so one graph serves every call on this workspace)
-    hipGraphExec_t gexec = nullptr;
-    const void *g_ws = nullptr;
-    const uint8_t *g_ph = nullptr;
-    bool g_eq = false;
-    bool g_fused = false;
-    bool g_merge = false;
-    int g_lc = -1;
-    int g_zvar = 0;
-    bool g_al = false;
+    // read from device memory, so one graph serves every call with the same
+    // key), held from the cache
+    GraphCache own_graphs;
+    GraphCache *graphs = &own_graphs;
+    GraphCache::Entry *gcur = nullptr;
+    bool graph_counted = false;  // this solve's graph already counted as a cache hit or miss
     bool use_graphs = true;
     // timed variants: one graph per poll slot (its own events), per mask
     hipGraphExec_t tgexec[kPollSlots] = {};
     int tg_mask = 0;
+    GraphKey tg_key{};
 
     ~Solver();
     void release();
+    int init_objects();
     int prepare(const SolverOps *o, void *user_ws, size_t user_bytes);
+    GraphKey graph_key(const uint8_t *d_phase) const;
     LaunchArgs args(const uint8_t *d_phase) const;
     int ensure_twiddles(hipStream_t s);
     int begin(const uint8_t *d_phase, const double k[3], double tol, const SolverOpts &o, hipStream_t s);
@@ -129,6 +177,17 @@ rve_status solve_one(struct ::rve_s *r, const double k[3], double tol, const Sol
                      double *hist, int hist_cap);
 rve_status batch_solve(int count, const rve_t *rves, const double *k, const double *tol, const SolverOpts &o,
                        rve_result *out);
+// FP64 continuation of the load cases an FP32 solve left STALLED (rve_opts
+// fp32_refine); src[lc]: base of the FP32 field holding load case lc.
+// refine_mask: the load cases to continue; refine_opts: the FP64 solve's
+// options; refine_merge: its results into the FP32 ones.
+int refine_mask(const rve_result &res, const SolverOpts &o);
+SolverOpts refine_opts(const SolverOpts &o, const rve_result &res, int mask, const void *const src[3],
+                       const SolverOps *ops32);
+void refine_merge(rve_result &res, const rve_result &r64, int mask, double *hist, int hist_cap, const double *h64);
+rve_status refine_fp64(struct ::rve_s *r, const SolverOps *ops32, const double k[3], double tol,
+                       const SolverOpts &o, rve_result &res, double *hist, int hist_cap, const void *const src[3],
+                       hipStream_t s);
 
 // Drive already-begun solvers to completion, interleaving their chunks.
 // finish(item) is called once per finished solver.

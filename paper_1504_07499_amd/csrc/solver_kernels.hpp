@@ -664,7 +664,14 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
     const int bt = blockIdx.x - (red_nper > 0 ? 1 : 0);
     const int lt = bt / TL::PER_LC, t = ztile_of<T, N, W>(bt - lt * TL::PER_LC);
     const int lc = lc0 + lt;  // the grid covers load cases lc0 .. (all three, or one)
-    if (__hip_atomic_load(&st->done[lc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    // the freeze flag, read once for the workgroup (the merged reduction of
+    // workgroup 0 may write it meanwhile) so that every wave takes the same
+    // exit; a load case frozen during this pass may leave its spectrum
+    // unprocessed, which is harmless (it is not read again)
+    __shared__ int s_done;
+    if (tid == 0) s_done = __hip_atomic_load(&st->done[lc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (s_done) return;
     Cx<T> *base;
     size_t cstride, zstride;
     int kx0, ky0, dkx, dky;  // kx(w) = kx0 + dkx*w, ky(w) = ky0 + dky*w

@@ -36,7 +36,8 @@ struct SolverOps {
     size_t nyq_elems;    // complex elements of nyq (9 N N)
     int grid[3];         // blocks of P1, P2, P3
     int threads[3];      // threads per block of P1, P2, P3
-    double bytes[3];     // algorithmic HBM bytes of one launch of P1, P2, P3 (all 3 load cases)
+    double bytes[3];     // algorithmic HBM field bytes of one launch of P1, P2, P3 (all load
+                         // cases; the phase image is phase_bytes)
     int eq_tiles;        // k_zeq blocks per load case
     double bytes_fused;  // algorithmic bytes of one fused inverse + forward launch
     // fused inverse pass + next forward pass, or nullptr where planes are split
@@ -63,6 +64,9 @@ struct SolverOps {
     int nc;
     // the reduction of the per-block partials as a launch of its own
     void (*reduce)(const LaunchArgs &, int nper, hipStream_t);
+    // the phase image (1 byte per voxel), counted once per launch of the
+    // passes that read it (P1, P3, fused) whatever the number of load cases
+    double phase_bytes;
 };
 
 const SolverOps *ops_f32(int n);

@@ -49,7 +49,9 @@ def run_set(res, nsp, layer, samples, k=PAPER_K, f=0.3, tol=1e-5, precision=0):
     iters = np.array([o.iters.max() for o in out])
     return {"res": res, "n_sp": nsp, "layer": layer, "samples": samples,
             "k_iso_mean": float(vals.mean()), "k_iso_std": float(vals.std(ddof=1)) if samples > 1 else 0.0,
-            "iters_mean": float(iters.mean()), "status": [int(o.status) for o in out]}
+            "iters_mean": float(iters.mean()), "status": [int(o.status) for o in out],
+            "seeds": [sample_seed(res, nsp, layer, i) for i in range(samples)],
+            "K": [o.K.tolist() for o in out]}
 
 
 def sweep(res_list=PAPER_RES, nsp_list=PAPER_NSP, layers=PAPER_LAYERS, samples=10, **kw):

@@ -3,6 +3,7 @@ streams from PyTorch, batched solves and the serving loop."""
 import numpy as np
 import pytest
 
+import oracle
 import paper_1504_07499_amd as rh
 from paper_1504_07499_amd import geom
 
@@ -34,13 +35,25 @@ def test_argument_errors():
 
 
 def test_fp32_stall_detection():
-    """tol below the FP32 floor: stops as STALLED, not after max_iter."""
+    """tol below the FP32 floor: without the FP64 continuation the solve stops
+    as STALLED, not after max_iter; with it (the default) the stalled load
+    cases continue in FP64 from their FP32 fields down to tol, and the tensor
+    is the FP64 solve's."""
     print("\n[case] stall", flush=True)
     ph, _, _ = geom.generate(32, 8, 0.2, 0.1, 1)
     with rh.rve_create_from_phases(ph) as r:
-        g = rh.homogenize(r, K3, 1e-14, precision=0, max_iter=3000)
-    assert g.status == rh.RVE_STALLED
-    assert g.iters.max() < 3000
+        g = rh.homogenize(r, K3, 1e-14, precision=0, max_iter=3000, fp32_refine=False)
+        assert g.status == rh.RVE_STALLED
+        assert g.iters.max() < 3000 and g.refine_iters.max() == 0
+        ref = rh.homogenize(r, K3, 1e-14, precision=0, max_iter=3000, hist_cap=3000)
+        f64 = rh.homogenize(r, K3, 1e-14, precision=1, max_iter=3000)
+    assert ref.status == rh.RVE_OK
+    assert np.all(ref.refine_iters > 0) and np.all(ref.iters > ref.refine_iters)
+    assert np.all(ref.final_residual < 1e-14)
+    for j in range(3):
+        h = ref.history[j]
+        assert len(h) == ref.iters[j] and h[-1] == ref.final_residual[j]
+    assert np.abs(ref.K - f64.K).max() <= 1e-12 * np.abs(f64.K).max()
 
 
 _TORCH_CHILD = r"""
@@ -108,6 +121,14 @@ def test_batch_equals_alone(precision, scheme):
     for a, b in zip(alone, mixed):
         assert np.array_equal(a.K, b.K)
         assert np.array_equal(a.iters, b.iters)
+    # and each batched tensor against the FP64 oracle on the same phases
+    sch = rh.SCHEMES[scheme]
+    for r, kk, t, b in zip(rves, ks, tols, mixed):
+        ref = oracle.homogenize(rh.rve_get_phases(r), kk, tol=t, scheme=sch)
+        err = np.abs(b.K - ref.K).max() / np.abs(ref.K).max()
+        assert err <= (1e-9 if precision else 1e-4), err
+        if precision:
+            assert list(b.iters) == list(ref.iters)
     for r in rves:
         r.close()
 
@@ -135,63 +156,102 @@ def test_server_results_match_alone():
         assert lat > 0
         with rh.rve_create(*q[:5]) as r:
             alone = rh.homogenize(r, q[5], q[6], precision=0)
+            ph = rh.rve_get_phases(r)
         assert np.array_equal(res.K, alone.K)
         assert np.array_equal(res.iters, alone.iters)
+        assert res.status == rh.RVE_OK
+        ref = oracle.homogenize(ph, q[5], tol=q[6])
+        assert np.abs(res.K - ref.K).max() / np.abs(ref.K).max() <= 1e-4
+
+
+def _footprint(n, precision):
+    """Device block of one served request: phase image, workspace and (FP32)
+    the FP64 continuation's workspace, each rounded up to 256 bytes."""
+    up = lambda b: (b + 255) // 256 * 256  # noqa: E731
+    with rh.rve_create_from_phases(np.zeros((n, n, n), np.uint8)) as r:
+        b = up(n ** 3) + up(rh.rve_workspace_size(r, precision))
+        if precision == 0:
+            b += up(rh.rve_workspace_size(r, 1))
+    return b
+
+
+def test_server_budget_admission_and_graph_reuse():
+    """A budget of 1.5 request footprints keeps one request resident at a
+    time, even when a backlog arrives while the server is idle; requests of
+    one grid size reuse the instantiated iteration graphs; results equal the
+    alone solves."""
+    print("\n[case] server budget", flush=True)
+    fp = _footprint(32, 0)
+    srv = rh.rve_server_create(int(1.5 * fp), 4, 0)
+    reqs = [(32, 8, 0.2, 0.1, 40 + i, [0.2, 0.3, 40.0 * (i + 1)], 1e-6) for i in range(5)]
+    tickets = [rh.rve_server_submit(srv, *q[:5], q[5], q[6]) for q in reqs]
+    rh.rve_server_drain(srv)
+    served = [rh.rve_server_poll(srv, t) for t in tickets]
+    st = rh.rve_server_get_stats(srv)
+    rh.rve_server_destroy(srv)
+    print(st, flush=True)
+    assert st["resident_peak"] == 1
+    assert st["peak_bytes"] <= st["arena_bytes"] and st["peak_bytes"] == fp
+    assert st["admitted"] == 5 and st["completed"] == 5
+    assert st["graph_hits"] > 0
+    for q, (res, _) in zip(reqs, served):
+        with rh.rve_create(*q[:5]) as r:
+            alone = rh.homogenize(r, q[5], q[6], precision=0)
+        assert np.array_equal(res.K, alone.K) and np.array_equal(res.iters, alone.iters)
+    # a request larger than the budget is refused at submission
+    srv = rh.rve_server_create(int(1.5 * fp), 2, 0)
+    with pytest.raises(rh.RveError) as ei:
+        rh.rve_server_submit(srv, 64, 8, 0.2, 0.1, 1, [0.2, 0.3, 400.0], 1e-6)
+    assert ei.value.status == rh.RVE_ERR_OOM
+    rh.rve_server_destroy(srv)
 
 
 def test_kernel_timing_does_not_change_results():
     """Events recorded inside the replayed graphs: same tensor, one timed
     launch per working iteration (single stream), positive durations; with
     the three load-case chains each chain times its own launches."""
-    import os
 
     print("\n[case] kernel timing", flush=True)
     ph, _, _ = geom.generate(48, 10, 0.25, 0.2, 8)
     with rh.rve_create_from_phases(ph) as r:
-        os.environ["RVEHOM_CHAINS"] = "0"
-        try:
-            plain = rh.homogenize(r, K3, 1e-6, precision=0)
-            timed = rh.homogenize(r, K3, 1e-6, precision=0, timing=True)
-            kt = rh.rve_get_kernel_times(r)
-            only = rh.homogenize(r, K3, 1e-6, precision=0, timing=4)
-            kt4 = rh.rve_get_kernel_times(r)
-            sampled = rh.homogenize(r, K3, 1e-6, precision=0, timing=4 | 16)
-            kts = rh.rve_get_kernel_times(r)
-        finally:
-            os.environ.pop("RVEHOM_CHAINS", None)
+        one = rh.PATH_NO_CHAINS
+        plain = rh.homogenize(r, K3, 1e-6, precision=0, path_flags=one)
+        timed = rh.homogenize(r, K3, 1e-6, precision=0, timing=True, path_flags=one)
+        kt = rh.rve_get_kernel_times(r)
+        only = rh.homogenize(r, K3, 1e-6, precision=0, timing=4, path_flags=one)
+        kt4 = rh.rve_get_kernel_times(r)
+        sampled = rh.homogenize(r, K3, 1e-6, precision=0, timing=4 | 16, path_flags=one)
+        kts = rh.rve_get_kernel_times(r)
         chained = rh.homogenize(r, K3, 1e-6, precision=0, timing=True)
         ktc = rh.rve_get_kernel_times(r)
     assert np.array_equal(plain.K, timed.K) and np.array_equal(plain.K, only.K)
     assert np.array_equal(plain.K, sampled.K) and np.array_equal(plain.K, chained.K)
+    # the kernel times cover the FP32 iterations (not the FP64 continuation)
+    it32 = plain.iters - plain.refine_iters
     # sampled: one batch of iterations in four carries events
-    assert 0 < kts[list(kts)[2]]["launches"] < int(plain.iters.max())
+    assert 0 < kts[list(kts)[2]]["launches"] < int(it32.max())
     assert kts[list(kts)[2]]["total_ms"] > 0
     names = list(kt)
     assert names[1] == "zgreen" and names[3] == "reduce"
     for name in names[1:]:
-        assert kt[name]["launches"] == int(plain.iters.max())
+        assert kt[name]["launches"] == int(it32.max())
         assert kt[name]["total_ms"] > 0
         # chains: every load case launches its own kernels
-        assert ktc[name]["launches"] == int(plain.iters.sum())
+        assert ktc[name]["launches"] == int(it32.sum())
         assert ktc[name]["total_ms"] > 0
-    assert kt4[names[2]]["launches"] == int(plain.iters.max())
+    assert kt4[names[2]]["launches"] == int(it32.max())
     assert kt4["zgreen"]["launches"] == 0
 
 
 def test_fused_pass_matches_separate_passes():
     """The fused inverse + next forward pass gives the separate passes'
     result (identical arithmetic, different kernel boundaries)."""
-    import os
 
     print("\n[case] fused vs separate", flush=True)
     ph, _, _ = geom.generate(64, 12, 0.3, 0.2, 21)
     with rh.rve_create_from_phases(ph) as r:
         fused = rh.homogenize(r, K3, 1e-6, precision=1)
-        os.environ["RVEHOM_FUSED"] = "0"
-        try:
-            sep = rh.homogenize(r, K3, 1e-6, precision=1)
-        finally:
-            os.environ.pop("RVEHOM_FUSED", None)
+        sep = rh.homogenize(r, K3, 1e-6, precision=1, path_flags=rh.PATH_NO_FUSED)
     assert np.array_equal(fused.iters, sep.iters)
     assert np.abs(fused.K - sep.K).max() <= 1e-12 * np.abs(sep.K).max()
 
@@ -201,17 +261,13 @@ def test_load_case_chains_match_single_stream(precision):
     """A full solve runs as three concurrent single-load-case solves (own
     streams and graphs); tensor, iteration counts and histories equal those
     of the single-stream solve of all three load cases."""
-    import os
 
     print(f"\n[case] chains vs single stream precision={precision}", flush=True)
     ph, _, _ = geom.generate(64, 12, 0.3, 0.2, 23)
     with rh.rve_create_from_phases(ph) as r:
         chained = rh.homogenize(r, K3, 1e-6, precision=precision, hist_cap=512)
-        os.environ["RVEHOM_CHAINS"] = "0"
-        try:
-            single = rh.homogenize(r, K3, 1e-6, precision=precision, hist_cap=512)
-        finally:
-            os.environ.pop("RVEHOM_CHAINS", None)
+        single = rh.homogenize(r, K3, 1e-6, precision=precision, hist_cap=512,
+                               path_flags=rh.PATH_NO_CHAINS)
         one = rh.homogenize(r, K3, 1e-6, precision=precision, lc_mask=2)
     assert np.array_equal(chained.K, single.K)
     assert np.array_equal(chained.iters, single.iters)
@@ -228,18 +284,13 @@ def test_z_tile_widths_give_identical_results(n, precision):
     """The autotuner picks one of two z-tile widths per grid size; both give
     bitwise the same result (the z transform of a pencil does not depend on
     how many pencils a tile holds)."""
-    import os
 
     print(f"\n[case] z tile widths n={n} precision={precision}", flush=True)
     ph, _, _ = geom.generate(n, 12, 0.3, 0.2, 31)
     out = []
     with rh.rve_create_from_phases(ph) as r:
-        for v in ("0", "1"):
-            os.environ["RVEHOM_ZTILE"] = v
-            try:
-                out.append(rh.homogenize(r, K3, 1e-6, precision=precision, max_iter=60))
-            finally:
-                os.environ.pop("RVEHOM_ZTILE", None)
+        for v in (rh.PATH_ZTILE_DEFAULT, rh.PATH_ZTILE_ALT):
+            out.append(rh.homogenize(r, K3, 1e-6, precision=precision, max_iter=60, path_flags=v))
     assert np.array_equal(out[0].K, out[1].K)
     assert np.array_equal(out[0].iters, out[1].iters)
 

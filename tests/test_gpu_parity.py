@@ -161,7 +161,10 @@ def test_config2_128_vs_stored_oracle(precision):
         assert list(g.iters) == ref["iters"]
         assert tensor_err(g.K, Kr) <= 1e-9
     else:
-        assert g.status in (rh.RVE_OK, rh.RVE_STALLED)
+        # FP32 stops at its rounding floor above tol; the FP64 continuation
+        # takes the stalled load cases below tol
+        assert g.status == rh.RVE_OK, (list(g.lc_status), list(g.refine_iters))
+        assert np.all(g.final_residual < ref["tol"])
         assert tensor_err(g.K, Kr) <= 1e-4
 
 
@@ -204,16 +207,11 @@ def test_graph_replays_match_eager_launches():
     """Chunks of iterations replayed from a captured graph give bitwise the
     result of kernel-by-kernel launches, over several solves with host work
     and synchronisation in between."""
-    import os
 
     print("\n[case] graph replay vs eager", flush=True)
     ph, _, _ = geom.generate(48, 10, 0.25, 0.2, 8)
     with rh.rve_create_from_phases(ph) as r:
-        os.environ["RVEHOM_GRAPHS"] = "0"
-        try:
-            eager = rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=0)
-        finally:
-            os.environ.pop("RVEHOM_GRAPHS", None)
+        eager = rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=0, path_flags=rh.PATH_NO_GRAPHS)
         for rep in range(3):
             g = rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=0)
             assert np.array_equal(g.K, eager.K), rep
@@ -299,7 +297,7 @@ def test_augmented_lagrangian_config2_128(precision):
     with rh.rve_create(g0["n"], g0["n_spheres"], g0["volume_fraction"], g0["layer"],
                        g0["seed"]) as r:
         g = rh.homogenize(r, ref["k_phases"], ref["tol"], precision=precision, scheme=AL)
-    assert g.status in ((rh.RVE_OK, rh.RVE_STALLED) if precision == 0 else (rh.RVE_OK,))
+    assert g.status == rh.RVE_OK  # FP32: with the FP64 continuation past its floor
     assert tensor_err(g.K, np.array(ref["K"])) <= (1e-4 if precision == 0 else 1e-5)
     assert int(min(g.iters)) > max(ref["iters"])
 
@@ -326,17 +324,12 @@ def test_augmented_lagrangian_256_split_and_five_pass():
 def test_augmented_lagrangian_fused_equals_separate_passes():
     """The fused pass and the separate forward / inverse passes carry the same
     augmented-Lagrangian iteration: FP64 tensors and iteration counts agree."""
-    import os
 
     print("\n[case] augmented lagrangian fused vs separate", flush=True)
     ph, _, _ = geom.generate(64, 12, 0.3, 0.2, 41)
     with rh.rve_create_from_phases(ph) as r:
         fused = rh.homogenize(r, K_PAPER_CFG, 1e-8, precision=1, scheme=AL)
-        os.environ["RVEHOM_FUSED"] = "0"
-        try:
-            sep = rh.homogenize(r, K_PAPER_CFG, 1e-8, precision=1, scheme=AL)
-        finally:
-            os.environ.pop("RVEHOM_FUSED", None)
+        sep = rh.homogenize(r, K_PAPER_CFG, 1e-8, precision=1, scheme=AL, path_flags=rh.PATH_NO_FUSED)
     assert np.array_equal(fused.iters, sep.iters)
     assert tensor_err(sep.K, fused.K) <= 1e-12
 
