@@ -170,6 +170,29 @@ size_t rve_workspace_size(rve_t rve, int precision);
 rve_status homogenize(rve_t rve, const double k_phases[3], double tol, const rve_opts *opts,
                       rve_result *out, double *residual_history, int hist_cap);
 
+/* homogenize for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same kernels
+ * in the same order and the same results as homogenize, with every device
+ * buffer beyond the RVE's phase image in one fixed array of device memory
+ * that belongs to the library image (64 MiB per GPU, held from the first
+ * call on that GPU until the process ends).  No hipMalloc, hipFree, pinned
+ * host allocation, stream, event or graph is created; parameters and
+ * results pass through stack buffers and the call synchronises opts->stream
+ * (NULL: the null stream) several times.
+ * Limit: the workspace (rve_workspace_size) of the precision, plus for FP32
+ * with fp32_refine the FP64 workspace of the continuation, must fit in
+ * 64 MiB (N <= 64); larger grids give RVE_ERR_ARG with the bytes needed.
+ * Honoured opts: precision, max_iter, stall_window, lc_mask, scheme,
+ * fp32_refine, stream and the path_flags 2, 4 and 32; init_field, out_field,
+ * workspace, timing or equilibrium_check give RVE_ERR_ARG.  solve_ms is
+ * host wall time.  Calls on one GPU share its array: the library
+ * serialises calls from threads of one process on a GPU (each call leaves
+ * the array in use until it returns), and every solve initialises what it
+ * reads; calls from different processes on one GPU each have their own
+ * copy of the library image. */
+rve_status homogenize_no_alloc(rve_t rve, const double k_phases[3], double tol, const rve_opts *opts,
+                               rve_result *out, double *residual_history, int hist_cap);
+
 /* Several RVEs (any mix of grid sizes) solved concurrently on the device.
  * k_phases: [3*count]; tol: [count]; opts applies to all (its fields and
  * workspace must be NULL); out: [count]. */

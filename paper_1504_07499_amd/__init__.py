@@ -26,7 +26,7 @@ from . import _build
 
 __all__ = [
     "RveError", "RVE", "HomResult", "rve_supported_n", "rve_create", "rve_create_from_phases",
-    "rve_get_phases", "rve_get_spheres", "rve_workspace_size", "homogenize", "homogenize_batch",
+    "rve_get_phases", "rve_get_spheres", "rve_workspace_size", "homogenize", "homogenize_batch", "homogenize_no_alloc",
     "rve_get_kernel_times", "rve_server_create", "rve_server_submit", "rve_server_poll",
     "rve_server_drain", "rve_server_get_stats", "rve_server_destroy", "rve_destroy", "rve_last_error", "library_path",
     "RVE_OK", "RVE_NOT_CONVERGED", "RVE_STALLED", "RVE_PENDING", "RVE_ERR_ARG", "RVE_ERR_JAMMED",
@@ -101,6 +101,7 @@ def _load_library():
         "rve_workspace_size": (c_size_t, [c_vp, c_int]),
         "homogenize": (c_int, [c_vp, P(c_double), c_double, P(_Opts), P(_Result), P(c_double), c_int]),
         "homogenize_batch": (c_int, [c_int, P(c_vp), P(c_double), P(c_double), P(_Opts), P(_Result)]),
+        "homogenize_no_alloc": (c_int, [c_vp, P(c_double), c_double, P(_Opts), P(_Result), P(c_double), c_int]),
         "rve_get_kernel_times": (c_int, [c_vp, P(_KTimes)]),
         "homogenize_elastic": (c_int, [c_vp, P(c_double), c_double, P(_Opts), P(_ElResult), P(c_double), c_int]),
         "rve_supported_n_elastic": (c_int, [c_int, P(c_int), c_int, P(c_int)]),
@@ -334,6 +335,23 @@ def homogenize(rve: RVE, k_phases, tol: float = 1e-6, *, max_iter: int = 0, prec
     rc = _check(_lib.homogenize(rve.handle, _dptr(k), float(tol), ctypes.byref(o), ctypes.byref(res),
                                 _dptr(hist) if hist is not None else None, int(hist_cap)))
     return _to_result(rc, res, hist, hist_cap, fld)
+
+
+def homogenize_no_alloc(rve: RVE, k_phases, tol: float = 1e-6, *, max_iter: int = 0, precision: int = 0,
+                        stall_window: int = -1, lc_mask: int = 7, stream=None, hist_cap: int = 0,
+                        scheme="accelerated", fp32_refine: bool = True, path_flags: int = 0) -> HomResult:
+    """homogenize without any allocation: the library's fixed device array
+    (64 MiB per GPU) holds the workspaces, so N <= 64."""
+    k = np.ascontiguousarray(k_phases, dtype=np.float64)
+    if k.shape != (3,):
+        raise RveError(RVE_ERR_ARG, "k_phases must hold 3 conductivities")
+    o = _opts(max_iter, precision, False, stall_window, lc_mask, False, stream, None, None, None, scheme,
+              fp32_refine, path_flags)
+    res = _Result()
+    hist = np.zeros(3 * hist_cap) if hist_cap > 0 else None
+    rc = _check(_lib.homogenize_no_alloc(rve.handle, _dptr(k), float(tol), ctypes.byref(o), ctypes.byref(res),
+                                         _dptr(hist) if hist is not None else None, int(hist_cap)))
+    return _to_result(rc, res, hist, hist_cap)
 
 
 @dataclass

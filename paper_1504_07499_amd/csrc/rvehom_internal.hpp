@@ -171,6 +171,8 @@ const SolverOps *lookup_ops_el(int precision, int n);
 void set_error(const char *fmt, ...);
 void clear_error();
 int validate_k(const double k[3], double tol);
+void fill_params(DevParams &p, const double k[3], double tol, int n, const SolverOpts &o);
+int check_scheme(const SolverOpts &o, const SolverOps *ops);
 SolverOpts resolve_opts(const rve_opts *opts);
 rve_status worst_status(const rve_result &r, int lc_mask);
 rve_status solve_one(struct ::rve_s *r, const double k[3], double tol, const SolverOpts &o, rve_result *out,
