@@ -85,7 +85,10 @@ template <typename T, int N> struct Instance {
     // relies on the frozen-load-case early exit)
     static int pgrid(int lc_sel) { return (lc_sel < 0 ? 9 : 3) * N * SP; }
     static int ch0(int lc_sel) { return lc_sel < 0 ? 0 : 3 * lc_sel; }
-    template <bool PHI> static void fwd_t(const LaunchArgs &a, hipStream_t s, int lc_sel) {
+    // split planes: the fused pass writes the parity layout (k_inv_plane with
+    // S = 2), read back by the z pass
+    static constexpr bool PARF = !FIVE && S == 2;
+    template <bool PHI, bool PAR = false> static void fwd_t(const LaunchArgs &a, hipStream_t s, int lc_sel) {
         if constexpr (FIVE) {
             hipLaunchKernelGGL((k_fwd_rows<T, N, G, NTR, PHI>), dim3(9 * N * (N / G)), dim3(NTR), 0, s,
                                (const T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq,
@@ -93,6 +96,10 @@ template <typename T, int N> struct Instance {
             hipLaunchKernelGGL((k_cols<T, N, WC, NTR, false, PHI>), dim3(ColTiles<N, WC>::ALL), dim3(NTR), 0,
                                s, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw,
                                (const DevState *)a.st);
+        } else if constexpr (PAR) {
+            hipLaunchKernelGGL((k_fwd_plane<T, N, SP, NTP, false, 3, true>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s,
+                               (const T *)a.e, a.ph, (Cx<T> *)a.spec2, (Cx<T> *)a.nyq2,
+                               (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st, ch0(lc_sel));
         } else {
             hipLaunchKernelGGL((k_fwd_plane<T, N, SP, NTP, PHI>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s,
                                (const T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq,
@@ -100,6 +107,9 @@ template <typename T, int N> struct Instance {
         }
     }
     static void fwd(const LaunchArgs &a, hipStream_t s, int lc_sel) { fwd_t<false>(a, s, lc_sel); }
+    static void fwd_par(const LaunchArgs &a, hipStream_t s, int lc_sel) {
+        if constexpr (PARF) fwd_t<false, true>(a, s, lc_sel);
+    }
     static void fwd_phi(const LaunchArgs &a, hipStream_t s) { fwd_t<true>(a, s, -1); }
     static void zeq(const LaunchArgs &a, hipStream_t s) {
         hipLaunchKernelGGL((k_zeq<T, N, W, NTZ>), dim3(3 * ZTiles<N, W>::PER_LC), dim3(NTZ), 0, s,
@@ -107,17 +117,25 @@ template <typename T, int N> struct Instance {
                            (const DevState *)a.st, a.peq);
     }
     // red_nper > 0: one extra workgroup reduces the previous inverse pass
-    template <int WV> static void zgreen_w(const LaunchArgs &a, hipStream_t s, int red_nper, int lc_sel) {
+    template <int WV, bool PAR = false>
+    static void zgreen_w(const LaunchArgs &a, hipStream_t s, int red_nper, int lc_sel) {
         const int lcs = FIVE || lc_sel < 0 ? 3 : 1;
-        hipLaunchKernelGGL((k_zgreen<T, N, WV, NTZ>), dim3(lcs * ZTiles<N, WV>::PER_LC + (red_nper > 0 ? 1 : 0)),
-                           dim3(NTZ), 0, s, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, a.st,
-                           (const double *)a.part, red_nper, a.hist, lcs == 3 ? 0 : lc_sel);
+        hipLaunchKernelGGL((k_zgreen<T, N, WV, NTZ, PAR>),
+                           dim3(lcs * ZTiles<N, WV>::PER_LC + (red_nper > 0 ? 1 : 0)), dim3(NTZ), 0, s,
+                           (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, a.st,
+                           (const double *)a.part, red_nper, a.hist, lcs == 3 ? 0 : lc_sel,
+                           (const Cx<T> *)a.spec2, (const Cx<T> *)a.nyq2);
     }
     static void zgreen(const LaunchArgs &a, hipStream_t s, int red_nper, int lc_sel) {
         zgreen_w<W>(a, s, red_nper, lc_sel);
     }
     static void zgreen_alt(const LaunchArgs &a, hipStream_t s, int red_nper, int lc_sel) {
         zgreen_w<W2>(a, s, red_nper, lc_sel);
+    }
+    // the parity layout's z pass (tiles of rows ky and ky + N/2 read the same
+    // two parity rows)
+    static void zgreen_par(const LaunchArgs &a, hipStream_t s, int red_nper, int lc_sel) {
+        if constexpr (PARF) zgreen_w<W, true>(a, s, red_nper, lc_sel);
     }
     template <bool AL> static void inv_t(const LaunchArgs &a, hipStream_t s, int lc_sel) {
         if constexpr (FIVE) {
@@ -129,7 +147,7 @@ template <typename T, int N> struct Instance {
         } else {
             hipLaunchKernelGGL((k_inv_plane<T, N, SP, NTP, false, AL>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s,
                                (T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
-                               (const DevState *)a.st, a.part, ch0(lc_sel));
+                               (const DevState *)a.st, a.part, ch0(lc_sel), (Cx<T> *)nullptr, (Cx<T> *)nullptr);
         }
     }
     static void inv(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_t<false>(a, s, lc_sel); }
@@ -144,7 +162,11 @@ template <typename T, int N> struct Instance {
         if constexpr (FUSED) {
             hipLaunchKernelGGL((k_inv_plane<T, N, 1, NTP, true, AL>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s,
                                (T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
-                               (const DevState *)a.st, a.part, ch0(lc_sel));
+                               (const DevState *)a.st, a.part, ch0(lc_sel), (Cx<T> *)nullptr, (Cx<T> *)nullptr);
+        } else if constexpr (PARF) {
+            hipLaunchKernelGGL((k_inv_plane<T, N, 2, NTP, true, AL>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s,
+                               (T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
+                               (const DevState *)a.st, a.part, ch0(lc_sel), (Cx<T> *)a.spec2, (Cx<T> *)a.nyq2);
         }
     }
     static void inv_fwd(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_fwd_t<false>(a, s, lc_sel); }
@@ -184,8 +206,8 @@ template <typename T, int N> struct Instance {
             {FIVE ? NTR : NTP, NTZ, FIVE ? NTR : NTP},
             {9.0 * M * rb + spec_b + extra, 2.0 * spec_b, spec_b + 2.0 * 9.0 * M * rb + extra},
             ZTiles<N, W>::PER_LC,
-            FUSED ? 2.0 * spec_b + 2.0 * 9.0 * M * rb : 0.0,
-            FUSED ? &inv_fwd : nullptr,
+            (FUSED || PARF) ? 2.0 * spec_b + 2.0 * 9.0 * M * rb : 0.0,
+            (FUSED || PARF) ? &inv_fwd : nullptr,
             &fwd,
             &fwd_phi,
             &zeq,
@@ -196,12 +218,14 @@ template <typename T, int N> struct Instance {
             &init,
             &from_f64,
             &to_f64,
-            FUSED ? &inv_fwd_al : nullptr,
+            (FUSED || PARF) ? &inv_fwd_al : nullptr,
             &inv_al,
             &to_tau,
             3,
             &launch_reduce,
             (double)M,
+            PARF ? &fwd_par : nullptr,
+            PARF ? &zgreen_par : nullptr,
         };
         return &o;
     }

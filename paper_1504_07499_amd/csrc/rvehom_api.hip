@@ -76,6 +76,9 @@ WsLayout ws_layout(const SolverOps *o) {
     L.st = take(sizeof(DevState));
     L.hist = take((size_t)o->nc * kHistCap * sizeof(double));
     L.peq = take((size_t)o->nc * (o->eq_tiles > 0 ? o->eq_tiles : 1) * 2 * sizeof(double));
+    // split planes: the parity-layout spectrum the fused pass writes
+    L.spec2 = o->zgreen_par ? take(o->spec_elems * 2 * rb) : 0;
+    L.nyq2 = o->zgreen_par ? take(o->nyq_elems * 2 * rb) : 0;
     L.total = off;
     return L;
 }
@@ -236,6 +239,8 @@ LaunchArgs Solver::args(const uint8_t *d_phase) const {
     a.part = (double *)(b + layout.part);
     a.hist = (double *)(b + layout.hist);
     a.peq = (double *)(b + layout.peq);
+    a.spec2 = layout.spec2 ? b + layout.spec2 : nullptr;
+    a.nyq2 = layout.nyq2 ? b + layout.nyq2 : nullptr;
     return a;
 }
 
@@ -659,7 +664,7 @@ int Solver::start(const uint8_t *d_phase, const SolverOpts &o, hipStream_t s) {
     if (!eq_check && (o.lc_mask == 1 || o.lc_mask == 2 || o.lc_mask == 4)) lc_sel = o.lc_mask == 1 ? 0 : (o.lc_mask == 2 ? 1 : 2);
     if (fused) {
         // the first forward pass; every later one is fused into the inverse pass
-        ops->fwd(a, s, lc_sel);
+        (ops->fwd_par ? ops->fwd_par : ops->fwd)(a, s, lc_sel);
         HIP_CHECK(hipGetLastError());
     }
     return RVE_OK;
@@ -682,7 +687,10 @@ int Solver::launch_iteration(const LaunchArgs &a, hipStream_t s, int mask, hipEv
         if (timed) HIP_CHECK(hipEventRecordWithFlags(ev[used], s, hipEventRecordExternal));
         switch (kk) {
         case 0: ops->fwd(a, s, lc_sel); break;
-        case 1: (zvar ? ops->zgreen_alt : ops->zgreen)(a, s, red_in_z ? ops->nper : 0, lc_sel); break;
+        case 1:
+            (fused && ops->zgreen_par ? ops->zgreen_par : zvar ? ops->zgreen_alt : ops->zgreen)(
+                a, s, red_in_z ? ops->nper : 0, lc_sel);
+            break;
         case 2: (fused ? (al ? ops->inv_fwd_al : ops->inv_fwd) : (al ? ops->inv_al : ops->inv))(a, s, lc_sel); break;
         default: ops->reduce(a, ops->nper, s); break;
         }

@@ -22,7 +22,7 @@ constexpr size_t kTwStageOffset = 4096;  // twiddle staging inside the pinned bl
 constexpr size_t kPinnedBytes = 4096 + 8192;  // N <= 512 complex doubles of twiddles
 
 struct WsLayout {
-    size_t e, spec, nyq, tw, part, prm, st, hist, peq, total;
+    size_t e, spec, nyq, tw, part, prm, st, hist, peq, spec2, nyq2, total;  // spec2 / nyq2: 0 if unused
 };
 WsLayout ws_layout(const SolverOps *o);
 

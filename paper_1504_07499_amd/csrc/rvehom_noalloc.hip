@@ -95,6 +95,8 @@ struct NaSolve {
         a.part = (double *)(ws + L.part);
         a.hist = (double *)(ws + L.hist);
         a.peq = (double *)(ws + L.peq);
+        a.spec2 = L.spec2 ? ws + L.spec2 : nullptr;
+        a.nyq2 = L.nyq2 ? ws + L.nyq2 : nullptr;
     }
 
     int run(const double k[3], double tol, const SolverOpts &o, hipStream_t s, int zvar, DevState &hs) {
@@ -135,8 +137,8 @@ struct NaSolve {
         NA_CHECK(hipGetLastError());
         const bool fused = ops->inv_fwd != nullptr && !(o.path_flags & PF_NO_FUSED);
         const bool merge = ops->nc == 3 && !(o.path_flags & PF_NO_MERGE);
-        auto zg = zvar ? ops->zgreen_alt : ops->zgreen;
-        if (fused) ops->fwd(a, s, -1);
+        auto zg = fused && ops->zgreen_par ? ops->zgreen_par : zvar ? ops->zgreen_alt : ops->zgreen;
+        if (fused) (ops->fwd_par ? ops->fwd_par : ops->fwd)(a, s, -1);
         int issued = 0, flag = 0;
         while (issued < o.max_iter) {
             const int count = std::min(kChunk, o.max_iter - issued);

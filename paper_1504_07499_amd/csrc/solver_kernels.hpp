@@ -398,6 +398,49 @@ __device__ __forceinline__ void al_update(T *a, const T *c, unsigned p, T dk0, T
     }
 }
 
+// Forward transform of a split plane after its x transform (S = 2, rows of
+// pitch N/2 + 1 in LDS, the N/2 rows of parity h).  Without PAR the rows
+// are the parity-h combinations of a decimation in frequency (rows y and
+// y + N/2 summed, or subtracted and turned by w_N^y), and the length-N/2 y
+// transform gives the output rows ky = 2 m + h of the spectrum.  With PAR
+// the rows are the samples y = 2 m + h themselves (decimation in time): the
+// y transform gives E (h = 0) or O (h = 1) with X[ky] = E[ky] + w_N^ky O[ky]
+// and X[ky + N/2] = E[ky] - w_N^ky O[ky] for ky < N/2, and this pass stores
+// E and w_N^ky O as rows ky and N/2 + ky of a parity-layout spectrum that
+// the z pass combines.
+template <typename T, int N, int NT, bool PAR>
+__device__ __forceinline__ void split_fwd_tail(Cx<T> *plane, const Cx<T> *__restrict__ tw, Cx<T> *sb, Cx<T> *nb,
+                                               int h, int tid) {
+    constexpr int H = N / 2, RS = H + 1, ROWS = N / 2;
+    for (int idx = tid; idx < ROWS * (H / 2 + 1); idx += NT) {
+        const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
+        if (!PAR && h) r2c_unpack<T, N, true>(plane + y * RS, k, tw, tw[y]);  // w_N^y of the parity split
+        else r2c_unpack<T, N, false>(plane + y * RS, k, tw, Cx<T>{(T)1, (T)0});
+    }
+    __syncthreads();
+    // y: complex FFT of length N/2 down the N/2 + 1 columns
+    fft_lds<T, ROWS, false, RS, RS, NT, N, SeqStride<1>>(plane, tw, tid);
+    if constexpr (PAR) {
+        for (int idx = tid; idx < ROWS * H / 2; idx += NT) {
+            const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
+            Cx<T> v0 = plane[m * RS + kx], v1 = plane[m * RS + kx + 1];
+            if (h) {
+                const Cx<T> w = tw[m];
+                v0 = v0 * w;
+                v1 = v1 * w;
+            }
+            gstore2<T>(sb + (size_t)(h * H + m) * H + kx, v0, v1);
+        }
+        for (int m = tid; m < ROWS; m += NT) nb[h * H + m] = h ? plane[m * RS + H] * tw[m] : plane[m * RS + H];
+    } else {
+        for (int idx = tid; idx < ROWS * H / 2; idx += NT) {
+            const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
+            gstore2<T>(sb + (size_t)(2 * m + h) * H + kx, plane[m * RS + kx], plane[m * RS + kx + 1]);
+        }
+        for (int m = tid; m < ROWS; m += NT) nb[2 * m + h] = plane[m * RS + H];
+    }
+}
+
 // Waves per SIMD asked of the plane kernels: as many workgroups per CU as
 // their LDS plane allows, capped at 4 waves per SIMD (at most 128 VGPRs).
 template <typename T, int N, int S, int NT> constexpr int plane_min_waves() {
@@ -428,7 +471,7 @@ template <int N, int S> __device__ __forceinline__ void plane_of_block(int b, in
 // P1: tau = (k - k0) e fused into the load; 2D R2C of the (ch, z) plane.
 // With PHI the same pass transforms the flux k e for the equilibrium check.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int S, int NT, bool PHI = false, int NC = 3>
+template <typename T, int N, int S, int NT, bool PHI = false, int NC = 3, bool PAR = false>
 __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_plane(const T *__restrict__ e, const uint8_t *__restrict__ ph,
                                                   Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
                                                   const Cx<T> *__restrict__ twg,
@@ -442,6 +485,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
     constexpr int PMX = (S == 1 && sizeof(T) == 4) ? kPairElem : kPairNone;
     constexpr int PMY = (S == 1 && sizeof(T) == 4) ? kPairSeq : kPairNone;
     static_assert(N % 4 == 0 && (S == 1 || S == 2), "plane kernel needs N % 4 == 0");
+    static_assert(!PAR || (S == 2 && !PHI), "the parity layout is a split-plane forward pass");
     __shared__ Cx<T> plane[ROWS * RS];
     const int tid = threadIdx.x;
     int ch, z, h;
@@ -460,10 +504,11 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
     const T *eb = e + (size_t)ch * N * NN + (size_t)z * NN;
     const uint8_t *pb = ph + (size_t)z * NN;
 
-    // load rows (S = 2: combine rows y and y + N/2 with sign (-1)^h); each
-    // batch issues all of its global loads before the first use
+    // load rows (S = 2: combine rows y and y + N/2 with sign (-1)^h; PAR:
+    // the rows 2 y + h of parity h alone); each batch issues all of its
+    // global loads before the first use
     constexpr int TOTL = ROWS * N / V, PERL = (TOTL + NT - 1) / NT;
-    constexpr int BL = S == 2 ? 4 : 8;
+    constexpr int BL = (S == 2 && !PAR) ? 4 : 8;
 #pragma unroll
     for (int i0 = 0; i0 < PERL; i0 += BL) {
         T a[BL][V], b[BL][V];
@@ -473,9 +518,10 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
             const int idx = tid + (i0 + i) * NT;
             if (i0 + i < PERL && (TOTL % NT == 0 || idx < TOTL)) {
                 const int y = idx / (N / V), x = (idx - y * (N / V)) * V;
-                vload<T>(eb + y * N + x, a[i]);
-                p[i] = pload<V>(pb + y * N + x);
-                if constexpr (S == 2) {
+                const int ys = PAR ? 2 * y + h : y;
+                vload<T>(eb + ys * N + x, a[i]);
+                p[i] = pload<V>(pb + ys * N + x);
+                if constexpr (S == 2 && !PAR) {
                     vload<T>(eb + (y + ROWS) * N + x, b[i]);
                     q[i] = pload<V>(pb + (y + ROWS) * N + x);
                 }
@@ -490,7 +536,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
 #pragma unroll
                 for (int j = 0; j < V; ++j) {
                     u[j] = pick<T>(ph_at(p[i], j), d0, d1, d2) * a[i][j] - tm;
-                    if constexpr (S == 2) {
+                    if constexpr (S == 2 && !PAR) {
                         const T t2 = pick<T>(ph_at(q[i], j), d0, d1, d2) * b[i][j] - tm;
                         u[j] = h ? u[j] - t2 : u[j] + t2;
                     }
@@ -521,19 +567,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
         fft_stages<T, ROWS, 0, num_stages(ROWS) - 1, false, H, RS, NT, N, SeqStride<1>, PMY>(plane, tw, tid);
         y_last_stage_store<T, N, NT, RS>(plane, tw, sb, nb, tid);
     } else {
-        for (int idx = tid; idx < ROWS * (H / 2 + 1); idx += NT) {
-            const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
-            if (h) r2c_unpack<T, N, true>(plane + y * RS, k, tw, tw[y]);  // w_N^y of the parity split
-            else r2c_unpack<T, N, false>(plane + y * RS, k, tw, Cx<T>{(T)1, (T)0});
-        }
-        __syncthreads();
-        // y: complex FFT of length N/S down the N/2 + 1 columns
-        fft_lds<T, ROWS, false, RS, RS, NT, N, SeqStride<1>>(plane, tw, tid);
-        for (int idx = tid; idx < ROWS * H / 2; idx += NT) {
-            const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
-            gstore2<T>(sb + (size_t)(S * m + h) * H + kx, plane[m * RS + kx], plane[m * RS + kx + 1]);
-        }
-        for (int m = tid; m < ROWS; m += NT) nb[S * m + h] = plane[m * RS + H];
+        split_fwd_tail<T, N, NT, PAR>(plane, tw, sb, nb, h, tid);
     }
 }
 
@@ -560,6 +594,26 @@ template <typename T, int N, int W> __device__ __forceinline__ int ztile_of(int 
                           (TL::H / W) % 2 == 0;
     if constexpr (PAIR) return (t & ~15) | ((t & 7) << 1) | ((t >> 3) & 1);
     return t;
+}
+
+// Tile of the t-th workgroup of a load case when the z pass reads a
+// parity-layout spectrum: the tiles of rows ky and ky + N/2 read the same
+// two rows ky mod N/2 and N/2 + ky mod N/2, and neighbouring kx chunks share
+// 128-byte lines, so the four tiles {ky, ky + N/2} x {chunks 2j, 2j + 1}
+// get workgroups 8 apart (one XCD, whose L2 then serves the repeated reads).
+// The same for the Nyquist column's tiles of W rows.
+template <int N, int W> __device__ __forceinline__ int ztile_par(int b) {
+    using TL = ZTiles<N, W>;
+    constexpr int H = N / 2, C = H / W;
+    static_assert(C % 2 == 0 && TL::MAIN % 32 == 0 && TL::NYQ % 32 == 0, "parity tiles come in groups of 32");
+    const bool main = b < TL::MAIN;
+    const int bb = main ? b : b - TL::MAIN;
+    const int lane = bb & 7, q = (bb >> 3) & 3, quad = (bb >> 5) * 8 + lane;
+    if (main) {
+        const int kyp = quad / (C / 2), j = quad - kyp * (C / 2);
+        return (kyp + (q >> 1) * H) * C + 2 * j + (q & 1);
+    }
+    return TL::MAIN + 2 * quad + (q & 1) + (q >> 1) * C;
 }
 
 // First stage of a length-N transform (forward, or inverse with INV) of a
@@ -645,12 +699,17 @@ template <typename T, int N, int W> constexpr int zpass_min_waves() {
     return (sizeof(T) == 4 && N == 128 && W == 8) ? 6 : 1;
 }
 
-template <typename T, int N, int W, int NT>
+// PAR: the forward spectrum arrives in the parity layout of split_fwd_tail
+// (specB, nyqB): the tile of row ky reads rows ky mod N/2 and N/2 + ky mod N/2
+// and forms X[ky] = B[ky mod N/2] +- B[N/2 + ky mod N/2] (+ for ky < N/2) as
+// it loads; the result goes to spec / nyq in the plain layout.
+template <typename T, int N, int W, int NT, bool PAR = false>
 __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
                                                const Cx<T> *__restrict__ twg,
                                                const DevParams *__restrict__ prm,
                                                DevState *__restrict__ st, const double *__restrict__ part,
-                                               int red_nper, double *__restrict__ hist, int lc0) {
+                                               int red_nper, double *__restrict__ hist, int lc0,
+                                               const Cx<T> *__restrict__ specB, const Cx<T> *__restrict__ nyqB) {
     using TL = ZTiles<N, W>;
     constexpr int H = N / 2, NW = N * W;
     static_assert(H % W == 0 && N % W == 0 && W % 2 == 0, "tile width must be even and divide N/2");
@@ -662,7 +721,10 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
         return;
     }
     const int bt = blockIdx.x - (red_nper > 0 ? 1 : 0);
-    const int lt = bt / TL::PER_LC, t = ztile_of<T, N, W>(bt - lt * TL::PER_LC);
+    const int lt = bt / TL::PER_LC;
+    int t;
+    if constexpr (PAR) t = ztile_par<N, W>(bt - lt * TL::PER_LC);
+    else t = ztile_of<T, N, W>(bt - lt * TL::PER_LC);
     const int lc = lc0 + lt;  // the grid covers load cases lc0 .. (all three, or one)
     // the freeze flag, read once for the workgroup (the merged reduction of
     // workgroup 0 may write it meanwhile) so that every wave takes the same
@@ -673,7 +735,8 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
     __syncthreads();
     if (s_done) return;
     Cx<T> *base;
-    size_t cstride, zstride;
+    const Cx<T> *pbase = nullptr;  // PAR: row ky mod N/2 of the parity layout
+    size_t cstride, zstride, poff = 0;  // poff: from that row to row N/2 + ky mod N/2
     int kx0, ky0, dkx, dky;  // kx(w) = kx0 + dkx*w, ky(w) = ky0 + dky*w
     if (t < TL::MAIN) {
         const int ky = t / (H / W);
@@ -682,6 +745,8 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
         dkx = 1;
         dky = 0;
         base = spec + (size_t)(3 * lc) * N * N * H + (size_t)ky * H + kx0;
+        if constexpr (PAR) pbase = specB + (size_t)(3 * lc) * N * N * H + (size_t)(ky % H) * H + kx0;
+        poff = (size_t)H * H;
         cstride = (size_t)N * N * H;
         zstride = (size_t)N * H;
     } else {
@@ -690,6 +755,8 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
         dkx = 0;
         dky = 1;
         base = nyq + (size_t)(3 * lc) * N * N + ky0;
+        if constexpr (PAR) pbase = nyqB + (size_t)(3 * lc) * N * N + (ky0 % H);
+        poff = H;
         cstride = (size_t)N * N;
         zstride = N;
     }
@@ -697,10 +764,37 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
     // z stage, and the last inverse stage straight back (except FP32 from
     // 256^3 on, measured faster with the pencils staged through LDS)
     constexpr bool DIRECT = zpass_direct<T, N>();
+    static_assert(!PAR || !DIRECT, "the parity layout is read through the staged load");
     constexpr int NP = 3 * NW / 2, PERP = (NP + NT - 1) / NT;
     ZFirstStage<T, N, W, NT> z0;
     if constexpr (DIRECT) {
         z0.load(base, cstride, zstride, tid);
+    } else if constexpr (PAR) {
+        // X = E +- w O from the two parity rows, in batches of loads
+        const bool upper = ky0 >= H;  // a tile's rows lie in one half (W divides N/2)
+        constexpr int BP = 6;
+#pragma unroll
+        for (int i0 = 0; i0 < PERP; i0 += BP) {
+            Cx<T> va[BP], vb[BP], ua[BP], ub[BP];
+#pragma unroll
+            for (int i = 0; i < BP; ++i) {
+                const int idx = tid + (i0 + i) * NT;
+                if (i0 + i < PERP && (NP % NT == 0 || idx < NP)) {
+                    const int e0 = 2 * idx, c = e0 / NW, r = e0 - c * NW, zz = r / W, w = r - zz * W;
+                    const Cx<T> *src = pbase + c * cstride + zz * zstride + w;
+                    gload2<T>(src, va[i], vb[i]);
+                    gload2<T>(src + poff, ua[i], ub[i]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < BP; ++i) {
+                const int idx = tid + (i0 + i) * NT;
+                if (i0 + i < PERP && (NP % NT == 0 || idx < NP)) {
+                    buf[2 * idx] = upper ? va[i] - ua[i] : va[i] + ua[i];
+                    buf[2 * idx + 1] = upper ? vb[i] - ub[i] : vb[i] + ub[i];
+                }
+            }
+        }
     } else {
         // two complex values per access, every load of a thread in flight
         // before the first LDS store
@@ -958,12 +1052,15 @@ template <typename T, int N, int NT, int RS> struct YFirstStage {
 // ---------------------------------------------------------------------------
 // P3: 2D C2R of the (ch, z) plane, then steps 6-7 and the flux, fused.
 // ---------------------------------------------------------------------------
-// FWD (S = 1 only): the same workgroup then forms tau = (k - k0) e+ of the
-// next iteration from the updated values it holds, runs the forward 2D R2C
-// of pass 1 and overwrites this plane's spectrum -- one read and one write
-// of the plane per iteration instead of two of each.  The mean subtracted
-// from tau is the previous iteration's (any constant is exact: the mean
-// mode of tau is replaced by E).
+// FWD: the same workgroup then forms tau = (k - k0) e+ of the next
+// iteration from the updated values it holds, runs the forward 2D R2C of
+// pass 1 and writes the plane's next spectrum -- one read and one write of
+// the plane per iteration instead of two of each.  Whole planes (S = 1)
+// overwrite their spectrum in place; split planes (S = 2), each of whose
+// two workgroups reads the whole plane's spectrum, write the parity layout
+// of split_fwd_tail to specB / nyqB instead.  The mean subtracted from tau
+// is the previous iteration's (any constant is exact: the mean mode of tau
+// is replaced by E).
 template <typename T, int N, int S, int NT, bool FWD = false, bool AL = false, int NC = 3>
 __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_plane(T *__restrict__ e, const uint8_t *__restrict__ ph,
                                                   Cx<T> *__restrict__ spec,
@@ -971,8 +1068,8 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
                                                   const Cx<T> *__restrict__ twg,
                                                   const DevParams *__restrict__ prm,
                                                   const DevState *__restrict__ st,
-                                                  double *__restrict__ part, int ch0) {
-    static_assert(!FWD || S == 1, "the fused inverse/forward pass needs a whole plane");
+                                                  double *__restrict__ part, int ch0,
+                                                  Cx<T> *__restrict__ specB, Cx<T> *__restrict__ nyqB) {
     // row pitch: even for whole planes (16-byte pair accesses, paired FFT
     // stages), N/2 + 1 for split planes
     constexpr int H = N / 2, RS = (S == 1) ? H + 2 : H + 1, ROWS = N / S, V = VecOf<T>::V, NN = N * N;
@@ -1152,11 +1249,16 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
         __syncthreads();
         const Cx<T> *twf = opaque_ptr(tw);
         fft_lds<T, H, false, ROWS, 1, NT, N, SeqStride<RS>, PMX>(plane, twf, tid);
-        r2c_unpack_rows<T, N, ROWS, NT, true, RS>(plane, twf, tid);
-        __syncthreads();
-        fft_stages<T, ROWS, 0, num_stages(ROWS) - 1, false, H, RS, NT, N, SeqStride<1>, PMY>(plane, twf, tid);
-        y_last_stage_store<T, N, NT, RS>(plane, twf, spec + ((size_t)ch * N + z) * N * H,
-                                         nyq + ((size_t)ch * N + z) * N, tid);
+        if constexpr (S == 1) {
+            r2c_unpack_rows<T, N, ROWS, NT, true, RS>(plane, twf, tid);
+            __syncthreads();
+            fft_stages<T, ROWS, 0, num_stages(ROWS) - 1, false, H, RS, NT, N, SeqStride<1>, PMY>(plane, twf, tid);
+            y_last_stage_store<T, N, NT, RS>(plane, twf, spec + ((size_t)ch * N + z) * N * H,
+                                             nyq + ((size_t)ch * N + z) * N, tid);
+        } else {
+            split_fwd_tail<T, N, NT, true>(plane, twf, specB + ((size_t)ch * N + z) * N * H,
+                                           nyqB + ((size_t)ch * N + z) * N, h, tid);
+        }
     }
 }
 

@@ -23,6 +23,8 @@ struct LaunchArgs {
     double *part;
     double *hist;
     double *peq;  // equilibrium-error partials [3][eq_tiles][2]
+    void *spec2;  // split planes: the parity-layout forward spectrum (or nullptr)
+    void *nyq2;
 };
 
 struct SolverOps {
@@ -67,6 +69,11 @@ struct SolverOps {
     // the phase image (1 byte per voxel), counted once per launch of the
     // passes that read it (P1, P3, fused) whatever the number of load cases
     double phase_bytes;
+    // split planes with the fused pass: the first forward pass and the z
+    // pass of the parity layout (the fused pass writes it to spec2 / nyq2,
+    // the z pass combines it into spec / nyq); nullptr elsewhere
+    void (*fwd_par)(const LaunchArgs &, hipStream_t, int lc_sel);
+    void (*zgreen_par)(const LaunchArgs &, hipStream_t, int red_nper, int lc_sel);
 };
 
 const SolverOps *ops_f32(int n);

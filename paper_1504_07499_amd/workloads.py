@@ -220,15 +220,19 @@ def run_512(n_spheres=100, f=0.30, layer=0.2, seed=7, k=K_BENCH, tol=1e-6):
 
 
 # ---------------------------------------------------------------------- solve
-def run_solve(n=256, n_spheres=100, f=0.40, layer=0.2, seed=3, k=K_BENCH, tol=1e-6, precision=0, repeat=2):
+def run_solve(n=256, n_spheres=100, f=0.40, layer=0.2, seed=3, k=K_BENCH, tol=1e-6, precision=0, repeat=2,
+              max_iter=0, path_flags=0, fp32_refine=True):
     """Repeated solves of one seeded RVE (RSA spheres, Sec. 2): iterations,
-    time and tensor of each, e.g. to profile one grid size."""
+    time and tensor of each, e.g. to profile one grid size (path_flags: the
+    PATH_* measurement switches, e.g. 8 for one stream)."""
     rows = []
     with rve_create(n, n_spheres, f, layer, seed) as h:
         for _ in range(repeat):
-            r = homogenize(h, k, tol, precision=precision)
-            row = {"n": n, "n_spheres": n_spheres, "f": f, "layer": layer, "seed": seed,
+            r = homogenize(h, k, tol, precision=precision, max_iter=max_iter, path_flags=path_flags,
+                           fp32_refine=fp32_refine)
+            row = {"n": n, "n_spheres": n_spheres, "f": f, "layer": layer, "seed": seed, "k": list(k),
                    "precision": "fp32" if precision == 0 else "fp64", "iters": r.iters.tolist(),
+                   "refine_iters": r.refine_iters.tolist(),
                    "status": r.lc_status.tolist(), "ms": r.solve_ms,
                    "voxel_iters_per_s_per_lc": n ** 3 * int(r.iters.sum()) / (r.solve_ms * 1e-3),
                    "K": r.K.tolist()}
@@ -349,6 +353,11 @@ def main(argv=None):
     so.add_argument("--seed", type=int, default=3)
     so.add_argument("--precision", type=int, default=0)
     so.add_argument("--repeat", type=int, default=2)
+    so.add_argument("--kc", type=float, default=K_BENCH[2], help="coating conductivity (matrix 0.2, inclusion 0.3)")
+    so.add_argument("--tol", type=float, default=1e-6)
+    so.add_argument("--max-iter", type=int, default=0)
+    so.add_argument("--path-flags", type=int, default=0)
+    so.add_argument("--no-refine", action="store_true")
     sub.add_parser("fibers")
     sub.add_parser("elastic")
     sc = sub.add_parser("schemes")
@@ -370,7 +379,9 @@ def main(argv=None):
     elif a.cmd == "run512":
         run_512()
     elif a.cmd == "solve":
-        run_solve(a.n, a.spheres, a.f, a.layer, a.seed, precision=a.precision, repeat=a.repeat)
+        run_solve(a.n, a.spheres, a.f, a.layer, a.seed, k=(K_BENCH[0], K_BENCH[1], a.kc), tol=a.tol,
+                  precision=a.precision, repeat=a.repeat, max_iter=a.max_iter, path_flags=a.path_flags,
+                  fp32_refine=not a.no_refine)
     elif a.cmd == "fibers":
         run_fibers()
     elif a.cmd == "elastic":

@@ -86,19 +86,40 @@ def test_fp32_converged_vs_oracle(n):
     assert tensor_err(g.K, ref.K) <= 1e-4
 
 
-def test_split_plane_path_256_fp32():
+@pytest.mark.parametrize("flags", [0, rh.PATH_NO_FUSED])
+def test_split_plane_path_256_fp32(flags):
     """256^3 in FP32 uses the row-parity split of the xy-plane (two
-    workgroups per plane): two iterations of load case e_1 on an RSA RVE,
-    field compared voxel by voxel with the oracle."""
-    print("\n[case] split plane 256 fp32", flush=True)
+    workgroups per plane), by default with the fused inverse + forward pass
+    writing the parity-layout spectrum that the z pass combines, else with
+    separate passes: two iterations of load case e_1 on an RSA RVE, field
+    compared voxel by voxel with the oracle."""
+    print(f"\n[case] split plane 256 fp32 flags={flags}", flush=True)
     ph, _, _ = geom.generate(256, 100, 0.3, 0.2, 3)
     ref = oracle.homogenize(ph, K_PAPER_CFG, tol=0.0, max_iter=2, want_field=True, lc_mask=1)
     with rh.rve_create_from_phases(ph) as r:
         g = rh.homogenize(r, K_PAPER_CFG, 0.0, max_iter=2, precision=0, lc_mask=1,
-                          want_field=True)
+                          want_field=True, path_flags=flags)
     assert field_err(g.field[0], ref.field[0]) <= 3e-5
     assert np.array_equal(g.field[1:], ref.field[1:])
     assert tensor_err(g.K[:, 0], ref.K[:, 0]) <= 3e-5
+
+
+def test_split_plane_fused_equals_separate_256():
+    """A full 256^3 FP32 solve (three load cases, every tile of the parity
+    layout and both spectrum buffers in use): the fused pass and the
+    separate passes reach the same tensor (FP32 rounding apart) in the same
+    number of iterations give or take the last one."""
+    print("\n[case] split plane fused vs separate 256", flush=True)
+    k = [0.2, 0.3, 20.0]
+    with rh.rve_create(256, 100, 0.4, 0.1, 3) as r:
+        a = rh.homogenize(r, k, 1e-5, precision=0, fp32_refine=False)
+        b = rh.homogenize(r, k, 1e-5, precision=0, fp32_refine=False, path_flags=rh.PATH_NO_FUSED)
+        c = rh.homogenize(r, k, 1e-5, precision=1)
+    print(list(a.iters), list(b.iters), list(c.iters), tensor_err(a.K, b.K), tensor_err(a.K, c.K), flush=True)
+    assert a.status == rh.RVE_OK and b.status == rh.RVE_OK
+    assert np.all(np.abs(a.iters - b.iters) <= 1)
+    assert tensor_err(a.K, b.K) <= 2e-6
+    assert tensor_err(a.K, c.K) <= 1e-5
 
 
 @pytest.mark.parametrize("precision", [0, 1])
