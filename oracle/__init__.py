@@ -53,7 +53,7 @@ def _load():
     lib.orc_homogenize.argtypes = [
         ctypes.c_int, ctypes.POINTER(ctypes.c_uint8), dp, ctypes.c_double,
         ctypes.c_int, ctypes.c_int, dp, dp, ip, ip, dp, dp, dp, ctypes.c_int, dp,
-        ctypes.c_int, ctypes.c_int]
+        ctypes.c_int, ctypes.c_int, ctypes.c_double]
     lib.orc_homogenize.restype = ctypes.c_int
     lib.orc_homogenize_elastic.argtypes = [
         ctypes.c_int, ctypes.POINTER(ctypes.c_uint8), dp, ctypes.c_int, dp, ctypes.c_double,
@@ -131,8 +131,10 @@ class OracleResult:
 def homogenize(phases: np.ndarray, k_phases, tol: float = 1e-6, max_iter: int = 10000,
                eq_check: bool = False, init_field: np.ndarray | None = None,
                want_field: bool = False, hist_cap: int | None = None,
-               lc_mask: int = 7, scheme: int = 0) -> OracleResult:
-    """Run the Algorithm (Sec. 3) for E = e_1, e_2, e_3 on a phase image."""
+               lc_mask: int = 7, scheme: int = 0, alpha: float = 2.0) -> OracleResult:
+    """Run the Algorithm (Sec. 3) for E = e_1, e_2, e_3 on a phase image.
+    scheme: 0 accelerated, 1 basic, 2 augmented Lagrangian, 3 dual,
+    4 polarization (relaxation alpha)."""
     lib = _load()
     ph = np.ascontiguousarray(phases, dtype=np.uint8)
     n = ph.shape[0]
@@ -156,7 +158,8 @@ def homogenize(phases: np.ndarray, k_phases, tol: float = 1e-6, max_iter: int = 
         int(max_iter), int(bool(eq_check)), _dp(init) if init is not None else None,
         _dp(K), iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
         status.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(res), _dp(eq),
-        _dp(hist), hc, _dp(field) if field is not None else None, int(lc_mask), int(scheme))
+        _dp(hist), hc, _dp(field) if field is not None else None, int(lc_mask), int(scheme),
+        float(alpha))
     if rc != 0:
         raise ValueError(f"oracle rejected its arguments (code {rc})")
     h = hist.reshape(3, hc)

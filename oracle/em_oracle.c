@@ -55,6 +55,11 @@
  *  R5  <phi> (after the algorithm) is taken on the field updated in the
  *      stopping iteration; column j of L_hom is <k e> for E = e_j.
  *  R6  The three load cases E = e_1, e_2, e_3 are solved independently.
+ *  R7  Dual scheme on an even grid: a field is divergence free at a mode when
+ *      xi . v = 0 for every sign of its Nyquist components (so the averaged
+ *      operator is a projection; the average of I - xi xi^T / |xi|^2 over the
+ *      signs, the complement of R3's symbol, is not, and leaves eigenvalues
+ *      near 0 that the dual iteration barely contracts).
  */
 #include <complex.h>
 #include <math.h>
@@ -248,6 +253,55 @@ void orc_green_apply(int n, double k0, const double E[3],
     }
 }
 
+/* R7 (dual scheme): the divergence-free fields at a mode are those whose
+ * divergence xi . v vanishes for every sign of the Nyquist components of xi:
+ * their Nyquist components are 0 and the others are orthogonal to the
+ * non-Nyquist part xi_A of xi.  P is the orthogonal projection on them:
+ * 0 on the Nyquist components, I - xi_A xi_A^T / |xi_A|^2 on the others (I if
+ * xi_A = 0).  Without Nyquist components this is I - xi xi^T / |xi|^2. */
+static void dual_projection(int n, const int kk[3], double P[3][3])
+{
+    double xa[3];
+    int nyq[3];
+    double a2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        nyq[d] = is_nyquist(kk[d], n);
+        xa[d] = nyq[d] ? 0.0 : wavenumber(kk[d], n);
+        a2 += xa[d] * xa[d];
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            if (nyq[i] || nyq[j]) {
+                P[i][j] = 0.0;
+                continue;
+            }
+            P[i][j] = (i == j ? 1.0 : 0.0) - (a2 > 0.0 ? xa[i] * xa[j] / a2 : 0.0);
+        }
+}
+
+/* The dual Green operator of the reference medium k0 on three full spectra
+ * in place: k0 P(xi) z^(xi) for xi != 0 (P of R7), k0 z^(0) at xi = 0. */
+static void dual_green_apply(int n, double k0, cplx *z)
+{
+    size_t M = (size_t)n * n * n;
+    #pragma omp parallel for schedule(static)
+    for (long idx = 0; idx < (long)M; ++idx) {
+        cplx zv[3] = {z[idx], z[M + idx], z[2 * M + idx]};
+        if (idx == 0) {
+            for (int i = 0; i < 3; ++i) z[i * M + idx] = k0 * zv[i];
+            continue;
+        }
+        int kk[3] = {(int)(idx % n), (int)((idx / n) % n), (int)(idx / ((long)n * n))};
+        double P[3][3];
+        dual_projection(n, kk, P);
+        for (int i = 0; i < 3; ++i) {
+            cplx acc = 0;
+            for (int j = 0; j < 3; ++j) acc += P[i][j] * zv[j];
+            z[i * M + idx] = k0 * acc;
+        }
+    }
+}
+
 /* eps_eq of R4: phi^ = FFT(k e) for one load case; returns
  * sqrt(sum_{xi != 0} |xi . phi^|^2 / |xi|^2) / |phi^(0)|. */
 static double equilibrium_error(int n, const double *kvox, const double *e3,
@@ -352,12 +406,42 @@ void orc_set_threads(int t)
  *             and lam = k e).  eq_check is not used.
  *             Parity unpinned against the cited work (its equations are not
  *             in the paper); pinned by the same closed forms as the others.
+ *             3 = the dual scheme named in Sec. 3: the flux phi is the
+ *             iterate, kept divergence free, with the dual Green operator of
+ *             the reference medium k0 (in Fourier space k0 P for xi != 0, P
+ *             the projection on divergence-free fields of R7, and k0 at
+ *             xi = 0):
+ *                 e    = phi / k
+ *                 phi+ = phi - Delta0 * (e - E)
+ *             from phi = k0 E, with k0 = 2 min k max k / (min k + max k)
+ *             (the mean of the extreme resistivities, the dual of the basic
+ *             scheme's choice).  At the fixed point e - E is a gradient of
+ *             zero mean, so e is compatible with <e> = E and phi = k e is
+ *             divergence free.  The residual is sqrt(<|phi+ - phi|^2>) / k0,
+ *             the distance of e from the compatible fields of mean E; the
+ *             tensor column is <phi+>; out_field returns phi.  init_field
+ *             and eq_check are refused.
+ *             4 = the polarization scheme named in Sec. 3, read as the
+ *             relaxed iteration on the polarization tau = (k - k0) e with
+ *             the compatible field of step 4 (k0 of Sec. 5):
+ *                 c    = E - Gamma0 tau
+ *                 g    = ((k - k0) c - tau) / (k + k0)
+ *                 tau+ = tau + alpha k0 g,   0 < alpha <= 2
+ *             from tau = (k - k0) E (or the start field); residual
+ *             sqrt(<g^2>), tensor column <tau+ + k0 c>.  alpha = 1 gives the
+ *             augmented-Lagrangian scheme (2), alpha = 2 the iterates of the
+ *             accelerated scheme (tau = (k - k0) e of scheme 0).  out_field
+ *             returns tau; eq_check is refused.
+ *             Both: parity unpinned against the cited works (their equations
+ *             are not in the paper); pinned by closed forms, the dense
+ *             solves of the discrete problem and their rate bounds.
+ *  alpha      relaxation of scheme 4 (ignored by the others)
  */
 int orc_homogenize(int n, const uint8_t *phase, const double kph[3], double tol,
                    int max_iter, int eq_check, const double *init_field,
                    double *K, int *iters, int *status, double *final_res,
                    double *eps_eq, double *hist, int hist_cap, double *out_field,
-                   int lc_mask, int scheme)
+                   int lc_mask, int scheme, double alpha)
 {
     if (n < 1 || max_iter < 1 || !(tol >= 0.0) || !phase || !kph || !K) return ORC_ERR_ARG;
     for (int p = 0; p < 3; ++p)
@@ -366,12 +450,18 @@ int orc_homogenize(int n, const uint8_t *phase, const double kph[3], double tol,
     for (size_t v = 0; v < M; ++v)
         if (phase[v] > 2) return ORC_ERR_ARG;
 
-    if (scheme < 0 || scheme > 2) return ORC_ERR_ARG;
+    if (scheme < 0 || scheme > 4) return ORC_ERR_ARG;
+    if (scheme >= 3 && eq_check) return ORC_ERR_ARG;
+    if (scheme == 3 && init_field) return ORC_ERR_ARG;
+    if (scheme == 4 && !(alpha > 0.0 && alpha <= 2.0)) return ORC_ERR_ARG;
     /* Sec. 5: L0 = -sqrt(min k * max k) I over the three given k (R1);
-     * the basic scheme takes the arithmetic mean of the extremes. */
+     * the basic scheme takes the arithmetic mean of the extremes, the dual
+     * scheme their harmonic mean. */
     double kmin = fmin(kph[0], fmin(kph[1], kph[2]));
     double kmax = fmax(kph[0], fmax(kph[1], kph[2]));
-    double k0 = scheme == 1 ? 0.5 * (kmin + kmax) : sqrt(kmin * kmax);
+    double k0 = scheme == 1 ? 0.5 * (kmin + kmax)
+              : scheme == 3 ? 2.0 * kmin * kmax / (kmin + kmax)
+                            : sqrt(kmin * kmax);
 
     double *kvox = malloc(sizeof(double) * M);
     double *e = malloc(sizeof(double) * 3 * M);
@@ -450,7 +540,76 @@ int orc_homogenize(int n, const uint8_t *phase, const double kph[3], double tol,
                 break;
             }
         }
-        while (scheme != 2 && it < max_iter) {
+        if (scheme == 3) /* the flux iterate starts at k0 E (divergence free) */
+            for (int i = 0; i < 3; ++i)
+                for (size_t v = 0; v < M; ++v) e[i * M + v] = k0 * E[i];
+        while (scheme == 3 && it < max_iter) {
+            /* e = phi / k; the dual Green operator on e - E */
+            for (int i = 0; i < 3; ++i)
+                for (size_t v = 0; v < M; ++v) t[i * M + v] = e[i * M + v] / kvox[v] - E[i];
+            for (int i = 0; i < 3; ++i) orc_fft3(n, (double *)(t + i * M), -1);
+            dual_green_apply(n, k0, t);
+            for (int i = 0; i < 3; ++i) orc_fft3(n, (double *)(t + i * M), +1);
+            /* phi+ = phi - Delta0 * (e - E); residual and mean flux */
+            double r2 = 0.0;
+            for (int i = 0; i < 3; ++i) {
+                double sF = 0.0;
+                for (size_t v = 0; v < M; ++v) {
+                    double d = creal(t[i * M + v]) / (double)M;
+                    r2 += d * d;
+                    e[i * M + v] -= d;
+                    sF += e[i * M + v];
+                }
+                F[i] = sF / (double)M;
+            }
+            r = sqrt(r2 / (double)M) / k0;
+            if (hist && it < hist_cap) hist[lc * hist_cap + it] = r;
+            ++it;
+            if (!isfinite(r)) {
+                st = ORC_ERR_NONFINITE;
+                break;
+            }
+            if (r < tol) {
+                st = ORC_OK;
+                break;
+            }
+        }
+        if (scheme == 4) /* the polarization of the start field */
+            for (int i = 0; i < 3; ++i)
+                for (size_t v = 0; v < M; ++v) e[i * M + v] *= kvox[v] - k0;
+        while (scheme == 4 && it < max_iter) {
+            /* c = E - Gamma0 tau (steps 3-5 on tau) */
+            for (int i = 0; i < 3; ++i)
+                for (size_t v = 0; v < M; ++v) t[i * M + v] = e[i * M + v];
+            for (int i = 0; i < 3; ++i) orc_fft3(n, (double *)(t + i * M), -1);
+            orc_green_apply(n, k0, E, (const double *)t, (double *)t);
+            for (int i = 0; i < 3; ++i) orc_fft3(n, (double *)(t + i * M), +1);
+            /* g = ((k - k0) c - tau) / (k + k0); tau+ = tau + alpha k0 g */
+            double r2 = 0.0;
+            for (int i = 0; i < 3; ++i) {
+                double sF = 0.0;
+                for (size_t v = 0; v < M; ++v) {
+                    double c = creal(t[i * M + v]) / (double)M;
+                    double g = ((kvox[v] - k0) * c - e[i * M + v]) / (kvox[v] + k0);
+                    r2 += g * g;
+                    e[i * M + v] += alpha * k0 * g;
+                    sF += e[i * M + v] + k0 * c;
+                }
+                F[i] = sF / (double)M;
+            }
+            r = sqrt(r2 / (double)M);
+            if (hist && it < hist_cap) hist[lc * hist_cap + it] = r;
+            ++it;
+            if (!isfinite(r)) {
+                st = ORC_ERR_NONFINITE;
+                break;
+            }
+            if (r < tol) {
+                st = ORC_OK;
+                break;
+            }
+        }
+        while (scheme <= 1 && it < max_iter) {
             eq = -1.0;
             /* step 2: tau = (k - k0) e */
             for (int i = 0; i < 3; ++i)
@@ -510,7 +669,8 @@ int orc_homogenize(int n, const uint8_t *phase, const double kph[3], double tol,
         if (iters) iters[lc] = it;
         if (status) status[lc] = st;
         if (final_res) final_res[lc] = r;
-        if (eps_eq) eps_eq[lc] = (eq >= 0.0) ? eq : equilibrium_error(n, kvox, e, t);
+        if (eps_eq)
+            eps_eq[lc] = (eq >= 0.0) ? eq : (scheme >= 3 ? -1.0 : equilibrium_error(n, kvox, e, t));
         if (out_field && scheme == 2)
             for (int i = 0; i < 3; ++i)
                 for (size_t v = 0; v < M; ++v)

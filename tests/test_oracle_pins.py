@@ -86,14 +86,14 @@ def test_green_reproduces_compatible_fields(n):
 
 
 # ----------------------------------------------------------- exact solutions
-@pytest.mark.parametrize("scheme", [0, 2])
+@pytest.mark.parametrize("scheme", [0, 2, 4])
 @pytest.mark.parametrize("n", [8, 9])
 @pytest.mark.parametrize("kv", [1.0, 2.0, 400.0])
 def test_homogeneous_medium_exact(n, kv, scheme):
     """One phase everywhere (k = k0 or not): K = k I after one iteration
-    (accelerated and augmented-Lagrangian schemes)."""
+    (accelerated, augmented-Lagrangian and polarization schemes)."""
     ph = np.zeros((n, n, n), np.uint8)
-    r = oracle.homogenize(ph, [kv, 0.2, 400.0], tol=1e-12, scheme=scheme)
+    r = oracle.homogenize(ph, [kv, 0.2, 400.0], tol=1e-12, scheme=scheme, alpha=1.5)
     np.testing.assert_allclose(r.K, kv * np.eye(3), atol=1e-13 * kv)
     assert list(r.iters) == [1, 1, 1]
     assert np.all(r.final_residual <= 1e-14)
@@ -114,14 +114,16 @@ def _laminate(n, axis, widths, phases):
     (12, [5, 1, 6], [2, 0, 1]),      # a one-voxel layer
 ])
 @pytest.mark.parametrize("axis", [0, 1, 2])
-@pytest.mark.parametrize("scheme", [0, 2])
+@pytest.mark.parametrize("scheme", [0, 2, 3, 4])
 def test_laminate_exact(n, widths, phases, axis, scheme):
     """Layered laminate: normal entry = harmonic mean, tangential entries =
-    arithmetic mean, off-diagonals 0 (series / parallel result)."""
-    k = K_PAPER
+    arithmetic mean, off-diagonals 0 (series / parallel result).  The dual
+    scheme, which contracts at the basic scheme's slow rate, runs at a
+    lower contrast."""
+    k = K_PAPER if scheme != 3 else np.array([1.0, 0.2, 4.0])
     ph = _laminate(n, axis, widths, phases)
     kv = k[ph]
-    r = oracle.homogenize(ph, k, tol=1e-13, max_iter=20000, scheme=scheme)
+    r = oracle.homogenize(ph, k, tol=1e-13, max_iter=200000, scheme=scheme, alpha=1.5)
     assert np.all(r.status == 0)
     Kex = np.eye(3) * kv.mean()
     Kex[axis, axis] = 1.0 / (1.0 / kv).mean()
@@ -150,15 +152,17 @@ def _spectral_direct_solve(ph, k):
 
 
 @pytest.mark.parametrize("n,seed", [(5, 1), (7, 2)])
-@pytest.mark.parametrize("scheme", [0, 2])
+@pytest.mark.parametrize("scheme", [0, 2, 3, 4])
 def test_odd_grid_matches_direct_spectral_solve(n, seed, scheme):
     """For odd N the fixed point of the Algorithm is the Galerkin spectral
     solution of div(k (E + grad u)) = 0, independent of k0 (and the same for
-    the augmented-Lagrangian scheme, whose fixed point has d = e, lam = k e)."""
+    the augmented-Lagrangian scheme, whose fixed point has d = e, lam = k e,
+    for the polarization scheme, tau = (k - k0) e, and for the dual scheme,
+    whose flux stays divergence free and whose e - E becomes a gradient)."""
     ph = geom.random_phases(n, seed)
     k = np.array([1.0, 0.2, 40.0])
     ref = _spectral_direct_solve(ph, k)
-    r = oracle.homogenize(ph, k, tol=1e-13, max_iter=20000, scheme=scheme)
+    r = oracle.homogenize(ph, k, tol=1e-13, max_iter=20000, scheme=scheme, alpha=1.5)
     assert np.all(r.status == 0)
     np.testing.assert_allclose(r.K, ref, atol=1e-10 * np.abs(ref).max())
 
@@ -178,7 +182,7 @@ def _sign_averaged_symbol(n, kk):
     return acc / cnt
 
 
-@pytest.mark.parametrize("scheme", [0, 2])
+@pytest.mark.parametrize("scheme", [0, 2, 4])
 def test_even_grid_fixed_point_dense_solve(scheme):
     """Even N: the converged iterate solves the discrete Lippmann-Schwinger
     equation e = E - (1/k0) IDFT(G DFT((k - k0) e)), assembled with dense DFT
@@ -204,7 +208,7 @@ def test_even_grid_fixed_point_dense_solve(scheme):
         for j in range(3):
             blk = np.real(F3i @ (G[i, j][:, None] * F3)) * (kv - k0)[None, :] / k0
             L[i * M:(i + 1) * M, j * M:(j + 1) * M] += blk
-    r = oracle.homogenize(ph, k, tol=1e-14, max_iter=50000, scheme=scheme)
+    r = oracle.homogenize(ph, k, tol=1e-14, max_iter=50000, scheme=scheme, alpha=1.5)
     for j in range(3):
         rhs = np.zeros(3 * M)
         rhs[j * M:(j + 1) * M] = 1.0
@@ -365,7 +369,9 @@ def test_first_iteration_residual_and_equilibrium_laminate(n, widths, phases, ax
 
 
 def test_residual_normalised_by_load():
-    """eps_comp is relative to |E|: scaling the field by s scales nothing."""
+    """From the start field s E (layers normal to y, load case e_y) the
+    compatible field is E - s (k - <k>) / k0 e_y, so the first residual is
+    sqrt((1 - s)^2 + s^2 var(k) / k0^2)."""
     n, axis = 8, 1
     ph = _laminate(n, axis, [3, 5], [0, 2])
     k = K_PAPER
@@ -376,8 +382,6 @@ def test_residual_normalised_by_load():
         for j in range(3):
             init[j, j] = s
         r = oracle.homogenize(ph, k, tol=0.0, max_iter=1, init_field=init)
-        # from e = s E the compatible field is E - s (k - <k>)/k0 e_a + (1 - s)... :
-        # c = E - Gamma((k - k0) s E), whose fluctuation is s times that from E
         c_minus_e = np.sqrt(((1.0 - s) ** 2) + (s * kv.std() / k0) ** 2)
         assert r.history[axis][0] == pytest.approx(c_minus_e, rel=1e-12)
 
@@ -559,3 +563,107 @@ def test_dilute_coated_fiber_maxwell_garnett():
     assert abs(res.K[0, 0] - res.K[1, 1]) <= 1e-10 * res.K[0, 0]
     assert abs(res.K[0, 0] - kmg) / kmg <= 0.015
     assert abs((res.K[0, 0] - 1.0) - (kmg - 1.0)) <= 0.12 * (kmg - 1.0)
+
+
+# ------------------------------------------------ dual and polarization schemes
+@pytest.mark.parametrize("kv", [0.5, 3.0, 8.0])
+def test_dual_scheme_homogeneous_closed_form(kv):
+    """One phase k: from phi = k0 E the dual update is phi+ = phi - k0 (phi/k - E),
+    so phi_n = k + (k0 - k) q^n with q = 1 - k0/k and the residual of
+    iteration n (counted from 0) is |q|^(n+1); K -> k I."""
+    n = 8
+    ph = np.zeros((n, n, n), np.uint8)
+    kk = np.array([kv, 0.2, 4.0])
+    k0 = 2 * kk.min() * kk.max() / (kk.min() + kk.max())
+    q = 1.0 - k0 / kv
+    r = oracle.homogenize(ph, kk, tol=1e-12, max_iter=5000, scheme=3)
+    assert np.all(r.status == 0)
+    np.testing.assert_allclose(r.K, kv * np.eye(3), rtol=1e-11, atol=1e-13)
+    for j in range(3):
+        h = r.history[j]
+        ref = np.abs(q) ** (np.arange(len(h)) + 1)
+        np.testing.assert_allclose(h, ref, rtol=1e-9, atol=1e-15)
+
+
+def test_dual_scheme_rate_at_most_basic_bound():
+    """The dual scheme contracts at most like the basic scheme,
+    (c - 1) / (c + 1) per iteration with its k0."""
+    ph = geom.random_phases(8, 21)
+    k = np.array([1.0, 0.2, 40.0])
+    r = oracle.homogenize(ph, k, tol=1e-12, max_iter=20000, scheme=3)
+    c = k.max() / k.min()
+    rho = (c - 1) / (c + 1)
+    h = r.history[0]
+    m = 40
+    assert (h[-1] / h[-1 - m]) ** (1.0 / m) <= rho * 1.01
+
+
+def test_dual_scheme_converges_to_primal_on_even_grids():
+    """Even N: at modes with a Nyquist component and another nonzero one the
+    dual scheme's divergence-free projection differs from the primal
+    symbol, so the two discrete solutions differ there; the gap vanishes as
+    the grid is refined (same spheres at 12^3 and 24^3), the dual tensor
+    stays within the Wiener bounds, and the dual iteration keeps the basic
+    scheme's rate (its operator is a projection at every mode)."""
+    k = np.array([1.0, 0.2, 4.0])
+    c = k.max() / k.min()
+    rho = (c - 1) / (c + 1)
+    gaps = []
+    for n in (12, 24):
+        ph, _, _ = geom.generate(n, 4, 0.25, 0.3, 6)
+        a = oracle.homogenize(ph, k, tol=1e-10, max_iter=20000, scheme=0)
+        d = oracle.homogenize(ph, k, tol=1e-10, max_iter=20000, scheme=3)
+        assert np.all(d.status == 0)
+        gaps.append(np.abs(a.K - d.K).max() / np.abs(a.K).max())
+        kv = k[ph]
+        lam = np.linalg.eigvalsh(0.5 * (d.K + d.K.T))
+        assert lam.min() >= 1.0 / (1.0 / kv).mean() - 1e-9 and lam.max() <= kv.mean() + 1e-9
+        assert max(d.iters) <= np.log(1e-10) / np.log(rho) + 10
+    assert gaps[1] < gaps[0] / 3 and gaps[1] < 5e-3
+
+
+@pytest.mark.parametrize("alpha", [0.5, 1.5])
+def test_polarization_rate_bound(alpha):
+    """The relaxed iteration averages the accelerated one with the identity:
+    its contraction is at most |1 - alpha/2| + (alpha/2) rho_EM."""
+    ph = geom.random_phases(8, 21)
+    k = np.array([1.0, 0.2, 40.0])
+    r = oracle.homogenize(ph, k, tol=1e-12, max_iter=20000, scheme=4, alpha=alpha)
+    c = k.max() / k.min()
+    rho = (np.sqrt(c) - 1) / (np.sqrt(c) + 1)
+    bound = abs(1 - alpha / 2) + alpha / 2 * rho
+    h = r.history[0]
+    m = 20
+    assert (h[-1] / h[-1 - m]) ** (1.0 / m) <= bound * 1.02
+
+
+def test_polarization_special_cases():
+    """alpha = 1 is the augmented-Lagrangian scheme (same residuals and
+    tensor); with alpha = 2 the polarization iterates are (k - k0) times
+    the accelerated scheme's iterates."""
+    ph = geom.random_phases(8, 7)
+    k = np.array([1.0, 0.2, 40.0])
+    al = oracle.homogenize(ph, k, tol=1e-9, max_iter=5000, scheme=2)
+    p1 = oracle.homogenize(ph, k, tol=1e-9, max_iter=5000, scheme=4, alpha=1.0)
+    assert list(al.iters) == list(p1.iters)
+    np.testing.assert_allclose(p1.K, al.K, rtol=1e-12, atol=1e-14)
+    for j in range(3):
+        np.testing.assert_allclose(p1.history[j], al.history[j], rtol=1e-8, atol=1e-15)
+    em = oracle.homogenize(ph, k, tol=0.0, max_iter=6, want_field=True, scheme=0)
+    p2 = oracle.homogenize(ph, k, tol=0.0, max_iter=6, want_field=True, scheme=4, alpha=2.0)
+    k0 = np.sqrt(k.min() * k.max())
+    for j in range(3):
+        np.testing.assert_allclose(p2.field[j], (k[ph] - k0)[None] * em.field[j], rtol=1e-10, atol=1e-11)
+
+
+def test_dual_and_polarization_rejections():
+    ph = geom.random_phases(8, 2)
+    init = np.ones((3, 3, 8, 8, 8))
+    with pytest.raises(ValueError):
+        oracle.homogenize(ph, K_CFG, scheme=3, init_field=init)
+    with pytest.raises(ValueError):
+        oracle.homogenize(ph, K_CFG, scheme=3, eq_check=True)
+    with pytest.raises(ValueError):
+        oracle.homogenize(ph, K_CFG, scheme=4, alpha=2.5)
+    with pytest.raises(ValueError):
+        oracle.homogenize(ph, K_CFG, scheme=5)
