@@ -87,7 +87,22 @@ typedef struct {
                                lam+ = lam + k0 (e+ - d), from d = e = E (or init_field)
                                and lam = k d; final_residual is sqrt<|e+ - d+|^2>, K the
                                flux <k d+>, out_field the state lam - k0 d; with
-                               equilibrium_check: RVE_ERR_ARG */
+                               equilibrium_check: RVE_ERR_ARG;
+                               3 = dual scheme named in Sec. 3: the flux phi is the
+                               iterate, phi+ = phi - Delta0 (phi / k - E) from phi = k0 E,
+                               k0 = 2 min k max k / (min k + max k), Delta0 the dual Green
+                               operator k0 P (P: projection on divergence-free fields; on an
+                               even grid those whose divergence vanishes for every sign of
+                               the Nyquist components) and k0 at xi = 0; final_residual is
+                               sqrt<|phi+ - phi|^2> / k0, K the flux <phi+>, out_field phi;
+                               with init_field or equilibrium_check: RVE_ERR_ARG;
+                               4 = polarization scheme named in Sec. 3 (k0 of Sec. 5): on
+                               tau = (k - k0) e, c = E - Gamma0 tau,
+                               g = ((k - k0) c - tau) / (k + k0), tau+ = tau + alpha k0 g;
+                               final_residual sqrt<g^2>, K <tau+ + k0 c>, out_field tau;
+                               alpha = 1 is scheme 2, and with alpha = 2 the iterates are
+                               (k - k0) times those of scheme 0; with equilibrium_check:
+                               RVE_ERR_ARG.  eps_eq is -1 for schemes 3 and 4 */
     int fp32_refine;        /* FP32 only.  0 = default: a load case that the FP32 rounding
                                floor stops above tol (RVE_STALLED by the floor or stall rule)
                                is continued in FP64 from its FP32 field, with the same scheme
@@ -103,6 +118,7 @@ typedef struct {
                                of inside the next z pass, 8 = one stream for the three load
                                cases instead of three concurrent chains, 16 / 32 = the default /
                                the alternative z-pass tile width instead of the autotuned one */
+    double alpha;           /* scheme 4: the relaxation alpha in (0, 2]; 0 = default 2 */
 } rve_opts;
 
 typedef struct {

@@ -50,7 +50,8 @@ class _Opts(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("init_field", ctypes.POINTER(ctypes.c_double)),
                 ("out_field", ctypes.POINTER(ctypes.c_double)), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("scheme", ctypes.c_int),
-                ("fp32_refine", ctypes.c_int), ("path_flags", ctypes.c_int)]
+                ("fp32_refine", ctypes.c_int), ("path_flags", ctypes.c_int),
+                ("alpha", ctypes.c_double)]
 
 
 class _Result(ctypes.Structure):
@@ -273,7 +274,7 @@ def _to_result(rc: int, r: _Result, hist=None, hist_cap=0, fld=None) -> HomResul
                      history, fld, np.array(r.refine_iters[:], dtype=np.int64))
 
 
-SCHEMES = {"accelerated": 0, "basic": 1, "augmented_lagrangian": 2}
+SCHEMES = {"accelerated": 0, "basic": 1, "augmented_lagrangian": 2, "dual": 3, "polarization": 4}
 
 # measurement switches of rve_opts.path_flags (results do not depend on them)
 PATH_NO_GRAPHS, PATH_NO_FUSED, PATH_NO_MERGE, PATH_NO_CHAINS = 1, 2, 4, 8
@@ -282,8 +283,9 @@ PATH_ZTILE_DEFAULT, PATH_ZTILE_ALT = 16, 32
 
 def _opts(max_iter=0, precision=0, equilibrium_check=False, stall_window=-1, lc_mask=7,
           timing=False, stream=None, init_field=None, out_field=None, workspace=None,
-          scheme="accelerated", fp32_refine=True, path_flags=0):
+          scheme="accelerated", fp32_refine=True, path_flags=0, alpha=0.0):
     o = _Opts()
+    o.alpha = float(alpha)
     o.fp32_refine = 0 if fp32_refine else -1
     o.path_flags = int(path_flags)
     o.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
@@ -308,14 +310,17 @@ def homogenize(rve: RVE, k_phases, tol: float = 1e-6, *, max_iter: int = 0, prec
                equilibrium_check: bool = False, stall_window: int = -1, lc_mask: int = 7,
                timing=False, stream=None, init_field: np.ndarray | None = None,
                want_field: bool = False, workspace=None, hist_cap: int = 0,
-               scheme="accelerated", fp32_refine: bool = True, path_flags: int = 0) -> HomResult:
+               scheme="accelerated", fp32_refine: bool = True, path_flags: int = 0,
+               alpha: float = 0.0) -> HomResult:
     """The Algorithm of Sec. 3 for E = e_1, e_2, e_3 on the device.
 
     scheme: "accelerated" (Eyre-Milton, the paper's choice), "basic" (the
     basic scheme the paper names as an alternative: e+ = c, k0 = mean of the
     extreme conductivities) or "augmented_lagrangian" (also named there; k0
     of Sec. 5; the field returned is its state lam - k0 d; no equilibrium
-    check).  fp32_refine (precision 0): continue load cases stopped by the
+    check), "dual" (the flux-based dual scheme, k0 the harmonic mean of the
+    extremes; no start field) or "polarization" (relaxation alpha in (0, 2],
+    0 = 2).  fp32_refine (precision 0): continue load cases stopped by the
     FP32 rounding floor in FP64 until eps_comp < tol.  path_flags: the
     PATH_* measurement switches."""
     k = np.ascontiguousarray(k_phases, dtype=np.float64)
@@ -329,7 +334,7 @@ def homogenize(rve: RVE, k_phases, tol: float = 1e-6, *, max_iter: int = 0, prec
             raise RveError(RVE_ERR_ARG, "init_field must hold 9 n^3 values")
     fld = np.zeros((3, 3, n, n, n)) if want_field else None
     o = _opts(max_iter, precision, equilibrium_check, stall_window, lc_mask, timing, stream, init,
-              fld, workspace, scheme, fp32_refine, path_flags)
+              fld, workspace, scheme, fp32_refine, path_flags, alpha)
     res = _Result()
     hist = np.zeros(3 * hist_cap) if hist_cap > 0 else None
     rc = _check(_lib.homogenize(rve.handle, _dptr(k), float(tol), ctypes.byref(o), ctypes.byref(res),
@@ -339,14 +344,15 @@ def homogenize(rve: RVE, k_phases, tol: float = 1e-6, *, max_iter: int = 0, prec
 
 def homogenize_no_alloc(rve: RVE, k_phases, tol: float = 1e-6, *, max_iter: int = 0, precision: int = 0,
                         stall_window: int = -1, lc_mask: int = 7, stream=None, hist_cap: int = 0,
-                        scheme="accelerated", fp32_refine: bool = True, path_flags: int = 0) -> HomResult:
+                        scheme="accelerated", fp32_refine: bool = True, path_flags: int = 0,
+                        alpha: float = 0.0) -> HomResult:
     """homogenize without any allocation: the library's fixed device array
     (64 MiB per GPU) holds the workspaces, so N <= 64."""
     k = np.ascontiguousarray(k_phases, dtype=np.float64)
     if k.shape != (3,):
         raise RveError(RVE_ERR_ARG, "k_phases must hold 3 conductivities")
     o = _opts(max_iter, precision, False, stall_window, lc_mask, False, stream, None, None, None, scheme,
-              fp32_refine, path_flags)
+              fp32_refine, path_flags, alpha)
     res = _Result()
     hist = np.zeros(3 * hist_cap) if hist_cap > 0 else None
     rc = _check(_lib.homogenize_no_alloc(rve.handle, _dptr(k), float(tol), ctypes.byref(o), ctypes.byref(res),
@@ -433,13 +439,14 @@ def rve_supported_n_elastic(precision: int = 0) -> list:
 
 def homogenize_batch(rves, k_phases, tol, *, max_iter: int = 0, precision: int = 0,
                      stall_window: int = -1, equilibrium_check: bool = False,
-                     scheme="accelerated", fp32_refine: bool = True) -> list:
+                     scheme="accelerated", fp32_refine: bool = True, alpha: float = 0.0) -> list:
     """Several RVEs (mixed N) solved concurrently; returns one HomResult each."""
     count = len(rves)
     k = np.ascontiguousarray(np.broadcast_to(np.asarray(k_phases, dtype=np.float64), (count, 3)))
     t = np.ascontiguousarray(np.broadcast_to(np.asarray(tol, dtype=np.float64), (count,)))
     hs = (ctypes.c_void_p * max(count, 1))(*[r.handle.value for r in rves])
-    o = _opts(max_iter, precision, equilibrium_check, stall_window, scheme=scheme, fp32_refine=fp32_refine)
+    o = _opts(max_iter, precision, equilibrium_check, stall_window, scheme=scheme, fp32_refine=fp32_refine,
+              alpha=alpha)
     out = (_Result * max(count, 1))()
     rc = _check(_lib.homogenize_batch(count, hs, _dptr(k), _dptr(t), ctypes.byref(o), out))
     res = []

@@ -210,13 +210,13 @@ template <typename T, int N> struct ElasticInstance {
                            (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st);
     }
     static void inv(const LaunchArgs &a, hipStream_t s, int) {
-        hipLaunchKernelGGL((k_inv_plane<T, N, S, NTP, false, false, NC>), dim3(PGRID), dim3(NTP), 0, s, (T *)a.e,
+        hipLaunchKernelGGL((k_inv_plane<T, N, S, NTP, false, 0, NC>), dim3(PGRID), dim3(NTP), 0, s, (T *)a.e,
                            a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st,
                            a.part, 0, (Cx<T> *)nullptr, (Cx<T> *)nullptr);
     }
     static void inv_fwd(const LaunchArgs &a, hipStream_t s, int) {
         if constexpr (FUSED) {
-            hipLaunchKernelGGL((k_inv_plane<T, N, 1, NTP, true, false, NC>), dim3(PGRID), dim3(NTP), 0, s, (T *)a.e,
+            hipLaunchKernelGGL((k_inv_plane<T, N, 1, NTP, true, 0, NC>), dim3(PGRID), dim3(NTP), 0, s, (T *)a.e,
                                a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
                                (const DevState *)a.st, a.part, 0, (Cx<T> *)nullptr, (Cx<T> *)nullptr);
         }
@@ -271,6 +271,8 @@ template <typename T, int N> struct ElasticInstance {
             NC,
             &reduce,
             (double)M,
+            nullptr,
+            nullptr,
             nullptr,
             nullptr,
         };

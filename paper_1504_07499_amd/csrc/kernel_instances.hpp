@@ -137,7 +137,7 @@ template <typename T, int N> struct Instance {
     static void zgreen_par(const LaunchArgs &a, hipStream_t s, int red_nper, int lc_sel) {
         if constexpr (PARF) zgreen_w<W, true>(a, s, red_nper, lc_sel);
     }
-    template <bool AL> static void inv_t(const LaunchArgs &a, hipStream_t s, int lc_sel) {
+    template <int AL> static void inv_t(const LaunchArgs &a, hipStream_t s, int lc_sel) {
         if constexpr (FIVE) {
             hipLaunchKernelGGL((k_cols<T, N, WC, NTR, true>), dim3(ColTiles<N, WC>::ALL), dim3(NTR), 0, s,
                                (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, (const DevState *)a.st);
@@ -150,15 +150,16 @@ template <typename T, int N> struct Instance {
                                (const DevState *)a.st, a.part, ch0(lc_sel), (Cx<T> *)nullptr, (Cx<T> *)nullptr);
         }
     }
-    static void inv(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_t<false>(a, s, lc_sel); }
-    static void inv_al(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_t<true>(a, s, lc_sel); }
+    static void inv(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_t<0>(a, s, lc_sel); }
+    static void inv_al(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_t<1>(a, s, lc_sel); }
+    static void inv_dual(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_t<2>(a, s, lc_sel); }
     static void to_tau(const LaunchArgs &a, size_t M, hipStream_t s) {
         hipLaunchKernelGGL((k_to_tau<T>), dim3(1024), dim3(256), 0, s, (T *)a.e, a.ph, M, a.prm);
     }
     // fused inverse + next forward pass (whole planes in LDS; not where the
     // fused kernel would spill registers heavily: FP32 96^3)
     static constexpr bool FUSED = !FIVE && S == 1 && !(sizeof(T) == 4 && N == 96);
-    template <bool AL> static void inv_fwd_t(const LaunchArgs &a, hipStream_t s, int lc_sel) {
+    template <int AL> static void inv_fwd_t(const LaunchArgs &a, hipStream_t s, int lc_sel) {
         if constexpr (FUSED) {
             hipLaunchKernelGGL((k_inv_plane<T, N, 1, NTP, true, AL>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s,
                                (T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
@@ -169,8 +170,9 @@ template <typename T, int N> struct Instance {
                                (const DevState *)a.st, a.part, ch0(lc_sel), (Cx<T> *)a.spec2, (Cx<T> *)a.nyq2);
         }
     }
-    static void inv_fwd(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_fwd_t<false>(a, s, lc_sel); }
-    static void inv_fwd_al(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_fwd_t<true>(a, s, lc_sel); }
+    static void inv_fwd(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_fwd_t<0>(a, s, lc_sel); }
+    static void inv_fwd_al(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_fwd_t<1>(a, s, lc_sel); }
+    static void inv_fwd_dual(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_fwd_t<2>(a, s, lc_sel); }
     static void init(const LaunchArgs &a, size_t M, hipStream_t s) {
         hipLaunchKernelGGL((k_init<T>), dim3(1024), dim3(256), 0, s, (T *)a.e, M, a.prm, a.st);
     }
@@ -226,6 +228,8 @@ template <typename T, int N> struct Instance {
             (double)M,
             PARF ? &fwd_par : nullptr,
             PARF ? &zgreen_par : nullptr,
+            (FUSED || PARF) ? &inv_fwd_dual : nullptr,
+            &inv_dual,
         };
         return &o;
     }

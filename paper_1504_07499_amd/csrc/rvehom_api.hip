@@ -455,26 +455,37 @@ void fill_params(DevParams &p, const double k[3], double tol, int n, const Solve
     const double kmin = std::min(k[0], std::min(k[1], k[2]));
     const double kmax = std::max(k[0], std::max(k[1], k[2]));
     // Sec. 5: L0 = -sqrt(min k * max k) I over the three given conductivities
-    // (accelerated and augmented-Lagrangian schemes); the basic scheme uses
-    // the arithmetic mean.
-    const double k0 = o.scheme == 1 ? 0.5 * (kmin + kmax) : std::sqrt(kmin * kmax);
+    // (accelerated, augmented-Lagrangian and polarization schemes); the basic
+    // scheme uses the arithmetic mean of the extremes, the dual scheme their
+    // harmonic mean.
+    const double k0 = o.scheme == 1   ? 0.5 * (kmin + kmax)
+                      : o.scheme == 3 ? 2.0 * kmin * kmax / (kmin + kmax)
+                                      : std::sqrt(kmin * kmax);
     const double M = (double)n * n * n;
     for (int i = 0; i < 3; ++i) {
         p.k[i] = k[i];
-        p.dk[i] = k[i] - k0;
-        // step 7: e+ = e + 2 k0 / (k + k0) (c - e); basic scheme: e+ = c
-        p.w[i] = o.scheme == 1 ? 1.0 : 2.0 * k0 / (k[i] + k0);
+        // step 2: tau = (k - k0) e; dual scheme: tau = -k0^2 phi / k, which
+        // the z pass turns into k0 G*(phi / k)
+        p.dk[i] = o.scheme == 3 ? -k0 * k0 / k[i] : k[i] - k0;
+        // step 7: e+ = e + 2 k0 / (k + k0) (c - e); basic scheme: e+ = c;
+        // dual scheme: phi+ = (1 - k0 / k) phi + c + k0 E
+        p.w[i] = o.scheme == 1 ? 1.0 : o.scheme == 3 ? 1.0 - k0 / k[i] : 2.0 * k0 / (k[i] + k0);
         p.gam[i] = 1.0 / (k[i] + k0);
     }
     p.k0 = k0;
     p.scheme = o.scheme;
+    p.relax = o.scheme == 4 ? o.alpha : 1.0;
     // contraction bound of the scheme at contrast c = kmax / kmin: Eyre-Milton
-    // (sqrt c - 1) / (sqrt c + 1), basic scheme (c - 1) / (c + 1); the
-    // augmented Lagrangian averages the Eyre-Milton operator with the
-    // identity (Douglas-Rachford form): (1 + rho_EM) / 2
+    // (sqrt c - 1) / (sqrt c + 1), basic and dual schemes (c - 1) / (c + 1);
+    // the augmented Lagrangian averages the Eyre-Milton operator with the
+    // identity (Douglas-Rachford form): (1 + rho_EM) / 2; the polarization
+    // scheme with relaxation alpha: |1 - alpha/2| + (alpha/2) rho_EM
     const double c = kmax / kmin;
     const double rem = (std::sqrt(c) - 1.0) / (std::sqrt(c) + 1.0);
-    const double rho = o.scheme == 1 ? (c - 1.0) / (c + 1.0) : (o.scheme == 2 ? 0.5 * (1.0 + rem) : rem);
+    const double rho = (o.scheme == 1 || o.scheme == 3) ? (c - 1.0) / (c + 1.0)
+                       : o.scheme == 2                 ? 0.5 * (1.0 + rem)
+                       : o.scheme == 4 ? std::fabs(1.0 - 0.5 * o.alpha) + 0.5 * o.alpha * rem
+                                       : rem;
     p.prog10 = 1.0 - std::pow(rho, 10.0);
     p.inv_k0M = 1.0 / (k0 * M);
     p.tol = tol;
@@ -545,6 +556,7 @@ SolverOpts resolve_opts(const rve_opts *opts) {
     o.workspace_bytes = opts ? opts->workspace_bytes : 0;
     o.scheme = opts ? opts->scheme : 0;
     o.fp32_refine = (opts && opts->fp32_refine < 0) ? -1 : 0;
+    o.alpha = (opts && opts->alpha != 0.0) ? opts->alpha : 2.0;
     o.path_flags = opts ? (opts->path_flags & 63) : 0;
     return o;
 }
@@ -650,7 +662,9 @@ int Solver::start(const uint8_t *d_phase, const SolverOpts &o, hipStream_t s) {
     slot = 0;
     launches.clear();
     eq_check = o.eq_check != 0;
-    al = o.scheme == 2;
+    scheme = o.scheme;
+    al = o.scheme == 2 || o.scheme == 4;
+    dual = o.scheme == 3;
     if (al && !o.dev_init_ops) {
         // the augmented-Lagrangian state: tau^0 = (k - k0) e^0 in the field buffer
         // (a continuation's fields hold tau already)
@@ -691,7 +705,7 @@ int Solver::launch_iteration(const LaunchArgs &a, hipStream_t s, int mask, hipEv
             (fused && ops->zgreen_par ? ops->zgreen_par : zvar ? ops->zgreen_alt : ops->zgreen)(
                 a, s, red_in_z ? ops->nper : 0, lc_sel);
             break;
-        case 2: (fused ? (al ? ops->inv_fwd_al : ops->inv_fwd) : (al ? ops->inv_al : ops->inv))(a, s, lc_sel); break;
+        case 2: inv_launcher(ops, fused, al, dual)(a, s, lc_sel); break;
         default: ops->reduce(a, ops->nper, s); break;
         }
         if (timed) {
@@ -888,7 +902,7 @@ int Solver::collect(const SolverOpts &o, hipStream_t s, rve_result *out, double 
                     rve_kernel_times *kt, rve_elastic_result *eout) {
     LaunchArgs a = args(d_phase_last);
     const int nlc = ops->nc;
-    if (ops->fwd_phi) {
+    if (ops->fwd_phi && scheme < 3) {
         // equilibrium error of the final field (step 1 quantity, reported at exit)
         launch_eq_request(a, s);
         ops->fwd_phi(a, s);
@@ -1174,12 +1188,21 @@ static rve_status solve_chains(rve_s *r, const SolverOps *ops, const double k[3]
 // The scheme option against the other options.
 int check_scheme(const SolverOpts &o, const SolverOps *ops) {
     (void)ops;
-    if (o.scheme < 0 || o.scheme > 2) {
-        set_error("scheme must be 0 (accelerated), 1 (basic) or 2 (augmented Lagrangian)");
+    if (o.scheme < 0 || o.scheme > 4) {
+        set_error("scheme must be 0 (accelerated), 1 (basic), 2 (augmented Lagrangian), 3 (dual) or "
+                  "4 (polarization)");
         return RVE_ERR_ARG;
     }
-    if (o.scheme == 2 && o.eq_check) {
-        set_error("the augmented-Lagrangian scheme has no equilibrium check");
+    if (o.scheme >= 2 && o.eq_check) {
+        set_error("the augmented-Lagrangian, dual and polarization schemes have no equilibrium check");
+        return RVE_ERR_ARG;
+    }
+    if (o.scheme == 3 && o.init_field) {
+        set_error("the dual scheme starts from the constant flux k0 E (no start field)");
+        return RVE_ERR_ARG;
+    }
+    if (o.scheme == 4 && !(o.alpha > 0.0 && o.alpha <= 2.0)) {
+        set_error("the polarization scheme's relaxation alpha must lie in (0, 2] (got %g)", o.alpha);
         return RVE_ERR_ARG;
     }
     return RVE_OK;

@@ -39,6 +39,7 @@ struct SolverOpts {
     double *out_field = nullptr;
     void *workspace = nullptr;
     size_t workspace_bytes = 0;
+    double alpha = 2.0;   // polarization scheme relaxation (rve_opts)
     int fp32_refine = 0;  // 0 on, -1 off (rve_opts)
     int path_flags = 0;   // PF_* measurement switches (rve_opts)
     // FP64 continuation: start from the FP32 fields on the device (per load
@@ -125,7 +126,9 @@ struct Solver {
     bool merge = false;  // each reduction runs inside the next iteration's z pass
     int lc_sel = -1;     // -1: all load cases; else the only load case iterated
     int zvar = 0;        // z-pass tile width: 0 default, 1 the other (autotuned)
-    bool al = false;     // augmented-Lagrangian update in the fused pass
+    bool al = false;     // augmented-Lagrangian family update (schemes 2 and 4)
+    bool dual = false;   // dual scheme update (scheme 3)
+    int scheme = 0;
     int path_flags = 0;  // PF_* of the current solve
     const uint8_t *d_phase_last = nullptr;
     // captured graph of kChunk iterations (kernels only; all parameters are
@@ -165,6 +168,14 @@ struct Solver {
     int collect(const SolverOpts &o, hipStream_t s, rve_result *out, double *hist, int hist_cap,
                 rve_kernel_times *kt, rve_elastic_result *eout = nullptr);
 };
+
+// The inverse pass of an iteration: fused with the next forward pass or
+// not, with the update of the scheme family.
+using InvFn = void (*)(const LaunchArgs &, hipStream_t, int);
+inline InvFn inv_launcher(const SolverOps *ops, bool fused, bool al, bool dual) {
+    if (fused) return dual ? ops->inv_fwd_dual : al ? ops->inv_fwd_al : ops->inv_fwd;
+    return dual ? ops->inv_dual : al ? ops->inv_al : ops->inv;
+}
 
 const SolverOps *lookup_ops(int precision, int n);
 const SolverOps *lookup_ops_el(int precision, int n);

@@ -132,7 +132,7 @@ struct NaSolve {
                 o.dev_init_ops->to_f64((double *)((char *)a.e + off * ops->real_bytes),
                                        (const char *)o.dev_init[lc] + off * o.dev_init_ops->real_bytes, 3 * M, s);
             }
-        const bool al = o.scheme == 2;
+        const bool al = o.scheme == 2 || o.scheme == 4, dual = o.scheme == 3;
         if (al && !o.dev_init_ops) ops->to_tau(a, M, s);
         NA_CHECK(hipGetLastError());
         const bool fused = ops->inv_fwd != nullptr && !(o.path_flags & PF_NO_FUSED);
@@ -146,7 +146,7 @@ struct NaSolve {
                 const bool red_in_z = merge && i > 0, defer = merge && i + 1 < count;
                 if (!fused) ops->fwd(a, s, -1);
                 zg(a, s, red_in_z ? ops->nper : 0, -1);
-                (fused ? (al ? ops->inv_fwd_al : ops->inv_fwd) : (al ? ops->inv_al : ops->inv))(a, s, -1);
+                inv_launcher(ops, fused, al, dual)(a, s, -1);
                 if (!defer) ops->reduce(a, ops->nper, s);
             }
             issued += count;
@@ -155,11 +155,14 @@ struct NaSolve {
             NA_CHECK(hipStreamSynchronize(s));
             if (flag) break;
         }
-        // equilibrium error of the final field, reported at exit
-        launch_eq_request(a, s);
-        ops->fwd_phi(a, s);
-        ops->zeq(a, s);
-        launch_eq_reduce(a, ops->eq_tiles, 1, s);
+        // equilibrium error of the final field, reported at exit (not for
+        // the dual and polarization schemes, whose buffer holds no gradient)
+        if (o.scheme < 3) {
+            launch_eq_request(a, s);
+            ops->fwd_phi(a, s);
+            ops->zeq(a, s);
+            launch_eq_reduce(a, ops->eq_tiles, 1, s);
+        }
         NA_CHECK(hipGetLastError());
         NA_CHECK(hipMemcpyAsync(&hs, a.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
         NA_CHECK(hipStreamSynchronize(s));

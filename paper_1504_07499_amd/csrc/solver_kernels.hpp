@@ -382,19 +382,70 @@ __device__ __forceinline__ void al_update_tau(T *a, const T *c, unsigned p, cons
 
 // The augmented-Lagrangian update of the separate inverse passes: as
 // al_update_tau, with the flux k d+ = tau+ + k0 c summed per voxel in FP64
-// (fl) and se = sum c.
+// (fl) and se = sum c.  step is the multiple of g added to tau: k0 for the
+// augmented Lagrangian, alpha k0 for the polarization scheme.
 template <typename T, int V>
 __device__ __forceinline__ void al_update(T *a, const T *c, unsigned p, T dk0, T dk1, T dk2, T gm0, T gm1, T gm2,
-                                          T k0, T ec, double &r2, double &fl, double &se) {
+                                          T k0, T step, T ec, double &r2, double &fl, double &se) {
 #pragma unroll
     for (int i = 0; i < V; ++i) {
         const T ci = c[i] + ec;
         const int pi = ph_at(p, i);
         const T g = (pick<T>(pi, dk0, dk1, dk2) * ci - a[i]) * pick<T>(pi, gm0, gm1, gm2);
         r2 += (double)g * (double)g;
-        a[i] = a[i] + k0 * g;
+        a[i] = a[i] + step * g;
         fl += (double)a[i] + (double)k0 * (double)ci;
         se += (double)ci;
+    }
+}
+
+// The dual scheme (named in Sec. 3 beside the accelerated one): the buffer
+// holds the flux phi, the forward pass transforms tau = -k0^2 phi / k, so
+// that the z pass, with the divergence-free projection of the dual scheme
+// in place of the Green symbol, returns c = k0 G*(phi / k) (G* = I - P) and
+//     phi+ = phi - Delta0 (phi / k - E) = (1 - k0 / k) phi + c + k0 E.
+// Residual: the increment |phi+ - phi| / k0; flux: phi+ itself.  wd[p] =
+// 1 - k0 / k, dd[p] = -k0^2 / k; e0 is k0 for the diagonal channel of the
+// load case, else 0.  For the fused pass: tau of the next iteration is
+// dd phi+ - tm, st collects sum (tau - tm) and se sum (phi+ - tau) / k0,
+// so that the caller's count tm + k0 se completes sum phi+ as for the other
+// updates (and the mean of tau follows in the reduction).
+template <typename T, int V>
+__device__ __forceinline__ void dual_update_tau(T *a, const T *c, unsigned p, const Cx<T> *lut, T tm, T e0, T ik0,
+                                                double &r2, double &st, double &se, T *tau) {
+    T r2v = (T)0, stv = (T)0, sev = (T)0;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+        const Cx<T> wd = lut[ph_at(p, i)];
+        const T f = wd.x * a[i] + c[i] + e0;
+        const T d = (f - a[i]) * ik0;
+        r2v += d * d;
+        a[i] = f;
+        const T t = wd.y * f;
+        tau[i] = t - tm;
+        stv += tau[i];
+        sev += (f - t) * ik0;
+    }
+    r2 += (double)r2v;
+    st += (double)stv;
+    se += (double)sev;
+}
+
+// The dual update of the separate inverse passes: fl = sum phi+, and se as
+// in dual_update_tau so that the reduction's mean of tau is that of
+// dd phi+ (the next forward pass subtracts it).
+template <typename T, int V>
+__device__ __forceinline__ void dual_update(T *a, const T *c, unsigned p, T wd0, T wd1, T wd2, T dd0, T dd1, T dd2,
+                                            T e0, T ik0, double &r2, double &fl, double &se) {
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+        const int pi = ph_at(p, i);
+        const T f = pick<T>(pi, wd0, wd1, wd2) * a[i] + c[i] + e0;
+        const T d = (f - a[i]) * ik0;
+        r2 += (double)d * (double)d;
+        a[i] = f;
+        fl += (double)f;
+        se += (double)((f - pick<T>(pi, dd0, dd1, dd2) * f) * ik0);
     }
 }
 
@@ -498,7 +549,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
     if (PHI ? !st->eq_pending[lc] : st->done[lc]) return;
     const bool dev = NC == 6 && ch % NC != 0;
     const double *lut = PHI ? prm->k : (dev ? prm->dk_dev : prm->dk);
-    const bool tau_in = !PHI && prm->scheme == 2;
+    const bool tau_in = !PHI && (prm->scheme == 2 || prm->scheme == 4);
     const T d0 = tau_in ? (T)1 : (T)lut[0], d1 = tau_in ? (T)1 : (T)lut[1], d2 = tau_in ? (T)1 : (T)lut[2];
     const T tm = PHI ? (T)0 : (T)st->tau_mean[ch];  // only the discarded mean mode changes
     const T *eb = e + (size_t)ch * N * NN + (size_t)z * NN;
@@ -828,6 +879,11 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
         fft_lds<T, N, false, 3 * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
     }
     const T sc = (T)prm->inv_k0M;
+    // the dual scheme takes G* = I - P, P the projection on the fields whose
+    // divergence vanishes for every sign of the Nyquist components (Nyquist
+    // components pass unchanged, the others see xi_A xi_A^T / |xi_A|^2 with
+    // xi_A the non-Nyquist part of xi)
+    const bool dual = prm->scheme == 3;
     for (int idx = tid; idx < NW; idx += NT) {
         const int kz = idx / W, w = idx - kz * W;
         const int ki[3] = {kx0 + dkx * w, ky0 + dky * w, kz};
@@ -847,13 +903,23 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
             for (int c = 0; c < 3; ++c) out[c] = Cx<T>{(T)0, (T)0};
         } else {
             Cx<T> sA = {(T)0, (T)0};
+            T a2 = (T)0;
 #pragma unroll
             for (int d = 0; d < 3; ++d)
-                if (!nq[d]) sA = sA + scale(tv[d], xi[d]);
-            const T x2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
-            const T f = -sc / x2;
+                if (!nq[d]) {
+                    sA = sA + scale(tv[d], xi[d]);
+                    a2 += xi[d] * xi[d];
+                }
+            if (dual) {
+                const T fa = a2 > (T)0 ? -sc / a2 : (T)0;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) out[c] = scale(nq[c] ? scale(tv[c], xi[c]) : sA, f * xi[c]);
+                for (int c = 0; c < 3; ++c) out[c] = nq[c] ? scale(tv[c], -sc) : scale(sA, fa * xi[c]);
+            } else {
+                const T x2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+                const T f = -sc / x2;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) out[c] = scale(nq[c] ? scale(tv[c], xi[c]) : sA, f * xi[c]);
+            }
         }
         buf[idx] = out[0];
         buf[NW + idx] = out[1];
@@ -1061,7 +1127,9 @@ template <typename T, int N, int NT, int RS> struct YFirstStage {
 // of split_fwd_tail to specB / nyqB instead.  The mean subtracted from tau
 // is the previous iteration's (any constant is exact: the mean mode of tau
 // is replaced by E).
-template <typename T, int N, int S, int NT, bool FWD = false, bool AL = false, int NC = 3>
+// UPD: the update of steps 6-7: 0 accelerated (and basic), 1 augmented
+// Lagrangian / polarization, 2 dual.
+template <typename T, int N, int S, int NT, bool FWD = false, int UPD = 0, int NC = 3>
 __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_plane(T *__restrict__ e, const uint8_t *__restrict__ ph,
                                                   Cx<T> *__restrict__ spec,
                                                   Cx<T> *__restrict__ nyq,
@@ -1145,7 +1213,8 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
     table_to_lds<T, N, NT>(tws, twg, tid);
     const Cx<T> *tw = tws;
     // per-phase {w, k - k0} of the update (fused form; augmented Lagrangian:
-    // {k - k0, 1 / (k + k0)})
+    // {k - k0, 1 / (k + k0)}; dual: {1 - k0 / k, -k0^2 / k})
+    constexpr bool AL = UPD == 1;
     __shared__ Cx<T> lut[3];
     if (FWD && tid < 3) lut[tid] = AL ? Cx<T>{(T)pdk[tid], (T)prm->gam[tid]} : Cx<T>{(T)pw[tid], (T)pdk[tid]};
     __syncthreads();
@@ -1169,8 +1238,10 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
     const T d0 = (T)pdk[0], d1 = (T)pdk[1], d2 = (T)pdk[2];
     const T tm = (T)st->tau_mean[ch];
     const T k0t = (T)k0c;
+    const T stp = (T)(prm->relax * k0c);  // the step of the augmented-Lagrangian family
     const T g0 = (T)prm->gam[0], g1 = (T)prm->gam[1], g2 = (T)prm->gam[2];
-    (void)d0, (void)d1, (void)d2, (void)tm, (void)k0t, (void)g0, (void)g1, (void)g2;
+    const T e0 = (T)(ec * k0c), ik0 = (T)(1.0 / k0c);  // dual: k0 E, 1 / k0
+    (void)d0, (void)d1, (void)d2, (void)tm, (void)k0t, (void)stp, (void)g0, (void)g1, (void)g2, (void)e0, (void)ik0;
     T *eb = e + (size_t)ch * N * NN + (size_t)z * NN;
     const uint8_t *pb = ph + (size_t)z * NN;
     double r2 = 0.0, fl = 0.0, se = 0.0;
@@ -1210,8 +1281,10 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
                     // next iteration's tau, packed in place of the c values just
                     // read; fl collects sum tau here (the flux follows below)
                     T tau[V];
-                    if constexpr (AL)
-                        al_update_tau<T, V>(a[i], c, p[i], lut, k0t, tm, ec, r2, fl, se, tau);
+                    if constexpr (UPD == 1)
+                        al_update_tau<T, V>(a[i], c, p[i], lut, stp, tm, ec, r2, fl, se, tau);
+                    else if constexpr (UPD == 2)
+                        dual_update_tau<T, V>(a[i], c, p[i], lut, tm, e0, ik0, r2, fl, se, tau);
                     else
                         em_update_tau<T, V>(a[i], c, p[i], lut, tm, ec, r2, fl, se, tau);
                     vstore<T>(eb + y * N + x, a[i]);
@@ -1222,8 +1295,10 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
                         for (int j = 0; j < V; j += 2) plane[m * RS + (x + j) / 2] = Cx<T>{tau[j], tau[j + 1]};
                     }
                 } else {
-                    if constexpr (AL)
-                        al_update<T, V>(a[i], c, p[i], d0, d1, d2, g0, g1, g2, k0t, ec, r2, fl, se);
+                    if constexpr (UPD == 1)
+                        al_update<T, V>(a[i], c, p[i], d0, d1, d2, g0, g1, g2, k0t, stp, ec, r2, fl, se);
+                    else if constexpr (UPD == 2)
+                        dual_update<T, V>(a[i], c, p[i], w0, w1, w2, d0, d1, d2, e0, ik0, r2, fl, se);
                     else
                         em_update<T, V>(a[i], c, p[i], w0, w1, w2, k0d, k1d, k2d, ec, r2, fl, se);
                     vstore<T>(eb + y * N + x, a[i]);
@@ -1285,7 +1360,8 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(const T *__restrict__ e, const 
     const int lc = ch / 3;
     if (PHI ? !st->eq_pending[lc] : st->done[lc]) return;
     const double *lut = PHI ? prm->k : prm->dk;
-    const bool tau_in = !PHI && prm->scheme == 2;  // augmented Lagrangian: the buffer holds tau
+    // augmented Lagrangian, polarization: the buffer holds tau
+    const bool tau_in = !PHI && (prm->scheme == 2 || prm->scheme == 4);
     const T d0 = tau_in ? (T)1 : (T)lut[0], d1 = tau_in ? (T)1 : (T)lut[1], d2 = tau_in ? (T)1 : (T)lut[2];
     const T tm = PHI ? (T)0 : (T)st->tau_mean[ch];
     const T *eb = e + (size_t)ch * N * NN + (size_t)z * NN + (size_t)y0 * N;
@@ -1371,7 +1447,7 @@ __global__ __launch_bounds__(NT) void k_cols(Cx<T> *__restrict__ spec, Cx<T> *__
     z_last_stage_store<T, N, W, NT, 1, INV>(buf, tw, base, 0, es, tid, ss);
 }
 
-template <typename T, int N, int G, int NT, bool AL = false>
+template <typename T, int N, int G, int NT, int UPD = 0>
 __global__ __launch_bounds__(NT) void k_inv_rows(T *__restrict__ e, const uint8_t *__restrict__ ph,
                                                  const Cx<T> *__restrict__ spec, const Cx<T> *__restrict__ nyq,
                                                  const Cx<T> *__restrict__ twg,
@@ -1419,9 +1495,12 @@ __global__ __launch_bounds__(NT) void k_inv_rows(T *__restrict__ e, const uint8_
             c[i] = zz.x;
             c[i + 1] = zz.y;
         }
-        if constexpr (AL)
+        if constexpr (UPD == 1)
             al_update<T, V>(a, c, p, (T)prm->dk[0], (T)prm->dk[1], (T)prm->dk[2], (T)prm->gam[0],
-                            (T)prm->gam[1], (T)prm->gam[2], (T)prm->k0, ec, r2, fl, se);
+                            (T)prm->gam[1], (T)prm->gam[2], (T)prm->k0, (T)(prm->relax * prm->k0), ec, r2, fl, se);
+        else if constexpr (UPD == 2)
+            dual_update<T, V>(a, c, p, w0, w1, w2, (T)prm->dk[0], (T)prm->dk[1], (T)prm->dk[2],
+                              (T)(ec * prm->k0), (T)(1.0 / prm->k0), r2, fl, se);
         else
             em_update<T, V>(a, c, p, w0, w1, w2, k0d, k1d, k2d, ec, r2, fl, se);
         vstore<T>(eb + y * N + x, a);
@@ -1455,9 +1534,11 @@ template <typename T>
 __global__ void k_init(T *__restrict__ e, size_t M, const DevParams *__restrict__ prm, DevState *__restrict__ st) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const int nc = prm->nc;
+    // the dual scheme's iterate is the flux, which starts at k0 E
+    const T one = prm->scheme == 3 ? (T)prm->k0 : (T)1;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)(nc * nc) * M; i += stride) {
         const int ch = (int)(i / M);
-        e[i] = (ch % (nc + 1) == 0) ? (T)1 : (T)0;  // ch = nc lc + comp, comp == lc
+        e[i] = (ch % (nc + 1) == 0) ? one : (T)0;  // ch = nc lc + comp, comp == lc
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->iter = 0;

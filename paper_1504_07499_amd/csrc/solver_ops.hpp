@@ -74,6 +74,10 @@ struct SolverOps {
     // the z pass combines it into spec / nyq); nullptr elsewhere
     void (*fwd_par)(const LaunchArgs &, hipStream_t, int lc_sel);
     void (*zgreen_par)(const LaunchArgs &, hipStream_t, int red_nper, int lc_sel);
+    // the dual scheme's update: fused pass (nullptr where there is none) and
+    // separate inverse pass
+    void (*inv_fwd_dual)(const LaunchArgs &, hipStream_t, int lc_sel);
+    void (*inv_dual)(const LaunchArgs &, hipStream_t, int lc_sel);
 };
 
 const SolverOps *ops_f32(int n);

@@ -15,6 +15,7 @@ struct DevParams {
     double invM;
     double prog10;  // 1 - rho^10: least progress of 10 iterations the scheme's contraction bound allows
     double gam[3];  // 1 / (k + k0) (augmented-Lagrangian local step)
+    double relax;   // multiple of k0 g added to tau: 1 augmented Lagrangian, alpha polarization
     // elastic case: the channels of the hydrostatic basis tensor use k, dk,
     // w, k0 above (3 kappa, 3 (kappa - kappa0), 2 kappa0 / (kappa + kappa0),
     // 3 kappa0); the five deviatoric ones use these (2 mu, ...)

@@ -362,7 +362,7 @@ def test_augmented_lagrangian_rejections():
         with pytest.raises(rh.RveError):
             rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=1, scheme=AL, equilibrium_check=True)
         with pytest.raises(rh.RveError):
-            rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=1, scheme=3)
+            rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=1, scheme=5)
         ok = rh.homogenize(r, K_PAPER_CFG, 1e-6, precision=1, scheme=AL)
         assert ok.status == rh.RVE_OK
 

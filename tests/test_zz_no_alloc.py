@@ -25,7 +25,7 @@ def _same(a, b):
 
 
 @pytest.mark.parametrize("precision,scheme", [(0, "accelerated"), (1, "accelerated"),
-                                              (0, "augmented_lagrangian")])
+                                              (0, "augmented_lagrangian"), (0, "dual"), (1, "polarization")])
 def test_no_alloc_equals_homogenize_two_calls(precision, scheme):
     print(f"\n[case] no-alloc precision={precision} scheme={scheme}", flush=True)
     for n, nsp, seed in ((64, 12, 51), (32, 8, 52)):  # second call: smaller grid
