@@ -154,13 +154,17 @@ def test_equilibrium_error_fp64(n):
     assert tensor_err(g2.K, ref2.K) <= 1e-9
 
 
-def _golden(name):
+def _golden_all():
     import json
     import os
 
     path = os.path.join(os.path.dirname(__file__), "golden", "oracle_refs.json")
     with open(path) as f:
-        return json.load(f)[name]
+        return json.load(f)
+
+
+def _golden(name):
+    return _golden_all()[name]
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -187,6 +191,35 @@ def test_config2_128_vs_stored_oracle(precision):
         assert g.status == rh.RVE_OK, (list(g.lc_status), list(g.refine_iters))
         assert np.all(g.final_residual < ref["tol"])
         assert tensor_err(g.K, Kr) <= 1e-4
+
+
+@pytest.mark.parametrize("name", ["rve256_100sph_f0.40_l0.10_c1e3_seed3", "rve256_100sph_f0.40_l0.20_c1e2_seed3",
+                                  "rve256_100sph_f0.40_l0.05_c1e4_seed3"])
+def test_config3_256_vs_stored_oracle(name):
+    """The 256^3 RVE (100 spheres, f = 0.40 through the generator's fallback,
+    seed 3) at the (layer, contrast) points with stored oracle solves
+    (tests/golden/make_oracle_refs.py): FP64 (five-pass form) with the
+    oracle's iteration counts and within 1e-9; FP32 in the configuration the
+    benchmark times (split planes, load-case chains, FP64 continuation past
+    the FP32 floor) within 1e-4, converged."""
+    refs = _golden_all()
+    if name not in refs:
+        pytest.skip(f"no stored oracle solve for {name}")
+    ref = refs[name]
+    print(f"\n[case] config3 {name}", flush=True)
+    g0 = ref["geometry"]
+    Kr = np.array(ref["K"])
+    with rh.rve_create(g0["n"], g0["n_spheres"], g0["volume_fraction"], g0["layer"], g0["seed"]) as r:
+        frac = np.bincount(rh.rve_get_phases(r).ravel(), minlength=3) / 256 ** 3
+        np.testing.assert_allclose(frac, ref["phase_fractions"], atol=1e-12)
+        g64 = rh.homogenize(r, ref["k_phases"], ref["tol"], precision=1)
+        g32 = rh.homogenize(r, ref["k_phases"], ref["tol"], precision=0)
+    print(list(g64.iters), list(g32.iters), list(g32.refine_iters), tensor_err(g64.K, Kr), tensor_err(g32.K, Kr),
+          flush=True)
+    assert g64.status == rh.RVE_OK and list(g64.iters) == ref["iters"]
+    assert tensor_err(g64.K, Kr) <= 1e-9
+    assert g32.status == rh.RVE_OK
+    assert tensor_err(g32.K, Kr) <= 1e-4
 
 
 def test_five_pass_256_fp64_vs_oracle():
