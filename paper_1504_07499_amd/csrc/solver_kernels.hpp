@@ -1230,6 +1230,23 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
             c2r_pack<T, N>(plane + y * RS, k, tw);
         }
     }
+    T *eb = e + (size_t)ch * N * NN + (size_t)z * NN;
+    const uint8_t *pb = ph + (size_t)z * NN;
+    constexpr int TOTL = ROWS * N / V, PERL = (TOTL + NT - 1) / NT, BL = 8;
+    // split planes, fused: the first NPF items of the update are loaded
+    // before the x transform, which hides their latency
+    constexpr int NPF = (S == 2 && FWD) ? 4 : 0;
+    T apre[NPF > 0 ? NPF : 1][V];
+    unsigned ppre[NPF > 0 ? NPF : 1];
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) {
+        const int idx = tid + i * NT;
+        if (i < PERL && (TOTL % NT == 0 || idx < TOTL)) {
+            const int m = idx / (N / V), x = (idx - m * (N / V)) * V, y = S * m + h;
+            vload<T>(eb + y * N + x, apre[i]);
+            ppre[i] = pload<V>(pb + y * N + x);
+        }
+    }
     __syncthreads();
     fft_lds<T, H, true, ROWS, 1, NT, N, SeqStride<RS>, PMX>(plane, tw, tid);
 
@@ -1242,10 +1259,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
     const T g0 = (T)prm->gam[0], g1 = (T)prm->gam[1], g2 = (T)prm->gam[2];
     const T e0 = (T)(ec * k0c), ik0 = (T)(1.0 / k0c);  // dual: k0 E, 1 / k0
     (void)d0, (void)d1, (void)d2, (void)tm, (void)k0t, (void)stp, (void)g0, (void)g1, (void)g2, (void)e0, (void)ik0;
-    T *eb = e + (size_t)ch * N * NN + (size_t)z * NN;
-    const uint8_t *pb = ph + (size_t)z * NN;
     double r2 = 0.0, fl = 0.0, se = 0.0;
-    constexpr int TOTL = ROWS * N / V, PERL = (TOTL + NT - 1) / NT, BL = 8;
 #pragma unroll
     for (int i0 = 0; i0 < PERL; i0 += BL) {
         T a[BL][V];
@@ -1255,8 +1269,14 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
             const int idx = tid + (i0 + i) * NT;
             if (i0 + i < PERL && (TOTL % NT == 0 || idx < TOTL)) {
                 const int m = idx / (N / V), x = (idx - m * (N / V)) * V, y = S * m + h;
-                vload<T>(eb + y * N + x, a[i]);
-                p[i] = pload<V>(pb + y * N + x);
+                if (i0 + i < NPF) {
+#pragma unroll
+                    for (int j = 0; j < V; ++j) a[i][j] = apre[(i0 + i) % (NPF > 0 ? NPF : 1)][j];
+                    p[i] = ppre[(i0 + i) % (NPF > 0 ? NPF : 1)];
+                } else {
+                    vload<T>(eb + y * N + x, a[i]);
+                    p[i] = pload<V>(pb + y * N + x);
+                }
             }
         }
 #pragma unroll
