@@ -24,7 +24,6 @@ against the FP64 single-RVE path); and the FP64 CPU oracle timed on a bounded
 sample of the same workload.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -32,6 +31,8 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+from paper_1504_07499_amd._build import kernel_source_hash  # noqa: E402
 
 METRIC = "voxel-iters/s per load case; RVE solves/s + p50/p99 at 1e-4 tensor err"
 HBM_PEAK_GBS = 8000.0
@@ -47,16 +48,6 @@ SECONDARY = {"workload": "rve128_50sph_f0.30_l0.20_seed2", "n": 128, "n_spheres"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rve256_fp32.txt")
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1504_07499_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(f.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(kernel: str, launches_bytes: float):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources; else None."""
@@ -68,7 +59,7 @@ def measured_traffic(kernel: str, launches_bytes: float):
             if "=" in line and not line.startswith("#"):
                 k, v = line.split("=", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("source_hash") != kernel_source_hash():
+    if vals.get("source_hash") != kernel_source_hash():  # counters of other kernel sources
         return None
     key = f"{kernel}_hbm_bytes_per_launch"
     return float(vals[key]) if key in vals else None

@@ -7,6 +7,7 @@
 from __future__ import annotations
 
 import glob
+import hashlib
 import os
 import subprocess
 
@@ -39,6 +40,18 @@ def build_geom() -> str:
 
 def hip_sources():
     return sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")))
+
+
+def kernel_source_hash() -> str:
+    """Short hash of the kernel sources (csrc/*.hip, *.hpp): counter summaries
+    record it, so that figures taken on other kernels are not reused."""
+    h = hashlib.sha256()
+    csrc = os.path.join(PKG, "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def hip_flags():

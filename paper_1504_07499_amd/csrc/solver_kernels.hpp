@@ -501,20 +501,25 @@ template <typename T, int N, int S, int NT> constexpr int plane_min_waves() {
     return waves < 1 ? 1 : (waves > 4 ? 4 : waves);
 }
 
-// Block index -> (channel, z, parity).  For S = 2 the two parities of one
-// plane are 8 blocks apart, so that both run on the same XCD (blocks are
-// dealt round-robin to the 8 XCDs) and the second read of the plane hits L2.
+// Block index -> (channel, z, parity).  Workgroups are dealt round-robin to
+// the 8 XCDs (block b to XCD b mod 8, as the (b / 8)-th there), each with its
+// own L2: the nch x S blocks of one z-plane (nch channels in the grid, S
+// parities) take consecutive places on XCD z mod 8, so that the plane's
+// phase image comes from HBM once for all channels and, for S = 2, the second
+// parity's read of the plane's spectrum hits L2.  Grids whose N is not a
+// multiple of 8 keep the channel-major order.
 template <int N, int S> __device__ __forceinline__ void plane_of_block(int b, int &ch, int &z, int &h) {
-    if constexpr (S == 1) {
+    if constexpr (N % 8 == 0) {
+        const int nch = (int)gridDim.x / (N * S), g = nch * S;
+        const int x = b & 7, slot = b >> 3, zq = slot / g, r = slot - zq * g;
+        z = zq * 8 + x;
+        ch = r / S;
+        h = r - ch * S;
+    } else {
+        static_assert(S == 1 || N % 8 == 0, "split planes need N % 8 == 0");
         ch = b / N;
         z = b - ch * N;
         h = 0;
-    } else {
-        const int g = b / (8 * S), r = b - g * 8 * S;
-        h = r / 8;
-        const int pr = g * 8 + (r - h * 8);
-        ch = pr / N;
-        z = pr - ch * N;
     }
 }
 
