@@ -65,17 +65,31 @@ def measured_traffic(kernel: str, launches_bytes: float):
     return float(vals[key]) if key in vals else None
 
 
-def cpu_baseline(phases, k, sample_iters: int):
+def cpu_baseline(phases, k, sample_iters: int, single_iters: int):
+    """The FP64 oracle on the host: sample_iters iterations of load case e_1
+    on all host threads, and single_iters on one thread."""
     import oracle
 
+    m = phases.size
+    cores = oracle.threads()
     t0 = time.perf_counter()
     r = oracle.homogenize(phases, k, tol=0.0, max_iter=sample_iters, lc_mask=1)
     dt = time.perf_counter() - t0
-    m = phases.size
-    return {"value": m * int(r.iters[0]) / dt, "unit": "voxel-iters/s per load case",
-            "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{sample_iters} iterations of load case e_1 on the same {phases.shape[0]}^3 "
-                      f"RVE (FP64, own FFT, OpenMP), {dt:.1f} s"}
+    out = {"value": m * int(r.iters[0]) / dt, "unit": "voxel-iters/s per load case",
+           "cores": cores, "kind": "oracle",
+           "sample": f"{sample_iters} iterations of load case e_1 on the same {phases.shape[0]}^3 "
+                     f"RVE (FP64, own FFT, OpenMP), {dt:.1f} s"}
+    if single_iters > 0:
+        oracle.set_threads(1)
+        try:
+            t0 = time.perf_counter()
+            r1 = oracle.homogenize(phases, k, tol=0.0, max_iter=single_iters, lc_mask=1)
+            d1 = time.perf_counter() - t0
+        finally:
+            oracle.set_threads(cores)
+        out["single_thread"] = {"value": m * int(r1.iters[0]) / d1, "cores": 1,
+                                "sample": f"{single_iters} iterations of load case e_1, {d1:.1f} s"}
+    return out
 
 
 def calibrate_copy(mib: int = 512, reps: int = 4) -> None:
@@ -196,6 +210,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--cpu-iters-single", type=int, default=1,
+                    help="oracle iterations timed on one host thread (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=100,
                     help="requests of the serving leg (0 = skip it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -316,7 +332,7 @@ def main():
         from paper_1504_07499_amd import geom
 
         ph, _, _ = geom.generate(n, w["n_spheres"], w["volume_fraction"], w["layer"], w["seed"])
-        cpu = cpu_baseline(ph, k, args.cpu_iters)
+        cpu = cpu_baseline(ph, k, args.cpu_iters, args.cpu_iters_single)
         progress("cpu baseline done")
 
     line = {

@@ -43,12 +43,14 @@ def hip_sources():
 
 
 def kernel_source_hash() -> str:
-    """Short hash of the kernel sources (csrc/*.hip, *.hpp): counter summaries
-    record it, so that figures taken on other kernels are not reused."""
+    """Short hash of the sources that define the kernels and their launch
+    shapes (csrc/*.hip and *.hpp except the host-side rvehom_* files):
+    counter summaries record it, so that figures taken on other kernels are
+    not reused."""
     h = hashlib.sha256()
     csrc = os.path.join(PKG, "csrc")
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
+        if name.endswith((".hip", ".hpp")) and not name.startswith("rvehom_"):
             with open(os.path.join(csrc, name), "rb") as f:
                 h.update(f.read())
     return h.hexdigest()[:16]
