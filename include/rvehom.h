@@ -147,6 +147,21 @@ typedef struct {
  * out: up to cap ints; count receives the number. */
 rve_status rve_supported_n(int precision, int *out, int cap, int *count);
 
+/* The autotuner's choices.  The first solve of each (GPU architecture,
+ * precision, N) in a process times the z pass at its two tile widths and
+ * keeps the faster (the results do not depend on the choice).  The choices
+ * are text lines "<gfx arch> <precision 0|1> <n> ztile <0|1>" (1 = the
+ * other width).
+ * rve_tune_export: copies the choices made or imported in this process into
+ *   buf (at most cap - 1 characters, then a terminating 0; buf may be null
+ *   with cap 0) and returns the size needed including the terminating 0.
+ * rve_tune_import: adds the choices of such text (blank lines ignored; a
+ *   line for another architecture is kept but applies only to devices of
+ *   that architecture); a malformed line gives RVE_ERR_ARG and imports
+ *   nothing.  Imported choices replace the timing for their grids. */
+size_t rve_tune_export(char *buf, size_t cap);
+rve_status rve_tune_import(const char *text);
+
 /* Sec. 2: RSA placement + voxelization of g, uploaded to the current HIP
  * device.  RVE_ERR_ARG for n unsupported, n_spheres < 1, f or l outside
  * (0, 1) or a sphere radius >= 0.5; RVE_ERR_JAMMED if the spheres do not

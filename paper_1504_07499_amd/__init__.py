@@ -94,6 +94,8 @@ def _load_library():
     c_int, c_double, c_size_t, c_vp = ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
     sig = {
         "rve_supported_n": (c_int, [c_int, P(c_int), c_int, P(c_int)]),
+        "rve_tune_export": (c_size_t, [ctypes.c_char_p, c_size_t]),
+        "rve_tune_import": (c_int, [ctypes.c_char_p]),
         "rve_create": (c_int, [P(_Geom), P(c_vp)]),
         "rve_create_from_phases": (c_int, [c_int, P(ctypes.c_uint8), P(c_vp)]),
         "rve_get_phases": (c_int, [c_vp, P(ctypes.c_uint8), c_size_t]),
@@ -204,6 +206,48 @@ def rve_supported_n(precision: int = 0) -> list:
     cnt = ctypes.c_int(0)
     _check(_lib.rve_supported_n(int(precision), out, 64, ctypes.byref(cnt)))
     return [int(out[i]) for i in range(min(cnt.value, 64))]
+
+
+def rve_tune_export() -> str:
+    """The autotuner's choices of this process, as text lines
+    "<gfx arch> <precision> <n> ztile <0|1>"."""
+    need = int(_lib.rve_tune_export(None, 0))
+    buf = ctypes.create_string_buffer(need)
+    _lib.rve_tune_export(buf, need)
+    return buf.value.decode()
+
+
+def rve_tune_import(text: str) -> None:
+    """Adds autotuner choices (text of rve_tune_export); they replace the
+    timing for their (architecture, precision, N)."""
+    _check(_lib.rve_tune_import(text.encode()))
+
+
+def rve_tune_save(path: str) -> None:
+    """Writes this process's autotuner choices to path (merged with the
+    choices already there for other grids or architectures)."""
+    lines = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            for ln in f:
+                if ln.strip():
+                    lines[tuple(ln.split()[:4])] = ln.strip()
+    for ln in rve_tune_export().splitlines():
+        if ln.strip():
+            lines[tuple(ln.split()[:4])] = ln.strip()
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        f.write("".join(v + "\n" for v in sorted(lines.values())))
+    os.replace(tmp, path)
+
+
+def rve_tune_load(path: str) -> bool:
+    """Imports the autotuner choices saved at path; False if there is no file."""
+    if not os.path.exists(path):
+        return False
+    with open(path) as f:
+        rve_tune_import(f.read())
+    return True
 
 
 def rve_create(n: int, n_spheres: int, volume_fraction: float, layer: float, seed: int) -> RVE:

@@ -20,6 +20,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "rvegeom.h"
@@ -568,8 +569,29 @@ SolverOpts resolve_opts(const rve_opts *opts) {
 // keep the default.  The z transform of a pencil does not depend on the tile
 // width, so the choice never changes a result.  PF_ZTILE_DEFAULT /
 // PF_ZTILE_ALT force the default / the other width.
+// The choices are kept per (GPU architecture, precision, N) and can be
+// exported and imported as text (rve_tune_export / rve_tune_import), so a
+// later process on the same architecture skips the timing.
+using TuneKey = std::tuple<std::string, int, int>;  // gfx arch, precision, N
 static std::mutex g_tune_mu;
-static std::map<const SolverOps *, int> g_ztune;
+static std::map<TuneKey, int> g_ztune;
+
+// gfx architecture name of the current device ("gfx950"), or "" on failure.
+static std::string current_arch() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return std::string();
+    static std::mutex mu;
+    static std::map<int, std::string> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return std::string();
+    std::string name(prop.gcnArchName);
+    name = name.substr(0, name.find(':'));  // drop feature suffixes (":sramecc+:xnack-")
+    cache[dev] = name;
+    return name;
+}
 
 int Solver::tune_zpass(const LaunchArgs &a, hipStream_t s) {
     zvar = 0;
@@ -578,9 +600,10 @@ int Solver::tune_zpass(const LaunchArgs &a, hipStream_t s) {
         zvar = (path_flags & PF_ZTILE_ALT) ? 1 : 0;
         return RVE_OK;
     }
+    const TuneKey key{current_arch(), ops->precision, ops->n};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_ztune.find(ops);
+        auto it = g_ztune.find(key);
         if (it != g_ztune.end()) {
             zvar = it->second;
             return RVE_OK;
@@ -602,7 +625,56 @@ int Solver::tune_zpass(const LaunchArgs &a, hipStream_t s) {
     HIP_CHECK(hipEventElapsedTime(&t1, ev[1], ev[2]));
     for (auto &e : ev) (void)hipEventDestroy(e);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    zvar = g_ztune.emplace(ops, t1 < 0.97f * t0 ? 1 : 0).first->second;
+    zvar = g_ztune.emplace(key, t1 < 0.97f * t0 ? 1 : 0).first->second;
+    return RVE_OK;
+}
+
+extern "C" size_t rve_tune_export(char *buf, size_t cap) {
+    std::string text;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const auto &kv : g_ztune) {
+            char line[160];
+            std::snprintf(line, sizeof line, "%s %d %d ztile %d\n", std::get<0>(kv.first).c_str(),
+                          std::get<1>(kv.first), std::get<2>(kv.first), kv.second);
+            text += line;
+        }
+    }
+    if (buf && cap > 0) {
+        const size_t m = std::min(cap - 1, text.size());
+        std::memcpy(buf, text.data(), m);
+        buf[m] = '\0';
+    }
+    return text.size() + 1;
+}
+
+extern "C" rve_status rve_tune_import(const char *text) {
+    clear_error();
+    if (!text) {
+        set_error("rve_tune_import: text is null");
+        return RVE_ERR_ARG;
+    }
+    std::vector<std::pair<TuneKey, int>> add;
+    const char *p = text;
+    int lineno = 0;
+    while (*p) {
+        const char *e = std::strchr(p, '\n');
+        std::string line(p, e ? (size_t)(e - p) : std::strlen(p));
+        p = e ? e + 1 : p + line.size();
+        ++lineno;
+        if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+        char arch[64], kind[16];
+        int prec = -1, n = 0, choice = -1, used = 0;
+        if (std::sscanf(line.c_str(), "%63s %d %d %15s %d %n", arch, &prec, &n, kind, &choice, &used) != 5 ||
+            line.find_first_not_of(" \t\r", used) != std::string::npos || std::strcmp(kind, "ztile") != 0 ||
+            (prec != 0 && prec != 1) || n <= 0 || (choice != 0 && choice != 1)) {
+            set_error("rve_tune_import: line %d is not \"<arch> <precision 0|1> <n> ztile <0|1>\"", lineno);
+            return RVE_ERR_ARG;
+        }
+        add.push_back({TuneKey{arch, prec, n}, choice});
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &kv : add) g_ztune[kv.first] = kv.second;
     return RVE_OK;
 }
 
@@ -632,8 +704,14 @@ int Solver::start(const uint8_t *d_phase, const SolverOpts &o, hipStream_t s) {
     const size_t M = (size_t)ops->n * ops->n * ops->n;
     ops->init(a, M, s);
     HIP_CHECK(hipGetLastError());
-    rc = tune_zpass(a, s);
-    if (rc != RVE_OK) return rc;
+    // the split planes' fused pass always takes the parity-layout z pass,
+    // whose tile width is fixed: nothing to tune there
+    const bool par_z = ops->zgreen_par && ops->inv_fwd && !o.eq_check && !(o.path_flags & PF_NO_FUSED);
+    zvar = 0;
+    if (!par_z) {
+        rc = tune_zpass(a, s);
+        if (rc != RVE_OK) return rc;
+    }
     if (o.dev_init_ops) {
         // continuation: each solved load case starts from its field in another
         // workspace (FP32 -> working precision)
@@ -750,6 +828,7 @@ GraphKey Solver::graph_key(const uint8_t *d_phase) const {
     k.fused = fused;
     k.merge = merge;
     k.al = al;
+    k.dual = dual;
     k.lc = lc_sel;
     k.zvar = zvar;
     return k;

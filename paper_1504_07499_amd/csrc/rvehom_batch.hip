@@ -59,16 +59,38 @@ rve_status batch_solve(int count, const rve_t *rves, const double *k, const doub
         return (int)RVE_OK;
     });
     if (rc != RVE_OK) return (rve_status)rc;
+    // FP64 continuation of the load cases stopped by the FP32 floor: every
+    // RVE that has some begins its FP64 solve from its FP32 field on its own
+    // stream, and these solves are driven together as the FP32 ones were
+    std::vector<BatchItem> ref;
+    std::vector<int> masks(count, 0);
+    for (int i = 0; i < count; ++i) {
+        rve_s *r = rves[i];
+        Solver &sv32 = r->sol[o.precision];
+        const int mask = refine_mask(out[i], o);
+        const SolverOps *ops64 = mask ? lookup_ops(1, r->n) : nullptr;
+        if (!ops64) continue;  // nothing to continue, or no FP64 build of this grid (stays STALLED)
+        Solver &sv = r->sol[1];
+        rc = sv.prepare(ops64, nullptr, 0);
+        if (rc != RVE_OK) return (rve_status)rc;
+        const void *src[3];
+        for (int lc = 0; lc < 3; ++lc) src[lc] = (const char *)sv32.ws + sv32.layout.e;
+        const SolverOpts o64 = refine_opts(o, out[i], mask, src, sv32.ops);
+        rc = sv.begin(r->d_phase, k + 3 * i, tol[i], o64, sv32.own_stream);
+        if (rc != RVE_OK) return (rve_status)rc;
+        masks[i] = mask;
+        ref.push_back({&sv, r->d_phase, sv32.own_stream, o64.max_iter, i, o64, 0});
+    }
+    rc = drive(ref, [&](BatchItem &a) {
+        rve_result r64{};
+        int c = a.sv->collect(a.opts, a.stream, &r64, nullptr, 0, nullptr);
+        if (c != RVE_OK) return c;
+        refine_merge(out[a.index], r64, masks[a.index], nullptr, 0, nullptr);
+        return (int)RVE_OK;
+    });
+    if (rc != RVE_OK) return (rve_status)rc;
     rve_status worst = RVE_OK;
     for (int i = 0; i < count; ++i) {
-        // FP64 continuation of load cases stopped by the FP32 floor, one RVE
-        // after another (each on its own stream)
-        rve_s *r = rves[i];
-        Solver &sv = r->sol[o.precision];
-        const void *src[3];
-        for (int lc = 0; lc < 3; ++lc) src[lc] = (const char *)sv.ws + sv.layout.e;
-        rc = refine_fp64(r, sv.ops, k + 3 * i, tol[i], o, out[i], nullptr, 0, src, sv.own_stream);
-        if (rc != RVE_OK) return (rve_status)rc;
         rve_status s = worst_status(out[i], o.lc_mask);
         if (s < 0 || (worst >= 0 && s > worst)) worst = s;
     }

@@ -73,11 +73,13 @@ struct GraphKey {
     const SolverOps *ops = nullptr;
     const void *ws = nullptr;
     const uint8_t *ph = nullptr;
-    bool eq = false, fused = false, merge = false, al = false;
+    // al / dual: the update kernels of the scheme (the accelerated and basic
+    // schemes share theirs, as do the augmented-Lagrangian and polarization)
+    bool eq = false, fused = false, merge = false, al = false, dual = false;
     int lc = -1, zvar = 0;
     bool operator==(const GraphKey &o) const {
         return ops == o.ops && ws == o.ws && ph == o.ph && eq == o.eq && fused == o.fused && merge == o.merge &&
-               al == o.al && lc == o.lc && zvar == o.zvar;
+               al == o.al && dual == o.dual && lc == o.lc && zvar == o.zvar;
     }
 };
 

@@ -44,3 +44,26 @@ def test_supported_sizes_and_host_validation():
         rh.rve_create(32, 1, 0.9, 0.1, 1)  # sphere radius >= 0.5
     with pytest.raises(rh.RveError):
         rh.rve_create(32, 8, 0.2, 1.2, 1)
+
+
+def test_tune_table_roundtrip(tmp_path):
+    """The autotuner's table as text: import, export, save and load (no GPU
+    call: the table is host state)."""
+    if not os.path.exists(_build.hip_lib_path()):
+        pytest.skip("HIP library not built")
+    rh.rve_tune_import("gfx950 0 96 ztile 1\n\ngfx942 1 128 ztile 0\n")
+    out = rh.rve_tune_export().splitlines()
+    assert "gfx950 0 96 ztile 1" in out and "gfx942 1 128 ztile 0" in out
+    for bad in ("gfx950 0 96 ztile 2", "gfx950 2 96 ztile 0", "gfx950 0 96 wtile 0",
+                "gfx950 0 96 ztile 0 extra", "gfx950 0 ztile 0"):
+        with pytest.raises(rh.RveError) as ei:
+            rh.rve_tune_import(bad)
+        assert ei.value.status == rh.RVE_ERR_ARG
+    path = str(tmp_path / "tune.txt")
+    with open(path, "w") as f:
+        f.write("gfx950 1 64 ztile 0\n")
+    rh.rve_tune_save(path)  # merged with what the file held
+    with open(path) as f:
+        saved = f.read().splitlines()
+    assert "gfx950 1 64 ztile 0" in saved and "gfx950 0 96 ztile 1" in saved
+    assert rh.rve_tune_load(path) and not rh.rve_tune_load(str(tmp_path / "absent.txt"))

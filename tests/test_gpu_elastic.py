@@ -88,6 +88,29 @@ def test_elastic_equal_shear_hill_64(precision):
     assert abs(g.C_basis[0, 0] / 3.0 - khill) <= (1e-9 if precision else 1e-5) * khill
 
 
+def test_elastic_equal_shear_hill_256_fp32():
+    """The same closed form on the 256^3 RVE of 100 RSA spheres at f = 0.40
+    (FP32; 8-column z tiles in 1024-thread workgroups, split planes): the
+    random geometry feeds every z tile and every plane of all six load
+    cases, and the hydrostatic load case must give Hill's bulk modulus."""
+    print("\n[case] elastic hill 256 fp32", flush=True)
+    mod = np.array([[4.0, 2.0], [40.0, 2.0], [150.0, 2.0]])
+    ph, _, _ = geom.generate(256, 100, 0.40, 0.1, 3)
+    kv = mod[ph, 0]
+    khill = 1.0 / np.mean(1.0 / (kv + 4.0 * 2.0 / 3.0)) - 4.0 * 2.0 / 3.0
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize_elastic(r, mod, 1e-6, precision=0)
+    C = np.asarray(g.C_basis)
+    assert abs(C[0, 0] / 3.0 - khill) <= 1e-5 * khill
+    # with one shear modulus a uniform deviatoric strain is the exact
+    # solution (its stress 2 mu E is uniform, hence in equilibrium), so the
+    # deviatoric block is 2 mu I and, by the major symmetry of the discrete
+    # problem, the hydrostatic load case carries no deviatoric mean stress
+    assert np.allclose(np.diag(C)[1:], 4.0, rtol=1e-6, atol=0)
+    off = C - np.diag(np.diag(C))
+    assert np.abs(off).max() <= 1e-5 * C[0, 0]
+
+
 @pytest.mark.parametrize("n,precision,axis", [(48, 1, 0), (48, 0, 0), (256, 0, 0), (256, 0, 2)])
 def test_elastic_laminate_backus(n, precision, axis):
     """Layers normal to x (or z) on an n^3 grid: the Backus stiffness (closed

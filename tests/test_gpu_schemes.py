@@ -118,3 +118,25 @@ def test_rejections():
             with pytest.raises(rh.RveError) as ei:
                 rh.homogenize(r, K_CFG, 1e-6, precision=1, **kw)
             assert ei.value.status == rh.RVE_ERR_ARG
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_scheme_switches_on_one_handle(precision):
+    """Solves of different schemes one after another on one RVE handle (the
+    solvers, workspaces and cached iteration graphs are reused) give what
+    each scheme gives on a fresh handle, bit for bit: the cached graphs are
+    keyed by the scheme's update kernels."""
+    print(f"\n[case] scheme switches precision={precision}", flush=True)
+    ph, _, _ = geom.generate(32, 8, 0.2, 0.1, 1)
+    order = [("accelerated", 0.0), ("dual", 0.0), ("augmented_lagrangian", 0.0), ("dual", 0.0),
+             ("polarization", 1.5), ("accelerated", 0.0), ("basic", 0.0), ("dual", 0.0)]
+    fresh = {}
+    for sch, alpha in set(order):
+        with rh.rve_create_from_phases(ph) as r:
+            fresh[sch] = rh.homogenize(r, K_LOW, 1e-6, precision=precision, scheme=sch, alpha=alpha)
+    with rh.rve_create_from_phases(ph) as r:
+        for sch, alpha in order:
+            g = rh.homogenize(r, K_LOW, 1e-6, precision=precision, scheme=sch, alpha=alpha)
+            assert g.status == rh.RVE_OK, sch
+            assert list(g.iters) == list(fresh[sch].iters), sch
+            assert np.array_equal(g.K, fresh[sch].K), sch
