@@ -143,8 +143,11 @@ typedef struct {
     double total_bytes[4];
 } rve_kernel_times;
 
-/* Grid sizes N the library supports for a precision (0 FP32, 1 FP64).
- * out: up to cap ints; count receives the number. */
+/* Grid sizes N the library supports for a precision (0 FP32, 1 FP64): the
+ * {2,3}-smooth N from 8 to 512 with N % 4 == 0 and at most two factors 3
+ * that it instantiates (8, 12, 16, 24, 32, 36, 48, 64, 72, 96, 128, 144,
+ * 192, 256, 288, 384, 512).  out: up to cap ints; count receives the
+ * number. */
 rve_status rve_supported_n(int precision, int *out, int cap, int *count);
 
 /* The autotuner's choices.  The first solve of each (GPU architecture,
@@ -186,7 +189,8 @@ int rve_n(rve_t rve);
  * workspace: a caller-provided one, or one solve of a single load case).  A
  * solve of all three load cases without a caller workspace, without the
  * two-stage stop and without a start or final field, on a grid whose
- * xy-planes fit in LDS (whole or split; not FP64 256^3 or 512^3), runs the
+ * xy-planes fit in LDS (whole or split; not FP64 256^3 and up, nor FP32
+ * 288^3 and up), runs the
  * load cases as three concurrent chains and allocates three such workspaces
  * (cached on the handle until rve_destroy); the results are the same. */
 size_t rve_workspace_size(rve_t rve, int precision);

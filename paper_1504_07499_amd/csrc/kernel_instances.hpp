@@ -19,13 +19,13 @@ template <typename T, int N> constexpr int plane_split() {
                                                                                     : 0;
 }
 
-// z-tile width: largest W <= 16 dividing N/2 and N with 3 N W complex in
+// z-tile width: largest even W <= 16 dividing N/2 and N with 3 N W complex in
 // 64 KiB of LDS; if that leaves fewer than 8 columns (long pencils), up to
 // 96 KiB is allowed so that global accesses keep >= 64-byte segments.
 template <typename T, int N> constexpr int ztile_cap(size_t cap) {
-    for (int w = 16; w >= 1; --w)
+    for (int w = 16; w >= 2; w -= 2)
         if ((N / 2) % w == 0 && N % w == 0 && (size_t)3 * N * w * sizeof(Cx<T>) <= cap) return w;
-    return 1;
+    return 2;
 }
 template <typename T, int N> constexpr int ztile() {
     // FP32 128^3: 8-column tiles (24 KiB, six workgroups per CU instead of
@@ -87,7 +87,7 @@ template <typename T, int N> struct Instance {
     static int ch0(int lc_sel) { return lc_sel < 0 ? 0 : 3 * lc_sel; }
     // split planes: the fused pass writes the parity layout (k_inv_plane with
     // S = 2), read back by the z pass
-    static constexpr bool PARF = !FIVE && S == 2;
+    static constexpr bool PARF = !FIVE && S == 2 && ztile_par_ok<N, ztile<T, N>()>();
     template <bool PHI, bool PAR = false> static void fwd_t(const LaunchArgs &a, hipStream_t s, int lc_sel) {
         if constexpr (FIVE) {
             hipLaunchKernelGGL((k_fwd_rows<T, N, G, NTR, PHI>), dim3(9 * N * (N / G)), dim3(NTR), 0, s,

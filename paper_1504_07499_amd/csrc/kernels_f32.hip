@@ -16,7 +16,7 @@ const SolverOps *ops_f32(int n) {
     case 128: return Instance<float, 128>::ops(0);
     case 256: return Instance<float, 256>::ops(0);
     case 512: return Instance<float, 512>::ops(0);
-    default: return nullptr;
+    default: return ops_f32_smooth(n);
     }
 }
 

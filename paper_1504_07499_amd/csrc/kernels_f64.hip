@@ -16,7 +16,7 @@ const SolverOps *ops_f64(int n) {
     case 128: return Instance<double, 128>::ops(1);
     case 256: return Instance<double, 256>::ops(1);
     case 512: return Instance<double, 512>::ops(1);
-    default: return nullptr;
+    default: return ops_f64_smooth(n);
     }
 }
 

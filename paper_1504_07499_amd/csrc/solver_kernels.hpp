@@ -658,10 +658,13 @@ template <typename T, int N, int W> __device__ __forceinline__ int ztile_of(int 
 // 128-byte lines, so the four tiles {ky, ky + N/2} x {chunks 2j, 2j + 1}
 // get workgroups 8 apart (one XCD, whose L2 then serves the repeated reads).
 // The same for the Nyquist column's tiles of W rows.
+template <int N, int W> constexpr bool ztile_par_ok() {
+    return (N / 2 / W) % 2 == 0 && ZTiles<N, W>::MAIN % 32 == 0 && ZTiles<N, W>::NYQ % 32 == 0;
+}
 template <int N, int W> __device__ __forceinline__ int ztile_par(int b) {
     using TL = ZTiles<N, W>;
     constexpr int H = N / 2, C = H / W;
-    static_assert(C % 2 == 0 && TL::MAIN % 32 == 0 && TL::NYQ % 32 == 0, "parity tiles come in groups of 32");
+    static_assert(ztile_par_ok<N, W>(), "parity tiles come in groups of 32");
     const bool main = b < TL::MAIN;
     const int bb = main ? b : b - TL::MAIN;
     const int lane = bb & 7, q = (bb >> 3) & 3, quad = (bb >> 5) * 8 + lane;
@@ -819,8 +822,8 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
     // the three components' pencils straight to the registers of the first
     // z stage, and the last inverse stage straight back (except FP32 from
     // 256^3 on, measured faster with the pencils staged through LDS)
-    constexpr bool DIRECT = zpass_direct<T, N>();
-    static_assert(!PAR || !DIRECT, "the parity layout is read through the staged load");
+    // the parity layout is read through the staged load
+    constexpr bool DIRECT = zpass_direct<T, N>() && !PAR;
     constexpr int NP = 3 * NW / 2, PERP = (NP + NT - 1) / NT;
     ZFirstStage<T, N, W, NT> z0;
     if constexpr (DIRECT) {

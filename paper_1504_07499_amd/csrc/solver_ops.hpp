@@ -82,6 +82,10 @@ struct SolverOps {
 
 const SolverOps *ops_f32(int n);
 const SolverOps *ops_f64(int n);
+// the {2,3}-smooth sizes with a factor 3 beyond 96 and its divisors (their
+// own translation units, compiled in parallel with the others)
+const SolverOps *ops_f32_smooth(int n);
+const SolverOps *ops_f64_smooth(int n);
 const SolverOps *ops_el_f32(int n);
 const SolverOps *ops_el_f64(int n);
 void launch_reduce(const LaunchArgs &a, int nper, hipStream_t s);

@@ -222,6 +222,41 @@ def test_config3_256_vs_stored_oracle(name):
     assert tensor_err(g32.K, Kr) <= 1e-4
 
 
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("n", [36, 72, 144, 192])
+def test_smooth_sizes_fixed_iterations(n, precision):
+    """{2,3}-smooth grids with two radix-3 stages (36, 144) or one beyond
+    96 (72, 192), on the paths their planes take (whole planes; split
+    planes for FP64 144 and 192, with the parity layout at 192): three
+    iterations from E, every voxel of every channel against the oracle."""
+    print(f"\n[case] smooth field n={n} precision={precision}", flush=True)
+    ph = geom.random_phases(n, seed=700 + n)
+    ref = oracle.homogenize(ph, K_PAPER_CFG, tol=0.0, max_iter=3, want_field=True)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize(r, K_PAPER_CFG, 0.0, max_iter=3, precision=precision,
+                          want_field=True, hist_cap=8)
+    bar = 1e-11 if precision == 1 else 3e-5
+    assert field_err(g.field, ref.field) <= bar
+    assert tensor_err(g.K, ref.K) <= bar
+    assert list(g.iters) == [3, 3, 3]
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("n", [288, 384])
+def test_smooth_sizes_five_pass(n, precision):
+    """288 and 384 run the five-pass form in both precisions: two
+    iterations of load case e_1 on an RSA RVE, voxel by voxel."""
+    print(f"\n[case] smooth five-pass n={n} precision={precision}", flush=True)
+    ph, _, _ = geom.generate(n, 60, 0.3, 0.2, 9)
+    ref = oracle.homogenize(ph, K_PAPER_CFG, tol=0.0, max_iter=2, want_field=True, lc_mask=1)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize(r, K_PAPER_CFG, 0.0, max_iter=2, precision=precision, lc_mask=1,
+                          want_field=True)
+    bar = 1e-11 if precision == 1 else 3e-5
+    assert field_err(g.field[0], ref.field[0]) <= bar
+    assert tensor_err(g.K[:, 0], ref.K[:, 0]) <= bar
+
+
 def test_five_pass_256_fp64_vs_oracle():
     """FP64 at 256^3 runs the five-pass form (the xy-plane does not fit in
     LDS): two iterations of load case e_1, voxel by voxel against the oracle."""
