@@ -207,7 +207,11 @@ int Solver::prepare(const SolverOps *o, void *user_ws, size_t user_bytes) {
             return RVE_ERR_ARG;
         }
         if (owned && ws) (void)hipFree(ws);
-        if (ws != user_ws) tw_ready = false;
+        // a workspace the solver does not own may have been written by
+        // others since this solver's last solve (another handle, or another
+        // served request's block at the same place): its twiddle table is
+        // uploaded again for every solve
+        tw_ready = false;
         ws = user_ws;
         owned = false;
         ws_bytes = user_bytes;

@@ -85,6 +85,50 @@ print("torch interop ok", list(ext.iters), flush=True)
 """
 
 
+_SHARED_WS_CHILD = r"""
+import sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+import torch
+torch.cuda.init()
+import paper_1504_07499_amd as rh
+from paper_1504_07499_amd import geom
+K3 = np.array([0.2, 0.3, 400.0])
+pa, _, _ = geom.generate(32, 8, 0.2, 0.1, 1)
+pb, _, _ = geom.generate(48, 10, 0.3, 0.2, 4)
+with rh.rve_create_from_phases(pa) as a, rh.rve_create_from_phases(pb) as b:
+    ws = torch.empty(max(rh.rve_workspace_size(a, 1), rh.rve_workspace_size(b, 1)), dtype=torch.uint8,
+                     device="cuda")
+    for prec in (1, 0):
+        a1 = rh.homogenize(a, K3, 1e-6, precision=prec, workspace=ws)
+        b1 = rh.homogenize(b, K3, 1e-6, precision=prec, workspace=ws)  # overwrites a's data in ws
+        a2 = rh.homogenize(a, K3, 1e-6, precision=prec, workspace=ws)
+        b2 = rh.homogenize(b, K3, 1e-6, precision=prec)
+        assert np.array_equal(a1.K, a2.K) and np.array_equal(a1.iters, a2.iters), prec
+        assert np.array_equal(b1.K, b2.K), prec
+print("shared workspace ok", flush=True)
+"""
+
+
+def test_workspace_shared_between_handles():
+    """One caller workspace used by two RVE handles of different N in turn:
+    each solve rebuilds what it needs in it (the twiddle table included),
+    so a handle's second solve equals its first bit for bit.  Child process
+    with torch, as test_torch_workspace_and_stream."""
+    import os
+    import subprocess
+    import sys
+
+    pytest.importorskip("torch")
+    print("\n[case] shared workspace (child process)", flush=True)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", _SHARED_WS_CHILD, root], capture_output=True,
+                         text=True, timeout=300)
+    print(out.stdout[-2000:], out.stderr[-2000:])
+    assert out.returncode == 0
+    assert "shared workspace ok" in out.stdout
+
+
 def test_torch_workspace_and_stream():
     """Device memory and the stream may come from PyTorch; the result is the
     same as with the library's own workspace.  Runs in a child process that
