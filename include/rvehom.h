@@ -273,7 +273,9 @@ typedef struct {
 rve_status homogenize_elastic(rve_t rve, const double moduli[6], double tol, const rve_opts *opts,
                               rve_elastic_result *out, double *residual_history, int hist_cap);
 
-/* Grid sizes N the elastic case supports for a precision. */
+/* Grid sizes N the elastic case supports for a precision: 8, 12, 16, 24,
+ * 32, 48, 64, 96, 128, 256 and 512 in both (FP64 from 256^3 on, and FP32
+ * 512^3, in the five-pass form). */
 rve_status rve_supported_n_elastic(int precision, int *out, int cap, int *count);
 
 /* Serving: a request loop that keeps fields resident on the device,

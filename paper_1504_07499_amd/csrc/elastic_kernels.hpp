@@ -188,7 +188,12 @@ __global__ void k_reduce_el(const double *part, int nper, const DevParams *prm, 
 template <typename T, int N> struct ElasticInstance {
     static constexpr int NC = 6, CH = NC * NC;
     static constexpr int S = plane_split<T, N>();
-    static_assert(S == 1 || S == 2, "the elastic case needs planes that fit in LDS (whole or split)");
+    // planes that do not fit in LDS (FP64 256^3, 512^3): the five-pass form
+    // of the conductivity case with six components per load case
+    static constexpr bool FIVE = (S == 0);
+    static constexpr int G = row_group<T, N>();
+    static constexpr int WC = col_tile<T, N>();
+    static constexpr int NTR = 256;
     static constexpr int W = ztile_el<T, N>();
     static_assert(W >= 2, "no z tile fits in LDS");
     static constexpr int NTP = plane_threads<T, N>();
@@ -197,22 +202,40 @@ template <typename T, int N> struct ElasticInstance {
     // than 256 threads at 128^3), 1024 for the one 96 KiB tile per CU at
     // 256^3; FP64: 256 (measured faster)
     static constexpr int NTZ = sizeof(T) == 4 ? (N == 256 ? 1024 : 512) : 256;
-    static constexpr int NPER = N * S;
+    static constexpr int NPER = FIVE ? N * (N / G) : N * S;
     static constexpr bool FUSED = S == 1 && !(sizeof(T) == 4 && N == 96);
-    static constexpr int PGRID = CH * N * S;
+    static constexpr int PGRID = FIVE ? CH * N * (N / G) : CH * N * S;
+    static constexpr int SP = FIVE ? 1 : S;
 
     static void fwd(const LaunchArgs &a, hipStream_t s, int) {
-        hipLaunchKernelGGL((k_fwd_plane<T, N, S, NTP, false, NC>), dim3(PGRID), dim3(NTP), 0, s, (const T *)a.e, a.ph,
-                           (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st, 0);
+        if constexpr (FIVE) {
+            hipLaunchKernelGGL((k_fwd_rows<T, N, G, NTR, false, NC>), dim3(PGRID), dim3(NTR), 0, s, (const T *)a.e,
+                               a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
+                               (const DevState *)a.st);
+            hipLaunchKernelGGL((k_cols<T, N, WC, NTR, false, false, NC>), dim3(ColTiles<N, WC, CH>::ALL), dim3(NTR),
+                               0, s, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, (const DevState *)a.st);
+        } else {
+            hipLaunchKernelGGL((k_fwd_plane<T, N, SP, NTP, false, NC>), dim3(PGRID), dim3(NTP), 0, s, (const T *)a.e,
+                               a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
+                               (const DevState *)a.st, 0);
+        }
     }
     static void zgreen(const LaunchArgs &a, hipStream_t s, int, int) {
         hipLaunchKernelGGL((k_zgreen_el<T, N, W, NTZ>), dim3(NC * ZTiles<N, W>::PER_LC), dim3(NTZ), 0, s,
                            (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st);
     }
     static void inv(const LaunchArgs &a, hipStream_t s, int) {
-        hipLaunchKernelGGL((k_inv_plane<T, N, S, NTP, false, 0, NC>), dim3(PGRID), dim3(NTP), 0, s, (T *)a.e,
-                           a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st,
-                           a.part, 0, (Cx<T> *)nullptr, (Cx<T> *)nullptr);
+        if constexpr (FIVE) {
+            hipLaunchKernelGGL((k_cols<T, N, WC, NTR, true, false, NC>), dim3(ColTiles<N, WC, CH>::ALL), dim3(NTR), 0,
+                               s, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, (const DevState *)a.st);
+            hipLaunchKernelGGL((k_inv_rows<T, N, G, NTR, 0, NC>), dim3(PGRID), dim3(NTR), 0, s, (T *)a.e, a.ph,
+                               (const Cx<T> *)a.spec, (const Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
+                               (const DevState *)a.st, a.part);
+        } else {
+            hipLaunchKernelGGL((k_inv_plane<T, N, SP, NTP, false, 0, NC>), dim3(PGRID), dim3(NTP), 0, s, (T *)a.e,
+                               a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
+                               (const DevState *)a.st, a.part, 0, (Cx<T> *)nullptr, (Cx<T> *)nullptr);
+        }
     }
     static void inv_fwd(const LaunchArgs &a, hipStream_t s, int) {
         if constexpr (FUSED) {
@@ -240,18 +263,20 @@ template <typename T, int N> struct ElasticInstance {
         constexpr double cb = (double)sizeof(Cx<T>);
         constexpr double rb = (double)sizeof(T);
         constexpr double spec_b = (double)CH * N * N * (H + 1) * cb;
+        // the five-pass form's column passes read and write the spectrum once more each way
+        constexpr double extra = FIVE ? 2.0 * spec_b : 0.0;
         static const SolverOps o = {
             N,
             precision,
-            S,
+            FIVE ? 0 : S,
             W,
             NPER,
             sizeof(T),
             (size_t)CH * N * N * H,
             (size_t)CH * N * N,
             {PGRID, NC * ZTiles<N, W>::PER_LC, PGRID},
-            {NTP, NTZ, NTP},
-            {CH * (double)M * rb + spec_b, 2.0 * spec_b, spec_b + 2.0 * CH * (double)M * rb},
+            {FIVE ? NTR : NTP, NTZ, FIVE ? NTR : NTP},
+            {CH * (double)M * rb + spec_b + extra, 2.0 * spec_b, spec_b + 2.0 * CH * (double)M * rb + extra},
             0,
             FUSED ? 2.0 * spec_b + 2.0 * CH * (double)M * rb : 0.0,
             FUSED ? &inv_fwd : nullptr,

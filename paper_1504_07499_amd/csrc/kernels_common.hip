@@ -91,8 +91,8 @@ __global__ __launch_bounds__(576) void k_reduce_el(const double *part, int nper,
 static const int kSizesF32[] = {8, 12, 16, 24, 32, 36, 48, 64, 72, 96, 128, 144, 192, 256, 288, 384, 512};
 static const int kSizesF64[] = {8, 12, 16, 24, 32, 36, 48, 64, 72, 96, 128, 144, 192, 256, 288, 384, 512};
 
-static const int kSizesElF32[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 256};
-static const int kSizesElF64[] = {8, 12, 16, 24, 32, 48, 64, 96, 128};
+static const int kSizesElF32[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 256, 512};
+static const int kSizesElF64[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 256, 512};
 
 int supported_sizes_el(int precision, const int **list) {
     if (precision == 0) {

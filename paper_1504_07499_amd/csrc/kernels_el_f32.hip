@@ -15,6 +15,7 @@ const SolverOps *ops_el_f32(int n) {
     case 96: return ElasticInstance<float, 96>::ops(0);
     case 128: return ElasticInstance<float, 128>::ops(0);
     case 256: return ElasticInstance<float, 256>::ops(0);
+    case 512: return ElasticInstance<float, 512>::ops(0);
     default: return nullptr;
     }
 }

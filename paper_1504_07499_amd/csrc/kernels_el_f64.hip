@@ -14,6 +14,8 @@ const SolverOps *ops_el_f64(int n) {
     case 64: return ElasticInstance<double, 64>::ops(1);
     case 96: return ElasticInstance<double, 96>::ops(1);
     case 128: return ElasticInstance<double, 128>::ops(1);
+    case 256: return ElasticInstance<double, 256>::ops(1);
+    case 512: return ElasticInstance<double, 512>::ops(1);
     default: return nullptr;
     }
 }

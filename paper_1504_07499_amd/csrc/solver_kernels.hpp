@@ -1374,7 +1374,9 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
 //   k_zgreen:    as in the three-pass form;
 //   k_inv_rows:  C2R of G rows fused with steps 6-7 and the flux.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int G, int NT, bool PHI = false>
+// NC: components per load case (3 conductivity, 6 elasticity: the grid then
+// covers 36 channels, the deviatoric ones with their own table).
+template <typename T, int N, int G, int NT, bool PHI = false, int NC = 3>
 __global__ __launch_bounds__(NT) void k_fwd_rows(const T *__restrict__ e, const uint8_t *__restrict__ ph,
                                                  Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
                                                  const Cx<T> *__restrict__ twg,
@@ -1385,11 +1387,12 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(const T *__restrict__ e, const 
     const int tid = threadIdx.x;
     const int ch = blockIdx.x / (N * GP), rem = blockIdx.x - ch * (N * GP);
     const int z = rem / GP, y0 = (rem - z * GP) * G;
-    const int lc = ch / 3;
+    const int lc = ch / NC;
     if (PHI ? !st->eq_pending[lc] : st->done[lc]) return;
-    const double *lut = PHI ? prm->k : prm->dk;
+    const bool dev = NC == 6 && ch % NC != 0;
+    const double *lut = PHI ? prm->k : (dev ? prm->dk_dev : prm->dk);
     // augmented Lagrangian, polarization: the buffer holds tau
-    const bool tau_in = !PHI && (prm->scheme == 2 || prm->scheme == 4);
+    const bool tau_in = NC == 3 && !PHI && (prm->scheme == 2 || prm->scheme == 4);
     const T d0 = tau_in ? (T)1 : (T)lut[0], d1 = tau_in ? (T)1 : (T)lut[1], d2 = tau_in ? (T)1 : (T)lut[2];
     const T tm = PHI ? (T)0 : (T)st->tau_mean[ch];
     const T *eb = e + (size_t)ch * N * NN + (size_t)z * NN + (size_t)y0 * N;
@@ -1424,19 +1427,19 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(const T *__restrict__ e, const 
     for (int y = tid; y < G; y += NT) nb[y] = rows[y * RS + H];
 }
 
-template <int N, int W> struct ColTiles {
+template <int N, int W, int NCH = 9> struct ColTiles {
     static constexpr int H = N / 2;
-    static constexpr int MAIN = 9 * N * (H / W);  // (ch, z, kx chunk)
-    static constexpr int NYQ = 9 * (N / W);       // (ch, chunk of W planes) of the kx = N/2 column
+    static constexpr int MAIN = NCH * N * (H / W);  // (ch, z, kx chunk)
+    static constexpr int NYQ = NCH * (N / W);       // (ch, chunk of W planes) of the kx = N/2 column
     static constexpr int ALL = MAIN + NYQ;
 };
 
 // GATE_EQ: run for load cases awaiting the equilibrium check instead of the
 // ones still iterating.
-template <typename T, int N, int W, int NT, bool INV, bool GATE_EQ = false>
+template <typename T, int N, int W, int NT, bool INV, bool GATE_EQ = false, int NC = 3>
 __global__ __launch_bounds__(NT) void k_cols(Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
                                              const Cx<T> *__restrict__ twg, const DevState *__restrict__ st) {
-    using TL = ColTiles<N, W>;
+    using TL = ColTiles<N, W, NC * NC>;
     constexpr int H = N / 2, NW = N * W;
     __shared__ Cx<T> buf[NW];  // [ky][w]
     const int tid = threadIdx.x;
@@ -1459,7 +1462,7 @@ __global__ __launch_bounds__(NT) void k_cols(Cx<T> *__restrict__ spec, Cx<T> *__
         es = 1;
         ss = N;
     }
-    const int lc = ch / 3;
+    const int lc = ch / NC;
     if (GATE_EQ ? !st->eq_pending[lc] : st->done[lc]) return;
     // the columns straight to the registers of the first stage, and the last
     // stage straight back
@@ -1475,21 +1478,27 @@ __global__ __launch_bounds__(NT) void k_cols(Cx<T> *__restrict__ spec, Cx<T> *__
     z_last_stage_store<T, N, W, NT, 1, INV>(buf, tw, base, 0, es, tid, ss);
 }
 
-template <typename T, int N, int G, int NT, int UPD = 0>
+template <typename T, int N, int G, int NT, int UPD = 0, int NC = 3>
 __global__ __launch_bounds__(NT) void k_inv_rows(T *__restrict__ e, const uint8_t *__restrict__ ph,
                                                  const Cx<T> *__restrict__ spec, const Cx<T> *__restrict__ nyq,
                                                  const Cx<T> *__restrict__ twg,
                                                  const DevParams *__restrict__ prm,
                                                  const DevState *__restrict__ st, double *__restrict__ part) {
     constexpr int H = N / 2, RS = H + 1, V = VecOf<T>::V, NN = N * N, GP = N / G;
+    static_assert(NC == 3 || UPD == 0, "the elastic case runs the accelerated update");
     __shared__ Cx<T> rows[G * RS];
     __shared__ double red[3 * (NT / 64)];
     const int tid = threadIdx.x;
     const int ch = blockIdx.x / (N * GP), rem = blockIdx.x - ch * (N * GP);
     const int z = rem / GP, yg = rem - z * GP, y0 = yg * G;
-    const int lc = ch / 3;
+    const int lc = ch / NC;
     if (st->done[lc]) return;
-    const T ec = (ch % 4 == 0) ? (T)1 : (T)0;
+    // E_comp of this channel (ch = NC lc + comp: the unit vector or basis
+    // tensor lc), and (elasticity) the deviatoric channels' own tables
+    const T ec = (ch % (NC + 1) == 0) ? (T)1 : (T)0;
+    const bool dev = NC == 6 && ch % NC != 0;
+    const double *pk = dev ? prm->k_dev : prm->k;
+    const double *pw = dev ? prm->w_dev : prm->w;
     const Cx<T> *sb = spec + (((size_t)ch * N + z) * N + y0) * H;
     const Cx<T> *nb = nyq + ((size_t)ch * N + z) * N + y0;
     for (int idx = tid; idx < G * RS; idx += NT) {
@@ -1507,8 +1516,8 @@ __global__ __launch_bounds__(NT) void k_inv_rows(T *__restrict__ e, const uint8_
     }
     __syncthreads();
     fft_lds<T, H, true, G, 1, NT, N, SeqStride<RS>>(rows, tw, tid);
-    const T w0 = (T)prm->w[0], w1 = (T)prm->w[1], w2 = (T)prm->w[2];
-    const double k0d = prm->k[0], k1d = prm->k[1], k2d = prm->k[2];
+    const T w0 = (T)pw[0], w1 = (T)pw[1], w2 = (T)pw[2];
+    const double k0d = pk[0], k1d = pk[1], k2d = pk[2];
     T *eb = e + (size_t)ch * N * NN + (size_t)z * NN + (size_t)y0 * N;
     const uint8_t *pb = ph + (size_t)z * NN + (size_t)y0 * N;
     double r2 = 0.0, fl = 0.0, se = 0.0;

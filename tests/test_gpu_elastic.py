@@ -111,6 +111,44 @@ def test_elastic_equal_shear_hill_256_fp32():
     assert np.abs(off).max() <= 1e-5 * C[0, 0]
 
 
+def test_elastic_five_pass_256_fp64_vs_oracle():
+    """FP64 at 256^3 runs the five-pass form with six components per load
+    case (the xy-plane does not fit in LDS): two iterations on an RSA RVE,
+    load case B_3 (a shear) voxel by voxel and its stiffness column against
+    the oracle."""
+    print("\n[case] elastic five-pass 256 fp64", flush=True)
+    ph, _, _ = geom.generate(256, 100, 0.3, 0.2, 3)
+    j = 3
+    ref = oracle.homogenize_elastic(ph, MOD, basis_strains()[[j]], tol=0.0, max_iter=2, want_field=True)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize_elastic(r, MOD, 0.0, max_iter=2, precision=1, want_field=True)
+    ref_field = to_basis(np.moveaxis(ref.field[0], 0, -1))  # (z, y, x, k)
+    assert tensor_err(np.moveaxis(g.field[j], 0, -1), ref_field) <= 1e-11
+    assert tensor_err(np.asarray(g.C_basis)[:, j], to_basis(ref.S)[0]) <= 1e-11
+    assert list(g.iters) == [2] * 6
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_elastic_equal_shear_hill_512(precision):
+    """512^3 (five-pass form in both precisions) on an RSA RVE of equal shear
+    moduli: Hill's bulk modulus, the exact deviatoric block 2 mu I and no
+    coupling, as at 256^3."""
+    print(f"\n[case] elastic hill 512 precision={precision}", flush=True)
+    mod = np.array([[4.0, 2.0], [40.0, 2.0], [150.0, 2.0]])
+    ph, _, _ = geom.generate(512, 100, 0.30, 0.2, 7)
+    kv = mod[ph, 0]
+    khill = 1.0 / np.mean(1.0 / (kv + 4.0 * 2.0 / 3.0)) - 4.0 * 2.0 / 3.0
+    del kv
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize_elastic(r, mod, 1e-11 if precision else 1e-6, precision=precision)
+    C = np.asarray(g.C_basis)
+    bar = 1e-9 if precision else 1e-5
+    assert abs(C[0, 0] / 3.0 - khill) <= bar * khill
+    assert np.allclose(np.diag(C)[1:], 4.0, rtol=bar, atol=0)
+    off = C - np.diag(np.diag(C))
+    assert np.abs(off).max() <= bar * C[0, 0]
+
+
 @pytest.mark.parametrize("n,precision,axis", [(48, 1, 0), (48, 0, 0), (256, 0, 0), (256, 0, 2)])
 def test_elastic_laminate_backus(n, precision, axis):
     """Layers normal to x (or z) on an n^3 grid: the Backus stiffness (closed
@@ -159,7 +197,14 @@ def test_elastic_rejections():
     with rh.rve_create_from_phases(geom.random_phases(16, 5)) as r:
         with pytest.raises(rh.RveError):
             rh.homogenize_elastic(r, [[1.0, 1.0], [2.0, -1.0], [3.0, 1.0]], 1e-6)
-    assert 512 not in rh.rve_supported_n_elastic(0) and 128 in rh.rve_supported_n_elastic(1)
+    for prec in (0, 1):
+        sizes = rh.rve_supported_n_elastic(prec)
+        assert 128 in sizes and 256 in sizes and 512 in sizes and 36 not in sizes
+    # a grid the elastic case does not instantiate is refused before any GPU work
+    with rh.rve_create_from_phases(geom.random_phases(36, 5)) as r:
+        with pytest.raises(rh.RveError) as ei:
+            rh.homogenize_elastic(r, MOD, 1e-6)
+        assert ei.value.status == rh.RVE_ERR_ARG
 
 
 def test_elastic_start_field_continues_the_iteration():
