@@ -322,7 +322,8 @@ def run_fibers(layers=(0.02, 0.05, 0.1, 0.2, 0.4, 0.8), n=128, n_fibers=40, f=0.
 
 
 # -------------------------------------------------------------------- elastic
-def run_elastic(sizes=((128, 0), (128, 1), (256, 0)), moduli=((4.0, 1.5), (40.0, 30.0), (150.0, 100.0)),
+def run_elastic(sizes=((128, 0), (128, 1), (256, 0), (256, 1), (512, 0), (512, 1)),
+                moduli=((4.0, 1.5), (40.0, 30.0), (150.0, 100.0)),
                 n_spheres=50, f=0.30, layer=0.2, seed=2, tol=1e-6, reps=3):
     """The elastic case (Sec. 6) on coated-sphere RVEs: six load cases,
     iterations, solve time, voxel-iterations/s per load case, the
@@ -335,17 +336,20 @@ def run_elastic(sizes=((128, 0), (128, 1), (256, 0)), moduli=((4.0, 1.5), (40.0,
         with rve_create(n, n_spheres, f, layer, seed) as h:
             r = homogenize_elastic(h, moduli, tol, precision=prec)
             best = r
-            for _ in range(reps):
+            for _ in range(reps if n <= 256 else 1):
                 g = homogenize_elastic(h, moduli, tol, precision=prec)
                 if g.solve_ms < best.solve_ms:
                     best = g
         M = n ** 3
         b = 4 if prec == 0 else 8
         fused = not (n == 96 and prec == 0) and (n <= 128 or (prec == 0 and n <= 192))
-        # per iteration of all six load cases: z pass 2 C; fused plane pass
-        # 2 C + 2 * 36 M b + 36 M (phases), separate passes C more + 36 M b + 36 M
+        five = (prec == 1 and n >= 256) or n >= 512
+        # per iteration of all six load cases (the phase image read once per
+        # pass): z pass 2 C; fused plane pass 2 C + 2 * 36 M b + M; separate
+        # plane passes 2 C + 3 * 36 M b + 2 M; the five-pass form adds the two
+        # column passes, 4 C
         C = 36 * n * n * (n // 2 + 1) * 2 * b
-        per_it = 2 * C + (2 * C + 72 * M * b + 36 * M if fused else 3 * C + 108 * M * b + 72 * M)
+        per_it = 2 * C + (2 * C + 72 * M * b + M if fused else 2 * C + 108 * M * b + 2 * M) + (4 * C if five else 0)
         its = float(best.iters.mean())
         Cm = best.C_basis
         row = {"n": n, "precision": "fp32" if prec == 0 else "fp64", "iters": best.iters.tolist(),

@@ -257,6 +257,21 @@ def test_smooth_sizes_five_pass(n, precision):
     assert tensor_err(g.K[:, 0], ref.K[:, 0]) <= bar
 
 
+@pytest.mark.parametrize("precision", [1, 0])
+def test_five_pass_512_vs_oracle(precision):
+    """512^3 (five-pass form in both precisions) on an RSA RVE: two
+    iterations of load case e_1, the tensor column and the residual history
+    against the oracle (the voxel field would need ~20 GB of host memory)."""
+    print(f"\n[case] five-pass 512 precision={precision}", flush=True)
+    ph, _, _ = geom.generate(512, 100, 0.3, 0.2, 7)
+    ref = oracle.homogenize(ph, K_PAPER_CFG, tol=0.0, max_iter=2, lc_mask=1)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize(r, K_PAPER_CFG, 0.0, max_iter=2, precision=precision, lc_mask=1, hist_cap=4)
+    bar = 1e-11 if precision == 1 else 3e-5
+    assert tensor_err(g.K[:, 0], ref.K[:, 0]) <= bar
+    np.testing.assert_allclose(g.history[0], ref.history[0], rtol=bar * 10)
+
+
 def test_five_pass_256_fp64_vs_oracle():
     """FP64 at 256^3 runs the five-pass form (the xy-plane does not fit in
     LDS): two iterations of load case e_1, voxel by voxel against the oracle."""
