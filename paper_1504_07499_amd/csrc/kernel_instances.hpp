@@ -88,6 +88,7 @@ template <typename T, int N> struct Instance {
     // split planes: the fused pass writes the parity layout (k_inv_plane with
     // S = 2), read back by the z pass
     static constexpr bool PARF = !FIVE && S == 2 && ztile_par_ok<N, ztile<T, N>()>();
+    static constexpr int PC = par_chunk<T, ztile<T, N>()>();  // parity-layout chunk
     template <bool PHI, bool PAR = false> static void fwd_t(const LaunchArgs &a, hipStream_t s, int lc_sel) {
         if constexpr (FIVE) {
             hipLaunchKernelGGL((k_fwd_rows<T, N, G, NTR, PHI>), dim3(9 * N * (N / G)), dim3(NTR), 0, s,
@@ -97,7 +98,7 @@ template <typename T, int N> struct Instance {
                                s, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw,
                                (const DevState *)a.st);
         } else if constexpr (PAR) {
-            hipLaunchKernelGGL((k_fwd_plane<T, N, SP, NTP, false, 3, true>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s,
+            hipLaunchKernelGGL((k_fwd_plane<T, N, SP, NTP, false, 3, true, PC>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s,
                                (const T *)a.e, a.ph, (Cx<T> *)a.spec2, (Cx<T> *)a.nyq2,
                                (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st, ch0(lc_sel));
         } else {
@@ -165,7 +166,7 @@ template <typename T, int N> struct Instance {
                                (T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
                                (const DevState *)a.st, a.part, ch0(lc_sel), (Cx<T> *)nullptr, (Cx<T> *)nullptr);
         } else if constexpr (PARF) {
-            hipLaunchKernelGGL((k_inv_plane<T, N, 2, NTP, true, AL>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s,
+            hipLaunchKernelGGL((k_inv_plane<T, N, 2, NTP, true, AL, 3, PC>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s,
                                (T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
                                (const DevState *)a.st, a.part, ch0(lc_sel), (Cx<T> *)a.spec2, (Cx<T> *)a.nyq2);
         }

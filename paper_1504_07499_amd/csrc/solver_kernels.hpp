@@ -449,6 +449,18 @@ __device__ __forceinline__ void dual_update(T *a, const T *c, unsigned p, T wd0,
     }
 }
 
+// The parity layout of split planes interleaves the two parities' rows in
+// chunks of PC columns: element (parity h, row m < N/2, column kx) of a
+// (channel, z) plane sits at m N + (kx / PC) 2 PC + h PC + kx % PC.  PC is
+// the smallest multiple of the z-tile width W that fills a 128-byte line, so
+// each workgroup of the plane pass writes whole lines, and a z tile finds
+// the two parities of its row next to each other (one DRAM page) instead of
+// N/2 rows apart.
+template <typename T, int W> constexpr int par_chunk() {
+    constexpr int wb = W * (int)sizeof(Cx<T>);
+    return W * ((128 + wb - 1) / wb);
+}
+
 // Forward transform of a split plane after its x transform (S = 2, rows of
 // pitch N/2 + 1 in LDS, the N/2 rows of parity h).  Without PAR the rows
 // are the parity-h combinations of a decimation in frequency (rows y and
@@ -457,12 +469,14 @@ __device__ __forceinline__ void dual_update(T *a, const T *c, unsigned p, T wd0,
 // the rows are the samples y = 2 m + h themselves (decimation in time): the
 // y transform gives E (h = 0) or O (h = 1) with X[ky] = E[ky] + w_N^ky O[ky]
 // and X[ky + N/2] = E[ky] - w_N^ky O[ky] for ky < N/2, and this pass stores
-// E and w_N^ky O as rows ky and N/2 + ky of a parity-layout spectrum that
-// the z pass combines.
-template <typename T, int N, int NT, bool PAR>
+// E and w_N^ky O as parity h of row ky of the parity layout (chunks of PC
+// columns, par_chunk), which the z pass combines; the kx = N/2 column goes
+// to rows ky and N/2 + ky of its own array.
+template <typename T, int N, int NT, bool PAR, int PC = 2>
 __device__ __forceinline__ void split_fwd_tail(Cx<T> *plane, const Cx<T> *__restrict__ tw, Cx<T> *sb, Cx<T> *nb,
                                                int h, int tid) {
     constexpr int H = N / 2, RS = H + 1, ROWS = N / 2;
+    static_assert(!PAR || (PC % 2 == 0 && H % PC == 0), "parity chunks of column pairs that tile a row");
     for (int idx = tid; idx < ROWS * (H / 2 + 1); idx += NT) {
         const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
         if (!PAR && h) r2c_unpack<T, N, true>(plane + y * RS, k, tw, tw[y]);  // w_N^y of the parity split
@@ -480,7 +494,7 @@ __device__ __forceinline__ void split_fwd_tail(Cx<T> *plane, const Cx<T> *__rest
                 v0 = v0 * w;
                 v1 = v1 * w;
             }
-            gstore2<T>(sb + (size_t)(h * H + m) * H + kx, v0, v1);
+            gstore2<T>(sb + (size_t)m * N + (kx / PC) * (2 * PC) + h * PC + kx % PC, v0, v1);
         }
         for (int m = tid; m < ROWS; m += NT) nb[h * H + m] = h ? plane[m * RS + H] * tw[m] : plane[m * RS + H];
     } else {
@@ -527,7 +541,7 @@ template <int N, int S> __device__ __forceinline__ void plane_of_block(int b, in
 // P1: tau = (k - k0) e fused into the load; 2D R2C of the (ch, z) plane.
 // With PHI the same pass transforms the flux k e for the equilibrium check.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int S, int NT, bool PHI = false, int NC = 3, bool PAR = false>
+template <typename T, int N, int S, int NT, bool PHI = false, int NC = 3, bool PAR = false, int PC = 2>
 __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_plane(const T *__restrict__ e, const uint8_t *__restrict__ ph,
                                                   Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
                                                   const Cx<T> *__restrict__ twg,
@@ -623,7 +637,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
         fft_stages<T, ROWS, 0, num_stages(ROWS) - 1, false, H, RS, NT, N, SeqStride<1>, PMY>(plane, tw, tid);
         y_last_stage_store<T, N, NT, RS>(plane, tw, sb, nb, tid);
     } else {
-        split_fwd_tail<T, N, NT, PAR>(plane, tw, sb, nb, h, tid);
+        split_fwd_tail<T, N, NT, PAR, PC>(plane, tw, sb, nb, h, tid);
     }
 }
 
@@ -654,9 +668,9 @@ template <typename T, int N, int W> __device__ __forceinline__ int ztile_of(int 
 
 // Tile of the t-th workgroup of a load case when the z pass reads a
 // parity-layout spectrum: the tiles of rows ky and ky + N/2 read the same
-// two rows ky mod N/2 and N/2 + ky mod N/2, and neighbouring kx chunks share
-// 128-byte lines, so the four tiles {ky, ky + N/2} x {chunks 2j, 2j + 1}
-// get workgroups 8 apart (one XCD, whose L2 then serves the repeated reads).
+// parity data of row ky mod N/2, and neighbouring kx tiles share 128-byte
+// lines, so the four tiles {ky, ky + N/2} x {tiles 2j, 2j + 1} get
+// workgroups 8 apart (one XCD, whose L2 then serves the repeated reads).
 // The same for the Nyquist column's tiles of W rows.
 template <int N, int W> constexpr bool ztile_par_ok() {
     return (N / 2 / W) % 2 == 0 && ZTiles<N, W>::MAIN % 32 == 0 && ZTiles<N, W>::NYQ % 32 == 0;
@@ -759,8 +773,9 @@ template <typename T, int N, int W> constexpr int zpass_min_waves() {
 }
 
 // PAR: the forward spectrum arrives in the parity layout of split_fwd_tail
-// (specB, nyqB): the tile of row ky reads rows ky mod N/2 and N/2 + ky mod N/2
-// and forms X[ky] = B[ky mod N/2] +- B[N/2 + ky mod N/2] (+ for ky < N/2) as
+// (specB, nyqB): the tile of row ky reads both parities E, w O of row
+// ky mod N/2 (neighbouring chunks of one row in specB; rows ky mod N/2 and
+// N/2 + ky mod N/2 in nyqB) and forms X[ky] = E +- w O (+ for ky < N/2) as
 // it loads; the result goes to spec / nyq in the plain layout.
 template <typename T, int N, int W, int NT, bool PAR = false>
 __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
@@ -795,7 +810,7 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
     if (s_done) return;
     Cx<T> *base;
     const Cx<T> *pbase = nullptr;  // PAR: row ky mod N/2 of the parity layout
-    size_t cstride, zstride, poff = 0;  // poff: from that row to row N/2 + ky mod N/2
+    size_t cstride, zstride, poff = 0;  // poff: from parity 0 to parity 1
     int kx0, ky0, dkx, dky;  // kx(w) = kx0 + dkx*w, ky(w) = ky0 + dky*w
     if (t < TL::MAIN) {
         const int ky = t / (H / W);
@@ -804,8 +819,13 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
         dkx = 1;
         dky = 0;
         base = spec + (size_t)(3 * lc) * N * N * H + (size_t)ky * H + kx0;
-        if constexpr (PAR) pbase = specB + (size_t)(3 * lc) * N * N * H + (size_t)(ky % H) * H + kx0;
-        poff = (size_t)H * H;
+        // the parity layout: row ky mod N/2, the tile's chunk, parity 0 and
+        // (poff further) parity 1
+        constexpr int PC = par_chunk<T, W>();
+        static_assert(!PAR || (PC % W == 0 && H % PC == 0), "z tiles inside parity chunks");
+        if constexpr (PAR)
+            pbase = specB + (size_t)(3 * lc) * N * N * H + (size_t)(ky % H) * N + (kx0 / PC) * (2 * PC) + kx0 % PC;
+        poff = PC;
         cstride = (size_t)N * N * H;
         zstride = (size_t)N * H;
     } else {
@@ -1137,7 +1157,7 @@ template <typename T, int N, int NT, int RS> struct YFirstStage {
 // is replaced by E).
 // UPD: the update of steps 6-7: 0 accelerated (and basic), 1 augmented
 // Lagrangian / polarization, 2 dual.
-template <typename T, int N, int S, int NT, bool FWD = false, int UPD = 0, int NC = 3>
+template <typename T, int N, int S, int NT, bool FWD = false, int UPD = 0, int NC = 3, int PC = 2>
 __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_plane(T *__restrict__ e, const uint8_t *__restrict__ ph,
                                                   Cx<T> *__restrict__ spec,
                                                   Cx<T> *__restrict__ nyq,
@@ -1359,7 +1379,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
             y_last_stage_store<T, N, NT, RS>(plane, twf, spec + ((size_t)ch * N + z) * N * H,
                                              nyq + ((size_t)ch * N + z) * N, tid);
         } else {
-            split_fwd_tail<T, N, NT, true>(plane, twf, specB + ((size_t)ch * N + z) * N * H,
+            split_fwd_tail<T, N, NT, true, PC>(plane, twf, specB + ((size_t)ch * N + z) * N * H,
                                            nyqB + ((size_t)ch * N + z) * N, h, tid);
         }
     }
