@@ -154,6 +154,25 @@ def test_equilibrium_error_fp64(n):
     assert tensor_err(g2.K, ref2.K) <= 1e-9
 
 
+@pytest.mark.parametrize("n,precision", [(128, 0), (144, 1), (192, 1), (256, 0), (256, 1)])
+def test_equilibrium_error_at_exit_every_path(n, precision):
+    """eps_eq reported at exit, on the paths whose flux transform differs from
+    the 16^3-32^3 whole planes: whole planes in FP32 (128), split planes in
+    FP64 (144; 192, whose iterations use the parity layout), split planes in
+    FP32 and the five-pass form (256).  Checked against the oracle's
+    equilibrium error of the final field the GPU returns, load case by load
+    case (the FP32 flux transform rounds at ~1e-6 of the flux)."""
+    print(f"\n[case] eps_eq at exit n={n} precision={precision}", flush=True)
+    ph, _, _ = geom.generate(n, 30, 0.3, 0.2, 11)
+    with rh.rve_create_from_phases(ph) as r:
+        g = rh.homogenize(r, K_PAPER_CFG, 0.0, max_iter=6, precision=precision, want_field=True)
+    kvox = np.asarray(K_PAPER_CFG)[ph]
+    for j in range(3):
+        ref = oracle.equilibrium_error(kvox, g.field[j])
+        assert ref > 0
+        assert abs(g.eps_eq[j] - ref) <= (1e-9 if precision == 1 else 1e-3) * ref, (j, g.eps_eq[j], ref)
+
+
 def _golden_all():
     import json
     import os
