@@ -143,7 +143,8 @@ def traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, n, rb, copy_bytes=
         tn = timing_name(name)
         # the pass as the solve loop runs it: the parity-layout z pass where
         # there is one (template argument 5), else the largest traffic
-        par = short_name(name).rstrip(">").endswith("true")
+        targs = short_name(name).split("<", 1)[1].rstrip(">").split(", ") if "<" in short_name(name) else []
+        par = len(targs) > 4 and targs[4] == "true"
         if tn and (tn not in keys or (tn == "zgreen" and par)):
             keys[tn] = (f, w)
     if source_hash:
