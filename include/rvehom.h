@@ -111,13 +111,19 @@ typedef struct {
                                grid is allocated on first use and cached on the handle.
                                -1 = off: the load case ends RVE_STALLED with the last FP32 K. */
     int path_flags;         /* measurement switches, 0 = the library's choice.  Results do not
-                               depend on them (the same arithmetic in the same order):
+                               depend on them (the same arithmetic in the same order) but
+                               where noted for 64 / 128:
                                1 = launch kernel by kernel instead of replaying iteration graphs,
                                2 = separate inverse and forward plane passes instead of the
                                    fused one, 4 = the reduction as a launch of its own instead
                                of inside the next z pass, 8 = one stream for the three load
                                cases instead of three concurrent chains, 16 / 32 = the default /
-                               the alternative z-pass tile width instead of the autotuned one */
+                               the alternative z-pass tile width instead of the autotuned one;
+                               64 / 128 = the default / the alternative thread count of the
+                               fused plane pass instead of the autotuned one (the same
+                               arithmetic per voxel, up to the compiler's instruction choice
+                               for each shape, and another grouping of the FP64 partial sums
+                               of eps_comp and the flux: results agree to rounding) */
     double alpha;           /* scheme 4: the relaxation alpha in (0, 2]; 0 = default 2 */
 } rve_opts;
 
@@ -151,10 +157,14 @@ typedef struct {
 rve_status rve_supported_n(int precision, int *out, int cap, int *count);
 
 /* The autotuner's choices.  The first solve of each (GPU architecture,
- * precision, N) in a process times the z pass at its two tile widths and
- * keeps the faster (the results do not depend on the choice).  The choices
- * are text lines "<gfx arch> <precision 0|1> <n> ztile <0|1>" (1 = the
- * other width).
+ * precision, N) in a process times the z pass at its two tile widths, and
+ * the fused plane pass (grids whose whole xy-plane fits in LDS) at its two
+ * thread counts per workgroup, and keeps the faster of each (path_flags 16
+ * to 128 fix them instead).  The z-tile choice does not change a result;
+ * the plane choice changes results at rounding level only.  The
+ * choices are text lines "<gfx arch> <precision 0|1> <n> ztile <0|1>" and
+ * "<gfx arch> <precision 0|1> <n> plane <0|1>" (1 = the other width or
+ * thread count).
  * rve_tune_export: copies the choices made or imported in this process into
  *   buf (at most cap - 1 characters, then a terminating 0; buf may be null
  *   with cap 0) and returns the size needed including the terminating 0.
@@ -218,7 +228,10 @@ rve_status homogenize(rve_t rve, const double k_phases[3], double tol, const rve
  * with fp32_refine the FP64 workspace of the continuation, must fit in
  * 64 MiB (N <= 64); larger grids give RVE_ERR_ARG with the bytes needed.
  * Honoured opts: precision, max_iter, stall_window, lc_mask, scheme,
- * fp32_refine, stream and the path_flags 2, 4 and 32; init_field, out_field,
+ * fp32_refine, stream and the path_flags 2, 4 and 16 to 128 (without them the
+ * z-tile width and the fused pass's thread count are the autotuner's choices
+ * made or imported in this process for the grid, else the defaults: this
+ * call times nothing); init_field, out_field,
  * workspace, timing or equilibrium_check give RVE_ERR_ARG.  solve_ms is
  * host wall time.  Calls on one GPU share its array: the library
  * serialises calls from threads of one process on a GPU (each call leaves

@@ -210,7 +210,8 @@ def rve_supported_n(precision: int = 0) -> list:
 
 def rve_tune_export() -> str:
     """The autotuner's choices of this process, as text lines
-    "<gfx arch> <precision> <n> ztile <0|1>"."""
+    "<gfx arch> <precision> <n> ztile <0|1>" (z-pass tile width) and
+    "<gfx arch> <precision> <n> plane <0|1>" (fused plane pass threads)."""
     need = int(_lib.rve_tune_export(None, 0))
     buf = ctypes.create_string_buffer(need)
     _lib.rve_tune_export(buf, need)
@@ -323,6 +324,7 @@ SCHEMES = {"accelerated": 0, "basic": 1, "augmented_lagrangian": 2, "dual": 3, "
 # measurement switches of rve_opts.path_flags (results do not depend on them)
 PATH_NO_GRAPHS, PATH_NO_FUSED, PATH_NO_MERGE, PATH_NO_CHAINS = 1, 2, 4, 8
 PATH_ZTILE_DEFAULT, PATH_ZTILE_ALT = 16, 32
+PATH_PLANE_DEFAULT, PATH_PLANE_ALT = 64, 128
 
 
 def _opts(max_iter=0, precision=0, equilibrium_check=False, stall_window=-1, lc_mask=7,

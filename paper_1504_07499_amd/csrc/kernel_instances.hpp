@@ -67,6 +67,18 @@ template <typename T, int N> constexpr int plane_threads() {
     return (elems * sizeof(Cx<T>) > 48 * 1024) ? 512 : 256;
 }
 
+// The other thread count the autotuner tries for the fused pass of whole
+// planes: 512 where the default is 256 (more threads per plane, for the
+// small grids whose launches do not fill the GPU), 256 where it is 512 (more
+// workgroups per CU where registers allow); split planes and the five-pass
+// form have one shape.  Both run the same arithmetic per voxel (up to the
+// compiler's instruction choice for each shape) and group the FP64 partial
+// sums differently: results agree to rounding.
+template <typename T, int N> constexpr int plane_threads_alt() {
+    if constexpr (plane_split<T, N>() != 1) return plane_threads<T, N>();
+    return plane_threads<T, N>() == 256 ? 512 : 256;
+}
+
 template <typename T, int N> struct Instance {
     static constexpr int S = plane_split<T, N>();
     static constexpr bool FIVE = (S == 0);  // plane does not fit in LDS
@@ -171,6 +183,18 @@ template <typename T, int N> struct Instance {
                                (const DevState *)a.st, a.part, ch0(lc_sel), (Cx<T> *)a.spec2, (Cx<T> *)a.nyq2);
         }
     }
+    static constexpr int NTP2 = plane_threads_alt<T, N>();
+    static constexpr bool FUSED2 = FUSED && NTP2 != NTP;
+    template <int AL> static void inv_fwd2_t(const LaunchArgs &a, hipStream_t s, int lc_sel) {
+        if constexpr (FUSED2) {
+            hipLaunchKernelGGL((k_inv_plane<T, N, 1, NTP2, true, AL>), dim3(pgrid(lc_sel)), dim3(NTP2), 0, s,
+                               (T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
+                               (const DevState *)a.st, a.part, ch0(lc_sel), (Cx<T> *)nullptr, (Cx<T> *)nullptr);
+        }
+    }
+    static void inv_fwd2(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_fwd2_t<0>(a, s, lc_sel); }
+    static void inv_fwd2_al(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_fwd2_t<1>(a, s, lc_sel); }
+    static void inv_fwd2_dual(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_fwd2_t<2>(a, s, lc_sel); }
     static void inv_fwd(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_fwd_t<0>(a, s, lc_sel); }
     static void inv_fwd_al(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_fwd_t<1>(a, s, lc_sel); }
     static void inv_fwd_dual(const LaunchArgs &a, hipStream_t s, int lc_sel) { inv_fwd_t<2>(a, s, lc_sel); }
@@ -231,6 +255,8 @@ template <typename T, int N> struct Instance {
             PARF ? &zgreen_par : nullptr,
             (FUSED || PARF) ? &inv_fwd_dual : nullptr,
             &inv_dual,
+            FUSED2 ? NTP2 : 0,
+            {FUSED2 ? &inv_fwd2 : nullptr, FUSED2 ? &inv_fwd2_al : nullptr, FUSED2 ? &inv_fwd2_dual : nullptr},
         };
         return &o;
     }

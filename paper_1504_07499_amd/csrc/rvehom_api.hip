@@ -562,23 +562,60 @@ SolverOpts resolve_opts(const rve_opts *opts) {
     o.scheme = opts ? opts->scheme : 0;
     o.fp32_refine = (opts && opts->fp32_refine < 0) ? -1 : 0;
     o.alpha = (opts && opts->alpha != 0.0) ? opts->alpha : 2.0;
-    o.path_flags = opts ? (opts->path_flags & 63) : 0;
+    o.path_flags = opts ? (opts->path_flags & 255) : 0;
     return o;
 }
 
 // Enqueue init (and optional warm start) on s.
-// Autotuner: the first solve of each (precision, N) in the process times the
-// z pass at its two tile widths on this workspace (before the first forward
-// pass overwrites the spectrum) and keeps the faster; differences under 3 %
-// keep the default.  The z transform of a pencil does not depend on the tile
-// width, so the choice never changes a result.  PF_ZTILE_DEFAULT /
-// PF_ZTILE_ALT force the default / the other width.
-// The choices are kept per (GPU architecture, precision, N) and can be
-// exported and imported as text (rve_tune_export / rve_tune_import), so a
-// later process on the same architecture skips the timing.
+// Autotuner: the first solve of each (precision, N) in the process times,
+// on this workspace and before the solve proper,
+// * the z pass at its two tile widths (before the first forward pass
+//   overwrites the spectrum).  The z transform of a pencil does not depend
+//   on the tile width, so the choice never changes a result.
+//   PF_ZTILE_DEFAULT / PF_ZTILE_ALT force the default / the other width;
+// * the fused plane pass at its two thread counts per workgroup (whole
+//   planes only; the field it overwrites is initialised again after).  The
+//   arithmetic per voxel is the same up to the compiler's instruction
+//   choice for each shape; the grouping of the FP64 partial sums differs,
+//   so results agree to rounding.  PF_PLANE_DEFAULT / PF_PLANE_ALT force
+//   the choice.
+// Each keeps the faster, differences under 3 % keeping the default.  The
+// choices are kept per (GPU architecture, precision, N) and can be exported
+// and imported as text (rve_tune_export / rve_tune_import), so a later
+// process on the same architecture skips the timing.
 using TuneKey = std::tuple<std::string, int, int>;  // gfx arch, precision, N
 static std::mutex g_tune_mu;
-static std::map<TuneKey, int> g_ztune;
+static std::map<TuneKey, int> g_ztune, g_ptune;
+
+// Times fa then fb, reps launches each after one untimed launch of each
+// (code load), on stream s; alt_wins = fb took under 0.97 of fa's time.
+template <class FA, class FB> static int time_two(hipStream_t s, FA fa, FB fb, bool &alt_wins) {
+    constexpr int reps = 6;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    int rc = RVE_OK;
+    float t0 = 0.f, t1 = 0.f;
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) rc = RVE_ERR_DEVICE;
+    if (rc == RVE_OK) {
+        fa();
+        fb();
+        bool ok = hipEventRecord(ev[0], s) == hipSuccess;
+        for (int i = 0; i < reps; ++i) fa();
+        ok = ok && hipEventRecord(ev[1], s) == hipSuccess;
+        for (int i = 0; i < reps; ++i) fb();
+        ok = ok && hipEventRecord(ev[2], s) == hipSuccess;
+        ok = ok && hipGetLastError() == hipSuccess && hipEventSynchronize(ev[2]) == hipSuccess &&
+             hipEventElapsedTime(&t0, ev[0], ev[1]) == hipSuccess && hipEventElapsedTime(&t1, ev[1], ev[2]) == hipSuccess;
+        if (!ok) {
+            set_error("autotuner: timing launches failed");
+            rc = RVE_ERR_DEVICE;
+        }
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    alt_wins = rc == RVE_OK && t1 < 0.97f * t0;
+    return rc;
+}
 
 // gfx architecture name of the current device ("gfx950"), or "" on failure.
 static std::string current_arch() {
@@ -613,23 +650,57 @@ int Solver::tune_zpass(const LaunchArgs &a, hipStream_t s) {
             return RVE_OK;
         }
     }
-    hipEvent_t ev[3];
-    for (auto &e : ev) HIP_CHECK(hipEventCreate(&e));
-    constexpr int reps = 6;
-    ops->zgreen(a, s, 0, -1);  // first launches (code load) outside the timing
-    ops->zgreen_alt(a, s, 0, -1);
-    HIP_CHECK(hipEventRecord(ev[0], s));
-    for (int i = 0; i < reps; ++i) ops->zgreen(a, s, 0, -1);
-    HIP_CHECK(hipEventRecord(ev[1], s));
-    for (int i = 0; i < reps; ++i) ops->zgreen_alt(a, s, 0, -1);
-    HIP_CHECK(hipEventRecord(ev[2], s));
-    HIP_CHECK(hipEventSynchronize(ev[2]));
-    float t0 = 0.f, t1 = 0.f;
-    HIP_CHECK(hipEventElapsedTime(&t0, ev[0], ev[1]));
-    HIP_CHECK(hipEventElapsedTime(&t1, ev[1], ev[2]));
-    for (auto &e : ev) (void)hipEventDestroy(e);
+    bool alt = false;
+    const int rc = time_two(
+        s, [&] { ops->zgreen(a, s, 0, -1); }, [&] { ops->zgreen_alt(a, s, 0, -1); }, alt);
+    if (rc != RVE_OK) return rc;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    zvar = g_ztune.emplace(key, t1 < 0.97f * t0 ? 1 : 0).first->second;
+    zvar = g_ztune.emplace(key, alt ? 1 : 0).first->second;
+    return RVE_OK;
+}
+
+// The choices the autotuner made or imported for this grid in this process,
+// without timing (0 where there is none); path_flags force them.
+void tuned_choices(const SolverOps *ops, int path_flags, int &zvar, int &pvar) {
+    const TuneKey key{current_arch(), ops->precision, ops->n};
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto iz = g_ztune.find(key);
+    auto ip = g_ptune.find(key);
+    zvar = ops->zgreen_alt ? (path_flags & (PF_ZTILE_DEFAULT | PF_ZTILE_ALT) ? (path_flags & PF_ZTILE_ALT ? 1 : 0)
+                                                                             : (iz != g_ztune.end() ? iz->second : 0))
+                           : 0;
+    pvar = ops->inv_fwd_alt[0] ? (path_flags & (PF_PLANE_DEFAULT | PF_PLANE_ALT) ? (path_flags & PF_PLANE_ALT ? 1 : 0)
+                                                                                 : (ip != g_ptune.end() ? ip->second : 0))
+                               : 0;
+}
+
+// ran: the timing launched the fused pass (the caller then initialises the
+// field again).  Needs the state initialised (no load case frozen), so that
+// every workgroup does its whole work.
+int Solver::tune_plane(const LaunchArgs &a, hipStream_t s, bool &ran) {
+    ran = false;
+    pvar = 0;
+    if (!ops->inv_fwd_alt[0]) return RVE_OK;
+    if (path_flags & (PF_PLANE_DEFAULT | PF_PLANE_ALT)) {
+        pvar = (path_flags & PF_PLANE_ALT) ? 1 : 0;
+        return RVE_OK;
+    }
+    const TuneKey key{current_arch(), ops->precision, ops->n};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_ptune.find(key);
+        if (it != g_ptune.end()) {
+            pvar = it->second;
+            return RVE_OK;
+        }
+    }
+    bool alt = false;
+    ran = true;
+    const int rc = time_two(
+        s, [&] { ops->inv_fwd(a, s, -1); }, [&] { ops->inv_fwd_alt[0](a, s, -1); }, alt);
+    if (rc != RVE_OK) return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    pvar = g_ptune.emplace(key, alt ? 1 : 0).first->second;
     return RVE_OK;
 }
 
@@ -637,12 +708,13 @@ extern "C" size_t rve_tune_export(char *buf, size_t cap) {
     std::string text;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        for (const auto &kv : g_ztune) {
-            char line[160];
-            std::snprintf(line, sizeof line, "%s %d %d ztile %d\n", std::get<0>(kv.first).c_str(),
-                          std::get<1>(kv.first), std::get<2>(kv.first), kv.second);
-            text += line;
-        }
+        for (int kind = 0; kind < 2; ++kind)
+            for (const auto &kv : kind ? g_ptune : g_ztune) {
+                char line[160];
+                std::snprintf(line, sizeof line, "%s %d %d %s %d\n", std::get<0>(kv.first).c_str(),
+                              std::get<1>(kv.first), std::get<2>(kv.first), kind ? "plane" : "ztile", kv.second);
+                text += line;
+            }
     }
     if (buf && cap > 0) {
         const size_t m = std::min(cap - 1, text.size());
@@ -658,7 +730,7 @@ extern "C" rve_status rve_tune_import(const char *text) {
         set_error("rve_tune_import: text is null");
         return RVE_ERR_ARG;
     }
-    std::vector<std::pair<TuneKey, int>> add;
+    std::vector<std::pair<TuneKey, int>> add[2];  // ztile, plane
     const char *p = text;
     int lineno = 0;
     while (*p) {
@@ -670,15 +742,18 @@ extern "C" rve_status rve_tune_import(const char *text) {
         char arch[64], kind[16];
         int prec = -1, n = 0, choice = -1, used = 0;
         if (std::sscanf(line.c_str(), "%63s %d %d %15s %d %n", arch, &prec, &n, kind, &choice, &used) != 5 ||
-            line.find_first_not_of(" \t\r", used) != std::string::npos || std::strcmp(kind, "ztile") != 0 ||
-            (prec != 0 && prec != 1) || n <= 0 || (choice != 0 && choice != 1)) {
-            set_error("rve_tune_import: line %d is not \"<arch> <precision 0|1> <n> ztile <0|1>\"", lineno);
+            line.find_first_not_of(" \t\r", used) != std::string::npos ||
+            (std::strcmp(kind, "ztile") != 0 && std::strcmp(kind, "plane") != 0) || (prec != 0 && prec != 1) ||
+            n <= 0 || (choice != 0 && choice != 1)) {
+            set_error("rve_tune_import: line %d is not \"<arch> <precision 0|1> <n> <ztile|plane> <0|1>\"",
+                      lineno);
             return RVE_ERR_ARG;
         }
-        add.push_back({TuneKey{arch, prec, n}, choice});
+        add[std::strcmp(kind, "plane") == 0].push_back({TuneKey{arch, prec, n}, choice});
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    for (const auto &kv : add) g_ztune[kv.first] = kv.second;
+    for (const auto &kv : add[0]) g_ztune[kv.first] = kv.second;
+    for (const auto &kv : add[1]) g_ptune[kv.first] = kv.second;
     return RVE_OK;
 }
 
@@ -715,6 +790,18 @@ int Solver::start(const uint8_t *d_phase, const SolverOpts &o, hipStream_t s) {
     if (!par_z) {
         rc = tune_zpass(a, s);
         if (rc != RVE_OK) return rc;
+    }
+    // the fused pass's thread count (whole planes; the timing overwrites the
+    // field, initialised again here)
+    pvar = 0;
+    if (!o.eq_check && !(o.path_flags & PF_NO_FUSED)) {
+        bool ran = false;
+        rc = tune_plane(a, s, ran);
+        if (rc != RVE_OK) return rc;
+        if (ran) {
+            ops->init(a, M, s);
+            HIP_CHECK(hipGetLastError());
+        }
     }
     if (o.dev_init_ops) {
         // continuation: each solved load case starts from its field in another
@@ -787,7 +874,7 @@ int Solver::launch_iteration(const LaunchArgs &a, hipStream_t s, int mask, hipEv
             (fused && ops->zgreen_par ? ops->zgreen_par : zvar ? ops->zgreen_alt : ops->zgreen)(
                 a, s, red_in_z ? ops->nper : 0, lc_sel);
             break;
-        case 2: inv_launcher(ops, fused, al, dual)(a, s, lc_sel); break;
+        case 2: inv_launcher(ops, fused, al, dual, pvar)(a, s, lc_sel); break;
         default: ops->reduce(a, ops->nper, s); break;
         }
         if (timed) {
@@ -835,6 +922,7 @@ GraphKey Solver::graph_key(const uint8_t *d_phase) const {
     k.dual = dual;
     k.lc = lc_sel;
     k.zvar = zvar;
+    k.pvar = pvar;
     return k;
 }
 
@@ -1132,7 +1220,7 @@ SolverOpts refine_opts(const SolverOpts &o, const rve_result &res, int mask, con
     o64.out_field = nullptr;
     o64.workspace = nullptr;
     o64.workspace_bytes = 0;
-    o64.path_flags = o.path_flags & ~(PF_ZTILE_DEFAULT | PF_ZTILE_ALT);
+    o64.path_flags = o.path_flags & ~(PF_ZTILE_DEFAULT | PF_ZTILE_ALT | PF_PLANE_DEFAULT | PF_PLANE_ALT);
     for (int lc = 0; lc < 3; ++lc) o64.dev_init[lc] = src[lc];
     o64.dev_init_ops = ops32;
     return o64;

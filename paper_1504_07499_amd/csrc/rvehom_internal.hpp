@@ -50,7 +50,7 @@ struct SolverOpts {
 };
 
 enum : int { PF_NO_GRAPHS = 1, PF_NO_FUSED = 2, PF_NO_MERGE = 4, PF_NO_CHAINS = 8, PF_ZTILE_DEFAULT = 16,
-             PF_ZTILE_ALT = 32 };
+             PF_ZTILE_ALT = 32, PF_PLANE_DEFAULT = 64, PF_PLANE_ALT = 128 };
 
 struct LaunchRec {
     int kernel;
@@ -76,10 +76,10 @@ struct GraphKey {
     // al / dual: the update kernels of the scheme (the accelerated and basic
     // schemes share theirs, as do the augmented-Lagrangian and polarization)
     bool eq = false, fused = false, merge = false, al = false, dual = false;
-    int lc = -1, zvar = 0;
+    int lc = -1, zvar = 0, pvar = 0;
     bool operator==(const GraphKey &o) const {
         return ops == o.ops && ws == o.ws && ph == o.ph && eq == o.eq && fused == o.fused && merge == o.merge &&
-               al == o.al && dual == o.dual && lc == o.lc && zvar == o.zvar;
+               al == o.al && dual == o.dual && lc == o.lc && zvar == o.zvar && pvar == o.pvar;
     }
 };
 
@@ -128,6 +128,7 @@ struct Solver {
     bool merge = false;  // each reduction runs inside the next iteration's z pass
     int lc_sel = -1;     // -1: all load cases; else the only load case iterated
     int zvar = 0;        // z-pass tile width: 0 default, 1 the other (autotuned)
+    int pvar = 0;        // fused-pass threads per workgroup: 0 default, 1 the other (autotuned)
     bool al = false;     // augmented-Lagrangian family update (schemes 2 and 4)
     bool dual = false;   // dual scheme update (scheme 3)
     int scheme = 0;
@@ -158,6 +159,7 @@ struct Solver {
                       hipStream_t s);
     int start(const uint8_t *d_phase, const SolverOpts &o, hipStream_t s);
     int tune_zpass(const LaunchArgs &a, hipStream_t s);
+    int tune_plane(const LaunchArgs &a, hipStream_t s, bool &ran);
     int enqueue(const uint8_t *d_phase, int count, int max_iter, int timing, hipStream_t s);
     int launch_iteration(const LaunchArgs &a, hipStream_t s, int mask, hipEvent_t *ev, bool red_in_z,
                          bool defer_red);
@@ -172,14 +174,20 @@ struct Solver {
 };
 
 // The inverse pass of an iteration: fused with the next forward pass or
-// not, with the update of the scheme family.
+// not, with the update of the scheme family; pvar: the fused pass at the
+// other thread count per workgroup.
 using InvFn = void (*)(const LaunchArgs &, hipStream_t, int);
-inline InvFn inv_launcher(const SolverOps *ops, bool fused, bool al, bool dual) {
+inline InvFn inv_launcher(const SolverOps *ops, bool fused, bool al, bool dual, int pvar = 0) {
+    if (fused && pvar && ops->inv_fwd_alt[0]) return ops->inv_fwd_alt[dual ? 2 : al ? 1 : 0];
     if (fused) return dual ? ops->inv_fwd_dual : al ? ops->inv_fwd_al : ops->inv_fwd;
     return dual ? ops->inv_dual : al ? ops->inv_al : ops->inv;
 }
 
 const SolverOps *lookup_ops(int precision, int n);
+// the autotuner's z-tile and fused-pass choices for a grid, as made or
+// imported in this process (no timing; defaults where there are none),
+// unless path_flags force them
+void tuned_choices(const SolverOps *ops, int path_flags, int &zvar, int &pvar);
 const SolverOps *lookup_ops_el(int precision, int n);
 void set_error(const char *fmt, ...);
 void clear_error();

@@ -99,7 +99,7 @@ struct NaSolve {
         a.nyq2 = L.nyq2 ? ws + L.nyq2 : nullptr;
     }
 
-    int run(const double k[3], double tol, const SolverOpts &o, hipStream_t s, int zvar, DevState &hs) {
+    int run(const double k[3], double tol, const SolverOpts &o, hipStream_t s, int zvar, int pvar, DevState &hs) {
         const int n = ops->n;
         const size_t M = (size_t)n * n * n;
         // twiddles exp(-2 pi i m / n) in FP64, rounded once, via the stack
@@ -146,7 +146,7 @@ struct NaSolve {
                 const bool red_in_z = merge && i > 0, defer = merge && i + 1 < count;
                 if (!fused) ops->fwd(a, s, -1);
                 zg(a, s, red_in_z ? ops->nper : 0, -1);
-                inv_launcher(ops, fused, al, dual)(a, s, -1);
+                inv_launcher(ops, fused, al, dual, pvar)(a, s, -1);
                 if (!defer) ops->reduce(a, ops->nper, s);
             }
             issued += count;
@@ -253,13 +253,14 @@ extern "C" rve_status homogenize_no_alloc(rve_t r, const double k_phases[3], dou
     if (rc != RVE_OK) return (rve_status)rc;
     std::lock_guard<std::mutex> lk(g_scratch_mu[r->device]);
     hipStream_t s = o.stream;
-    const int zvar = (o.path_flags & PF_ZTILE_ALT) && ops->zgreen_alt ? 1 : 0;
+    int zvar = 0, pvar = 0;
+    tuned_choices(ops, o.path_flags, zvar, pvar);
     const auto t0 = std::chrono::steady_clock::now();
 
     NaSolve a;
     a.bind(ops, (char *)base, r->d_phase);
     DevState hs;
-    rc = a.run(k_phases, tol, o, s, zvar, hs);
+    rc = a.run(k_phases, tol, o, s, zvar, pvar, hs);
     if (rc != RVE_OK) return (rve_status)rc;
     rve_result res{};
     to_result(hs, 7, res);
@@ -276,7 +277,9 @@ extern "C" rve_status homogenize_no_alloc(rve_t r, const double k_phases[3], dou
         NaSolve b;
         b.bind(ops64, (char *)base + ws0, r->d_phase);
         DevState h64;
-        rc = b.run(k_phases, tol, o64, s, 0, h64);
+        int z64 = 0, p64 = 0;
+        tuned_choices(ops64, o64.path_flags, z64, p64);
+        rc = b.run(k_phases, tol, o64, s, z64, p64, h64);
         if (rc != RVE_OK) return (rve_status)rc;
         rve_result r64{};
         to_result(h64, mask, r64);

@@ -78,6 +78,11 @@ struct SolverOps {
     // separate inverse pass
     void (*inv_fwd_dual)(const LaunchArgs &, hipStream_t, int lc_sel);
     void (*inv_dual)(const LaunchArgs &, hipStream_t, int lc_sel);
+    // the fused pass at the other thread count per workgroup that the
+    // autotuner tries (0 / nullptr where there is none): the accelerated
+    // and basic, augmented-Lagrangian and polarization, and dual updates
+    int plane_threads_alt;
+    void (*inv_fwd_alt[3])(const LaunchArgs &, hipStream_t, int lc_sel);
 };
 
 const SolverOps *ops_f32(int n);

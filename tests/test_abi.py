@@ -51,11 +51,15 @@ def test_tune_table_roundtrip(tmp_path):
     call: the table is host state)."""
     if not os.path.exists(_build.hip_lib_path()):
         pytest.skip("HIP library not built")
-    rh.rve_tune_import("gfx950 0 96 ztile 1\n\ngfx942 1 128 ztile 0\n")
+    rh.rve_tune_import("gfx950 0 96 ztile 1\n\ngfx942 1 128 ztile 0\ngfx950 0 64 plane 1\n")
     out = rh.rve_tune_export().splitlines()
-    assert "gfx950 0 96 ztile 1" in out and "gfx942 1 128 ztile 0" in out
+    assert "gfx950 0 96 ztile 1" in out and "gfx942 1 128 ztile 0" in out and "gfx950 0 64 plane 1" in out
+    # a plane choice and a z-tile choice of one grid are separate entries
+    rh.rve_tune_import("gfx950 0 64 ztile 0")
+    out = rh.rve_tune_export().splitlines()
+    assert "gfx950 0 64 plane 1" in out and "gfx950 0 64 ztile 0" in out
     for bad in ("gfx950 0 96 ztile 2", "gfx950 2 96 ztile 0", "gfx950 0 96 wtile 0",
-                "gfx950 0 96 ztile 0 extra", "gfx950 0 ztile 0"):
+                "gfx950 0 96 ztile 0 extra", "gfx950 0 ztile 0", "gfx950 0 96 plane 3"):
         with pytest.raises(rh.RveError) as ei:
             rh.rve_tune_import(bad)
         assert ei.value.status == rh.RVE_ERR_ARG

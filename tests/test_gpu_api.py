@@ -339,6 +339,36 @@ def test_z_tile_widths_give_identical_results(n, precision):
     assert np.array_equal(out[0].iters, out[1].iters)
 
 
+@pytest.mark.parametrize("n,precision", [(32, 1), (64, 0), (128, 0), (48, 1)])
+def test_plane_thread_counts_agree(n, precision):
+    """The autotuner picks one of two thread counts per workgroup for the
+    fused plane pass.  Both run the same arithmetic per voxel (up to the
+    compiler's instruction choice for each shape) and group the FP64
+    partial sums (residual, flux) differently.  The fields after a fixed
+    number of iterations match the oracle's at either count (FP64 within
+    1e-9, FP32 within 3e-5 of the largest value), and the forced
+    alternative converges like the oracle (FP64: the same iteration counts,
+    tensor within 1e-9)."""
+    print(f"\n[case] plane thread counts n={n} precision={precision}", flush=True)
+    ph, _, _ = geom.generate(n, 12, 0.3, 0.2, 31)
+    ref20 = oracle.homogenize(ph, K3, tol=0.0, max_iter=20, want_field=True)
+    scale = np.max(np.abs(ref20.field))
+    bar = 1e-9 if precision == 1 else 3e-5
+    with rh.rve_create_from_phases(ph) as r:
+        for v in (rh.PATH_PLANE_DEFAULT, rh.PATH_PLANE_ALT):
+            g = rh.homogenize(r, K3, 0.0, precision=precision, max_iter=20, want_field=True, path_flags=v)
+            assert np.max(np.abs(g.field - ref20.field)) <= bar * scale
+            assert np.max(np.abs(g.K - ref20.K)) <= bar * np.max(np.abs(ref20.K))
+        if n <= 32 and precision == 1:
+            ref = oracle.homogenize(ph, K3, tol=1e-6)
+            g = rh.homogenize(r, K3, 1e-6, precision=1, path_flags=rh.PATH_PLANE_ALT)
+            assert np.array_equal(g.iters, ref.iters)
+            assert np.max(np.abs(g.K - ref.K)) <= 1e-9 * np.max(np.abs(ref.K))
+        # the autotuned solve leaves a plane choice for this grid in the table
+        rh.homogenize(r, K3, 1e-6, precision=precision, max_iter=5)
+    assert any(ln.split()[1:4] == [str(precision), str(n), "plane"] for ln in rh.rve_tune_export().splitlines())
+
+
 @pytest.mark.parametrize("precision", [1, 0])
 def test_nonfinite_start_field_is_reported(precision):
     """A NaN in the start field of load case e_2 makes its residual
