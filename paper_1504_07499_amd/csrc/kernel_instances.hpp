@@ -101,8 +101,21 @@ template <typename T, int N> struct Instance {
     // S = 2), read back by the z pass
     static constexpr bool PARF = !FIVE && S == 2 && ztile_par_ok<N, ztile<T, N>()>();
     static constexpr int PC = par_chunk<T, ztile<T, N>()>();  // parity-layout chunk
+    // FP64 256^3, whose half plane does not fit in LDS: the fused pass in
+    // quarter planes (S = 4, 132 KiB, one workgroup per CU) with its own
+    // first forward pass and the four-quarter z pass (tiles of one column x
+    // four quarters, 48 KiB; parity chunks of one column); the other passes
+    // keep the five-pass form.  The fused pass writes the five-pass form's
+    // partial slots (N / G per plane).
+    static constexpr bool QF = FIVE && sizeof(T) == 8 && N == 256;
+    static constexpr int NTQ = 512, WQ = 4;
+    static constexpr bool PARX = PARF || QF;  // a parity-layout fused path
     template <bool PHI, bool PAR = false> static void fwd_t(const LaunchArgs &a, hipStream_t s, int lc_sel) {
-        if constexpr (FIVE) {
+        if constexpr (PAR && QF) {
+            hipLaunchKernelGGL((k_fwd_plane<T, N, 4, NTQ, false, 3, true, WQ / 4>), dim3((lc_sel < 0 ? 9 : 3) * N * 4),
+                               dim3(NTQ), 0, s, (const T *)a.e, a.ph, (Cx<T> *)a.spec2, (Cx<T> *)a.nyq2,
+                               (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st, ch0(lc_sel));
+        } else if constexpr (FIVE) {
             hipLaunchKernelGGL((k_fwd_rows<T, N, G, NTR, PHI>), dim3(9 * N * (N / G)), dim3(NTR), 0, s,
                                (const T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq,
                                (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st);
@@ -121,7 +134,7 @@ template <typename T, int N> struct Instance {
     }
     static void fwd(const LaunchArgs &a, hipStream_t s, int lc_sel) { fwd_t<false>(a, s, lc_sel); }
     static void fwd_par(const LaunchArgs &a, hipStream_t s, int lc_sel) {
-        if constexpr (PARF) fwd_t<false, true>(a, s, lc_sel);
+        if constexpr (PARX) fwd_t<false, true>(a, s, lc_sel);
     }
     static void fwd_phi(const LaunchArgs &a, hipStream_t s) { fwd_t<true>(a, s, -1); }
     static void zeq(const LaunchArgs &a, hipStream_t s) {
@@ -133,7 +146,7 @@ template <typename T, int N> struct Instance {
     template <int WV, bool PAR = false>
     static void zgreen_w(const LaunchArgs &a, hipStream_t s, int red_nper, int lc_sel) {
         const int lcs = FIVE || lc_sel < 0 ? 3 : 1;
-        hipLaunchKernelGGL((k_zgreen<T, N, WV, NTZ, PAR>),
+        hipLaunchKernelGGL((k_zgreen<T, N, WV, NTZ, PAR, (PAR && QF) ? 4 : 2>),
                            dim3(lcs * ZTiles<N, WV>::PER_LC + (red_nper > 0 ? 1 : 0)), dim3(NTZ), 0, s,
                            (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, a.st,
                            (const double *)a.part, red_nper, a.hist, lcs == 3 ? 0 : lc_sel,
@@ -148,7 +161,7 @@ template <typename T, int N> struct Instance {
     // the parity layout's z pass (tiles of rows ky and ky + N/2 read the same
     // two parity rows)
     static void zgreen_par(const LaunchArgs &a, hipStream_t s, int red_nper, int lc_sel) {
-        if constexpr (PARF) zgreen_w<W, true>(a, s, red_nper, lc_sel);
+        if constexpr (PARX) zgreen_w<QF ? WQ : W, true>(a, s, red_nper, lc_sel);
     }
     template <int AL> static void inv_t(const LaunchArgs &a, hipStream_t s, int lc_sel) {
         if constexpr (FIVE) {
@@ -181,6 +194,11 @@ template <typename T, int N> struct Instance {
             hipLaunchKernelGGL((k_inv_plane<T, N, 2, NTP, true, AL, 3, PC>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s,
                                (T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
                                (const DevState *)a.st, a.part, ch0(lc_sel), (Cx<T> *)a.spec2, (Cx<T> *)a.nyq2);
+        } else if constexpr (QF) {
+            hipLaunchKernelGGL((k_inv_plane<T, N, 4, NTQ, true, AL, 3, WQ / 4, N / G>), dim3((lc_sel < 0 ? 9 : 3) * N * 4),
+                               dim3(NTQ), 0, s, (T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq,
+                               (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st, a.part, ch0(lc_sel),
+                               (Cx<T> *)a.spec2, (Cx<T> *)a.nyq2);
         }
     }
     static constexpr int NTP2 = plane_threads_alt<T, N>();
@@ -233,8 +251,8 @@ template <typename T, int N> struct Instance {
             {FIVE ? NTR : NTP, NTZ, FIVE ? NTR : NTP},
             {9.0 * M * rb + spec_b + extra, 2.0 * spec_b, spec_b + 2.0 * 9.0 * M * rb + extra},
             ZTiles<N, W>::PER_LC,
-            (FUSED || PARF) ? 2.0 * spec_b + 2.0 * 9.0 * M * rb : 0.0,
-            (FUSED || PARF) ? &inv_fwd : nullptr,
+            (FUSED || PARX) ? 2.0 * spec_b + 2.0 * 9.0 * M * rb : 0.0,
+            (FUSED || PARX) ? &inv_fwd : nullptr,
             &fwd,
             &fwd_phi,
             &zeq,
@@ -245,15 +263,15 @@ template <typename T, int N> struct Instance {
             &init,
             &from_f64,
             &to_f64,
-            (FUSED || PARF) ? &inv_fwd_al : nullptr,
+            (FUSED || PARX) ? &inv_fwd_al : nullptr,
             &inv_al,
             &to_tau,
             3,
             &launch_reduce,
             (double)M,
-            PARF ? &fwd_par : nullptr,
-            PARF ? &zgreen_par : nullptr,
-            (FUSED || PARF) ? &inv_fwd_dual : nullptr,
+            PARX ? &fwd_par : nullptr,
+            PARX ? &zgreen_par : nullptr,
+            (FUSED || PARX) ? &inv_fwd_dual : nullptr,
             &inv_dual,
             FUSED2 ? NTP2 : 0,
             {FUSED2 ? &inv_fwd2 : nullptr, FUSED2 ? &inv_fwd2_al : nullptr, FUSED2 ? &inv_fwd2_dual : nullptr},

@@ -449,54 +449,66 @@ __device__ __forceinline__ void dual_update(T *a, const T *c, unsigned p, T wd0,
     }
 }
 
-// The parity layout of split planes interleaves the two parities' rows in
-// chunks of PC columns: element (parity h, row m < N/2, column kx) of a
-// (channel, z) plane sits at m N + (kx / PC) 2 PC + h PC + kx % PC.  PC is
-// the smallest multiple of the z-tile width W that fills a 128-byte line, so
-// each workgroup of the plane pass writes whole lines, and a z tile finds
-// the two parities of its row next to each other (one DRAM page) instead of
-// N/2 rows apart.
+// The parity layout of split planes interleaves the S parities' rows in
+// chunks of PC columns: element (parity h, row m < N/S, column kx) of a
+// (channel, z) plane sits at m S N/2 + (kx / PC) S PC + h PC + kx % PC.  PC
+// is the smallest multiple of the z-tile width W that fills a 128-byte line,
+// so each workgroup of the plane pass writes whole lines, and a z tile finds
+// the S parities of its row next to each other (one DRAM page) instead of
+// N/S rows apart.
 template <typename T, int W> constexpr int par_chunk() {
     constexpr int wb = W * (int)sizeof(Cx<T>);
     return W * ((128 + wb - 1) / wb);
 }
 
-// Forward transform of a split plane after its x transform (S = 2, rows of
-// pitch N/2 + 1 in LDS, the N/2 rows of parity h).  Without PAR the rows
-// are the parity-h combinations of a decimation in frequency (rows y and
-// y + N/2 summed, or subtracted and turned by w_N^y), and the length-N/2 y
-// transform gives the output rows ky = 2 m + h of the spectrum.  With PAR
-// the rows are the samples y = 2 m + h themselves (decimation in time): the
-// y transform gives E (h = 0) or O (h = 1) with X[ky] = E[ky] + w_N^ky O[ky]
-// and X[ky + N/2] = E[ky] - w_N^ky O[ky] for ky < N/2, and this pass stores
-// E and w_N^ky O as parity h of row ky of the parity layout (chunks of PC
-// columns, par_chunk), which the z pass combines; the kx = N/2 column goes
-// to rows ky and N/2 + ky of its own array.
-template <typename T, int N, int NT, bool PAR, int PC = 2>
+// Forward transform of a split plane after its x transform (S parities,
+// rows of pitch N/2 + 1 in LDS, the N/S rows of parity h).  Without PAR
+// (S = 2 only) the rows are the parity-h combinations of a decimation in
+// frequency (rows y and y + N/2 summed, or subtracted and turned by w_N^y),
+// and the length-N/2 y transform gives the output rows ky = 2 m + h of the
+// spectrum.  With PAR the rows are the samples y = S m + h themselves
+// (decimation in time): the length-N/S y transform gives Z_h, with
+//     X[k + q N/S] = sum_h exp(-2 pi i q h / S) w_N^(k h) Z_h[k],  k < N/S,
+// and this pass stores T_h = w_N^(k h) Z_h as parity h of row k of the
+// parity layout (chunks of PC columns, par_chunk; S = 4: PC = 2), which the
+// z pass combines; the kx = N/2 column goes to row h N/S + k of its own
+// array (S = 4: to (k / PC) 4 PC + h PC + k % PC, rows grouped as the
+// columns).
+template <typename T, int N, int NT, bool PAR, int PC = 2, int S = 2>
 __device__ __forceinline__ void split_fwd_tail(Cx<T> *plane, const Cx<T> *__restrict__ tw, Cx<T> *sb, Cx<T> *nb,
                                                int h, int tid) {
-    constexpr int H = N / 2, RS = H + 1, ROWS = N / 2;
-    static_assert(!PAR || (PC % 2 == 0 && H % PC == 0), "parity chunks of column pairs that tile a row");
+    constexpr int H = N / 2, RS = H + 1, ROWS = N / S;
+    static_assert(!PAR || ((PC == 1 || PC % 2 == 0) && H % PC == 0), "parity chunks that tile a row");
+    static_assert(PAR || S == 2, "the frequency-decimated split is a two-parity one");
     for (int idx = tid; idx < ROWS * (H / 2 + 1); idx += NT) {
         const int y = idx / (H / 2 + 1), k = idx - y * (H / 2 + 1);
         if (!PAR && h) r2c_unpack<T, N, true>(plane + y * RS, k, tw, tw[y]);  // w_N^y of the parity split
         else r2c_unpack<T, N, false>(plane + y * RS, k, tw, Cx<T>{(T)1, (T)0});
     }
     __syncthreads();
-    // y: complex FFT of length N/2 down the N/2 + 1 columns
+    // y: complex FFT of length N/S down the N/2 + 1 columns
     fft_lds<T, ROWS, false, RS, RS, NT, N, SeqStride<1>>(plane, tw, tid);
     if constexpr (PAR) {
         for (int idx = tid; idx < ROWS * H / 2; idx += NT) {
             const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
             Cx<T> v0 = plane[m * RS + kx], v1 = plane[m * RS + kx + 1];
             if (h) {
-                const Cx<T> w = tw[m];
+                const Cx<T> w = tw[m * h];
                 v0 = v0 * w;
                 v1 = v1 * w;
             }
-            gstore2<T>(sb + (size_t)m * N + (kx / PC) * (2 * PC) + h * PC + kx % PC, v0, v1);
+            Cx<T> *o = sb + (size_t)m * (S * H) + (kx / PC) * (S * PC) + h * PC + kx % PC;
+            if constexpr (PC == 1) {
+                o[0] = v0;
+                o[S] = v1;  // column kx + 1: the next chunk
+            } else {
+                gstore2<T>(o, v0, v1);
+            }
         }
-        for (int m = tid; m < ROWS; m += NT) nb[h * H + m] = h ? plane[m * RS + H] * tw[m] : plane[m * RS + H];
+        for (int m = tid; m < ROWS; m += NT) {
+            const int o = S == 4 ? (m / PC) * (4 * PC) + h * PC + m % PC : h * ROWS + m;
+            nb[o] = h ? plane[m * RS + H] * tw[m * h] : plane[m * RS + H];
+        }
     } else {
         for (int idx = tid; idx < ROWS * H / 2; idx += NT) {
             const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
@@ -554,8 +566,8 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
     // 16-byte access, and pairs would double the registers of a butterfly)
     constexpr int PMX = (S == 1 && sizeof(T) == 4) ? kPairElem : kPairNone;
     constexpr int PMY = (S == 1 && sizeof(T) == 4) ? kPairSeq : kPairNone;
-    static_assert(N % 4 == 0 && (S == 1 || S == 2), "plane kernel needs N % 4 == 0");
-    static_assert(!PAR || (S == 2 && !PHI), "the parity layout is a split-plane forward pass");
+    static_assert(N % 4 == 0 && (S == 1 || S == 2 || (S == 4 && PAR)), "plane kernel needs N % 4 == 0");
+    static_assert(!PAR || (S >= 2 && !PHI), "the parity layout is a split-plane forward pass");
     __shared__ Cx<T> plane[ROWS * RS];
     const int tid = threadIdx.x;
     int ch, z, h;
@@ -575,7 +587,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
     const uint8_t *pb = ph + (size_t)z * NN;
 
     // load rows (S = 2: combine rows y and y + N/2 with sign (-1)^h; PAR:
-    // the rows 2 y + h of parity h alone); each batch issues all of its
+    // the rows S y + h of parity h alone); each batch issues all of its
     // global loads before the first use
     constexpr int TOTL = ROWS * N / V, PERL = (TOTL + NT - 1) / NT;
     constexpr int BL = (S == 2 && !PAR) ? 4 : 8;
@@ -588,7 +600,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
             const int idx = tid + (i0 + i) * NT;
             if (i0 + i < PERL && (TOTL % NT == 0 || idx < TOTL)) {
                 const int y = idx / (N / V), x = (idx - y * (N / V)) * V;
-                const int ys = PAR ? 2 * y + h : y;
+                const int ys = PAR ? S * y + h : y;
                 vload<T>(eb + ys * N + x, a[i]);
                 p[i] = pload<V>(pb + ys * N + x);
                 if constexpr (S == 2 && !PAR) {
@@ -637,7 +649,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_fwd_pl
         fft_stages<T, ROWS, 0, num_stages(ROWS) - 1, false, H, RS, NT, N, SeqStride<1>, PMY>(plane, tw, tid);
         y_last_stage_store<T, N, NT, RS>(plane, tw, sb, nb, tid);
     } else {
-        split_fwd_tail<T, N, NT, PAR, PC>(plane, tw, sb, nb, h, tid);
+        split_fwd_tail<T, N, NT, PAR, PC, S>(plane, tw, sb, nb, h, tid);
     }
 }
 
@@ -687,6 +699,25 @@ template <int N, int W> __device__ __forceinline__ int ztile_par(int b) {
         return (kyp + (q >> 1) * H) * C + 2 * j + (q & 1);
     }
     return TL::MAIN + 2 * quad + (q & 1) + (q >> 1) * C;
+}
+
+// z * exp(2 pi i s / 4), a quarter turn s mod 4 (exact: a swap and signs)
+template <int QS, typename T> __device__ __forceinline__ Cx<T> quarter_turn(Cx<T> v) {
+    constexpr int s = QS & 3;
+    if constexpr (s == 0) return v;
+    else if constexpr (s == 1) return Cx<T>{-v.y, v.x};
+    else if constexpr (s == 2) return Cx<T>{-v.x, -v.y};
+    else return Cx<T>{v.y, -v.x};
+}
+
+// sum_h exp(SGN 2 pi i K h / SP) v[h] with K fixed (a DFT of length SP = 2 or
+// 4 at one output index: sums of swapped and negated inputs)
+template <int SP, int K, int SGN, typename T> __device__ __forceinline__ Cx<T> parity_sum(const Cx<T> *v) {
+    Cx<T> x = v[0];
+    if constexpr (SP > 1) x = x + quarter_turn<SGN * (4 / SP) * K * 1>(v[1]);
+    if constexpr (SP > 2) x = x + quarter_turn<SGN * (4 / SP) * K * 2>(v[2]);
+    if constexpr (SP > 3) x = x + quarter_turn<SGN * (4 / SP) * K * 3>(v[3]);
+    return x;
 }
 
 // First stage of a length-N transform (forward, or inverse with INV) of a
@@ -773,11 +804,20 @@ template <typename T, int N, int W> constexpr int zpass_min_waves() {
 }
 
 // PAR: the forward spectrum arrives in the parity layout of split_fwd_tail
-// (specB, nyqB): the tile of row ky reads both parities E, w O of row
-// ky mod N/2 (neighbouring chunks of one row in specB; rows ky mod N/2 and
-// N/2 + ky mod N/2 in nyqB) and forms X[ky] = E +- w O (+ for ky < N/2) as
-// it loads; the result goes to spec / nyq in the plain layout.
-template <typename T, int N, int W, int NT, bool PAR = false>
+// (specB, nyqB).  SP = 2: the tile of row ky reads both parities E, w O of
+// row ky mod N/2 (neighbouring chunks of one row in specB; rows ky mod N/2
+// and N/2 + ky mod N/2 in nyqB) and forms X[ky] = E +- w O (+ for ky < N/2)
+// as it loads; the result goes to spec / nyq in the plain layout.  SP = 4
+// (W = 4 CW, CW = 2 in FP32, 1 in FP64): a tile holds CW columns
+// kx0 .. kx0 + CW - 1 (or CW rows of the kx = N/2 column) of row k < N/4 in
+// all four quarters ky = k + q N/4, W pencils per component ordered
+// p = 4 w + q.  It reads the four parities of its columns (one 64-byte run
+// per z and component: the parity layout's chunks are CW columns), forms
+// X_q = sum_h exp(-2 pi i q h / 4) T_h (a length-4 DFT per column) in LDS,
+// and writes the result in the quarter layout that the quarter-plane pass
+// reads: element (q, k, kx) at k 2N + 4 kx + q (kx = N/2 column: 4 k + q),
+// again one 64-byte run per z and component.
+template <typename T, int N, int W, int NT, bool PAR = false, int SP = 2>
 __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
                                                const Cx<T> *__restrict__ twg,
                                                const DevParams *__restrict__ prm,
@@ -786,7 +826,11 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
                                                const Cx<T> *__restrict__ specB, const Cx<T> *__restrict__ nyqB) {
     using TL = ZTiles<N, W>;
     constexpr int H = N / 2, NW = N * W;
+    constexpr bool Q4 = PAR && SP == 4;
     static_assert(H % W == 0 && N % W == 0 && W % 2 == 0, "tile width must be even and divide N/2");
+    static_assert(SP == 2 || (Q4 && (W == 8 || W == 4) && N % 8 == 0),
+                  "four parities: tiles of W / 4 columns x 4 quarters");
+    constexpr int CW = Q4 ? W / 4 : 1;  // Q4: columns (or kx = N/2 rows) per tile
     static_assert(NT == 256, "the merged reduction runs on a 256-thread workgroup");
     __shared__ Cx<T> buf[3 * NW];
     const int tid = threadIdx.x;
@@ -797,7 +841,7 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
     const int bt = blockIdx.x - (red_nper > 0 ? 1 : 0);
     const int lt = bt / TL::PER_LC;
     int t;
-    if constexpr (PAR) t = ztile_par<N, W>(bt - lt * TL::PER_LC);
+    if constexpr (PAR && !Q4) t = ztile_par<N, W>(bt - lt * TL::PER_LC);
     else t = ztile_of<T, N, W>(bt - lt * TL::PER_LC);
     const int lc = lc0 + lt;  // the grid covers load cases lc0 .. (all three, or one)
     // the freeze flag, read once for the workgroup (the merged reduction of
@@ -812,7 +856,34 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
     const Cx<T> *pbase = nullptr;  // PAR: row ky mod N/2 of the parity layout
     size_t cstride, zstride, poff = 0;  // poff: from parity 0 to parity 1
     int kx0, ky0, dkx, dky;  // kx(w) = kx0 + dkx*w, ky(w) = ky0 + dky*w
-    if (t < TL::MAIN) {
+    if constexpr (Q4) {
+        // the same offset in both layouts: parity layout k 2N + 4 CW j +
+        // CW h + w, quarter layout k 2N + 4 CW j + 4 w + q (j: the tile's
+        // group of CW columns)
+        if (t < TL::MAIN) {
+            const int k = t / (H / CW), j = t - k * (H / CW);
+            kx0 = CW * j;
+            ky0 = k;
+            dkx = 1;
+            dky = 0;
+            const size_t off = (size_t)(3 * lc) * N * N * H + (size_t)k * (4 * H) + 4 * CW * j;
+            base = spec + off;
+            pbase = specB + off;
+            cstride = (size_t)N * N * H;
+            zstride = (size_t)N * H;
+        } else {
+            const int j = t - TL::MAIN;
+            kx0 = H;
+            ky0 = CW * j;
+            dkx = 0;
+            dky = 1;
+            const size_t off = (size_t)(3 * lc) * N * N + 4 * CW * j;
+            base = nyq + off;
+            pbase = nyqB + off;
+            cstride = (size_t)N * N;
+            zstride = N;
+        }
+    } else if (t < TL::MAIN) {
         const int ky = t / (H / W);
         kx0 = (t - ky * (H / W)) * W;
         ky0 = ky;
@@ -848,7 +919,7 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
     ZFirstStage<T, N, W, NT> z0;
     if constexpr (DIRECT) {
         z0.load(base, cstride, zstride, tid);
-    } else if constexpr (PAR) {
+    } else if constexpr (PAR && !Q4) {
         // X = E +- w O from the two parity rows, in batches of loads
         const bool upper = ky0 >= H;  // a tile's rows lie in one half (W divides N/2)
         constexpr int BP = 6;
@@ -876,14 +947,15 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
         }
     } else {
         // two complex values per access, every load of a thread in flight
-        // before the first LDS store
+        // before the first LDS store (Q4: the raw parities, combined below)
+        const Cx<T> *src = Q4 ? pbase : base;
         Cx<T> va[PERP], vb[PERP];
 #pragma unroll
         for (int i = 0; i < PERP; ++i) {
             const int idx = tid + i * NT;
             if (NP % NT == 0 || idx < NP) {
                 const int e0 = 2 * idx, c = e0 / NW, r = e0 - c * NW, zz = r / W, w = r - zz * W;
-                gload2<T>(base + c * cstride + zz * zstride + w, va[i], vb[i]);
+                gload2<T>(src + c * cstride + zz * zstride + w, va[i], vb[i]);
             }
         }
 #pragma unroll
@@ -904,6 +976,25 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
         fft_stages<T, N, 1, num_stages(N), false, 3 * W, W, NT, N, SeqBlocked<W, NW>, kPairNone>(buf, tw, tid);
     } else {
         __syncthreads();
+        if constexpr (Q4) {
+            // per (component, z) row: slots CW h + w -> 4 w + q, X_q the
+            // length-4 DFT over h of column w
+            for (int row = tid; row < 3 * N; row += NT) {
+                Cx<T> v[W];
+#pragma unroll
+                for (int i = 0; i < W; ++i) v[i] = buf[row * W + i];
+#pragma unroll
+                for (int w = 0; w < CW; ++w) {
+                    Cx<T> a[4];
+#pragma unroll
+                    for (int hh = 0; hh < 4; ++hh) a[hh] = v[CW * hh + w];
+                    dft4<T, false>(a);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) buf[row * W + 4 * w + q] = a[q];
+                }
+            }
+            __syncthreads();
+        }
         fft_lds<T, N, false, 3 * W, W, NT, N, SeqBlocked<W, NW>>(buf, tw, tid);
     }
     const T sc = (T)prm->inv_k0M;
@@ -913,8 +1004,10 @@ __global__ __launch_bounds__(NT, (zpass_min_waves<T, N, W>())) void k_zgreen(Cx<
     // xi_A the non-Nyquist part of xi)
     const bool dual = prm->scheme == 3;
     for (int idx = tid; idx < NW; idx += NT) {
-        const int kz = idx / W, w = idx - kz * W;
-        const int ki[3] = {kx0 + dkx * w, ky0 + dky * w, kz};
+        const int kz = idx / W, p = idx - kz * W;
+        // Q4: pencil p = 4 w + q in quarter q of the rows
+        const int w = Q4 ? p >> 2 : p, qq = Q4 ? p & 3 : 0;
+        const int ki[3] = {kx0 + dkx * w, ky0 + dky * w + qq * (N / 4), kz};
         T xi[3];
         bool nq[3];
 #pragma unroll
@@ -1157,7 +1250,101 @@ template <typename T, int N, int NT, int RS> struct YFirstStage {
 // is replaced by E).
 // UPD: the update of steps 6-7: 0 accelerated (and basic), 1 augmented
 // Lagrangian / polarization, 2 dual.
-template <typename T, int N, int S, int NT, bool FWD = false, int UPD = 0, int NC = 3, int PC = 2>
+// The value of the neighbouring lane within each pair (lanes 2j <-> 2j + 1,
+// a DPP quad permutation [1, 0, 3, 2]).
+__device__ __forceinline__ float dpp_quad_swap1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double dpp_quad_swap1(double v) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), 0xB1, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Load of a split plane's parity HP of S from the half spectrum (main
+// columns, two complex values per access, all loads of a batch in flight
+// before the LDS stores; the kx = N/2 column into LDS column N/2): row
+// m < N/S gets Y[m] = w_N^(-m HP) sum_q exp(2 pi i q HP / S) X[m + q N/S] (a
+// decimation in frequency), whose length-N/S inverse transform gives the
+// rows y = S m' + HP of the plane.  S = 2 reads the plain layout (rows
+// m + q N/2), S = 4 the quarter layout of the z pass (X[m + q N/4][kx] at
+// m 2N + 4 kx + q, the kx = N/2 column at 4 m + q): the eight values of a
+// column pair in one 64-byte run.
+template <typename T, int N, int S, int NT, int RS, int HP>
+__device__ __forceinline__ void split_inv_load(Cx<T> *plane, const Cx<T> *__restrict__ sb,
+                                               const Cx<T> *__restrict__ nb, const Cx<T> *__restrict__ twg,
+                                               int tid) {
+    constexpr int H = N / 2, ROWS = N / S;
+    if constexpr (S == 4) {
+        // 16-byte units u of row m in lane order (each load instruction one
+        // contiguous run): unit u holds quarters 2b, 2b + 1 (b = u & 1) of
+        // column u / 2, so the four lanes of a quad hold one column pair.
+        // Each lane forms its two quarters' share of the sum,
+        // (-1)^(b HP) (X_2b + i^HP X_2b+1), and adds its neighbour's (lane
+        // b ^ 1) by a DPP swap; lanes b = 0 store the column.
+        constexpr int NU = ROWS * 2 * H, PERU = NU / NT, BU = 8;
+        static_assert(NU % NT == 0 && PERU % BU == 0 && NT % 64 == 0 && (2 * H) % 4 == 0,
+                      "units of a row in whole quads");
+        const int b = tid & 1;  // u = tid (mod 4): NT and the row's 2 H units are multiples of 4
+#pragma unroll
+        for (int i0 = 0; i0 < PERU; i0 += BU) {
+            Cx<T> lo[BU], hi[BU];
+#pragma unroll
+            for (int i = 0; i < BU; ++i) {
+                const int idx = tid + (i0 + i) * NT, m = idx / (2 * H), u = idx - m * (2 * H);
+                gload2<T>(sb + (size_t)m * (4 * H) + 2 * u, lo[i], hi[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < BU; ++i) {
+                const int idx = tid + (i0 + i) * NT, m = idx / (2 * H), u = idx - m * (2 * H);
+                Cx<T> pp = lo[i] + quarter_turn<HP>(hi[i]);
+                if ((HP & 1) && b) pp = Cx<T>{-pp.x, -pp.y};
+                Cx<T> y = pp + Cx<T>{dpp_quad_swap1(pp.x), dpp_quad_swap1(pp.y)};
+                if constexpr (HP > 0) y = y * conj(twg[m * HP]);
+                if (!b) plane[m * RS + (u >> 1)] = y;
+            }
+        }
+    } else {
+        constexpr int NP = ROWS * H / 2, PERP = (NP + NT - 1) / NT, BP = 4;
+#pragma unroll
+        for (int i0 = 0; i0 < PERP; i0 += BP) {
+            Cx<T> va[BP][S], vb[BP][S];
+#pragma unroll
+            for (int i = 0; i < BP; ++i) {
+                const int idx = tid + (i0 + i) * NT;
+                if (i0 + i < PERP && (NP % NT == 0 || idx < NP)) {
+                    const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
+#pragma unroll
+                    for (int q = 0; q < S; ++q) gload2<T>(sb + (size_t)(m + q * ROWS) * H + kx, va[i][q], vb[i][q]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < BP; ++i) {
+                const int idx = tid + (i0 + i) * NT;
+                if (i0 + i < PERP && (NP % NT == 0 || idx < NP)) {
+                    const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
+                    Cx<T> a0 = parity_sum<S, HP, 1>(va[i]), a1 = parity_sum<S, HP, 1>(vb[i]);
+                    if constexpr (HP > 0) {
+                        const Cx<T> r = conj(twg[m * HP]);
+                        a0 = a0 * r;
+                        a1 = a1 * r;
+                    }
+                    st_pair<T, RS % 2 == 0>(plane + m * RS + kx, a0, a1);
+                }
+            }
+        }
+    }
+    for (int m = tid; m < ROWS; m += NT) {
+        Cx<T> v[S];
+#pragma unroll
+        for (int q = 0; q < S; ++q) v[q] = S == 4 ? nb[4 * m + q] : nb[m + q * ROWS];
+        const Cx<T> x = parity_sum<S, HP, 1>(v);
+        plane[m * RS + H] = HP > 0 ? x * conj(twg[m * HP]) : x;
+    }
+}
+
+template <typename T, int N, int S, int NT, bool FWD = false, int UPD = 0, int NC = 3, int PC = 2, int PS = S>
 __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_plane(T *__restrict__ e, const uint8_t *__restrict__ ph,
                                                   Cx<T> *__restrict__ spec,
                                                   Cx<T> *__restrict__ nyq,
@@ -1204,36 +1391,17 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
         y0.load(sb, tid);
         for (int m = tid; m < ROWS; m += NT) plane[m * RS + H] = nb[m];
     } else {
-        // main columns, two complex values per access, all loads of a batch
-        // in flight before the LDS stores (rows m and m + N/2 combined)
-        constexpr int NP = ROWS * H / 2, PERP = (NP + NT - 1) / NT, BP = 4;
-#pragma unroll
-        for (int i0 = 0; i0 < PERP; i0 += BP) {
-            Cx<T> va[BP], vb[BP], ua[BP], ub[BP];
-#pragma unroll
-            for (int i = 0; i < BP; ++i) {
-                const int idx = tid + (i0 + i) * NT;
-                if (i0 + i < PERP && (NP % NT == 0 || idx < NP)) {
-                    const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
-                    gload2<T>(sb + (size_t)m * H + kx, va[i], vb[i]);
-                    gload2<T>(sb + (size_t)(m + ROWS) * H + kx, ua[i], ub[i]);
-                }
+        // parity h, a compile-time constant in the loads' combination
+        if constexpr (S == 2) {
+            if (h) split_inv_load<T, N, S, NT, RS, 1>(plane, sb, nb, twg, tid);
+            else split_inv_load<T, N, S, NT, RS, 0>(plane, sb, nb, twg, tid);
+        } else {
+            switch (h) {
+            case 0: split_inv_load<T, N, S, NT, RS, 0>(plane, sb, nb, twg, tid); break;
+            case 1: split_inv_load<T, N, S, NT, RS, 1>(plane, sb, nb, twg, tid); break;
+            case 2: split_inv_load<T, N, S, NT, RS, 2>(plane, sb, nb, twg, tid); break;
+            default: split_inv_load<T, N, S, NT, RS, 3>(plane, sb, nb, twg, tid); break;
             }
-#pragma unroll
-            for (int i = 0; i < BP; ++i) {
-                const int idx = tid + (i0 + i) * NT;
-                if (i0 + i < PERP && (NP % NT == 0 || idx < NP)) {
-                    const int m = idx / (H / 2), kx = (idx - m * (H / 2)) * 2;
-                    const Cx<T> r = conj(twg[m]);
-                    const Cx<T> a0 = h ? (va[i] - ua[i]) * r : va[i] + ua[i];
-                    const Cx<T> a1 = h ? (vb[i] - ub[i]) * r : vb[i] + ub[i];
-                    st_pair<T, RS % 2 == 0>(plane + m * RS + kx, a0, a1);
-                }
-            }
-        }
-        for (int m = tid; m < ROWS; m += NT) {
-            const Cx<T> v = nb[m], u = nb[m + ROWS];
-            plane[m * RS + H] = h ? (v - u) * conj(twg[m]) : v + u;
         }
     }
     // twiddle table (length N) in LDS: short-latency loads inside the stages
@@ -1263,7 +1431,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
     constexpr int TOTL = ROWS * N / V, PERL = (TOTL + NT - 1) / NT, BL = 8;
     // split planes, fused: the first NPF items of the update are loaded
     // before the x transform, which hides their latency
-    constexpr int NPF = (S == 2 && FWD) ? 4 : 0;
+    constexpr int NPF = (S >= 2 && FWD) ? 4 : 0;
     T apre[NPF > 0 ? NPF : 1][V];
     unsigned ppre[NPF > 0 ? NPF : 1];
 #pragma unroll
@@ -1362,11 +1530,16 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
     }
     double v3[3] = {r2, fl, se};
     block_sum<NT, 3>(v3, red);
+    // PS partial slots per plane (PS >= S: a grid whose other plane passes
+    // split planes further; the first workgroup of a plane clears the spare
+    // slots, whose zeros leave the fixed-order sums unchanged)
     if (tid == 0) {
-        double *pp = part + ((size_t)ch * (N * S) + (size_t)z * S + h) * 3;
+        double *pp = part + ((size_t)ch * (N * PS) + (size_t)z * PS + h) * 3;
         pp[0] = v3[0];
         pp[1] = v3[1];
         pp[2] = v3[2];
+        if (PS > S && h == 0)
+            for (int j = 3 * S; j < 3 * PS; ++j) pp[j] = 0.0;
     }
     if constexpr (FWD) {
         __syncthreads();
@@ -1379,7 +1552,7 @@ __global__ __launch_bounds__(NT, (plane_min_waves<T, N, S, NT>())) void k_inv_pl
             y_last_stage_store<T, N, NT, RS>(plane, twf, spec + ((size_t)ch * N + z) * N * H,
                                              nyq + ((size_t)ch * N + z) * N, tid);
         } else {
-            split_fwd_tail<T, N, NT, true, PC>(plane, twf, specB + ((size_t)ch * N + z) * N * H,
+            split_fwd_tail<T, N, NT, true, PC, S>(plane, twf, specB + ((size_t)ch * N + z) * N * H,
                                            nyqB + ((size_t)ch * N + z) * N, h, tid);
         }
     }

@@ -159,7 +159,8 @@ def test_equilibrium_error_at_exit_every_path(n, precision):
     """eps_eq reported at exit, on the paths whose flux transform differs from
     the 16^3-32^3 whole planes: whole planes in FP32 (128), split planes in
     FP64 (144; 192, whose iterations use the parity layout), split planes in
-    FP32 and the five-pass form (256).  Checked against the oracle's
+    FP32 and the five-pass flux transform (256; FP64 iterates in quarter
+    planes).  Checked against the oracle's
     equilibrium error of the final field the GPU returns, load case by load
     case (the FP32 flux transform rounds at ~1e-6 of the flux)."""
     print(f"\n[case] eps_eq at exit n={n} precision={precision}", flush=True)
@@ -217,7 +218,7 @@ def test_config2_128_vs_stored_oracle(precision):
 def test_config3_256_vs_stored_oracle(name):
     """The 256^3 RVE (100 spheres, f = 0.40 through the generator's fallback,
     seed 3) at the (layer, contrast) points with stored oracle solves
-    (tests/golden/make_oracle_refs.py): FP64 (five-pass form) with the
+    (tests/golden/make_oracle_refs.py): FP64 (quarter planes) with the
     oracle's iteration counts and within 1e-9; FP32 in the configuration the
     benchmark times (split planes, load-case chains, FP64 continuation past
     the FP32 floor) within 1e-4, converged."""
@@ -291,16 +292,20 @@ def test_five_pass_512_vs_oracle(precision):
     np.testing.assert_allclose(g.history[0], ref.history[0], rtol=bar * 10)
 
 
-def test_five_pass_256_fp64_vs_oracle():
-    """FP64 at 256^3 runs the five-pass form (the xy-plane does not fit in
-    LDS): two iterations of load case e_1, voxel by voxel against the oracle."""
-    print("\n[case] five-pass 256 fp64", flush=True)
+@pytest.mark.parametrize("flags", [0, 2])
+def test_five_pass_256_fp64_vs_oracle(flags):
+    """FP64 at 256^3, whose half xy-plane does not fit in LDS: by default
+    the fused pass in quarter planes with the four-quarter z pass (the
+    first forward pass too), else (flags 2) the five-pass form: two
+    iterations of load case e_1, voxel by voxel against the oracle."""
+    print(f"\n[case] 256 fp64 flags={flags}", flush=True)
     ph, _, _ = geom.generate(256, 100, 0.3, 0.2, 3)
     ref = oracle.homogenize(ph, K_PAPER_CFG, tol=0.0, max_iter=2, want_field=True, lc_mask=1)
     with rh.rve_create_from_phases(ph) as r:
         g = rh.homogenize(r, K_PAPER_CFG, 0.0, max_iter=2, precision=1, lc_mask=1,
-                          want_field=True)
+                          want_field=True, path_flags=flags)
     assert field_err(g.field[0], ref.field[0]) <= 1e-11
+    assert np.array_equal(g.field[1:], ref.field[1:])
     assert tensor_err(g.K[:, 0], ref.K[:, 0]) <= 1e-11
 
 
@@ -426,18 +431,19 @@ def test_augmented_lagrangian_config2_128(precision):
 
 
 def test_augmented_lagrangian_256_split_and_five_pass():
-    """256^3 runs the augmented-Lagrangian update in the separate inverse
-    passes: split planes in FP32, the five-pass form in FP64.  Two
+    """256^3 with the augmented-Lagrangian update: in the fused passes
+    (split planes with the parity layout in FP32, quarter planes in FP64)
+    and in the five-pass form's inverse pass (FP64, flags 2).  Two
     iterations of load case e_1 on an RSA RVE, voxel by voxel against the
     oracle."""
     print("\n[case] augmented lagrangian 256", flush=True)
     ph, _, _ = geom.generate(256, 100, 0.3, 0.2, 3)
     ref = oracle.homogenize(ph, K_PAPER_CFG, tol=0.0, max_iter=2, want_field=True, lc_mask=1, scheme=2)
     with rh.rve_create_from_phases(ph) as r:
-        for prec, bar in ((0, 3e-5), (1, 1e-11)):
-            print(f"[case] augmented lagrangian 256 precision={prec}", flush=True)
+        for prec, bar, flags in ((0, 3e-5, 0), (1, 1e-11, 0), (1, 1e-11, 2)):
+            print(f"[case] augmented lagrangian 256 precision={prec} flags={flags}", flush=True)
             g = rh.homogenize(r, K_PAPER_CFG, 0.0, max_iter=2, precision=prec, lc_mask=1,
-                              want_field=True, hist_cap=4, scheme=AL)
+                              want_field=True, hist_cap=4, scheme=AL, path_flags=flags)
             assert field_err(g.field[0], ref.field[0]) <= bar
             assert tensor_err(g.K[:, 0], ref.K[:, 0]) <= bar
             for j in range(2):

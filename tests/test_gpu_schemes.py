@@ -65,17 +65,18 @@ def test_converged_vs_oracle(scheme, alpha, k):
 
 @pytest.mark.parametrize("scheme,alpha", [(3, 0.0), (4, 1.5)])
 def test_256_split_and_five_pass(scheme, alpha):
-    """256^3: split planes with the parity-layout fused pass in FP32, the
-    five-pass form in FP64.  Two iterations of load case e_1 on an RSA RVE,
+    """256^3: split planes with the parity-layout fused pass in FP32,
+    quarter planes with the four-quarter z pass in FP64, and the five-pass
+    form in FP64 (flags 2).  Two iterations of load case e_1 on an RSA RVE,
     voxel by voxel against the oracle."""
     print(f"\n[case] scheme {scheme} 256", flush=True)
     ph, _, _ = geom.generate(256, 100, 0.3, 0.2, 3)
     ref = oracle.homogenize(ph, K_CFG, tol=0.0, max_iter=2, want_field=True, lc_mask=1, scheme=scheme,
                             alpha=alpha if alpha else 2.0)
     with rh.rve_create_from_phases(ph) as r:
-        for prec, bar in ((0, 3e-5), (1, 1e-11)):
+        for prec, bar, flags in ((0, 3e-5, 0), (1, 1e-11, 0), (1, 1e-11, 2)):
             g = rh.homogenize(r, K_CFG, 0.0, max_iter=2, precision=prec, lc_mask=1, want_field=True,
-                              hist_cap=4, scheme=scheme, alpha=alpha)
+                              hist_cap=4, scheme=scheme, alpha=alpha, path_flags=flags)
             assert field_err(g.field[0], ref.field[0]) <= bar
             assert tensor_err(g.K[:, 0], ref.K[:, 0]) <= bar
 
