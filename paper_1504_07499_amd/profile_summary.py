@@ -6,9 +6,10 @@ rocprofv3 (ROCm 7) writes its results as an SQLite database
 view) of such databases and prints one table per run:
 
 * trace: calls, average duration, grid, workgroup, LDS bytes and VGPRs per
-  kernel, and -- for the solver's passes -- the algorithmic HBM bytes per
-  launch (all three load cases: each pass reads and writes its fields once,
-  the phase image once) and the rate they imply;
+  kernel, and -- for the solver's passes in the trace's precision
+  (--real-bytes) -- the algorithmic HBM bytes per launch (all three load
+  cases: each pass reads and writes its fields once, the phase image once)
+  and the rate they imply;
 * counters: the average per dispatch of every collected counter, plus, for
   FETCH_SIZE / WRITE_SIZE, the HBM bytes per launch scaled by the reading of
   a device-to-device copy of known size (``bench.py --calibrate-copy``), and
@@ -47,7 +48,9 @@ def algorithmic_bytes(name: str, n: int, rb: int) -> float | None:
     """HBM bytes per launch of a solver pass over all three load cases
     (9 channels): e is 9 n^3 reals, the half spectrum 9 n^2 (n/2 + 1)
     complex values, the phase image n^3 bytes.  rb: bytes per real of FP32
-    kernels (FP64 kernels, first template argument double, take 8)."""
+    kernels (FP64 kernels, first template argument double, take 8).  The
+    plane passes, the z pass and the five-pass form's passes (k_fwd_rows,
+    k_cols, k_inv_rows) of the conductivity case."""
     s = short_name(name)
     args = s.split("<", 1)[1].rstrip(">").split(", ") if "<" in s else []
     if args and args[0] == "double":
@@ -63,6 +66,15 @@ def algorithmic_bytes(name: str, n: int, rb: int) -> float | None:
         return field + spec + phase
     if s.startswith("k_zgreen"):
         return 2 * spec
+    # the five-pass form (conductivity: last template argument NC = 3): rows
+    # forward e -> spectrum, a column pass in place, rows inverse
+    if args and args[-1] == "3":
+        if s.startswith("k_fwd_rows"):
+            return field + spec + phase
+        if s.startswith("k_cols"):
+            return 2 * spec
+        if s.startswith("k_inv_rows"):
+            return spec + 2 * field + phase
     return None
 
 
@@ -79,6 +91,11 @@ def trace(db: str, n: int, rb: int) -> str:
            f"{'avg_us':>9s} {'alg_MB':>9s} {'TB/s':>6s} {'frac8':>6s}"]
     for name, calls, avg, grid, wg, lds, vgpr, agpr in rows:
         ab = algorithmic_bytes(name, n, rb)
+        # kernels of the other precision (an FP64 continuation in an FP32
+        # trace runs on the load cases still active): no byte count
+        s_args = short_name(name).split("<", 1)[1].split(", ") if "<" in short_name(name) else []
+        if s_args and s_args[0] in ("float", "double") and (8 if s_args[0] == "double" else 4) != rb:
+            ab = None
         us = avg / 1e3
         rate = ab / (avg * 1e-9) / 1e12 if ab else None
         out.append(f"{short_name(name)[:58]:58s} {grid // max(wg, 1):8d} {wg:5d} {lds:7d} {vgpr:5d} {calls:6d} "
