@@ -182,12 +182,13 @@ template <typename T, int N> struct Instance {
     static void to_tau(const LaunchArgs &a, size_t M, hipStream_t s) {
         hipLaunchKernelGGL((k_to_tau<T>), dim3(1024), dim3(256), 0, s, (T *)a.e, a.ph, M, a.prm);
     }
-    // fused inverse + next forward pass (whole planes in LDS; not where the
-    // fused kernel would spill registers heavily: FP32 96^3)
-    static constexpr bool FUSED = !FIVE && S == 1 && !(sizeof(T) == 4 && N == 96);
+    // fused inverse + next forward pass (whole planes in LDS); FP32 96^3
+    // runs it at 512 threads per workgroup (at 256 it spills registers)
+    static constexpr bool FUSED = !FIVE && S == 1;
+    static constexpr int NTF = (sizeof(T) == 4 && N == 96) ? 512 : NTP;
     template <int AL> static void inv_fwd_t(const LaunchArgs &a, hipStream_t s, int lc_sel) {
         if constexpr (FUSED) {
-            hipLaunchKernelGGL((k_inv_plane<T, N, 1, NTP, true, AL>), dim3(pgrid(lc_sel)), dim3(NTP), 0, s,
+            hipLaunchKernelGGL((k_inv_plane<T, N, 1, NTF, true, AL>), dim3(pgrid(lc_sel)), dim3(NTF), 0, s,
                                (T *)a.e, a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
                                (const DevState *)a.st, a.part, ch0(lc_sel), (Cx<T> *)nullptr, (Cx<T> *)nullptr);
         } else if constexpr (PARF) {
@@ -201,8 +202,8 @@ template <typename T, int N> struct Instance {
                                (Cx<T> *)a.spec2, (Cx<T> *)a.nyq2);
         }
     }
-    static constexpr int NTP2 = plane_threads_alt<T, N>();
-    static constexpr bool FUSED2 = FUSED && NTP2 != NTP;
+    static constexpr int NTP2 = NTF != NTP ? NTF : plane_threads_alt<T, N>();
+    static constexpr bool FUSED2 = FUSED && NTP2 != NTF;
     template <int AL> static void inv_fwd2_t(const LaunchArgs &a, hipStream_t s, int lc_sel) {
         if constexpr (FUSED2) {
             hipLaunchKernelGGL((k_inv_plane<T, N, 1, NTP2, true, AL>), dim3(pgrid(lc_sel)), dim3(NTP2), 0, s,
