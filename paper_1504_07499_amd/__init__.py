@@ -446,7 +446,7 @@ def moduli_from_young_poisson(young, poisson):
 
 def homogenize_elastic(rve: RVE, moduli, tol: float = 1e-6, *, max_iter: int = 0, precision: int = 0,
                        stall_window: int = -1, stream=None, init_field: np.ndarray | None = None,
-                       want_field: bool = False, hist_cap: int = 0) -> ElasticResult:
+                       want_field: bool = False, hist_cap: int = 0, path_flags: int = 0) -> ElasticResult:
     """The accelerated scheme for isotropic elastic phases (the elastic case
     Sec. 6 names as the extension): moduli (3, 2) = (bulk, shear) of matrix,
     inclusion, coating; six load cases E = B_j."""
@@ -460,7 +460,7 @@ def homogenize_elastic(rve: RVE, moduli, tol: float = 1e-6, *, max_iter: int = 0
         if init.size != 36 * n ** 3:
             raise RveError(RVE_ERR_ARG, "init_field must hold 36 n^3 values")
     fld = np.zeros((6, 6, n, n, n)) if want_field else None
-    o = _opts(max_iter, precision, False, stall_window, 0, False, stream, init, fld, None)
+    o = _opts(max_iter, precision, False, stall_window, 0, False, stream, init, fld, None, path_flags=path_flags)
     res = _ElResult()
     hist = np.zeros(6 * hist_cap) if hist_cap > 0 else None
     rc = _check(_lib.homogenize_elastic(rve.handle, _dptr(m), float(tol), ctypes.byref(o), ctypes.byref(res),

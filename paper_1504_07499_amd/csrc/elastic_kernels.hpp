@@ -42,21 +42,29 @@ template <typename T, int N> constexpr int ztile_el() {
 //   beta = (lambda0 + mu0) / (mu0 (lambda0 + 2 mu0)),
 // with T^ = sum_l tau^_l B_l, averaged over the signs of the Nyquist
 // components (the conductivity reading of even grids), c^(0) = 0 (E is added
-// after the inverse transform), inverse z FFT.
-template <typename T, int N, int W, int NT>
+// after the inverse transform), inverse z FFT.  PAR: the forward spectrum
+// arrives in the parity layout of the split-plane fused pass (specB, nyqB),
+// combined as X = E +- w O while it loads, as in k_zgreen<PAR>.
+template <typename T, int N, int W, int NT, bool PAR = false>
 __global__ __launch_bounds__(NT) void k_zgreen_el(Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
                                                   const Cx<T> *__restrict__ twg,
                                                   const DevParams *__restrict__ prm,
-                                                  const DevState *__restrict__ st) {
+                                                  const DevState *__restrict__ st,
+                                                  const Cx<T> *__restrict__ specB = nullptr,
+                                                  const Cx<T> *__restrict__ nyqB = nullptr) {
     using TL = ZTiles<N, W>;
     constexpr int H = N / 2, NW = N * W, NC = 6;
     static_assert(H % W == 0 && N % W == 0 && W % 2 == 0, "tile width must be even and divide N/2");
     __shared__ Cx<T> buf[NC * NW];
     const int tid = threadIdx.x;
-    const int lc = blockIdx.x / TL::PER_LC, t = ztile_of<T, N, W>(blockIdx.x - lc * TL::PER_LC);
+    const int lc = blockIdx.x / TL::PER_LC;
+    int t;
+    if constexpr (PAR) t = ztile_par<N, W>(blockIdx.x - lc * TL::PER_LC);
+    else t = ztile_of<T, N, W>(blockIdx.x - lc * TL::PER_LC);
     if (st->done[lc]) return;
     Cx<T> *base;
-    size_t cstride, zstride;
+    const Cx<T> *pbase = nullptr;  // PAR: row ky mod N/2 of the parity layout
+    size_t cstride, zstride, poff = 0;  // poff: from parity 0 to parity 1
     int kx0, ky0, dkx, dky;
     if (t < TL::MAIN) {
         const int ky = t / (H / W);
@@ -65,6 +73,11 @@ __global__ __launch_bounds__(NT) void k_zgreen_el(Cx<T> *__restrict__ spec, Cx<T
         dkx = 1;
         dky = 0;
         base = spec + (size_t)(NC * lc) * N * N * H + (size_t)ky * H + kx0;
+        constexpr int PC = par_chunk<T, W>();
+        static_assert(!PAR || (PC % W == 0 && H % PC == 0), "z tiles inside parity chunks");
+        if constexpr (PAR)
+            pbase = specB + (size_t)(NC * lc) * N * N * H + (size_t)(ky % H) * N + (kx0 / PC) * (2 * PC) + kx0 % PC;
+        poff = PC;
         cstride = (size_t)N * N * H;
         zstride = (size_t)N * H;
     } else {
@@ -73,6 +86,8 @@ __global__ __launch_bounds__(NT) void k_zgreen_el(Cx<T> *__restrict__ spec, Cx<T
         dkx = 0;
         dky = 1;
         base = nyq + (size_t)(NC * lc) * N * N + ky0;
+        if constexpr (PAR) pbase = nyqB + (size_t)(NC * lc) * N * N + (ky0 % H);
+        poff = H;
         cstride = (size_t)N * N;
         zstride = N;
     }
@@ -80,11 +95,24 @@ __global__ __launch_bounds__(NT) void k_zgreen_el(Cx<T> *__restrict__ spec, Cx<T
     // stage, and the last inverse stage straight back (measured faster below
     // 256^3 in FP32 and below 128^3 in FP64; the 4-column tiles of the larger
     // grids keep the staged form)
-    constexpr bool DIRECT = !(N >= 256 || (sizeof(T) == 8 && N >= 128));
+    constexpr bool DIRECT = !(N >= 256 || (sizeof(T) == 8 && N >= 128)) && !PAR;
     constexpr int NP = NC * NW / 2;
     ZFirstStage<T, N, W, NT, NC> z0;
     if constexpr (DIRECT) {
         z0.load(base, cstride, zstride, tid);
+    } else if constexpr (PAR) {
+        // X = E +- w O from the two parity rows (a tile's rows lie in one
+        // half: W divides N/2)
+        const bool upper = ky0 >= H;
+        for (int idx = tid; idx < NP; idx += NT) {
+            const int e0 = 2 * idx, c = e0 / NW, r = e0 - c * NW, zz = r / W, w = r - zz * W;
+            const Cx<T> *src = pbase + c * cstride + zz * zstride + w;
+            Cx<T> a, b, u, v;
+            gload2<T>(src, a, b);
+            gload2<T>(src + poff, u, v);
+            buf[e0] = upper ? a - u : a + u;
+            buf[e0 + 1] = upper ? b - v : b + v;
+        }
     } else {
         for (int idx = tid; idx < NP; idx += NT) {
             const int e0 = 2 * idx, c = e0 / NW, r = e0 - c * NW, zz = r / W, w = r - zz * W;
@@ -203,7 +231,13 @@ template <typename T, int N> struct ElasticInstance {
     // 256^3; FP64: 256 (measured faster)
     static constexpr int NTZ = sizeof(T) == 4 ? (N == 256 ? 1024 : 512) : 256;
     static constexpr int NPER = FIVE ? N * (N / G) : N * S;
+    // the fused inverse + next forward pass: whole planes (not FP32 96^3,
+    // whose fused pass spills at 256 threads and at 512 measured no faster
+    // than the separate passes), and split planes writing the parity layout
+    // that the z pass combines (FP32 256^3)
     static constexpr bool FUSED = S == 1 && !(sizeof(T) == 4 && N == 96);
+    static constexpr bool PARF = S == 2 && ztile_par_ok<N, W>();
+    static constexpr int PC = par_chunk<T, W>();
     static constexpr int PGRID = FIVE ? CH * N * (N / G) : CH * N * S;
     static constexpr int SP = FIVE ? 1 : S;
 
@@ -222,7 +256,21 @@ template <typename T, int N> struct ElasticInstance {
     }
     static void zgreen(const LaunchArgs &a, hipStream_t s, int, int) {
         hipLaunchKernelGGL((k_zgreen_el<T, N, W, NTZ>), dim3(NC * ZTiles<N, W>::PER_LC), dim3(NTZ), 0, s,
-                           (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st);
+                           (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st,
+                           (const Cx<T> *)nullptr, (const Cx<T> *)nullptr);
+    }
+    // split planes: the first forward pass and the z pass of the parity layout
+    static void fwd_par(const LaunchArgs &a, hipStream_t s, int) {
+        if constexpr (PARF)
+            hipLaunchKernelGGL((k_fwd_plane<T, N, 2, NTP, false, NC, true, PC>), dim3(PGRID), dim3(NTP), 0, s,
+                               (const T *)a.e, a.ph, (Cx<T> *)a.spec2, (Cx<T> *)a.nyq2, (const Cx<T> *)a.tw, a.prm,
+                               (const DevState *)a.st, 0);
+    }
+    static void zgreen_par(const LaunchArgs &a, hipStream_t s, int, int) {
+        if constexpr (PARF)
+            hipLaunchKernelGGL((k_zgreen_el<T, N, W, NTZ, true>), dim3(NC * ZTiles<N, W>::PER_LC), dim3(NTZ), 0, s,
+                               (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st,
+                               (const Cx<T> *)a.spec2, (const Cx<T> *)a.nyq2);
     }
     static void inv(const LaunchArgs &a, hipStream_t s, int) {
         if constexpr (FIVE) {
@@ -242,6 +290,10 @@ template <typename T, int N> struct ElasticInstance {
             hipLaunchKernelGGL((k_inv_plane<T, N, 1, NTP, true, 0, NC>), dim3(PGRID), dim3(NTP), 0, s, (T *)a.e,
                                a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
                                (const DevState *)a.st, a.part, 0, (Cx<T> *)nullptr, (Cx<T> *)nullptr);
+        } else if constexpr (PARF) {
+            hipLaunchKernelGGL((k_inv_plane<T, N, 2, NTP, true, 0, NC, PC>), dim3(PGRID), dim3(NTP), 0, s, (T *)a.e,
+                               a.ph, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
+                               (const DevState *)a.st, a.part, 0, (Cx<T> *)a.spec2, (Cx<T> *)a.nyq2);
         }
     }
     static void init(const LaunchArgs &a, size_t M, hipStream_t s) {
@@ -278,8 +330,8 @@ template <typename T, int N> struct ElasticInstance {
             {FIVE ? NTR : NTP, NTZ, FIVE ? NTR : NTP},
             {CH * (double)M * rb + spec_b + extra, 2.0 * spec_b, spec_b + 2.0 * CH * (double)M * rb + extra},
             0,
-            FUSED ? 2.0 * spec_b + 2.0 * CH * (double)M * rb : 0.0,
-            FUSED ? &inv_fwd : nullptr,
+            (FUSED || PARF) ? 2.0 * spec_b + 2.0 * CH * (double)M * rb : 0.0,
+            (FUSED || PARF) ? &inv_fwd : nullptr,
             &fwd,
             nullptr,
             nullptr,
@@ -296,8 +348,8 @@ template <typename T, int N> struct ElasticInstance {
             NC,
             &reduce,
             (double)M,
-            nullptr,
-            nullptr,
+            PARF ? &fwd_par : nullptr,
+            PARF ? &zgreen_par : nullptr,
             nullptr,
             nullptr,
         };

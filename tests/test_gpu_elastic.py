@@ -72,13 +72,14 @@ def test_elastic_converged_fp64_vs_oracle():
     assert np.abs(g.C - g.C.T).max() <= 1e-9 * np.abs(g.C).max()
 
 
-@pytest.mark.parametrize("precision", [1, 0])
-def test_elastic_equal_shear_hill_64(precision):
-    """Phases of equal shear modulus on a 64^3 RSA RVE: the hydrostatic load
-    case gives Hill's exact bulk modulus (closed form, any geometry)."""
-    print(f"\n[case] elastic hill 64 precision={precision}", flush=True)
+@pytest.mark.parametrize("n,precision", [(64, 1), (64, 0), (96, 0)])
+def test_elastic_equal_shear_hill(n, precision):
+    """Phases of equal shear modulus on an RSA RVE (64^3; 96^3 in FP32, a
+    radix-3 grid on the separate passes): the hydrostatic load case gives
+    Hill's exact bulk modulus (closed form, any geometry)."""
+    print(f"\n[case] elastic hill {n} precision={precision}", flush=True)
     mod = np.array([[4.0, 2.0], [40.0, 2.0], [150.0, 2.0]])
-    ph, _, _ = geom.generate(64, 12, 0.3, 0.2, 6)
+    ph, _, _ = geom.generate(n, 12, 0.3, 0.2, 6)
     kv = mod[ph, 0]
     khill = 1.0 / np.mean(1.0 / (kv + 4.0 * 2.0 / 3.0)) - 4.0 * 2.0 / 3.0
     with rh.rve_create_from_phases(ph) as r:
@@ -88,18 +89,21 @@ def test_elastic_equal_shear_hill_64(precision):
     assert abs(g.C_basis[0, 0] / 3.0 - khill) <= (1e-9 if precision else 1e-5) * khill
 
 
-def test_elastic_equal_shear_hill_256_fp32():
+@pytest.mark.parametrize("flags", [0, 2])
+def test_elastic_equal_shear_hill_256_fp32(flags):
     """The same closed form on the 256^3 RVE of 100 RSA spheres at f = 0.40
-    (FP32; 8-column z tiles in 1024-thread workgroups, split planes): the
-    random geometry feeds every z tile and every plane of all six load
-    cases, and the hydrostatic load case must give Hill's bulk modulus."""
-    print("\n[case] elastic hill 256 fp32", flush=True)
+    (FP32; split planes, by default with the fused pass writing the parity
+    layout that the z pass combines, with flags 2 in separate passes;
+    8-column z tiles in 1024-thread workgroups): the random geometry feeds
+    every z tile and every plane of all six load cases, and the hydrostatic
+    load case must give Hill's bulk modulus."""
+    print(f"\n[case] elastic hill 256 fp32 flags={flags}", flush=True)
     mod = np.array([[4.0, 2.0], [40.0, 2.0], [150.0, 2.0]])
     ph, _, _ = geom.generate(256, 100, 0.40, 0.1, 3)
     kv = mod[ph, 0]
     khill = 1.0 / np.mean(1.0 / (kv + 4.0 * 2.0 / 3.0)) - 4.0 * 2.0 / 3.0
     with rh.rve_create_from_phases(ph) as r:
-        g = rh.homogenize_elastic(r, mod, 1e-6, precision=0)
+        g = rh.homogenize_elastic(r, mod, 1e-6, precision=0, path_flags=flags)
     C = np.asarray(g.C_basis)
     assert abs(C[0, 0] / 3.0 - khill) <= 1e-5 * khill
     # with one shear modulus a uniform deviatoric strain is the exact
