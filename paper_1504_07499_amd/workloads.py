@@ -342,7 +342,8 @@ def run_elastic(sizes=((128, 0), (128, 1), (256, 0), (256, 1), (512, 0), (512, 1
                     best = g
         M = n ** 3
         b = 4 if prec == 0 else 8
-        fused = not (n == 96 and prec == 0) and (n <= 128 or (prec == 0 and n <= 192))
+        # fused: whole planes (not FP32 96^3) and the FP32 256^3 split planes
+        fused = not (n == 96 and prec == 0) and (n <= 128 or (prec == 0 and n <= 256))
         five = (prec == 1 and n >= 256) or n >= 512
         # per iteration of all six load cases (the phase image read once per
         # pass): z pass 2 C; fused plane pass 2 C + 2 * 36 M b + M; separate
