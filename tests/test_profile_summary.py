@@ -104,3 +104,17 @@ def test_traffic_scaled_by_the_copy(tmp_path):
     assert float(keys["inv_fwd_plane_fetch_bytes_per_launch"]) == pytest.approx(1240e6, rel=1e-6)
     assert float(keys["inv_fwd_plane_write_bytes_per_launch"]) == pytest.approx(1213e6, rel=1e-6)
     assert float(keys["inv_fwd_plane_hbm_bytes_per_launch"]) == pytest.approx(2453e6, rel=1e-6)
+
+
+def test_committed_traffic_summary_matches_the_kernel_sources():
+    """The bench reports the counter traffic of its dominant kernel only from
+    a summary taken on the kernel sources in the tree: the committed one must
+    carry their hash and the three passes' bytes per launch."""
+    import bench
+
+    for k in ("inv_fwd_plane", "zgreen", "fwd_plane"):
+        v = bench.measured_traffic(k, 0)
+        assert v is not None and v > 1e9, k
+    # within a few per cent of the algorithmic bytes (no re-reads to speak of)
+    alg = ps.algorithmic_bytes("k_inv_plane<float, 256, 2, 1024, true, 0, 3, 16, 2>", 256, 4)
+    assert 1.0 <= bench.measured_traffic("inv_fwd_plane", 0) / alg <= 1.1
