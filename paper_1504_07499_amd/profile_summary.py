@@ -5,8 +5,10 @@ rocprofv3 (ROCm 7) writes its results as an SQLite database
 (``kernels`` view) and the counter collections (``counters_collection``
 view) of such databases and prints one table per run:
 
-* trace: calls, average duration, grid, workgroup, LDS bytes and VGPRs per
-  kernel, and -- for the solver's passes in the trace's precision
+* trace: calls, average duration of the launches that did the whole pass
+  (early exits after convergence left out and counted), grid, workgroup,
+  LDS bytes and VGPRs per kernel, and -- for the solver's passes in the
+  trace's precision
   (--real-bytes) -- the algorithmic HBM bytes per launch (all three load
   cases: each pass reads and writes its fields once, the phase image once)
   and the rate they imply;
@@ -45,19 +47,33 @@ def short_name(name: str) -> str:
 
 
 def algorithmic_bytes(name: str, n: int, rb: int) -> float | None:
-    """HBM bytes per launch of a solver pass over all three load cases
-    (9 channels): e is 9 n^3 reals, the half spectrum 9 n^2 (n/2 + 1)
-    complex values, the phase image n^3 bytes.  rb: bytes per real of FP32
-    kernels (FP64 kernels, first template argument double, take 8).  The
-    plane passes, the z pass and the five-pass form's passes (k_fwd_rows,
-    k_cols, k_inv_rows) of the conductivity case."""
+    """HBM bytes per launch of a solver pass over all load cases: for the
+    conductivity case (9 channels) e is 9 n^3 reals, the half spectrum
+    9 n^2 (n/2 + 1) complex values, the phase image n^3 bytes; the elastic
+    case (template argument NC = 6, and k_zgreen_el) has 36 channels.  rb:
+    bytes per real of FP32 kernels (FP64 kernels, first template argument
+    double, take 8).  The plane passes, the z pass and the five-pass form's
+    passes (k_fwd_rows, k_cols, k_inv_rows)."""
     s = short_name(name)
     args = s.split("<", 1)[1].rstrip(">").split(", ") if "<" in s else []
     if args and args[0] == "double":
         rb = 8
+    # components per load case: <T, N, S, NT, FWD, UPD, NC, ...> for
+    # k_inv_plane, <T, N, S, NT, PHI, NC, ...> for k_fwd_plane, the last
+    # argument of the five-pass kernels
+    nc = 3
+    if s.startswith("k_zgreen_el"):
+        nc = 6
+    elif s.startswith("k_inv_plane") and len(args) > 6:
+        nc = int(args[6])
+    elif s.startswith("k_fwd_plane") and len(args) > 5:
+        nc = int(args[5])
+    elif s.startswith(("k_fwd_rows", "k_cols", "k_inv_rows")) and args:
+        nc = int(args[-1])
+    ch = nc * nc
     m = n ** 3
-    field = 9.0 * m * rb
-    spec = 9.0 * n * n * (n // 2 + 1) * 2 * rb
+    field = ch * m * rb
+    spec = ch * n * n * (n // 2 + 1) * 2 * rb
     phase = float(m)
     if s.startswith("k_inv_plane"):
         fused = len(args) > 4 and args[4] == "true"  # <T, N, S, NT, FWD, ...>
@@ -66,15 +82,14 @@ def algorithmic_bytes(name: str, n: int, rb: int) -> float | None:
         return field + spec + phase
     if s.startswith("k_zgreen"):
         return 2 * spec
-    # the five-pass form (conductivity: last template argument NC = 3): rows
-    # forward e -> spectrum, a column pass in place, rows inverse
-    if args and args[-1] == "3":
-        if s.startswith("k_fwd_rows"):
-            return field + spec + phase
-        if s.startswith("k_cols"):
-            return 2 * spec
-        if s.startswith("k_inv_rows"):
-            return spec + 2 * field + phase
+    # the five-pass form: rows forward e -> spectrum, a column pass in
+    # place, rows inverse
+    if s.startswith("k_fwd_rows"):
+        return field + spec + phase
+    if s.startswith("k_cols"):
+        return 2 * spec
+    if s.startswith("k_inv_rows"):
+        return spec + 2 * field + phase
     return None
 
 
@@ -82,14 +97,33 @@ def _connect(db):
     return sqlite3.connect(f"file:{db}?mode=ro", uri=True)
 
 
+def full_launches(durations):
+    """The launches that did the pass's work: the solver launches whole
+    batches of iterations, and a launch after every load case has converged
+    exits at once (as does one whose load cases are partly frozen, with
+    less work); those under 0.8 of the median duration are left out of the
+    average."""
+    v = sorted(durations)
+    med = v[len(v) // 2]
+    return [d for d in durations if d >= 0.8 * med]
+
+
 def trace(db: str, n: int, rb: int) -> str:
+    """calls: all launches; short: those left out of avg_us (full_launches);
+    avg_us and the rate: the launches that did the whole pass."""
     con = _connect(db)
-    rows = con.execute(
-        "select name, count(*), avg(duration), grid_x, workgroup_x, lds_size, vgpr_count, accum_vgpr_count "
-        "from kernels group by name, grid_x order by sum(duration) desc").fetchall()
-    out = [f"{'kernel':58s} {'grid':>8s} {'wg':>5s} {'lds':>7s} {'vgpr':>5s} {'calls':>6s} "
+    groups = collections.OrderedDict()
+    for name, dur, grid, wg, lds, vgpr in con.execute(
+            "select name, duration, grid_x, workgroup_x, lds_size, vgpr_count from kernels"):
+        g = groups.setdefault((name, grid), {"d": [], "wg": wg, "lds": lds, "vgpr": vgpr})
+        g["d"].append(dur)
+    rows = sorted(groups.items(), key=lambda kv: -sum(kv[1]["d"]))
+    out = [f"{'kernel':58s} {'grid':>8s} {'wg':>5s} {'lds':>7s} {'vgpr':>5s} {'calls':>6s} {'short':>5s} "
            f"{'avg_us':>9s} {'alg_MB':>9s} {'TB/s':>6s} {'frac8':>6s}"]
-    for name, calls, avg, grid, wg, lds, vgpr, agpr in rows:
+    for (name, grid), g in rows:
+        wg, lds, vgpr = g["wg"], g["lds"], g["vgpr"]
+        full = full_launches(g["d"])
+        avg = sum(full) / len(full)
         ab = algorithmic_bytes(name, n, rb)
         # kernels of the other precision (an FP64 continuation in an FP32
         # trace runs on the load cases still active): no byte count
@@ -98,7 +132,8 @@ def trace(db: str, n: int, rb: int) -> str:
             ab = None
         us = avg / 1e3
         rate = ab / (avg * 1e-9) / 1e12 if ab else None
-        out.append(f"{short_name(name)[:58]:58s} {grid // max(wg, 1):8d} {wg:5d} {lds:7d} {vgpr:5d} {calls:6d} "
+        out.append(f"{short_name(name)[:58]:58s} {grid // max(wg, 1):8d} {wg:5d} {lds:7d} {vgpr:5d} "
+                   f"{len(g['d']):6d} {len(g['d']) - len(full):5d} "
                    f"{us:9.1f} " + (f"{ab / 1e6:9.1f} {rate:6.2f} {rate / 8.0:6.3f}" if ab else
                                     f"{'':>9s} {'':>6s} {'':>6s}"))
     return "\n".join(out)

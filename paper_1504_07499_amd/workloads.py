@@ -391,7 +391,10 @@ def main(argv=None):
     so.add_argument("--path-flags", type=int, default=0)
     so.add_argument("--no-refine", action="store_true")
     sub.add_parser("fibers")
-    sub.add_parser("elastic")
+    el = sub.add_parser("elastic")
+    el.add_argument("--n", type=int, nargs="*", default=None, help="grid sizes (default 128, 256, 512)")
+    el.add_argument("--precision", type=int, nargs="*", default=None, help="precisions (default 0 and 1)")
+    el.add_argument("--reps", type=int, default=3)
     sc = sub.add_parser("schemes")
     sc.add_argument("--precision", type=int, default=1)
     rs = sub.add_parser("rates")
@@ -417,7 +420,11 @@ def main(argv=None):
     elif a.cmd == "fibers":
         run_fibers()
     elif a.cmd == "elastic":
-        run_elastic()
+        if a.n or a.precision:
+            sizes = [(n, p) for n in (a.n or [128, 256, 512]) for p in (a.precision if a.precision else [0, 1])]
+            run_elastic(sizes=sizes, reps=a.reps)
+        else:
+            run_elastic(reps=a.reps)
     elif a.cmd == "schemes":
         run_schemes(precision=a.precision)
     elif a.cmd == "rates":

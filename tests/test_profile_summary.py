@@ -37,8 +37,12 @@ def test_algorithmic_bytes_of_each_pass(n):
     assert ab(f"k_fwd_rows<double, {n}, 16, 256, false, 3>", n, 8) == f64 + s64 + phase
     assert ab(f"k_cols<double, {n}, 16, 256, true, false, 3>", n, 8) == 2 * s64
     assert ab(f"k_inv_rows<double, {n}, 16, 256, 0, 3>", n, 8) == s64 + 2 * f64 + phase
-    # the elastic case's passes (36 channels) and other kernels are not counted
-    assert ab(f"k_inv_rows<float, {n}, 16, 256, 0, 6>", n, 4) is None
+    # the elastic case (six components per load case: 36 channels)
+    assert ab(f"k_inv_rows<float, {n}, 16, 256, 0, 6>", n, 4) == 4 * (spec + 2 * field) + phase
+    assert ab(f"k_inv_plane<float, {n}, 2, 1024, true, 0, 6, 16, 2>", n, 4) == 4 * (2 * spec + 2 * field) + phase
+    assert ab(f"k_fwd_plane<float, {n}, 2, 1024, false, 6, true, 16>", n, 4) == 4 * (field + spec) + phase
+    assert ab(f"k_zgreen_el<float, {n}, 8, 1024, true>", n, 4) == 4 * 2 * spec
+    # other kernels are not counted
     assert ab("k_reduce", n, 4) is None
     # the 256^3 FP32 figures quoted with the profiles
     if n == 256:
@@ -71,21 +75,24 @@ def _db(path, kernels=(), counters=()):
 def test_trace_rates_and_precision_filter(tmp_path):
     fused = "k_inv_plane<float, 256, 2, 1024, true, 0, 3, 16, 2>"
     fp64 = "k_inv_plane<double, 256, 4, 512, true, 0, 3, 1, 16>"
+    # two full launches and one that exited at once (every load case frozen)
     db = _db(tmp_path / "t.db", kernels=[(fused, 600e3, 4608 * 1024, 1024, 134552, 64, 0),
                                          (fused, 620e3, 4608 * 1024, 1024, 134552, 64, 0),
+                                         (fused, 8e3, 4608 * 1024, 1024, 134552, 64, 0),
                                          (fp64, 450e3, 9216 * 512, 512, 136432, 112, 0)])
     rows = {ln.split()[0]: ln.split() for ln in ps.trace(db, 256, 4).splitlines()[1:]}
     r = rows["k_inv_plane<float,"]
-    # grid in workgroups, calls, average duration, bytes, rate and fraction of 8 TB/s
+    # grid in workgroups, calls, short launches, average duration of the
+    # full ones, bytes, rate and fraction of 8 TB/s
     cols = r[len(fused.split()):]
-    assert cols[0] == "4608" and cols[4] == "2"
-    assert float(cols[5]) == pytest.approx(610.0)
+    assert cols[0] == "4608" and cols[4] == "3" and cols[5] == "1"
+    assert float(cols[6]) == pytest.approx(610.0)
     alg = ps.algorithmic_bytes(fused, 256, 4)
-    assert float(cols[6]) == pytest.approx(alg / MB, abs=0.05)
-    assert float(cols[7]) == pytest.approx(alg / 610e-6 / 1e12, abs=0.005)
-    assert float(cols[8]) == pytest.approx(alg / 610e-6 / 8e12, abs=0.0005)
+    assert float(cols[7]) == pytest.approx(alg / MB, abs=0.05)
+    assert float(cols[8]) == pytest.approx(alg / 610e-6 / 1e12, abs=0.005)
+    assert float(cols[9]) == pytest.approx(alg / 610e-6 / 8e12, abs=0.0005)
     # an FP64 kernel in an FP32 trace (a continuation on fewer load cases): no byte count
-    assert len(rows["k_inv_plane<double,"]) == len(fp64.split()) + 6
+    assert len(rows["k_inv_plane<double,"]) == len(fp64.split()) + 7
 
 
 def test_traffic_scaled_by_the_copy(tmp_path):
