@@ -220,8 +220,9 @@ __global__ __launch_bounds__(NT) void k_zgreen_el(Cx<T> *__restrict__ spec, Cx<T
     }
 }
 
-// The parity-layout z pass of k_zgreen_el<PAR> in two halves, for tiles
-// whose six components would fill a CU's LDS (FP32 256^3: 96 KiB).  The
+// The z pass of k_zgreen_el in two halves, for tiles whose six components
+// would fill a CU's LDS (96 KiB at FP32 256^3 and 512^3, FP64 256^3 and
+// 512^3); PAR as in k_zgreen_el (the parity layout, FP32 256^3).  The
 // tile is transformed three components at a time in 48 KiB: components
 // 0-2 forward, then held in registers at the Green points each thread
 // evaluates, while components 3-5 go forward in the same LDS; the Green
@@ -229,7 +230,7 @@ __global__ __launch_bounds__(NT) void k_zgreen_el(Cx<T> *__restrict__ spec, Cx<T
 // 3-5 go back and are stored, and components 0-2 return from registers,
 // go back and are stored.  Two or three tiles then share a CU, so one
 // tile's loads and stores run beside another's transforms.
-template <typename T, int N, int W, int NT>
+template <typename T, int N, int W, int NT, bool PAR = true>
 __global__ __launch_bounds__(NT) void k_zgreen_el_half(Cx<T> *__restrict__ spec, Cx<T> *__restrict__ nyq,
                                                        const Cx<T> *__restrict__ twg,
                                                        const DevParams *__restrict__ prm,
@@ -240,15 +241,18 @@ __global__ __launch_bounds__(NT) void k_zgreen_el_half(Cx<T> *__restrict__ spec,
     constexpr int H = N / 2, NW = N * W, NC = 6, NH = 3, NPH = NH * NW / 2, GP = NW / NT;
     constexpr int PC = par_chunk<T, W>();
     static_assert(NW % NT == 0, "whole Green points per thread");
-    static_assert(PC % W == 0 && H % PC == 0 && H % W == 0, "z tiles inside parity chunks");
+    static_assert(!PAR || (PC % W == 0 && H % PC == 0), "z tiles inside parity chunks");
+    static_assert(H % W == 0 && N % W == 0 && W % 2 == 0, "tile width must be even and divide N/2");
     __shared__ Cx<T> buf[NH * NW];
     __shared__ Cx<T> tws[N];
     const int tid = threadIdx.x;
     const int lc = blockIdx.x / TL::PER_LC;
-    const int t = ztile_par<N, W>(blockIdx.x - lc * TL::PER_LC);
+    int t;
+    if constexpr (PAR) t = ztile_par<N, W>(blockIdx.x - lc * TL::PER_LC);
+    else t = ztile_of<T, N, W>(blockIdx.x - lc * TL::PER_LC);
     if (st->done[lc]) return;
     Cx<T> *base;
-    const Cx<T> *pbase;
+    const Cx<T> *pbase = nullptr;
     size_t cstride, zstride, poff;
     int kx0, ky0, dkx, dky;
     if (t < TL::MAIN) {
@@ -258,7 +262,8 @@ __global__ __launch_bounds__(NT) void k_zgreen_el_half(Cx<T> *__restrict__ spec,
         dkx = 1;
         dky = 0;
         base = spec + (size_t)(NC * lc) * N * N * H + (size_t)ky * H + kx0;
-        pbase = specB + (size_t)(NC * lc) * N * N * H + (size_t)(ky % H) * N + (kx0 / PC) * (2 * PC) + kx0 % PC;
+        if constexpr (PAR)
+            pbase = specB + (size_t)(NC * lc) * N * N * H + (size_t)(ky % H) * N + (kx0 / PC) * (2 * PC) + kx0 % PC;
         poff = PC;
         cstride = (size_t)N * N * H;
         zstride = (size_t)N * H;
@@ -268,7 +273,7 @@ __global__ __launch_bounds__(NT) void k_zgreen_el_half(Cx<T> *__restrict__ spec,
         dkx = 0;
         dky = 1;
         base = nyq + (size_t)(NC * lc) * N * N + ky0;
-        pbase = nyqB + (size_t)(NC * lc) * N * N + (ky0 % H);
+        if constexpr (PAR) pbase = nyqB + (size_t)(NC * lc) * N * N + (ky0 % H);
         poff = H;
         cstride = (size_t)N * N;
         zstride = N;
@@ -278,12 +283,19 @@ __global__ __launch_bounds__(NT) void k_zgreen_el_half(Cx<T> *__restrict__ spec,
     auto load_half = [&](int c0) {
         for (int idx = tid; idx < NPH; idx += NT) {
             const int e0 = 2 * idx, c = e0 / NW, r = e0 - c * NW, zz = r / W, w = r - zz * W;
-            const Cx<T> *src = pbase + (c0 + c) * cstride + zz * zstride + w;
-            Cx<T> a, b, u, v;
-            gload2<T>(src, a, b);
-            gload2<T>(src + poff, u, v);
-            buf[e0] = upper ? a - u : a + u;
-            buf[e0 + 1] = upper ? b - v : b + v;
+            if constexpr (PAR) {
+                const Cx<T> *src = pbase + (c0 + c) * cstride + zz * zstride + w;
+                Cx<T> a, b, u, v;
+                gload2<T>(src, a, b);
+                gload2<T>(src + poff, u, v);
+                buf[e0] = upper ? a - u : a + u;
+                buf[e0 + 1] = upper ? b - v : b + v;
+            } else {
+                Cx<T> a, b;
+                gload2<T>(base + (c0 + c) * cstride + zz * zstride + w, a, b);
+                buf[e0] = a;
+                buf[e0 + 1] = b;
+            }
         }
     };
     auto store_half = [&](int c0) {
@@ -369,6 +381,13 @@ template <typename T, int N> struct ElasticInstance {
     // threads at 198 VGPRs 2248 us)
     static constexpr bool HALF = PARF && sizeof(T) == 4 && N == 256;
     static constexpr int NTH = 512;
+    // the plain-layout z pass in two halves wherever the six-component tile
+    // needs more than 64 KiB (FP32 256^3 outside the parity layout, 512^3;
+    // FP64 256^3, 512^3): two workgroups per CU, 512 threads in FP32 (107-121
+    // VGPRs), 256 in FP64 (208-220); per launch FP64 256^3 5195 -> 3224 us,
+    // FP32 512^3 30.8 -> 21.9 ms, FP64 512^3 77.5 -> 54.4 ms
+    static constexpr bool HALFZ = (size_t)6 * N * W * sizeof(Cx<T>) > 64 * 1024;
+    static constexpr int NTZH = sizeof(T) == 4 ? 512 : 256;
     static constexpr int PGRID = FIVE ? CH * N * (N / G) : CH * N * S;
     static constexpr int SP = FIVE ? 1 : S;
 
@@ -386,9 +405,14 @@ template <typename T, int N> struct ElasticInstance {
         }
     }
     static void zgreen(const LaunchArgs &a, hipStream_t s, int, int) {
-        hipLaunchKernelGGL((k_zgreen_el<T, N, W, NTZ>), dim3(NC * ZTiles<N, W>::PER_LC), dim3(NTZ), 0, s,
-                           (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st,
-                           (const Cx<T> *)nullptr, (const Cx<T> *)nullptr);
+        if constexpr (HALFZ)
+            hipLaunchKernelGGL((k_zgreen_el_half<T, N, W, NTZH, false>), dim3(NC * ZTiles<N, W>::PER_LC), dim3(NTZH),
+                               0, s, (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm,
+                               (const DevState *)a.st, (const Cx<T> *)nullptr, (const Cx<T> *)nullptr);
+        else
+            hipLaunchKernelGGL((k_zgreen_el<T, N, W, NTZ>), dim3(NC * ZTiles<N, W>::PER_LC), dim3(NTZ), 0, s,
+                               (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st,
+                               (const Cx<T> *)nullptr, (const Cx<T> *)nullptr);
     }
     // split planes: the first forward pass and the z pass of the parity layout
     static void fwd_par(const LaunchArgs &a, hipStream_t s, int) {
@@ -399,7 +423,7 @@ template <typename T, int N> struct ElasticInstance {
     }
     static void zgreen_par(const LaunchArgs &a, hipStream_t s, int, int) {
         if constexpr (HALF)
-            hipLaunchKernelGGL((k_zgreen_el_half<T, N, W, NTH>), dim3(NC * ZTiles<N, W>::PER_LC), dim3(NTH), 0, s,
+            hipLaunchKernelGGL((k_zgreen_el_half<T, N, W, NTH, true>), dim3(NC * ZTiles<N, W>::PER_LC), dim3(NTH), 0, s,
                                (Cx<T> *)a.spec, (Cx<T> *)a.nyq, (const Cx<T> *)a.tw, a.prm, (const DevState *)a.st,
                                (const Cx<T> *)a.spec2, (const Cx<T> *)a.nyq2);
         else if constexpr (PARF)
