@@ -666,14 +666,18 @@ template <int N, int W> struct ZTiles {
 };
 
 // Tile of the t-th workgroup of a load case.  When a tile row is shorter than
-// a 128-byte line, the two tiles that share each line (neighbouring kx chunks
-// of one ky, or neighbouring ky groups of the kx = N/2 column) go to
-// workgroups 8 apart: workgroups are dealt round-robin to the 8 XCDs, so both
-// run on one XCD and the second read of the line hits its L2.
+// a 128-byte line, the tiles that share each line (neighbouring kx chunks of
+// one ky, or neighbouring ky groups of the kx = N/2 column: two of 64-byte
+// rows, four of 32-byte rows) go to workgroups 8 apart: workgroups are dealt
+// round-robin to the 8 XCDs, so they run on one XCD and the repeated reads
+// of the line hit its L2.  Within each block of 16 (pairs) or 32 (quads)
+// workgroups this is a permutation, so every tile is taken once.
 template <typename T, int N, int W> __device__ __forceinline__ int ztile_of(int t) {
     using TL = ZTiles<N, W>;
-    constexpr bool PAIR = W * (int)sizeof(Cx<T>) < 128 && TL::MAIN % 16 == 0 && TL::NYQ % 16 == 0 &&
-                          (TL::H / W) % 2 == 0;
+    constexpr int RB = W * (int)sizeof(Cx<T>);
+    constexpr bool QUAD = RB <= 32 && TL::MAIN % 32 == 0 && TL::NYQ % 32 == 0 && (TL::H / W) % 4 == 0;
+    constexpr bool PAIR = !QUAD && RB < 128 && TL::MAIN % 16 == 0 && TL::NYQ % 16 == 0 && (TL::H / W) % 2 == 0;
+    if constexpr (QUAD) return (t & ~31) | ((t & 7) << 2) | ((t >> 3) & 3);
     if constexpr (PAIR) return (t & ~15) | ((t & 7) << 1) | ((t >> 3) & 1);
     return t;
 }
